@@ -1,0 +1,185 @@
+"""Single-path (Alg. 1) and multi-path (Alg. 2) drivers of the oracle.
+
+Oracle -- test infrastructure only (see the package docstring).
+
+Chunk construction (Sec. IV-C): operations are scanned in order; unitary gates
+are appended to the branch's chunk; a classically controlled gate is appended
+when its condition holds on the branch's register and skipped otherwise
+(Sec. IV-B2); a chunk is compressed when it holds k operations, or, when it is
+non-empty, before a measurement; a residual chunk is compressed at the end.
+
+Single path (Alg. 1): a measurement samples outcome m with probability p_m
+(here: m = 0 when the supplied uniform u < p_0), p <- p p_m, the outcome is
+written to its bit, and the fidelity estimate is the product of the partial
+fidelities (Sec. III-C).
+
+Multi path (Alg. 2): a measurement replaces each branch by one child per
+outcome with p_m > eps (m = 0 first), each with p p_m, the updated register,
+the parent's fidelity and an empty chunk; after the measurement, if more than
+M branches are live only the M with the largest p are kept (stable order on
+ties; no renormalisation, the dropped mass is reported).  Multi-path fidelity
+is the probability-weighted mean of the branch fidelities (Sec. V-C).
+"""
+from __future__ import annotations
+
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+from inputs.circuits import CGate, Circuit, Gate, Measure
+from inputs.randomness import bra_init_gaussians
+
+from . import mps as M
+
+EPS_BRANCH = 1e-10
+
+
+def holds(cond, c) -> bool:
+    """Condition phi(c): XOR of the selected bits equals the stated value."""
+    return (sum(int(c[b]) for b in cond.bits) % 2) == int(cond.value)
+
+
+class Simulator:
+    """Parameters shared by both strategies: bond cap chi, chunk size k,
+    sweeps s, the seed of the starting guess."""
+
+    def __init__(self, n: int, chi: int, k: int, n_sweeps: int = 2, init_seed: int = 7):
+        self.n, self.chi, self.k, self.s, self.init_seed = n, chi, k, n_sweeps, init_seed
+        self._bra = {}
+
+    def bra_init(self, chi: int) -> List[np.ndarray]:
+        if chi not in self._bra:
+            self._bra[chi] = M.generic_bra(bra_init_gaussians(self.n, chi, self.init_seed))
+        return self._bra[chi]
+
+    def compress(self, state, chunk, chi: int):
+        mpo = M.chunk_mpo(self.n, chunk)
+        new, f, centre = M.compress(state, mpo, self.bra_init(chi), self.s)
+        return new, f
+
+
+def _unitary(op):
+    g = op.gate if isinstance(op, CGate) else op
+    return (tuple(g.qubits), g.mat)
+
+
+def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[float]] = None,
+                    outcomes: Optional[Sequence[int]] = None) -> Dict:
+    """Alg. 1.  Outcomes come from ``outcomes`` when given (replay), else from
+    ``uniforms`` (m = 0 iff u < p_0).  Returns the fidelity estimate, path
+    probability, register, final MPS and the per-measurement records."""
+    state = M.zero_state(circ.n_qubits, sim.chi)
+    c = [0] * circ.n_bits
+    p, fid = 1.0, 1.0
+    chunk: List = []
+    rec = {"outcomes": [], "pms": [], "p0s": [], "fids": []}
+    i_meas = 0
+
+    def flush():
+        nonlocal state, fid, chunk
+        state, f = sim.compress(state, chunk, sim.chi)
+        fid *= f
+        rec["fids"].append(f)
+        chunk = []
+
+    for op in circ.ops:
+        if isinstance(op, CGate) and not holds(op.cond, c):
+            continue
+        if isinstance(op, Measure):
+            if chunk:
+                flush()
+            n0, n1 = M.outcome_norms(state, op.qubit)
+            p0 = n0 / (n0 + n1)
+            if outcomes is not None:
+                m = int(outcomes[i_meas])
+            else:
+                m = 0 if uniforms[i_meas] < p0 else 1
+            nm = (n0, n1)[m]
+            pm = nm / (n0 + n1)
+            if pm <= EPS_BRANCH:
+                raise ValueError("sampled an outcome of vanishing probability")
+            state = M.collapse(state, op.qubit, m, nm)
+            p *= pm
+            c[op.bit] = m
+            rec["outcomes"].append(m)
+            rec["pms"].append(pm)
+            rec["p0s"].append(p0)
+            i_meas += 1
+        else:
+            chunk.append(_unitary(op))
+            if len(chunk) == sim.k:
+                flush()
+    if chunk:
+        flush()
+    return {"F": fid, "p": p, "c": c, "mps": state, **rec}
+
+
+def topk_by_weight(weights: Sequence[float], k: int):
+    """Indices of the k largest weights in descending order, ties kept in
+    list order (stable), and the total weight of the rest."""
+    order = sorted(range(len(weights)), key=lambda i: -weights[i])   # stable
+    keep = order[:k]
+    dropped = float(sum(weights[i] for i in order[k:]))
+    return keep, dropped
+
+
+def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = None,
+                   chi_of: Optional[Callable[[tuple], int]] = None,
+                   eps: float = EPS_BRANCH) -> Dict:
+    """Alg. 2.  ``chi_of(path)`` gives a child's bond cap (default: sim.chi).
+    Returns the live branches (path, p, c, F, mps, chi), the dropped mass and
+    the probability-weighted fidelity."""
+    live = [{"path": (), "p": 1.0, "c": [0] * circ.n_bits, "F": 1.0, "chunk": [],
+             "mps": M.zero_state(circ.n_qubits, sim.chi), "chi": sim.chi}]
+    dropped = 0.0
+    n_compress = 0
+    for op in circ.ops:
+        nxt = []
+        for b in live:
+            if isinstance(op, CGate) and not holds(op.cond, b["c"]):
+                nxt.append(b)
+                continue
+            if isinstance(op, Measure):
+                if b["chunk"]:
+                    b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
+                    b["F"] *= f
+                    b["chunk"] = []
+                    n_compress += 1
+                n0, n1 = M.outcome_norms(b["mps"], op.qubit)
+                for m, nm in ((0, n0), (1, n1)):
+                    pm = nm / (n0 + n1)
+                    if pm > eps:
+                        c = list(b["c"])
+                        c[op.bit] = m
+                        path = b["path"] + (m,)
+                        nxt.append({"path": path, "p": b["p"] * pm, "c": c, "F": b["F"],
+                                    "chunk": [], "mps": M.collapse(b["mps"], op.qubit, m, nm),
+                                    "chi": chi_of(path) if chi_of else b["chi"]})
+            else:
+                b["chunk"].append(_unitary(op))
+                if len(b["chunk"]) == sim.k:
+                    b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
+                    b["F"] *= f
+                    b["chunk"] = []
+                    n_compress += 1
+                nxt.append(b)
+        live = nxt
+        if isinstance(op, Measure) and max_branches is not None and len(live) > max_branches:
+            keep, d = topk_by_weight([b["p"] for b in live], max_branches)
+            dropped += d
+            live = [live[i] for i in keep]
+    for b in live:
+        if b["chunk"]:
+            b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
+            b["F"] *= f
+            b["chunk"] = []
+            n_compress += 1
+    ptot = sum(b["p"] for b in live)
+    fmp = sum(b["p"] * b["F"] for b in live) / ptot if ptot > 0 else float("nan")
+    return {"branches": live, "dropped": dropped, "F_mp": fmp, "n_compress": n_compress}
+
+
+def tvd(p: Dict, q: Dict) -> float:
+    """Total variation distance 1/2 sum |p_g - q_g| over the union of paths."""
+    keys = set(p) | set(q)
+    return 0.5 * sum(abs(p.get(k, 0.0) - q.get(k, 0.0)) for k in keys)

@@ -1,0 +1,206 @@
+"""Pins of the oracle's MPS compression step and dynamic operations against
+brute force, closed forms and the Eckart-Young bound (no oracle formula is
+re-typed here: each check uses an independent route to the same number)."""
+import numpy as np
+import pytest
+
+from inputs import circuits as C
+from inputs.randomness import bra_init_gaussians
+from oracle import dynamic as D
+from oracle import mps as M
+from oracle import statevector as SV
+
+
+def _random_chunk(rng, n, layers, one_qubit=True):
+    ops = []
+    for layer in range(layers):
+        for q in range(layer % 2, n - 1, 2):
+            ops.append(((q, q + 1), C.haar_unitary(rng, 4)))
+        if one_qubit:
+            q = int(rng.integers(n))
+            ops.append(((q,), C.haar_unitary(rng, 2)))
+    return ops
+
+
+def _mpo_full_operator(mpo):
+    """Contract the layered operator into a 2^n x 2^n matrix."""
+    t = mpo[0][0]                                   # [s, t, w]
+    out_dim = 2
+    t = t.reshape(2, 2, -1)
+    for w in mpo[1:]:
+        t = np.einsum("ijw,wstv->isjtv", t, w).reshape(out_dim * 2, out_dim * 2, -1)
+        out_dim *= 2
+    return t[:, :, 0]
+
+
+def test_split_ranks():
+    rng = np.random.default_rng(1)
+    assert M.split_two_qubit(C.haar_unitary(rng, 4))[0].shape[3] == 4
+    assert M.split_two_qubit(C.CNOT_01)[0].shape[3] == 2
+    assert M.split_two_qubit(np.kron(C.H, C.X))[0].shape[3] == 1
+
+
+@pytest.mark.parametrize("layers", [1, 2, 3])
+def test_chunk_operator_equals_gate_product(layers):
+    rng = np.random.default_rng(10 + layers)
+    n = 5
+    ops = _random_chunk(rng, n, layers)
+    full = np.eye(2 ** n, dtype=complex)
+    for qubits, mat in ops:
+        full = SV.full_operator(n, qubits, mat) @ full
+    np.testing.assert_allclose(_mpo_full_operator(M.chunk_mpo(n, ops)), full, atol=1e-12)
+
+
+def test_asap_layering_order():
+    # a 1q gate between two 2q gates on the same qubit must stay between them
+    g = np.eye(4)
+    ops = [((0, 1), g), ((1,), np.eye(2)), ((1, 2), g), ((0,), np.eye(2))]
+    lay = M.asap_layers(ops)
+    assert [len(x) for x in lay] == [1, 2, 1]
+    assert lay[1][0][0] == (1,) and lay[1][1][0] == (0,)
+
+
+def test_generic_bra_is_right_canonical():
+    b = M.generic_bra(bra_init_gaussians(9, 8, 3))
+    for j in range(1, 9):
+        a = b[j].reshape(b[j].shape[0], -1)
+        np.testing.assert_allclose(a @ a.conj().T, np.eye(a.shape[0]), atol=1e-13)
+
+
+def _exact_case(n, n_sweeps, seed):
+    rng = np.random.default_rng(seed)
+    chi = 2 ** (n // 2)
+    circ_ops = _random_chunk(rng, n, 3)
+    # a random normalised input MPS (exactly representable at this chi)
+    psi0 = [rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape)
+            for a in M.zero_state(n, chi)]
+    nrm = np.sqrt(M.norm_sq(psi0))
+    psi0[0] = psi0[0] / nrm
+    new, f, centre = M.compress(psi0, M.chunk_mpo(n, circ_ops), M.generic_bra(
+        bra_init_gaussians(n, chi, seed)), n_sweeps)
+    sv = M.to_statevector(psi0)
+    for qubits, mat in circ_ops:
+        sv = SV.apply_gate(sv, n, qubits, mat)
+    return new, f, centre, sv
+
+
+@pytest.mark.parametrize("n,n_sweeps", [(4, 1), (6, 1), (6, 2), (8, 2), (10, 2), (7, 3)])
+def test_compress_exact_regime(n, n_sweeps):
+    new, f, centre, sv = _exact_case(n, n_sweeps, seed=100 + n)
+    v = M.to_statevector(new)
+    assert abs(np.linalg.norm(v) - 1) < 1e-12
+    assert abs(abs(np.vdot(sv, v)) ** 2 - 1) < 1e-12
+    assert abs(f - 1) < 1e-12
+    assert centre == (n - 1 if n_sweeps % 2 == 1 else 0)
+
+
+def test_compress_gauge_after_sweeps():
+    n = 8
+    for s, expect in ((1, "left"), (2, "right")):
+        new, f, centre, _ = _exact_case(n, s, seed=7)
+        for j in range(n):
+            if j == centre:
+                continue
+            a = new[j]
+            if expect == "left":
+                m = a.reshape(-1, a.shape[2])
+                np.testing.assert_allclose(m.conj().T @ m, np.eye(m.shape[1]), atol=1e-12)
+            else:
+                m = a.reshape(a.shape[0], -1)
+                np.testing.assert_allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-12)
+
+
+@pytest.mark.parametrize("chi,s", [(2, 1), (4, 2), (3, 2), (4, 4)])
+def test_truncated_fidelity_is_overlap(chi, s):
+    """f equals |<psi~'|U|psi~>|^2 computed from contracted vectors."""
+    n = 8
+    rng = np.random.default_rng(chi * 10 + s)
+    psi = M.zero_state(n, chi)
+    ops0 = _random_chunk(rng, n, 2, one_qubit=False)
+    sim_init = M.generic_bra(bra_init_gaussians(n, chi, 1))
+    psi, _, _ = M.compress(psi, M.chunk_mpo(n, ops0), sim_init, 2)
+    ops = _random_chunk(rng, n, 2)
+    new, f, _ = M.compress(psi, M.chunk_mpo(n, ops), sim_init, s)
+    target = M.to_statevector(psi)
+    for qubits, mat in ops:
+        target = SV.apply_gate(target, n, qubits, mat)
+    v = M.to_statevector(new)
+    assert abs(np.linalg.norm(v) - 1) < 1e-12
+    assert abs(abs(np.vdot(v, target)) ** 2 - f) < 1e-12
+    assert 0.0 < f <= 1.0 + 1e-12
+
+
+def test_eckart_young_single_bond():
+    """Truncation at one bond only: f never exceeds the sum of the kept squared
+    Schmidt coefficients and reaches it when the sweeps converge."""
+    n, chi = 4, 2
+    rng = np.random.default_rng(42)
+    start = [((0,), C.H), ((0, 1), C.CNOT_01), ((2,), C.H), ((2, 3), C.CNOT_01)]
+    init = M.generic_bra(bra_init_gaussians(n, chi, 5))
+    psi, f0, _ = M.compress(M.zero_state(n, chi), M.chunk_mpo(n, start), init, 2)
+    assert abs(f0 - 1) < 1e-12
+    gate = [((1, 2), C.haar_unitary(rng, 4))]
+    target = M.to_statevector(psi)
+    target = SV.apply_gate(target, n, (1, 2), gate[0][1])
+    sv = np.linalg.svd(target.reshape(4, 4), compute_uv=False)
+    bound = float(np.sum(sv[:chi] ** 2))
+    assert bound < 1 - 1e-3                        # the gate really is truncated
+    for s in (1, 2, 3):
+        _, f, _ = M.compress(psi, M.chunk_mpo(n, gate), init, s)
+        assert f <= bound + 1e-12
+    prev = 0.0
+    for s in (4, 8, 16):                           # monotone approach
+        _, f, _ = M.compress(psi, M.chunk_mpo(n, gate), init, s)
+        assert prev - 1e-14 <= f <= bound + 1e-12
+        prev = f
+    _, f40, _ = M.compress(psi, M.chunk_mpo(n, gate), init, 40)
+    assert abs(f40 - bound) < 1e-12
+
+
+def test_measure_and_collapse_match_statevector():
+    n, chi = 7, 8
+    rng = np.random.default_rng(9)
+    psi = M.zero_state(n, chi)
+    init = M.generic_bra(bra_init_gaussians(n, chi, 2))
+    psi, _, _ = M.compress(psi, M.chunk_mpo(n, _random_chunk(rng, n, 3)), init, 2)
+    sv = M.to_statevector(psi)
+    for q in range(n):
+        n0, n1 = M.outcome_norms(psi, q)
+        s0, s1 = SV.outcome_norms(sv, n, q)
+        assert abs(n0 - s0) < 1e-13 and abs(n1 - s1) < 1e-13
+        for m, nm in ((0, n0), (1, n1)):
+            post = M.to_statevector(M.collapse(psi, q, m, nm))
+            np.testing.assert_allclose(post, SV.project(sv, n, q, m, nm), atol=1e-12)
+
+
+def test_single_path_exact_regime_replays_statevector():
+    circ, p = C.workload("cfg1_n10_chi16", n=8, depth=8, chi=16)
+    sim = D.Simulator(8, 16, k=1000, n_sweeps=2, init_seed=7)
+    u = np.random.default_rng(11).random(64)
+    r = D.run_single_path(circ, sim, uniforms=u)
+    ref = SV.replay(circ, r["outcomes"])
+    assert abs(r["p"] - ref["p"]) < 1e-12
+    np.testing.assert_allclose(r["pms"], ref["pms"], atol=1e-12)
+    assert abs(r["F"] - 1) < 1e-11
+    v = M.to_statevector(r["mps"])
+    assert abs(abs(np.vdot(ref["psi"], v)) ** 2 - 1) < 1e-11
+
+
+def test_single_path_chunking_with_small_k():
+    """Chunk size 3 forces compressions in the middle of unitary segments; in
+    the exact regime the result must not change."""
+    circ, p = C.workload("cfg1_n10_chi16", n=6, depth=6, chi=8)
+    u = np.random.default_rng(2).random(64)
+    r1 = D.run_single_path(circ, D.Simulator(6, 8, k=1000), uniforms=u)
+    r2 = D.run_single_path(circ, D.Simulator(6, 8, k=3), uniforms=u)
+    assert r1["outcomes"] == r2["outcomes"]
+    assert len(r2["fids"]) > len(r1["fids"])
+    assert abs(abs(M.overlap(r1["mps"], r2["mps"])) ** 2 - 1) < 1e-11
+
+
+def test_topk_stable_and_mass():
+    keep, dropped = D.topk_by_weight([0.1, 0.3, 0.3, 0.05, 0.25], 3)
+    assert keep == [1, 2, 4]
+    assert abs(dropped - 0.15) < 1e-15
+    keep, dropped = D.topk_by_weight([0.2] * 5, 2)
+    assert keep == [0, 1] and abs(dropped - 0.6) < 1e-15
