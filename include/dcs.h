@@ -1,0 +1,207 @@
+/*
+ * dcs.h -- C ABI of the MI355X (gfx950) library for tensor-network simulation
+ * of dynamic circuits: the MPS compression step of a unitary chunk, the
+ * measurement probability, the collapse on an outcome and top-M branch
+ * retention.
+ *
+ * Method (Fulginiti, Poggiali, Mendl, "Tensor Network Simulation of Dynamic
+ * Circuits"):
+ *   Sec. III-B    MPS state: site tensors A_j[chi_j][2][chi_{j+1}]
+ *   Sec. III-C    compression step of a unitary chunk (Defs. "Unitary chunk",
+ *                 "Compression step"), optimum T = F / sqrt(<F|F>), partial
+ *                 fidelity f, global fidelity = product of the f
+ *   Sec. IV-A     branch = (p, classical register, TN state)
+ *   Sec. IV-B1    p_m = <psi|P_m|psi> by contraction; collapse = projector on
+ *                 the local leg and renormalisation by 1/sqrt(p_m)
+ *   Sec. IV-C     chunk construction (done by the caller)
+ *   Alg. 1 / 2    single-path sampling and multi-path branching with top-M
+ *                 retention (control flow done by the caller)
+ *
+ * Conventions
+ *   - Every function returns an int status: DCS_OK (0) or a negative code;
+ *     no function aborts or throws.  dcs_last_error() gives a thread-local
+ *     message for the last failure on the calling thread.
+ *   - Complex numbers on the host are interleaved (re, im) doubles.
+ *   - Device memory of a state is owned by the caller (one buffer of
+ *     dcs_state_bytes() bytes, at least 256-byte aligned) and must outlive the
+ *     state; the library never frees it.  Host arrays are only read during a
+ *     call.  Opaque handles are owned by the caller and released with the
+ *     matching *_destroy.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     of a call is enqueued on it; calls that return host values synchronise
+ *     that stream before returning.
+ *   - Qubit q of the chain is the paper's Q_{q+1}; two-qubit gates act on
+ *     adjacent qubits (q, q+1).
+ *   - Bond dimensions are fixed and zero padded: for bond cap chi the bond b
+ *     (between sites b-1 and b) has chi_b = min(chi, 2^b, 2^(n-b)).
+ *   - A state holds `capacity` branch slots; a branch is named by its slot
+ *     id in [0, capacity).  Calls that take arrays of ids run all listed
+ *     branches together (batched launches); ids in one call must be distinct.
+ *   - Calls on one state are not thread-safe; use one host thread per state.
+ */
+#ifndef DCS_H
+#define DCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum dcs_status {
+  DCS_OK = 0,
+  DCS_EINVAL = -1,      /* bad argument (range, null pointer, duplicate id) */
+  DCS_ENONLOCAL = -2,   /* two-qubit gate not on adjacent qubits (q, q+1)   */
+  DCS_EZEROPROB = -3,   /* collapse on an outcome with p_m <= eps           */
+  DCS_ECAPACITY = -4,   /* branch id outside the state's capacity           */
+  DCS_ENOMEM = -5,      /* buffer too small / chunk operator wider than the
+                           state's maximum operator bond                     */
+  DCS_EHIP = -6,        /* a HIP runtime call failed                        */
+  DCS_ESTATE = -7,      /* call not valid in the branch's current state
+                           (branch not live, collapse without a measurement,
+                           no starting guess registered for its bond cap)   */
+  DCS_ENUMERIC = -8     /* vanishing environment tensor (<F|F> = 0)         */
+};
+
+enum dcs_precision {
+  DCS_C128 = 0,         /* complex128 storage and contractions (FP64 MFMA)  */
+  DCS_C64 = 1           /* complex64 storage, contractions on FP32 MFMA with
+                           FP32 accumulation; QR, norms, probabilities and
+                           renormalisation stay in FP64                      */
+};
+
+typedef struct dcs_ctx dcs_ctx;
+typedef struct dcs_state dcs_state;
+typedef struct dcs_chunk dcs_chunk;
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *dcs_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int dcs_version(void);
+
+/* Context bound to one HIP device: holds host-side caches (gate splits,
+ * pinned staging) and optional launch timing.  `device` is a HIP ordinal. */
+int dcs_ctx_create(dcs_ctx **out, int device);
+int dcs_ctx_destroy(dcs_ctx *ctx);
+
+/* Per-kernel-class launch timing with HIP events on the caller's stream
+ * (off by default).  Classes: 0 contraction GEMMs of the compression step,
+ * 1 gate-operator application, 2 QR/LQ gauge shift, 3 measurement
+ * contractions, 4 other.  dcs_ctx_timing returns, per class, the number of
+ * launches, their summed duration in ms, and the algorithmic flops and HBM
+ * bytes (unpadded shapes) of those launches; arrays have 5 entries. */
+int dcs_ctx_set_timing(dcs_ctx *ctx, int enabled);
+int dcs_ctx_timing(dcs_ctx *ctx, long long *launches, double *ms, double *flops,
+                   double *bytes, int reset);
+
+/* Bytes of device memory a state needs: `precision` a dcs_precision; n_qubits
+ * >= 1; capacity branch slots; chi_max the largest bond cap any branch uses;
+ * mpo_bond_max the largest operator bond dimension of any chunk that will be
+ * compressed (1-2 layers of 2-qubit gates: 4; 3 layers: 16); n_init_slots the
+ * number of distinct bond caps with a registered starting guess. */
+int dcs_state_bytes(int precision, int n_qubits, int capacity, int chi_max,
+                    int mpo_bond_max, int n_init_slots, size_t *bytes_out);
+
+/* Create a state over the caller's device buffer `d_buffer` of `bytes` bytes
+ * (from dcs_state_bytes with the same arguments).  All slots start released. */
+int dcs_state_create(dcs_ctx *ctx, dcs_state **out, int precision, int n_qubits,
+                     int capacity, int chi_max, int mpo_bond_max, int n_init_slots,
+                     void *d_buffer, size_t bytes, void *stream);
+int dcs_state_destroy(dcs_state *st);
+
+/* Register the starting guess of every compression step into bond cap
+ * `chi_cap` (Sec. III-C leaves it open; here a fixed generic right-canonical
+ * MPS).  `gauss` holds the random Gaussian site tensors G_j (host, complex128
+ * interleaved, sites j = 0..n-1 concatenated, each row-major
+ * [chi_j][2][chi_{j+1}] for the padded dims of chi_cap).  Site j >= 1 becomes
+ * the orthonormal-row factor of LQ(G_j as chi_j x 2chi_{j+1}) (FP64 on the
+ * GPU); site 0 becomes G_0 / |G_0|. */
+int dcs_state_set_init(dcs_state *st, int chi_cap, const double *gauss, void *stream);
+
+/* Make the listed slots live branches in |0...0> (A_j[0][0][0] = 1) with bond
+ * caps chi_caps[i] (1 <= cap <= chi_max). */
+int dcs_branch_init_zero(dcs_state *st, int n, const int *ids, const int *chi_caps,
+                         void *stream);
+/* Change the bond cap the next compression step of each branch compresses
+ * into (the current tensors keep their dims until then). */
+int dcs_branch_set_chi(dcs_state *st, int n, const int *ids, const int *chi_caps);
+/* Release slots (their contents become undefined). */
+int dcs_branch_release(dcs_state *st, int n, const int *ids);
+/* Bond dims chi_0..chi_n (n_qubits+1 ints) of a live branch's tensors. */
+int dcs_branch_dims(const dcs_state *st, int id, int *dims_out);
+
+/* Compile one chunk (Def. "Unitary chunk", Sec. IV-C) of n_ops unitaries in
+ * time order into one layered operator per site: q0[i] the first qubit, q1[i]
+ * = q0[i] + 1 for a two-qubit gate or -1 for a one-qubit gate; `mats` holds
+ * the matrices back to back (complex128 interleaved, row-major, 2x2 or 4x4 in
+ * basis |q0 q1> with q0 the more significant bit).  Gates are placed in ASAP
+ * layers; a two-qubit gate is split across its qubits by an SVD of its
+ * operator-Schmidt matrix (singular values above 1e-14 of the largest kept);
+ * per site the layer operators are multiplied in time order.  Errors:
+ * DCS_ENONLOCAL for a non-adjacent pair, DCS_EINVAL for a qubit out of range.
+ * Host-only; the handle is independent of any state.  `ctx` may be NULL
+ * (no caching of gate splits across calls). */
+int dcs_chunk_compile(dcs_ctx *ctx, dcs_chunk **out, int n_qubits, int n_ops,
+                      const int *q0, const int *q1, const double *mats);
+/* Operator bond dims w_0..w_n (n_qubits+1 ints; w_0 = w_n = 1). */
+int dcs_chunk_bonds(const dcs_chunk *ch, int *w_out);
+int dcs_chunk_destroy(dcs_chunk *ch);
+
+/* Compression step (Sec. III-C) of branch ids[i] with chunk chunks[i], all
+ * branches swept together: starting guess of the branch's bond cap, right
+ * environments, then n_sweeps alternating sweeps (first left-to-right over
+ * sites 0..n-1, then right-to-left over n-2..0, ...).  At each visited site
+ * F = environment contraction, T = F/|F|; QR (moving right) or LQ (moving
+ * left) of T in FP64 gives the site tensor and the next environment; the last
+ * update keeps T and gives the partial fidelity f = <F|F>, written to
+ * fid_out[i] (host).  Afterwards the orthogonality centre is site 0 (even
+ * n_sweeps) or n-1 (odd).  Synchronises `stream`. */
+int dcs_compress_step(dcs_state *st, int n, const int *ids,
+                      const dcs_chunk *const *chunks, int n_sweeps, double *fid_out,
+                      void *stream);
+
+/* Measurement probability (Sec. IV-B1) of qubit qubits[i] of branch ids[i]:
+ * n_m = <psi|P_m|psi> (m = 0, 1) contracted in FP64 from the network,
+ * p0_out[i] = n_0 / (n_0 + n_1) (host).  The norms are kept for the next
+ * dcs_collapse of that branch.  Synchronises `stream`. */
+int dcs_measure_prob(dcs_state *st, int n, const int *ids, const int *qubits,
+                     double *p0_out, void *stream);
+
+/* Collapse (Sec. IV-B1, Alg. 2 "Collapse"): for each i, the branch src_ids[i]
+ * measured on qubits[i] by the last dcs_measure_prob becomes, in slot
+ * dst_ids[i], P_m psi / sqrt(n_m) with m = outcomes[i]: the slice 1-m of the
+ * site tensor is zeroed and slice m scaled by 1/sqrt(n_m) (FP64 factor).
+ * dst == src collapses in place; otherwise the branch is first copied to the
+ * (released) slot dst, which becomes live with the source's bond cap.  All
+ * copies happen before any in-place update, so one source may feed two
+ * children (one in place, one copied).  pm_out[i] = n_m / (n_0 + n_1) (host,
+ * may be NULL).  DCS_EZEROPROB if p_m <= eps (nothing is changed). */
+int dcs_collapse(dcs_state *st, int n, const int *src_ids, const int *qubits,
+                 const int *outcomes, const int *dst_ids, double eps, double *pm_out,
+                 void *stream);
+
+/* Top-M retention (Alg. 2, after a measurement): indices of the k largest of
+ * weights[0..n) in descending order, ties in index order (stable), into
+ * keep_idx_out (capacity >= min(n, k)); *n_keep_out = min(n, k);
+ * *discarded_out = sum of the weights not kept.  Host-only, pure. */
+int dcs_topk_by_weight(int n, const double *weights, int k, int *keep_idx_out,
+                       int *n_keep_out, double *discarded_out);
+
+/* FP64 host copy of branch `id`'s MPS: sites concatenated, each row-major
+ * [chi_j][2][chi_{j+1}] complex128 interleaved (2 * sum chi_j*2*chi_{j+1}
+ * doubles, at most cap_doubles); dims_out gets chi_0..chi_n. */
+int dcs_export_mps(dcs_state *st, int id, double *host_out, size_t cap_doubles,
+                   int *dims_out, void *stream);
+/* Load an MPS into branch `id` (becomes live, bond cap chi_cap) from the same
+ * layout; dims_in[b] <= min(chi_max, 2^b, 2^(n-b)), dims_in[0] = dims_in[n]
+ * = 1.  No canonical form is assumed. */
+int dcs_import_mps(dcs_state *st, int id, int chi_cap, const double *host_in,
+                   const int *dims_in, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCS_H */

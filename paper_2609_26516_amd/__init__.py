@@ -1,0 +1,10 @@
+"""MI355X (gfx950) implementation of the hot path of tensor-network simulation
+of dynamic circuits: the MPS compression step of a unitary chunk, measurement
+probability, collapse and top-M branch retention, behind the C ABI of
+include/dcs.h (libdcs.so, built in-tree by ``python -m
+paper_2609_26516_amd.build``).
+
+Modules: ``capi`` (ctypes binding, same names as the C functions),
+``engine`` (single-path and multi-path drivers over the binding).
+"""
+__all__ = ["capi", "engine", "build"]

@@ -1,0 +1,72 @@
+"""Build the gfx950 shared library libdcs.so in-tree with hipcc.
+
+Usage: python -m paper_2609_26516_amd.build   (or call build())
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libdcs.so")
+SOURCES = ["gemm.hip", "kernels.hip", "runtime.cpp"]
+
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions are disabled for all device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-result", "-Wno-pass-failed",
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm toolchain required)")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source for gfx950 and link libdcs.so next to this file."""
+    cc = hipcc()
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    with tempfile.TemporaryDirectory(prefix="dcs_build_") as tmp:
+        objs = []
+        procs = []
+        for src in SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            cmd = [cc, *FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+            if src.endswith(".cpp"):
+                cmd.insert(1, "-xhip")
+            procs.append((src, cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                     stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = []
+        for src, cmd, p in procs:
+            out, _ = p.communicate()
+            out = "\n".join(line for line in out.splitlines()
+                            if "packed-fp32-ops" not in line)
+            if verbose and out.strip():
+                print(out)
+            if p.returncode != 0:
+                failed.append((src, out))
+        if failed:
+            msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
+            raise RuntimeError("hipcc failed:\n" + msg)
+        tmp_lib = os.path.join(tmp, "libdcs.so")
+        cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp_lib]
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed:\n" + r.stdout)
+        shutil.copyfile(tmp_lib, LIB + ".tmp")
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

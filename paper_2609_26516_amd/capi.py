@@ -1,0 +1,243 @@
+"""ctypes binding of libdcs.so: the C functions of include/dcs.h under the same
+names, with argument marshalling only (numpy arrays for host arrays, integers
+for device pointers and hipStream_t handles).  Every non-zero status raises
+DcsError carrying the library's message.  There is no fallback: if the
+library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_longlong, c_size_t, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdcs.so")
+
+DCS_OK, DCS_EINVAL, DCS_ENONLOCAL, DCS_EZEROPROB = 0, -1, -2, -3
+DCS_ECAPACITY, DCS_ENOMEM, DCS_EHIP, DCS_ESTATE, DCS_ENUMERIC = -4, -5, -6, -7, -8
+DCS_C128, DCS_C64 = 0, 1
+STATUS_NAMES = {0: "DCS_OK", -1: "DCS_EINVAL", -2: "DCS_ENONLOCAL", -3: "DCS_EZEROPROB",
+                -4: "DCS_ECAPACITY", -5: "DCS_ENOMEM", -6: "DCS_EHIP", -7: "DCS_ESTATE",
+                -8: "DCS_ENUMERIC"}
+EXPORTED = [
+    "dcs_last_error", "dcs_version", "dcs_ctx_create", "dcs_ctx_destroy", "dcs_ctx_set_timing",
+    "dcs_ctx_timing", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
+    "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
+    "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
+    "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
+    "dcs_export_mps", "dcs_import_mps",
+]
+
+
+class DcsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2609_26516_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = c_void_p
+_IP = POINTER(c_int)
+_DP = POINTER(c_double)
+
+_SIGS = {
+    "dcs_last_error": (ctypes.c_char_p, []),
+    "dcs_version": (c_int, []),
+    "dcs_ctx_create": (c_int, [POINTER(c_void_p), c_int]),
+    "dcs_ctx_destroy": (c_int, [_P]),
+    "dcs_ctx_set_timing": (c_int, [_P, c_int]),
+    "dcs_ctx_timing": (c_int, [_P, POINTER(c_longlong), _DP, _DP, _DP, c_int]),
+    "dcs_state_bytes": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
+    "dcs_state_create": (c_int, [_P, POINTER(c_void_p), c_int, c_int, c_int, c_int, c_int, c_int,
+                                 _P, c_size_t, _P]),
+    "dcs_state_destroy": (c_int, [_P]),
+    "dcs_state_set_init": (c_int, [_P, c_int, _DP, _P]),
+    "dcs_branch_init_zero": (c_int, [_P, c_int, _IP, _IP, _P]),
+    "dcs_branch_set_chi": (c_int, [_P, c_int, _IP, _IP]),
+    "dcs_branch_release": (c_int, [_P, c_int, _IP]),
+    "dcs_branch_dims": (c_int, [_P, c_int, _IP]),
+    "dcs_chunk_compile": (c_int, [_P, POINTER(c_void_p), c_int, c_int, _IP, _IP, _DP]),
+    "dcs_chunk_bonds": (c_int, [_P, _IP]),
+    "dcs_chunk_destroy": (c_int, [_P]),
+    "dcs_compress_step": (c_int, [_P, c_int, _IP, POINTER(c_void_p), c_int, _DP, _P]),
+    "dcs_measure_prob": (c_int, [_P, c_int, _IP, _IP, _DP, _P]),
+    "dcs_collapse": (c_int, [_P, c_int, _IP, _IP, _IP, _IP, c_double, _DP, _P]),
+    "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
+    "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
+    "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc: int) -> None:
+    if rc != DCS_OK:
+        raise DcsError(rc, _lib.dcs_last_error().decode())
+
+
+def _ints(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+
+
+def _dbl(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(_IP)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def dcs_last_error() -> str:
+    return _lib.dcs_last_error().decode()
+
+
+def dcs_version() -> int:
+    return _lib.dcs_version()
+
+
+def dcs_ctx_create(device: int) -> int:
+    h = c_void_p()
+    _check(_lib.dcs_ctx_create(ctypes.byref(h), device))
+    return h.value
+
+
+def dcs_ctx_destroy(ctx: int) -> None:
+    _check(_lib.dcs_ctx_destroy(ctx))
+
+
+def dcs_ctx_set_timing(ctx: int, enabled: bool) -> None:
+    _check(_lib.dcs_ctx_set_timing(ctx, 1 if enabled else 0))
+
+
+def dcs_ctx_timing(ctx: int, reset: bool = False):
+    launches = (c_longlong * 5)()
+    ms, flops, byts = (c_double * 5)(), (c_double * 5)(), (c_double * 5)()
+    _check(_lib.dcs_ctx_timing(ctx, launches, ms, flops, byts, 1 if reset else 0))
+    return list(launches), list(ms), list(flops), list(byts)
+
+
+def dcs_state_bytes(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots) -> int:
+    out = c_size_t()
+    _check(_lib.dcs_state_bytes(precision, n_qubits, capacity, chi_max, mpo_bond_max,
+                                n_init_slots, ctypes.byref(out)))
+    return out.value
+
+
+def dcs_state_create(ctx, precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots,
+                     d_buffer: int, nbytes: int, stream: int) -> int:
+    h = c_void_p()
+    _check(_lib.dcs_state_create(ctx, ctypes.byref(h), precision, n_qubits, capacity, chi_max,
+                                 mpo_bond_max, n_init_slots, d_buffer, nbytes, stream))
+    return h.value
+
+
+def dcs_state_destroy(st: int) -> None:
+    _check(_lib.dcs_state_destroy(st))
+
+
+def dcs_state_set_init(st: int, chi_cap: int, gauss: np.ndarray, stream: int) -> None:
+    g = np.ascontiguousarray(gauss, dtype=np.complex128).view(np.float64)
+    _check(_lib.dcs_state_set_init(st, chi_cap, _dp(g), stream))
+
+
+def dcs_branch_init_zero(st, ids, chi_caps, stream) -> None:
+    i, c = _ints(ids), _ints(chi_caps)
+    _check(_lib.dcs_branch_init_zero(st, len(i), _ip(i), _ip(c), stream))
+
+
+def dcs_branch_set_chi(st, ids, chi_caps) -> None:
+    i, c = _ints(ids), _ints(chi_caps)
+    _check(_lib.dcs_branch_set_chi(st, len(i), _ip(i), _ip(c)))
+
+
+def dcs_branch_release(st, ids) -> None:
+    i = _ints(ids)
+    _check(_lib.dcs_branch_release(st, len(i), _ip(i)))
+
+
+def dcs_branch_dims(st, bid, n_qubits) -> np.ndarray:
+    out = np.zeros(n_qubits + 1, dtype=np.int32)
+    _check(_lib.dcs_branch_dims(st, bid, _ip(out)))
+    return out
+
+
+def dcs_chunk_compile(ctx, n_qubits, q0, q1, mats: np.ndarray) -> int:
+    a, b = _ints(q0), _ints(q1)
+    m = np.ascontiguousarray(mats, dtype=np.complex128).view(np.float64)
+    h = c_void_p()
+    _check(_lib.dcs_chunk_compile(ctx, ctypes.byref(h), n_qubits, len(a), _ip(a), _ip(b), _dp(m)))
+    return h.value
+
+
+def dcs_chunk_bonds(ch, n_qubits) -> np.ndarray:
+    out = np.zeros(n_qubits + 1, dtype=np.int32)
+    _check(_lib.dcs_chunk_bonds(ch, _ip(out)))
+    return out
+
+
+def dcs_chunk_destroy(ch) -> None:
+    _check(_lib.dcs_chunk_destroy(ch))
+
+
+def dcs_compress_step(st, ids, chunks, n_sweeps, stream) -> np.ndarray:
+    i = _ints(ids)
+    arr = (c_void_p * len(i))(*chunks)
+    fid = np.zeros(len(i), dtype=np.float64)
+    _check(_lib.dcs_compress_step(st, len(i), _ip(i), arr, n_sweeps, _dp(fid), stream))
+    return fid
+
+
+def dcs_measure_prob(st, ids, qubits, stream) -> np.ndarray:
+    i, q = _ints(ids), _ints(qubits)
+    p0 = np.zeros(len(i), dtype=np.float64)
+    _check(_lib.dcs_measure_prob(st, len(i), _ip(i), _ip(q), _dp(p0), stream))
+    return p0
+
+
+def dcs_collapse(st, src_ids, qubits, outcomes, dst_ids, eps, stream) -> np.ndarray:
+    s, q, o, d = _ints(src_ids), _ints(qubits), _ints(outcomes), _ints(dst_ids)
+    pm = np.zeros(len(s), dtype=np.float64)
+    _check(_lib.dcs_collapse(st, len(s), _ip(s), _ip(q), _ip(o), _ip(d), eps, _dp(pm), stream))
+    return pm
+
+
+def dcs_topk_by_weight(weights, k):
+    w = _dbl(weights)
+    keep = np.zeros(max(1, min(len(w), k)), dtype=np.int32)
+    nk = c_int()
+    disc = c_double()
+    _check(_lib.dcs_topk_by_weight(len(w), _dp(w), k, _ip(keep), ctypes.byref(nk),
+                                   ctypes.byref(disc)))
+    return keep[:nk.value].copy(), disc.value
+
+
+def dcs_export_mps(st, bid, n_qubits, chi_max, stream):
+    dims = np.zeros(n_qubits + 1, dtype=np.int32)
+    cap = 2 * sum(2 * min(chi_max, 2 ** j, 2 ** (n_qubits - j))
+                  * min(chi_max, 2 ** (j + 1), 2 ** (n_qubits - j - 1)) for j in range(n_qubits))
+    buf = np.zeros(cap, dtype=np.float64)
+    _check(_lib.dcs_export_mps(st, bid, _dp(buf), cap, _ip(dims), stream))
+    out, o = [], 0
+    flat = buf.view(np.complex128)
+    for j in range(n_qubits):
+        e = int(dims[j]) * 2 * int(dims[j + 1])
+        out.append(flat[o:o + e].reshape(int(dims[j]), 2, int(dims[j + 1])).copy())
+        o += e
+    return out
+
+
+def dcs_import_mps(st, bid, chi_cap, sites, stream) -> None:
+    dims = _ints([sites[0].shape[0]] + [a.shape[2] for a in sites])
+    flat = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).reshape(-1)
+                           for a in sites]).view(np.float64)
+    _check(_lib.dcs_import_mps(st, bid, chi_cap, _dp(flat), _ip(dims), stream))

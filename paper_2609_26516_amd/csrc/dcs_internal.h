@@ -1,0 +1,122 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dcs {
+
+// Storage type of a complex operand.
+enum CType { CT_F32 = 0, CT_F64 = 1 };
+
+// Operand transformation in a GEMM C = op(A) op(B):
+//   N  as stored (A: M x K row-major, B: K x N row-major)
+//   T  transposed (B only: stored N x K)
+//   C  conjugate transpose (A only: stored K x M)
+//   J  conjugate, not transposed (A only: stored M x K)
+enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2, OP_J = 3 };
+
+// One batched operand: item b lives at base + idx(b) * stride bytes, where
+// idx(b) = ids[b] (slot addressing) or b (call-local addressing).
+struct Operand {
+  const void* base;
+  long long stride;
+  int by_slot;
+  int pad_;
+};
+
+struct GemmGroup {
+  Operand a, b, c;
+  const int* ids;
+  int M, N, K, lda, ldb, ldc;
+  int batch;
+  int tiles_n, tiles_per_item;
+  int tile_begin;
+};
+
+constexpr int GEMM_MAX_GROUPS = 16;
+struct GemmArgs {
+  GemmGroup g[GEMM_MAX_GROUPS];
+  int ngroups;
+  int total_tiles;
+};
+
+hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb,
+                       const GemmArgs& args, hipStream_t s);
+
+// Gate-operator application (one batch item per branch).
+//   dir 0 (moving right):  X1[a][wl][t][y] -> X2[a][s][wr][y]
+//   dir 1 (moving left):   Y1[x][t][c][wr] -> Y2[wl][x][s][c]
+// W[wl][s][t][wr] (complex, path precision), addressed call-locally.
+struct MpoGroup {
+  Operand in, out, w;
+  const int* ids;
+  int d0, d1;      // dir 0: (chi_l bra, chi_r ket); dir 1: (chi_l ket, chi_r bra)
+  int wl, wr;
+  int batch;
+  int blk_per_item;
+  int blk_begin;
+};
+constexpr int MPO_MAX_GROUPS = 16;
+struct MpoArgs {
+  MpoGroup g[MPO_MAX_GROUPS];
+  int ngroups;
+  int total_blocks;
+};
+hipError_t launch_mpo(int ct, int dir, const MpoArgs& args, hipStream_t s);
+
+// FP64 Householder QR / LQ of the environment tensor (one workgroup per
+// branch).  mode 0: F is m x n row-major (m >= n), Q (m x n) written in the
+// same layout.  mode 1: F is n x m row-major (n <= m), QR of F^H, Q^H (n x m)
+// written.  mode 2: no factorisation, T = F / |F| written in F's layout.
+// In every mode |F|^2 is written to nrm2 (FP64, slot- or call-addressed).
+struct QrGroup {
+  Operand f, q, ws, nrm2;
+  const int* ids;
+  int m, n, mode;
+  int batch;
+  int blk_begin;
+};
+constexpr int QR_MAX_GROUPS = 16;
+struct QrArgs {
+  QrGroup g[QR_MAX_GROUPS];
+  int ngroups;
+  int total_blocks;
+  int use_lds;     // factor in LDS (all groups fit) instead of the global workspace
+};
+hipError_t launch_qr(int ct_in, int ct_out, const QrArgs& args, size_t lds_bytes, hipStream_t s);
+size_t qr_lds_limit();
+
+// n_m = Re sum_{a,b} conj(A[a][m][b]) Z[a][m][b] for m = 0, 1 (FP64), one
+// workgroup per branch; Z = A when z.base is null.
+struct NormGroup {
+  Operand a, z, out;
+  const int* ids;
+  int dl, dr;
+  int batch;
+  int blk_begin;
+};
+constexpr int NORM_MAX_GROUPS = 16;
+struct NormArgs {
+  NormGroup g[NORM_MAX_GROUPS];
+  int ngroups;
+  int total_blocks;
+};
+hipError_t launch_norms(int ct_a, int ct_z, const NormArgs& args, hipStream_t s);
+
+// Collapse site tensor A[dl][2][dr]: slice 1-m zeroed, slice m scaled by the
+// FP64 factor `scale` (= 1/sqrt(n_m)).
+struct CollapseItem {
+  void* a;
+  double scale;
+  int dl, dr, m;
+  int pad_;
+};
+hipError_t launch_collapse(int ct, const CollapseItem* items_dev, int n_items, int max_elems,
+                           hipStream_t s);
+
+// Writes (1, 0), (0, 0) as two complex words at each listed address.
+hipError_t launch_fill_unit(int ct, void* const* ptrs_dev, int n, hipStream_t s);
+
+}  // namespace dcs

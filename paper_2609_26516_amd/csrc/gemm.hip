@@ -1,0 +1,311 @@
+// Batched / grouped complex GEMM on CDNA4 matrix cores.
+//
+// C = op(A) op(B) for complex operands stored interleaved (re, im), with the
+// complex product split into four real MFMA products per 16x16 block
+// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  FP32 operands use
+// v_mfma_f32_16x16x4_f32 (FP32 accumulation), FP64 operands
+// v_mfma_f64_16x16x4_f64.  Mixed storage (e.g. complex64 site tensors against
+// a complex128 environment) is converted while staging into LDS.
+//
+// Tiling: one 256-thread workgroup (4 wave64) per 64x64 output tile, each
+// wave a 32x32 quadrant (2x2 MFMA blocks, real and imaginary accumulators);
+// K advances in steps of 16 complex columns through LDS held as split real /
+// imaginary planes in [k][m] order, so the 16 lanes of an MFMA operand row
+// read consecutive words.  The next K tile is fetched into registers while
+// the current one is multiplied.  Workgroup ids are remapped so consecutive
+// tiles (same batch item, shared operands) land on the same XCD / L2.
+//
+// Every group of a launch is a batch of equal-shape problems; item b of a
+// group addresses its operands through the slot-id table or its call-local
+// index, with stride 0 for an operand shared by all items.
+#include "dcs_internal.h"
+
+namespace dcs {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using V = v4f;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<double> {
+  using V = v4d;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int CT>
+struct Store;
+template <>
+struct Store<CT_F32> {
+  using T = float2;
+};
+template <>
+struct Store<CT_F64> {
+  using T = double2;
+};
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 4;
+
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+  const int q = total >> 3, r = total & 7;
+  const int x = bid & 7, i = bid >> 3;
+  return x * q + min(x, r) + i;
+}
+
+__device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids, int b) {
+  const long long idx = o.by_slot ? ids[b] : b;
+  return static_cast<const char*>(o.base) + idx * o.stride;
+}
+
+template <int TA, int TB, int TC, typename R, int OPA, int OPB>
+__global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
+  using CA = typename Store<TA>::T;
+  using CB = typename Store<TB>::T;
+  using CC = typename Store<TC>::T;
+  using V = typename Mfma<R>::V;
+
+  __shared__ R sAr[BK][BM + PAD];
+  __shared__ R sAi[BK][BM + PAD];
+  __shared__ R sBr[BK][BN + PAD];
+  __shared__ R sBi[BK][BN + PAD];
+
+  const int tile = xcd_remap(blockIdx.x, args.total_tiles);
+  int gi = 0;
+  while (gi + 1 < args.ngroups && tile >= args.g[gi + 1].tile_begin) ++gi;
+  const GemmGroup& G = args.g[gi];
+  const int local = tile - G.tile_begin;
+  const int item = local / G.tiles_per_item;
+  const int t = local - item * G.tiles_per_item;
+  const int m0 = (t / G.tiles_n) * BM;
+  const int n0 = (t % G.tiles_n) * BN;
+  const int M = G.M, N = G.N, K = G.K;
+  const int lda = G.lda, ldb = G.ldb, ldc = G.ldc;
+
+  const CA* __restrict__ A = reinterpret_cast<const CA*>(item_ptr(G.a, G.ids, item));
+  const CB* __restrict__ B = reinterpret_cast<const CB*>(item_ptr(G.b, G.ids, item));
+  CC* __restrict__ C = reinterpret_cast<CC*>(const_cast<char*>(item_ptr(G.c, G.ids, item)));
+
+  const int tid = threadIdx.x;
+  R ar[4], ai[4], br[4], bi[4];
+
+  auto load_a = [&](int k0) {
+    if constexpr (OPA == OP_N || OPA == OP_J) {
+      const int row = tid >> 2, kq = (tid & 3) * 4;
+      const int m = m0 + row;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + kq + u;
+        R re = 0, im = 0;
+        if (m < M && k < K) {
+          const CA v = A[(long long)m * lda + k];
+          re = v.x;
+          im = v.y;
+        }
+        ar[u] = re;
+        ai[u] = (OPA == OP_J) ? -im : im;
+      }
+    } else {  // OP_C: stored K x M, conjugated
+      const int kr = tid >> 4, mq = (tid & 15) * 4;
+      const int k = k0 + kr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = m0 + mq + u;
+        R re = 0, im = 0;
+        if (m < M && k < K) {
+          const CA v = A[(long long)k * lda + m];
+          re = v.x;
+          im = v.y;
+        }
+        ar[u] = re;
+        ai[u] = -im;
+      }
+    }
+  };
+  auto store_a = [&]() {
+    if constexpr (OPA == OP_N || OPA == OP_J) {
+      const int row = tid >> 2, kq = (tid & 3) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sAr[kq + u][row] = ar[u];
+        sAi[kq + u][row] = ai[u];
+      }
+    } else {
+      const int kr = tid >> 4, mq = (tid & 15) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sAr[kr][mq + u] = ar[u];
+        sAi[kr][mq + u] = ai[u];
+      }
+    }
+  };
+  auto load_b = [&](int k0) {
+    if constexpr (OPB == OP_N) {  // stored K x N
+      const int kr = tid >> 4, nq = (tid & 15) * 4;
+      const int k = k0 + kr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int n = n0 + nq + u;
+        R re = 0, im = 0;
+        if (n < N && k < K) {
+          const CB v = B[(long long)k * ldb + n];
+          re = v.x;
+          im = v.y;
+        }
+        br[u] = re;
+        bi[u] = im;
+      }
+    } else {  // OP_T: stored N x K
+      const int nr = tid >> 2, kq = (tid & 3) * 4;
+      const int n = n0 + nr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + kq + u;
+        R re = 0, im = 0;
+        if (n < N && k < K) {
+          const CB v = B[(long long)n * ldb + k];
+          re = v.x;
+          im = v.y;
+        }
+        br[u] = re;
+        bi[u] = im;
+      }
+    }
+  };
+  auto store_b = [&]() {
+    if constexpr (OPB == OP_N) {
+      const int kr = tid >> 4, nq = (tid & 15) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sBr[kr][nq + u] = br[u];
+        sBi[kr][nq + u] = bi[u];
+      }
+    } else {
+      const int nr = tid >> 2, kq = (tid & 3) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sBr[kq + u][nr] = br[u];
+        sBi[kq + u][nr] = bi[u];
+      }
+    }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+
+  V cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[i][j][r] = 0;
+        ci[i][j][r] = 0;
+      }
+
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    load_a(0);
+    load_b(0);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store_a();
+    store_b();
+    __syncthreads();
+    if (kt + 1 < nk) {
+      load_a((kt + 1) * BK);
+      load_b((kt + 1) * BK);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + lk;
+      R xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        xr[i] = sAr[kr][wm + i * 16 + li];
+        xi[i] = sAi[kr][wm + i * 16 + li];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        yr[j] = sBr[kr][wn + j * 16 + li];
+        yi[j] = sBi[kr][wn + j * 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = Mfma<R>::mma(xr[i], yr[j], cr[i][j]);
+          cr[i][j] = Mfma<R>::mma(-xi[i], yi[j], cr[i][j]);
+          ci[i][j] = Mfma<R>::mma(xr[i], yi[j], ci[i][j]);
+          ci[i][j] = Mfma<R>::mma(xi[i], yr[j], ci[i][j]);
+        }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + 4 * lk + r;
+        if (row < M && col < N) {
+          CC v;
+          v.x = cr[i][j][r];
+          v.y = ci[i][j][r];
+          C[(long long)row * ldc + col] = v;
+        }
+      }
+    }
+}
+
+template <int TA, int TB, int TC, typename R, int OPA, int OPB>
+hipError_t run(const GemmArgs& args, hipStream_t s) {
+  if (args.total_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB>), dim3(args.total_tiles), dim3(NT), 0,
+                     s, args);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, const GemmArgs& args,
+                       hipStream_t s) {
+#define DCS_GEMM_CASE(TA, TB, TC, R, OA, OB)                                             \
+  if (ta == TA && tb == TB && tc == TC && tacc == (sizeof(R) == 8 ? CT_F64 : CT_F32) && \
+      opa == OA && opb == OB)                                                            \
+    return run<TA, TB, TC, R, OA, OB>(args, s);
+  // compression-step contractions in path precision
+  DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_N, OP_N)
+  DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_N, OP_T)
+  DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_C, OP_N)
+  DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_J, OP_T)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F32, float, OP_N, OP_N)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F32, float, OP_N, OP_T)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F32, float, OP_C, OP_N)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F32, float, OP_J, OP_T)
+  // FP64 measurement contractions over complex64 site tensors
+  DCS_GEMM_CASE(CT_F64, CT_F32, CT_F64, double, OP_N, OP_N)
+  DCS_GEMM_CASE(CT_F32, CT_F64, CT_F64, double, OP_C, OP_N)
+  DCS_GEMM_CASE(CT_F32, CT_F64, CT_F64, double, OP_N, OP_T)
+  DCS_GEMM_CASE(CT_F32, CT_F64, CT_F64, double, OP_J, OP_T)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F64, double, OP_C, OP_N)
+  DCS_GEMM_CASE(CT_F32, CT_F32, CT_F64, double, OP_J, OP_T)
+#undef DCS_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dcs

@@ -1,0 +1,530 @@
+// Non-GEMM kernels of the compression step and the dynamic operations:
+// layered gate-operator application, FP64 Householder QR / LQ of the local
+// tensor (gauge shift), outcome norms for the measurement probability, and
+// the collapse of a site tensor.
+#include "dcs_internal.h"
+
+namespace dcs {
+namespace {
+
+constexpr int NT = 256;
+
+template <int CT>
+struct St;
+template <>
+struct St<CT_F32> {
+  using T = float2;
+  using R = float;
+};
+template <>
+struct St<CT_F64> {
+  using T = double2;
+  using R = double;
+};
+
+__device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids, int b) {
+  const long long idx = o.by_slot ? ids[b] : b;
+  return static_cast<const char*>(o.base) + idx * o.stride;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// conj(a) * b
+__device__ __forceinline__ double2 cdotc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the 256-thread block; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  return scratch[0] + scratch[1] + scratch[2] + scratch[3];
+}
+
+template <int GROUPS, typename G>
+__device__ __forceinline__ int find_group(const G* g, int ngroups, int blk) {
+  int gi = 0;
+  while (gi + 1 < ngroups && blk >= g[gi + 1].blk_begin) ++gi;
+  return gi;
+}
+
+// ---------------------------------------------------------------------------
+// Gate-operator application.  WMAX bounds the operator bond dims so the
+// per-thread inputs stay in registers (loops fully unrolled, predicated).
+
+template <int CT, int WMAX>
+__global__ __launch_bounds__(NT) void mpo_right_kernel(const MpoArgs args) {
+  // X1[a][wl][t][y] -> X2[a][s][wr][y]
+  using T = typename St<CT>::T;
+  using R = typename St<CT>::R;
+  __shared__ T sW[WMAX * 4 * WMAX];
+  const int gi = find_group<MPO_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const MpoGroup& G = args.g[gi];
+  const int local = blockIdx.x - G.blk_begin;
+  const int item = local / G.blk_per_item;
+  const int sub = local - item * G.blk_per_item;
+  const int wl = G.wl, wr = G.wr, d0 = G.d0, d1 = G.d1;
+  const T* __restrict__ X1 = reinterpret_cast<const T*>(item_ptr(G.in, G.ids, item));
+  T* __restrict__ X2 = reinterpret_cast<T*>(const_cast<char*>(item_ptr(G.out, G.ids, item)));
+  const T* __restrict__ W = reinterpret_cast<const T*>(item_ptr(G.w, G.ids, item));
+  const int nw = wl * 4 * wr;
+  for (int i = threadIdx.x; i < nw; i += NT) sW[i] = W[i];
+  __syncthreads();
+  const long long idx = (long long)sub * NT + threadIdx.x;
+  if (idx >= (long long)d0 * d1) return;
+  const int a = (int)(idx / d1), y = (int)(idx % d1);
+  R xr[2 * WMAX], xi[2 * WMAX];
+#pragma unroll
+  for (int k = 0; k < 2 * WMAX; ++k) {
+    xr[k] = 0;
+    xi[k] = 0;
+    if (k < 2 * wl) {   // k = wl_i * 2 + t
+      const T v = X1[((long long)a * 2 * wl + k) * d1 + y];
+      xr[k] = v.x;
+      xi[k] = v.y;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int o = 0; o < WMAX; ++o) {
+      if (o < wr) {
+        R accr = 0, acci = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * WMAX; ++k) {
+          if (k < 2 * wl) {
+            const int wli = k >> 1, t = k & 1;
+            const T w = sW[((wli * 2 + s) * 2 + t) * wr + o];
+            accr += w.x * xr[k] - w.y * xi[k];
+            acci += w.x * xi[k] + w.y * xr[k];
+          }
+        }
+        T out;
+        out.x = accr;
+        out.y = acci;
+        X2[(((long long)a * 2 + s) * wr + o) * d1 + y] = out;
+      }
+    }
+  }
+}
+
+template <int CT, int WMAX>
+__global__ __launch_bounds__(NT) void mpo_left_kernel(const MpoArgs args) {
+  // Y1[x][t][c][wr] -> Y2[wl][x][s][c]
+  using T = typename St<CT>::T;
+  using R = typename St<CT>::R;
+  __shared__ T sW[WMAX * 4 * WMAX];
+  const int gi = find_group<MPO_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const MpoGroup& G = args.g[gi];
+  const int local = blockIdx.x - G.blk_begin;
+  const int item = local / G.blk_per_item;
+  const int sub = local - item * G.blk_per_item;
+  const int wl = G.wl, wr = G.wr, d0 = G.d0, d1 = G.d1;
+  const T* __restrict__ Y1 = reinterpret_cast<const T*>(item_ptr(G.in, G.ids, item));
+  T* __restrict__ Y2 = reinterpret_cast<T*>(const_cast<char*>(item_ptr(G.out, G.ids, item)));
+  const T* __restrict__ W = reinterpret_cast<const T*>(item_ptr(G.w, G.ids, item));
+  const int nw = wl * 4 * wr;
+  for (int i = threadIdx.x; i < nw; i += NT) sW[i] = W[i];
+  __syncthreads();
+  const long long idx = (long long)sub * NT + threadIdx.x;
+  if (idx >= (long long)d0 * d1) return;
+  const int x = (int)(idx / d1), c = (int)(idx % d1);
+  R yr[2 * WMAX], yi[2 * WMAX];
+#pragma unroll
+  for (int k = 0; k < 2 * WMAX; ++k) {   // k = t * WMAX + wr_i
+    yr[k] = 0;
+    yi[k] = 0;
+    const int t = k / WMAX, o = k % WMAX;
+    if (o < wr) {
+      const T v = Y1[(((long long)x * 2 + t) * d1 + c) * wr + o];
+      yr[k] = v.x;
+      yi[k] = v.y;
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < WMAX; ++l) {
+    if (l < wl) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        R accr = 0, acci = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * WMAX; ++k) {
+          const int t = k / WMAX, o = k % WMAX;
+          if (o < wr) {
+            const T w = sW[((l * 2 + s) * 2 + t) * wr + o];
+            accr += w.x * yr[k] - w.y * yi[k];
+            acci += w.x * yi[k] + w.y * yr[k];
+          }
+        }
+        T out;
+        out.x = accr;
+        out.y = acci;
+        Y2[(((long long)l * d0 + x) * 2 + s) * d1 + c] = out;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Householder QR in the LAPACK convention (zgeqr2 reflectors
+// H_k = I - tau_k v v^H, v_k = 1, beta = -sign(Re alpha) |(alpha, x)|,
+// tau = ((beta - Re alpha) / beta, -Im alpha / beta), v = x / (alpha - beta);
+// tau = 0 when x = 0 and alpha is real), then the thin Q = H_0 ... H_{n-1}
+// [I; 0] accumulated backwards (zung2r).  The m x n working matrix is held
+// column-major either in LDS or in the branch's global workspace.
+
+template <typename TI>
+__device__ __forceinline__ double2 to_d2(TI v) {
+  return make_double2((double)v.x, (double)v.y);
+}
+
+template <int CTI, int CTO>
+__global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
+  using TI = typename St<CTI>::T;
+  using TO = typename St<CTO>::T;
+  extern __shared__ double2 dyn_lds[];
+  __shared__ double2 s_tau[1024];
+  __shared__ double s_red[4];
+  __shared__ double2 s_bc[2];
+
+  const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const QrGroup& G = args.g[gi];
+  const int item = blockIdx.x - G.blk_begin;
+  const int m = G.m, n = G.n, mode = G.mode;
+  const TI* __restrict__ F = reinterpret_cast<const TI*>(item_ptr(G.f, G.ids, item));
+  TO* __restrict__ Q = reinterpret_cast<TO*>(const_cast<char*>(item_ptr(G.q, G.ids, item)));
+  double* nrm = reinterpret_cast<double*>(const_cast<char*>(item_ptr(G.nrm2, G.ids, item)));
+  double2* W = args.use_lds
+                   ? dyn_lds
+                   : reinterpret_cast<double2*>(const_cast<char*>(item_ptr(G.ws, G.ids, item)));
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long mn = (long long)m * n;
+
+  // load (column-major working copy of T, or of T^H in mode 1) and |F|^2
+  double part = 0;
+  if (mode == 0) {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+      const int i = (int)(idx / n), j = (int)(idx % n);
+      W[i + (long long)j * m] = v;
+    }
+  } else if (mode == 1) {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+      W[idx] = cconj(v);   // F is n x m row-major: F[j][i] -> W[i + j m]
+    }
+  } else {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+    }
+  }
+  const double nu2 = block_sum(part, s_red);
+  if (tid == 0) *nrm = nu2;
+  if (mode == 2) {
+    const double sc = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0;
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      TO o;
+      o.x = v.x * sc;
+      o.y = v.y * sc;
+      Q[idx] = o;
+    }
+    return;
+  }
+  __syncthreads();
+
+  // factorisation
+  for (int k = 0; k < n; ++k) {
+    double2* colk = W + (long long)k * m;
+    double p = 0;
+    for (int i = k + 1 + tid; i < m; i += NT) {
+      const double2 v = colk[i];
+      p += v.x * v.x + v.y * v.y;
+    }
+    const double xn2 = block_sum(p, s_red);
+    if (tid == 0) {
+      const double2 alpha = colk[k];
+      double2 tau = make_double2(0.0, 0.0), scal = make_double2(1.0, 0.0);
+      if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+        const double nrm_all = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 d = make_double2(alpha.x - beta, alpha.y);   // alpha - beta
+        const double dd = d.x * d.x + d.y * d.y;
+        scal = make_double2(d.x / dd, -d.y / dd);                    // 1 / (alpha - beta)
+        colk[k] = make_double2(beta, 0.0);
+      }
+      s_tau[k] = tau;
+      s_bc[0] = tau;
+      s_bc[1] = scal;
+    }
+    __syncthreads();
+    const double2 tau = s_bc[0], scal = s_bc[1];
+    if (tau.x == 0.0 && tau.y == 0.0) {
+      __syncthreads();
+      continue;
+    }
+    for (int i = k + 1 + tid; i < m; i += NT) colk[i] = cmul(colk[i], scal);
+    __syncthreads();
+    const double2 ctau = cconj(tau);
+    for (int j = k + 1 + wave; j < n; j += 4) {
+      double2* colj = W + (long long)j * m;
+      double sr = 0, si = 0;
+      for (int i = k + lane; i < m; i += 64) {
+        const double2 v = (i == k) ? make_double2(1.0, 0.0) : colk[i];
+        const double2 w = cdotc(v, colj[i]);
+        sr += w.x;
+        si += w.y;
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      const double2 c = cmul(ctau, make_double2(sr, si));
+      for (int i = k + lane; i < m; i += 64) {
+        const double2 v = (i == k) ? make_double2(1.0, 0.0) : colk[i];
+        const double2 u = cmul(v, c);
+        colj[i] = make_double2(colj[i].x - u.x, colj[i].y - u.y);
+      }
+    }
+    __syncthreads();
+  }
+
+  // thin Q, accumulated backwards
+  for (int k = n - 1; k >= 0; --k) {
+    const double2 tau = s_tau[k];
+    double2* colk = W + (long long)k * m;
+    if (k < n - 1 && !(tau.x == 0.0 && tau.y == 0.0)) {
+      for (int j = k + 1 + wave; j < n; j += 4) {
+        double2* colj = W + (long long)j * m;
+        double sr = 0, si = 0;
+        for (int i = k + lane; i < m; i += 64) {
+          const double2 v = (i == k) ? make_double2(1.0, 0.0) : colk[i];
+          const double2 w = cdotc(v, colj[i]);
+          sr += w.x;
+          si += w.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        const double2 c = cmul(tau, make_double2(sr, si));
+        for (int i = k + lane; i < m; i += 64) {
+          const double2 v = (i == k) ? make_double2(1.0, 0.0) : colk[i];
+          const double2 u = cmul(v, c);
+          colj[i] = make_double2(colj[i].x - u.x, colj[i].y - u.y);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) {
+      if (i < k) {
+        colk[i] = make_double2(0.0, 0.0);
+      } else if (i == k) {
+        colk[i] = make_double2(1.0 - tau.x, -tau.y);
+      } else {
+        const double2 v = colk[i];
+        colk[i] = make_double2(-(tau.x * v.x - tau.y * v.y), -(tau.x * v.y + tau.y * v.x));
+      }
+    }
+    __syncthreads();
+  }
+
+  // write Q (mode 0, m x n row-major) or Q^H (mode 1, n x m row-major)
+  if (mode == 0) {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const int i = (int)(idx / n), j = (int)(idx % n);
+      const double2 v = W[i + (long long)j * m];
+      TO o;
+      o.x = v.x;
+      o.y = v.y;
+      Q[idx] = o;
+    }
+  } else {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = W[idx];
+      TO o;
+      o.x = v.x;
+      o.y = -v.y;
+      Q[idx] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outcome norms n_m = Re sum conj(A[a][m][b]) Z[a][m][b], FP64 accumulation.
+
+template <int CTA, int CTZ>
+__global__ __launch_bounds__(NT) void norms_kernel(const NormArgs args) {
+  using TA = typename St<CTA>::T;
+  using TZ = typename St<CTZ>::T;
+  __shared__ double s_red[4];
+  const int gi = find_group<NORM_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const NormGroup& G = args.g[gi];
+  const int item = blockIdx.x - G.blk_begin;
+  const TA* __restrict__ A = reinterpret_cast<const TA*>(item_ptr(G.a, G.ids, item));
+  const TZ* __restrict__ Z = G.z.base ? reinterpret_cast<const TZ*>(item_ptr(G.z, G.ids, item))
+                                      : reinterpret_cast<const TZ*>(A);
+  double* out = reinterpret_cast<double*>(const_cast<char*>(item_ptr(G.out, G.ids, item)));
+  const int dl = G.dl, dr = G.dr;
+  const long long tot = (long long)dl * 2 * dr;
+  double p0 = 0, p1 = 0;
+  for (long long idx = threadIdx.x; idx < tot; idx += NT) {
+    const double2 a = to_d2(A[idx]);
+    const double2 z = to_d2(Z[idx]);
+    const double v = a.x * z.x + a.y * z.y;
+    const int s = (int)((idx / dr) & 1);
+    if (s == 0)
+      p0 += v;
+    else
+      p1 += v;
+  }
+  p0 = block_sum(p0, s_red);
+  p1 = block_sum(p1, s_red);
+  if (threadIdx.x == 0) {
+    out[0] = p0;
+    out[1] = p1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+template <int CT>
+__global__ __launch_bounds__(NT) void collapse_kernel(const CollapseItem* items) {
+  using T = typename St<CT>::T;
+  const CollapseItem it = items[blockIdx.y];
+  const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
+  const long long tot = (long long)it.dl * it.dr;
+  if (idx >= tot) return;
+  const int a = (int)(idx / it.dr), b = (int)(idx % it.dr);
+  T* A = reinterpret_cast<T*>(it.a);
+  const double sc = it.scale;
+  T& keep = A[((long long)a * 2 + it.m) * it.dr + b];
+  T& drop = A[((long long)a * 2 + (1 - it.m)) * it.dr + b];
+  T k = keep;
+  k.x = (double)k.x * sc;
+  k.y = (double)k.y * sc;
+  keep = k;
+  T z;
+  z.x = 0;
+  z.y = 0;
+  drop = z;
+}
+
+// Writes the complex pair (1, 0) at each listed address: the 1 x 2 x 1 site
+// tensor of |0>, or a 1 x 1 x 1 boundary environment (its second word is
+// alignment padding).
+template <int CT>
+__global__ void fill_unit_kernel(void* const* ptrs, int n) {
+  using T = typename St<CT>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T one, zero;
+  one.x = 1;
+  one.y = 0;
+  zero.x = 0;
+  zero.y = 0;
+  T* p = reinterpret_cast<T*>(ptrs[i]);
+  p[0] = one;
+  p[1] = zero;
+}
+
+}  // namespace
+
+hipError_t launch_mpo(int ct, int dir, const MpoArgs& args, hipStream_t s) {
+  if (args.total_blocks <= 0) return hipSuccess;
+  int wmax = 1;
+  for (int i = 0; i < args.ngroups; ++i) wmax = max(wmax, max(args.g[i].wl, args.g[i].wr));
+  const dim3 grid(args.total_blocks), blk(NT);
+#define DCS_MPO(CT, DIR, WM)                                                      \
+  if (ct == CT && dir == DIR && wmax <= WM) {                                     \
+    if (DIR == 0)                                                                 \
+      hipLaunchKernelGGL((mpo_right_kernel<CT, WM>), grid, blk, 0, s, args);      \
+    else                                                                          \
+      hipLaunchKernelGGL((mpo_left_kernel<CT, WM>), grid, blk, 0, s, args);       \
+    return hipGetLastError();                                                     \
+  }
+  DCS_MPO(CT_F32, 0, 4)
+  DCS_MPO(CT_F32, 0, 16)
+  DCS_MPO(CT_F32, 1, 4)
+  DCS_MPO(CT_F32, 1, 16)
+  DCS_MPO(CT_F64, 0, 4)
+  DCS_MPO(CT_F64, 0, 16)
+  DCS_MPO(CT_F64, 1, 4)
+  DCS_MPO(CT_F64, 1, 16)
+#undef DCS_MPO
+  return hipErrorInvalidValue;
+}
+
+size_t qr_lds_limit() {
+  // dynamic LDS for the working matrix next to the static arrays (16.1 KB),
+  // within the 64 KB a workgroup gets without an opt-in
+  return 64 * 1024 - 17 * 1024;
+}
+
+hipError_t launch_qr(int ct_in, int ct_out, const QrArgs& args, size_t lds_bytes, hipStream_t s) {
+  if (args.total_blocks <= 0) return hipSuccess;
+  if (!args.use_lds) lds_bytes = 0;
+  const dim3 grid(args.total_blocks), blk(NT);
+#define DCS_QR(I, O)                                                                        \
+  if (ct_in == I && ct_out == O) {                                                          \
+    static hipError_t attr = hipFuncSetAttribute(                                          \
+        reinterpret_cast<const void*>(&qr_kernel<I, O>),                                    \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_lds_limit());                   \
+    if (lds_bytes > 0 && attr != hipSuccess) return attr;                                   \
+    hipLaunchKernelGGL((qr_kernel<I, O>), grid, blk, lds_bytes, s, args);                   \
+    return hipGetLastError();                                                               \
+  }
+  DCS_QR(CT_F32, CT_F32)
+  DCS_QR(CT_F64, CT_F64)
+  DCS_QR(CT_F64, CT_F32)
+#undef DCS_QR
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_norms(int ct_a, int ct_z, const NormArgs& args, hipStream_t s) {
+  if (args.total_blocks <= 0) return hipSuccess;
+  const dim3 grid(args.total_blocks), blk(NT);
+  if (ct_a == CT_F32 && ct_z == CT_F32)
+    hipLaunchKernelGGL((norms_kernel<CT_F32, CT_F32>), grid, blk, 0, s, args);
+  else if (ct_a == CT_F32 && ct_z == CT_F64)
+    hipLaunchKernelGGL((norms_kernel<CT_F32, CT_F64>), grid, blk, 0, s, args);
+  else if (ct_a == CT_F64 && ct_z == CT_F64)
+    hipLaunchKernelGGL((norms_kernel<CT_F64, CT_F64>), grid, blk, 0, s, args);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_collapse(int ct, const CollapseItem* items_dev, int n_items, int max_elems,
+                           hipStream_t s) {
+  if (n_items <= 0 || max_elems <= 0) return hipSuccess;
+  const dim3 grid((max_elems + NT - 1) / NT, n_items), blk(NT);
+  if (ct == CT_F32)
+    hipLaunchKernelGGL((collapse_kernel<CT_F32>), grid, blk, 0, s, items_dev);
+  else
+    hipLaunchKernelGGL((collapse_kernel<CT_F64>), grid, blk, 0, s, items_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_unit(int ct, void* const* ptrs_dev, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + 127) / 128), blk(128);
+  if (ct == CT_F32)
+    hipLaunchKernelGGL((fill_unit_kernel<CT_F32>), grid, blk, 0, s, ptrs_dev, n);
+  else
+    hipLaunchKernelGGL((fill_unit_kernel<CT_F64>), grid, blk, 0, s, ptrs_dev, n);
+  return hipGetLastError();
+}
+
+}  // namespace dcs

@@ -1,0 +1,271 @@
+"""Drivers of the dynamic-circuit strategies over the C ABI.
+
+The classical side of the method stays here, on the host: scanning the
+operation list, evaluating the Boolean conditions of classically controlled
+gates on each branch's register (Sec. IV-B2), building chunks (Sec. IV-C),
+sampling outcomes (Alg. 1) or branching on them (Alg. 2) and keeping the
+top-M branches.  Every tensor operation (compression step, measurement
+probability, collapse) runs in libdcs.so on the GPU; PyTorch only provides
+the device buffer and the stream.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from inputs.circuits import CGate, Circuit, Gate, Measure
+
+from . import capi
+
+EPS_BRANCH = 1e-10
+PRECISIONS = {"c128": capi.DCS_C128, "c64": capi.DCS_C64}
+
+
+def _cond_true(cond, regs: np.ndarray) -> np.ndarray:
+    """phi evaluated on every row of a (branches x bits) register array."""
+    par = np.zeros(regs.shape[0], dtype=np.int64)
+    for b in cond.bits:
+        par ^= regs[:, b].astype(np.int64)
+    return par == int(cond.value)
+
+
+def _gate_of(op) -> Gate:
+    return op.gate if isinstance(op, CGate) else op
+
+
+class Engine:
+    """One HIP device: the library context plus a cache of compiled chunks."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required")
+        self.device = device
+        torch.cuda.set_device(device)
+        self.ctx = capi.dcs_ctx_create(device)
+        self._chunks: Dict[tuple, int] = {}
+
+    def stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def chunk(self, circ: Circuit, op_ids: Sequence[int]) -> int:
+        """Compiled chunk of the listed operations (cached by op indices)."""
+        key = (id(circ), tuple(op_ids))
+        h = self._chunks.get(key)
+        if h is None:
+            q0, q1, mats = [], [], []
+            for i in op_ids:
+                g = _gate_of(circ.ops[i])
+                q0.append(g.qubits[0])
+                q1.append(g.qubits[1] if len(g.qubits) == 2 else -1)
+                mats.append(np.asarray(g.mat, dtype=np.complex128).reshape(-1))
+            h = capi.dcs_chunk_compile(self.ctx, circ.n_qubits, q0, q1, np.concatenate(mats))
+            self._chunks[key] = h
+        return h
+
+    def clear_chunks(self) -> None:
+        for h in self._chunks.values():
+            capi.dcs_chunk_destroy(h)
+        self._chunks.clear()
+
+    def timing(self, enabled: bool) -> None:
+        capi.dcs_ctx_set_timing(self.ctx, enabled)
+
+    def timing_stats(self, reset: bool = False):
+        return capi.dcs_ctx_timing(self.ctx, reset)
+
+    def close(self) -> None:
+        self.clear_chunks()
+        if self.ctx:
+            capi.dcs_ctx_destroy(self.ctx)
+            self.ctx = 0
+
+
+class State:
+    """Branch slots of one circuit size in a caller-owned device buffer."""
+
+    def __init__(self, eng: Engine, precision: str, n_qubits: int, capacity: int, chi_max: int,
+                 mpo_bond_max: int = 4, init_chis: Sequence[int] = (), init_seed: int = 7,
+                 gaussians=None):
+        self.eng, self.n, self.capacity, self.chi_max = eng, n_qubits, capacity, chi_max
+        self.precision = PRECISIONS[precision]
+        chis = sorted(set(init_chis)) or [chi_max]
+        nbytes = capi.dcs_state_bytes(self.precision, n_qubits, capacity, chi_max, mpo_bond_max,
+                                      len(chis))
+        self.nbytes = nbytes
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{eng.device}")
+        ptr = self.buf.data_ptr()
+        self.ptr = (ptr + 255) // 256 * 256
+        self.h = capi.dcs_state_create(eng.ctx, self.precision, n_qubits, capacity, chi_max,
+                                       mpo_bond_max, len(chis), self.ptr, nbytes, eng.stream())
+        if gaussians is None:
+            from inputs.randomness import bra_init_gaussians
+            gaussians = lambda chi: bra_init_gaussians(n_qubits, chi, init_seed)  # noqa: E731
+        for chi in chis:
+            g = gaussians(chi)
+            flat = np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in g])
+            capi.dcs_state_set_init(self.h, chi, flat, eng.stream())
+        self.free = list(range(capacity - 1, -1, -1))
+
+    def alloc(self, k: int = 1) -> List[int]:
+        if len(self.free) < k:
+            raise capi.DcsError(capi.DCS_ECAPACITY, "no free branch slot")
+        return [self.free.pop() for _ in range(k)]
+
+    def release(self, ids: Sequence[int]) -> None:
+        if len(ids):
+            capi.dcs_branch_release(self.h, ids)
+            self.free.extend(int(i) for i in ids)
+
+    def reset(self) -> None:
+        capi.dcs_branch_release(self.h, list(range(self.capacity)))
+        self.free = list(range(self.capacity - 1, -1, -1))
+
+    def export(self, bid: int):
+        return capi.dcs_export_mps(self.h, bid, self.n, self.chi_max, self.eng.stream())
+
+    def close(self) -> None:
+        if self.h:
+            capi.dcs_state_destroy(self.h)
+            self.h = 0
+            self.buf = None
+
+
+def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int, k: int,
+                    n_sweeps: int = 2, uniforms: Optional[np.ndarray] = None,
+                    outcomes: Optional[np.ndarray] = None) -> Dict:
+    """Alg. 1 for `shots` independent trajectories advanced in lockstep.
+
+    Outcome of measurement i of shot s: outcomes[s, i] when given (replay),
+    else 0 if uniforms[s, i] < p_0 and 1 otherwise.  Chunks of all shots that
+    are due at the same operation are compressed in one batched call."""
+    stream = eng.stream()
+    ids = np.array(st.alloc(shots), dtype=np.int32)
+    capi.dcs_branch_init_zero(st.h, ids, np.full(shots, chi), stream)
+    regs = np.zeros((shots, max(circ.n_bits, 1)), dtype=np.int8)
+    p = np.ones(shots)
+    fid = np.ones(shots)
+    chunk: List[List[int]] = [[] for _ in range(shots)]
+    rec_out, rec_p0, rec_f = [], [], []
+    i_meas = 0
+
+    def compress(sel: np.ndarray) -> None:
+        if len(sel) == 0:
+            return
+        hs = [eng.chunk(circ, chunk[s]) for s in sel]
+        f = capi.dcs_compress_step(st.h, ids[sel], hs, n_sweeps, stream)
+        fid[sel] *= f
+        f_all = np.full(shots, np.nan)
+        f_all[sel] = f
+        rec_f.append(f_all)
+        for s in sel:
+            chunk[s] = []
+
+    try:
+        for li, op in enumerate(circ.ops):
+            if isinstance(op, Measure):
+                compress(np.array([s for s in range(shots) if chunk[s]], dtype=np.int64))
+                q = np.full(shots, op.qubit)
+                p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+                if outcomes is not None:
+                    m = np.asarray(outcomes[:, i_meas], dtype=np.int32)
+                else:
+                    m = (uniforms[:, i_meas] >= p0).astype(np.int32)
+                pm = capi.dcs_collapse(st.h, ids, q, m, ids, EPS_BRANCH, stream)
+                p *= pm
+                regs[:, op.bit] = m
+                rec_out.append(m.copy())
+                rec_p0.append(p0.copy())
+                i_meas += 1
+                continue
+            if isinstance(op, CGate):
+                active = np.nonzero(_cond_true(op.cond, regs))[0]
+            else:
+                active = range(shots)
+            due = []
+            for s in active:
+                chunk[s].append(li)
+                if len(chunk[s]) == k:
+                    due.append(s)
+            compress(np.array(due, dtype=np.int64))
+        compress(np.array([s for s in range(shots) if chunk[s]], dtype=np.int64))
+    except Exception:
+        st.release(ids)
+        raise
+    return {"ids": ids, "F": fid, "p": p, "regs": regs,
+            "outcomes": np.array(rec_out).T if rec_out else np.zeros((shots, 0), np.int32),
+            "p0s": np.array(rec_p0).T if rec_p0 else np.zeros((shots, 0)),
+            "fids": rec_f}
+
+
+def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sweeps: int = 2,
+                   max_branches: Optional[int] = None, chi_of=None,
+                   eps: float = EPS_BRANCH) -> Dict:
+    """Alg. 2: every measurement splits each live branch into its outcomes with
+    p_m > eps (m = 0 kept in place, m = 1 copied to a new slot); after the
+    measurement at most `max_branches` branches with the largest p are kept.
+    `chi_of(path)` gives a new child's bond cap.  Chunks of all branches due
+    at the same operation are compressed in one batched call."""
+    stream = eng.stream()
+    first = st.alloc(1)[0]
+    capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
+    br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
+           "F": 1.0, "chunk": []}]
+    dropped = 0.0
+
+    def compress(sel: List[dict]) -> None:
+        if not sel:
+            return
+        hs = [eng.chunk(circ, b["chunk"]) for b in sel]
+        f = capi.dcs_compress_step(st.h, [b["id"] for b in sel], hs, n_sweeps, stream)
+        for b, fv in zip(sel, f):
+            b["F"] *= float(fv)
+            b["chunk"] = []
+
+    for li, op in enumerate(circ.ops):
+        if isinstance(op, Measure):
+            compress([b for b in br if b["chunk"]])
+            ids = [b["id"] for b in br]
+            q = [op.qubit] * len(br)
+            p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+            src, dst, outc, qq, kids = [], [], [], [], []
+            for b, pz in zip(br, p0):
+                opts = [m for m, pm in ((0, pz), (1, 1.0 - pz)) if pm > eps]
+                for j, m in enumerate(opts):
+                    did = b["id"] if j == 0 else st.alloc(1)[0]
+                    src.append(b["id"])
+                    dst.append(did)
+                    outc.append(m)
+                    qq.append(op.qubit)
+                    kids.append((b, m, did))
+            pm = capi.dcs_collapse(st.h, src, qq, outc, dst, eps, stream)
+            nxt = []
+            for (b, m, did), pmv in zip(kids, pm):
+                c = b["c"].copy()
+                c[op.bit] = m
+                nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
+                            "c": c, "F": b["F"], "chunk": []})
+            br = nxt
+            if chi_of is not None:
+                capi.dcs_branch_set_chi(st.h, [b["id"] for b in br],
+                                        [chi_of(b["path"]) for b in br])
+            if max_branches is not None and len(br) > max_branches:
+                keep, disc = capi.dcs_topk_by_weight([b["p"] for b in br], max_branches)
+                dropped += disc
+                kept = set(int(i) for i in keep)
+                st.release([b["id"] for i, b in enumerate(br) if i not in kept])
+                br = [br[int(i)] for i in keep]
+            continue
+        due = []
+        for b in br:
+            if isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0]:
+                continue
+            b["chunk"].append(li)
+            if len(b["chunk"]) == k:
+                due.append(b)
+        compress(due)
+    compress([b for b in br if b["chunk"]])
+    ptot = sum(b["p"] for b in br)
+    fmp = sum(b["p"] * b["F"] for b in br) / ptot if ptot > 0 else float("nan")
+    return {"branches": br, "dropped": dropped, "F_mp": fmp}
