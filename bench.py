@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the dynamic-circuit simulation hot path on one MI355X.
+
+Workload (the precision form): 40-qubit chain, depth-20 Haar brickwork, a
+round of 4 mid-circuit Z measurements (qubits 1..38) every 2 layers with X on
+the right and Z on the left neighbour when the outcome is 1; bond cap 256;
+single-path sampling (Alg. 1), two sweeps per compression step, chunks broken
+only at measurements.  One step = one batch of `--shots` independent shots
+simulated in lockstep from |0...0> to the end of the circuit (every
+compression step, measurement probability and collapse of every shot).
+
+The timed form stores and contracts in complex64 (FP32 MFMA, FP32
+accumulation) with FP64 QR, norms and renormalisation; the plain FP64 path
+(complex128 on FP64 MFMA) is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "cfg2_n40_chi256"
+PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA")}
+HBM_PEAK_GBS = 8000.0
+CLASSES = ["gemm", "gate_operator", "qr", "measure", "other"]
+
+
+def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool):
+    import torch
+    from inputs import circuits as C
+    from inputs.randomness import shot_uniforms
+    from paper_2609_26516_amd import engine as E
+
+    circ, prm = C.workload(WORKLOAD)
+    n, chi = prm["n"], prm["chi"]
+    k = C.segment_max(circ)
+    eng = E.Engine(0)
+    st = E.State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
+    nm = circ.n_measurements()
+
+    def one_step(step):
+        u = np.stack([shot_uniforms(prm["seed"], step * shots + s, nm) for s in range(shots)])
+        res = E.run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
+        st.release(res["ids"])
+        return res
+
+    for w in range(warmup):
+        one_step(10_000 + w)
+    torch.cuda.synchronize()
+    eng.timing(timing)
+    eng.timing_stats(reset=True)
+    t0 = time.perf_counter()
+    fids = []
+    for s in range(steps):
+        r = one_step(s)
+        fids.append(float(np.mean(r["F"])))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = eng.timing_stats(reset=True) if timing else None
+    eng.timing(False)
+    st.close()
+    eng.close()
+    return dt, stats, fids
+
+
+def roofline(stats, prec):
+    launches, ms, flops, byts = stats
+    dom = int(np.argmax(ms))
+    avg_ms = ms[dom] / max(1, launches[dom])
+    per_launch_flops = flops[dom] / max(1, launches[dom])
+    per_launch_bytes = byts[dom] / max(1, launches[dom])
+    if CLASSES[dom] in ("gemm", "measure") or (CLASSES[dom] == "qr" and False):
+        peak, _ = PEAK[prec]
+        ach = per_launch_flops / (avg_ms * 1e-3) / 1e12
+        rl = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+              "frac": round(ach / peak, 4), "traffic": None}
+    elif CLASSES[dom] == "qr":
+        ach = per_launch_flops / (avg_ms * 1e-3) / 1e12
+        rl = {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
+              "frac": round(ach / 78.6, 4), "traffic": None}
+    else:
+        ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        rl = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    rl["kernel"] = CLASSES[dom]
+    rl["avg_launch_ms"] = round(avg_ms, 5)
+    rl["launches"] = int(launches[dom])
+    rl["time_share"] = round(ms[dom] / max(1e-12, sum(ms)), 4)
+    rl["classes_ms"] = {c: round(v, 2) for c, v in zip(CLASSES, ms)}
+    return rl
+
+
+def cpu_baseline(rounds: int):
+    """The FP64 oracle on the first `rounds` measurement rounds of one shot of
+    the same workload, scaled to shots/s by the fraction of rounds done."""
+    from threadpoolctl import threadpool_info
+    from inputs import circuits as C
+    from inputs.randomness import shot_uniforms
+    from oracle import dynamic as OD
+
+    circ, prm = C.workload(WORKLOAD)
+    n, chi = prm["n"], prm["chi"]
+    per_round = prm["layers_per_round"] * (n // 2) + 2 * prm["meas_per_round"]
+    total_rounds = prm["depth"] // prm["layers_per_round"]
+    ops, seen = [], 0
+    for op in circ.ops:
+        ops.append(op)
+        if isinstance(op, C.Measure):
+            seen += 1
+            if seen == rounds * prm["meas_per_round"]:
+                break
+    sub = C.Circuit(circ.n_qubits, circ.n_bits, ops, name="prefix")
+    sim = OD.Simulator(n, chi, C.segment_max(circ), 2, prm["init_seed"])
+    sim.bra_init(chi)   # starting guess built before the clock starts
+    u = shot_uniforms(prm["seed"], 0, circ.n_measurements())
+    t0 = time.perf_counter()
+    OD.run_single_path(sub, sim, uniforms=u)
+    dt = time.perf_counter() - t0
+    threads = sum(i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas")
+    del per_round
+    return {"value": round((rounds / total_rounds) / dt, 6), "unit": "shots/s",
+            "cores": int(threads or 1), "kind": "oracle",
+            "sample": f"first {rounds} of {total_rounds} rounds (compression + 4 measurements "
+                      f"each) of one shot, {dt:.1f} s, scaled by {rounds}/{total_rounds}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--cpu-rounds", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(shots shard across GPUs without communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, timing=True)
+    value = args.shots * args.steps / dt
+    out = {
+        "metric": "shots/s (batched FP32-MFMA form, chi=256), FP64 path beside it",
+        "value": round(value, 4), "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic: seeded Haar brickwork dynamic circuit",
+        "config": {"workload": "n40_depth20_chi256_4meas_per_2layers_single_path",
+                   "shots_per_step": args.shots, "n_qubits": 40, "depth": 20, "chi": 256,
+                   "sweeps": 2, "precision": "complex64 contractions, FP64 QR/norms"},
+        "roofline": roofline(stats, "c64"),
+        "mean_fidelity_estimate": round(float(np.mean(fids)), 6),
+    }
+    if not args.no_fp64:
+        dt64, _, _ = run_gpu("c128", args.shots, args.fp64_steps, 0, timing=False)
+        out["fp64_path"] = {"value": round(args.shots * args.fp64_steps / dt64, 4),
+                            "unit": "shots/s", "steps": args.fp64_steps, "dtype": "c128"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rounds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,46 @@
+/*
+ * dcs_testing.h -- kernel-level entry points of libdcs.so for unit tests.
+ *
+ * Each call runs one internal kernel of the compression step on host data
+ * (complex128 interleaved in, complex128 interleaved out), allocating and
+ * freeing its own device buffers, and synchronises `stream` (hipStream_t).
+ * Storage types: 0 complex64, 1 complex128.  They exist so the contraction,
+ * gate-operator and QR kernels can be checked one by one against plain
+ * references; the simulation path does not use them.  Status codes as in
+ * dcs.h.
+ */
+#ifndef DCS_TESTING_H
+#define DCS_TESTING_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b] = op(A[b]) op(B[b]) for b < batch.  opa: 0 N (A stored M x K),
+ * 2 C (conjugate transpose, A stored K x M), 3 J (conjugate, stored M x K);
+ * opb: 0 N (B stored K x N), 1 T (B stored N x K).  Items are contiguous:
+ * A[b] at b * M * K, B[b] at b * K * N, C[b] at b * M * N.  ta/tb/tc are the
+ * storage types of A, B, C and tacc the accumulation type (1 = FP64 MFMA,
+ * 0 = FP32 MFMA); only the combinations the library uses are available
+ * (DCS_EINVAL otherwise). */
+int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
+                  int batch, const double *A, const double *B, double *C, void *stream);
+
+/* Gate-operator application.  dir 0: in X1[d0][wl][2][d1] -> out
+ * X2[d0][2][wr][d1]; dir 1: in Y1[d0][2][d1][wr] -> out Y2[wl][d0][2][d1];
+ * w = W[wl][2][2][wr]. */
+int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double *in,
+                 const double *w, double *out, void *stream);
+
+/* FP64 Householder QR of one matrix.  mode 0: F is m x n row-major, Q (m x n)
+ * returned; mode 1: F is n x m row-major, Q^H of QR(F^H) (n x m) returned;
+ * mode 2: F / |F| returned.  *nrm2_out = |F|^2.  use_lds selects the LDS
+ * variant when the matrix fits. */
+int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, const double *F,
+                double *Q, double *nrm2_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCS_TESTING_H */

@@ -28,6 +28,7 @@ EXPORTED = [
     "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
     "dcs_export_mps", "dcs_import_mps",
 ]
+EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr"]
 
 
 class DcsError(RuntimeError):
@@ -69,6 +70,9 @@ _SIGS = {
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
+    "dcs_test_gemm": (c_int, [c_int] * 10 + [_DP, _DP, _DP, _P]),
+    "dcs_test_mpo": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
+    "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -241,3 +245,40 @@ def dcs_import_mps(st, bid, chi_cap, sites, stream) -> None:
     flat = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).reshape(-1)
                            for a in sites]).view(np.float64)
     _check(_lib.dcs_import_mps(st, bid, chi_cap, _dp(flat), _ip(dims), stream))
+
+
+# --- kernel-level test entry points (include/dcs_testing.h) -----------------
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b, stream=0) -> np.ndarray:
+    """a: (batch, rows, cols) as stored; b likewise; returns (batch, M, N)."""
+    a, b = _c128(a), _c128(b)
+    batch = a.shape[0]
+    m = a.shape[2] if opa == 2 else a.shape[1]
+    k = a.shape[1] if opa == 2 else a.shape[2]
+    n = b.shape[1] if opb == 1 else b.shape[2]
+    c = np.zeros((batch, m, n), dtype=np.complex128)
+    _check(_lib.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, m, n, k, batch,
+                              _dp(a.view(np.float64)), _dp(b.view(np.float64)),
+                              _dp(c.view(np.float64)), stream))
+    return c
+
+
+def dcs_test_mpo(ct, direction, d0, d1, wl, wr, x, w, stream=0) -> np.ndarray:
+    x, w = _c128(x), _c128(w)
+    out = np.zeros(d0 * d1 * 2 * (wr if direction == 0 else wl), dtype=np.complex128)
+    _check(_lib.dcs_test_mpo(ct, direction, d0, d1, wl, wr, _dp(x.view(np.float64)),
+                             _dp(w.view(np.float64)), _dp(out.view(np.float64)), stream))
+    return out
+
+
+def dcs_test_qr(ct_in, ct_out, m, n, mode, use_lds, f, stream=0):
+    f = _c128(f)
+    q = np.zeros(m * n, dtype=np.complex128)
+    nrm = np.zeros(1)
+    _check(_lib.dcs_test_qr(ct_in, ct_out, m, n, mode, 1 if use_lds else 0,
+                            _dp(f.view(np.float64)), _dp(q.view(np.float64)), _dp(nrm), stream))
+    return q, float(nrm[0])

@@ -28,12 +28,16 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename R>
 struct Mfma;
+// Operand layout of both 16x16x4 forms: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Result: lane l, item r holds D[row][l % 16] with
+// row = 4 (l / 16) + r for FP32 and row = l / 16 + 4 r for FP64.
 template <>
 struct Mfma<float> {
   using V = v4f;
   static __device__ __forceinline__ V mma(float a, float b, V c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 template <>
 struct Mfma<double> {
@@ -41,6 +45,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ V mma(double a, double b, V c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
 };
 
 template <int CT>
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
       const int col = n0 + wn + j * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + 4 * lk + r;
+        const int row = m0 + wm + i * 16 + Mfma<R>::row(lk, r);
         if (row < M && col < N) {
           CC v;
           v.x = cr[i][j][r];

@@ -59,6 +59,10 @@ size_t csize_of(int ct) { return ct == CT_F32 ? 8 : 16; }
 
 }  // namespace
 
+namespace dcs {
+int testing_fail(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace dcs
+
 // ---------------------------------------------------------------------------
 // Opaque handles
 

@@ -1,0 +1,201 @@
+// Kernel-level test entry points (include/dcs_testing.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dcs.h"
+#include "dcs_internal.h"
+#include "dcs_testing.h"
+
+using namespace dcs;
+
+namespace dcs {
+int testing_fail(int code, const std::string& msg);
+}
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+size_t csz(int ct) { return ct == CT_F32 ? 8 : 16; }
+
+std::vector<char> pack(int ct, const double* src, size_t count) {
+  std::vector<char> out(count * csz(ct));
+  for (size_t i = 0; i < count; ++i) {
+    if (ct == CT_F32) {
+      reinterpret_cast<float2*>(out.data())[i] = make_float2((float)src[2 * i], (float)src[2 * i + 1]);
+    } else {
+      reinterpret_cast<double2*>(out.data())[i] = make_double2(src[2 * i], src[2 * i + 1]);
+    }
+  }
+  return out;
+}
+
+void unpack(int ct, const std::vector<char>& in, double* dst, size_t count) {
+  for (size_t i = 0; i < count; ++i) {
+    if (ct == CT_F32) {
+      const float2 v = reinterpret_cast<const float2*>(in.data())[i];
+      dst[2 * i] = v.x;
+      dst[2 * i + 1] = v.y;
+    } else {
+      const double2 v = reinterpret_cast<const double2*>(in.data())[i];
+      dst[2 * i] = v.x;
+      dst[2 * i + 1] = v.y;
+    }
+  }
+}
+
+#define T_HIP(expr)                                                                           \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return testing_fail(DCS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int upload(int ct, const double* src, size_t count, DevBuf& b, hipStream_t s) {
+  std::vector<char> h = pack(ct, src, count);
+  T_HIP(hipMalloc(&b.p, std::max<size_t>(h.size(), 256)));
+  T_HIP(hipMemcpyAsync(b.p, h.data(), h.size(), hipMemcpyHostToDevice, s));
+  T_HIP(hipStreamSynchronize(s));
+  return DCS_OK;
+}
+
+Operand op_of(const void* p, long long stride) {
+  Operand o;
+  o.base = p;
+  o.stride = stride;
+  o.by_slot = 0;
+  o.pad_ = 0;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
+                  int batch, const double* A, const double* B, double* C, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C)
+    return testing_fail(DCS_EINVAL, "bad gemm test arguments");
+  if ((opa != OP_N && opa != OP_C && opa != OP_J) || (opb != OP_N && opb != OP_T))
+    return testing_fail(DCS_EINVAL, "bad op");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf da, db, dc;
+  const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
+  int rc = upload(ta, A, na, da, s);
+  if (rc) return rc;
+  rc = upload(tb, B, nb, db, s);
+  if (rc) return rc;
+  T_HIP(hipMalloc(&dc.p, nc * csz(tc)));
+  GemmArgs args;
+  std::memset(&args, 0, sizeof(args));
+  GemmGroup& g = args.g[0];
+  g.a = op_of(da.p, (long long)M * K * csz(ta));
+  g.b = op_of(db.p, (long long)K * N * csz(tb));
+  g.c = op_of(dc.p, (long long)M * N * csz(tc));
+  g.ids = nullptr;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = (opa == OP_C) ? M : K;
+  g.ldb = (opb == OP_T) ? K : N;
+  g.ldc = N;
+  g.batch = batch;
+  g.tiles_n = (N + 63) / 64;
+  g.tiles_per_item = ((M + 63) / 64) * g.tiles_n;
+  g.tile_begin = 0;
+  args.ngroups = 1;
+  args.total_tiles = g.tiles_per_item * batch;
+  hipError_t e = launch_gemm(ta, tb, tc, tacc, opa, opb, args, s);
+  if (e == hipErrorInvalidValue) return testing_fail(DCS_EINVAL, "type/op combination not built");
+  T_HIP(e);
+  std::vector<char> h(nc * csz(tc));
+  T_HIP(hipMemcpyAsync(h.data(), dc.p, h.size(), hipMemcpyDeviceToHost, s));
+  T_HIP(hipStreamSynchronize(s));
+  unpack(tc, h, C, nc);
+  return DCS_OK;
+}
+
+int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double* in,
+                 const double* w, double* out, void* stream) {
+  if (d0 < 1 || d1 < 1 || wl < 1 || wr < 1 || wl > 16 || wr > 16 || !in || !w || !out)
+    return testing_fail(DCS_EINVAL, "bad mpo test arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf di, dw, dout;
+  const size_t nin = (size_t)d0 * d1 * 2 * (dir == 0 ? wl : wr);
+  const size_t nout = (size_t)d0 * d1 * 2 * (dir == 0 ? wr : wl);
+  int rc = upload(ct, in, nin, di, s);
+  if (rc) return rc;
+  rc = upload(ct, w, (size_t)wl * 4 * wr, dw, s);
+  if (rc) return rc;
+  T_HIP(hipMalloc(&dout.p, nout * csz(ct)));
+  MpoArgs args;
+  std::memset(&args, 0, sizeof(args));
+  MpoGroup& g = args.g[0];
+  g.in = op_of(di.p, 0);
+  g.out = op_of(dout.p, 0);
+  g.w = op_of(dw.p, 0);
+  g.ids = nullptr;
+  g.d0 = d0;
+  g.d1 = d1;
+  g.wl = wl;
+  g.wr = wr;
+  g.batch = 1;
+  g.blk_per_item = (int)(((long long)d0 * d1 + 255) / 256);
+  g.blk_begin = 0;
+  args.ngroups = 1;
+  args.total_blocks = g.blk_per_item;
+  T_HIP(launch_mpo(ct, dir, args, s));
+  std::vector<char> h(nout * csz(ct));
+  T_HIP(hipMemcpyAsync(h.data(), dout.p, h.size(), hipMemcpyDeviceToHost, s));
+  T_HIP(hipStreamSynchronize(s));
+  unpack(ct, h, out, nout);
+  return DCS_OK;
+}
+
+int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, const double* F,
+                double* Q, double* nrm2_out, void* stream) {
+  if (m < 1 || n < 1 || n > 1024 || (mode != 2 && m < n) || mode < 0 || mode > 2 || !F || !Q ||
+      !nrm2_out)
+    return testing_fail(DCS_EINVAL, "bad qr test arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf df, dq, dws, dn;
+  const size_t mn = (size_t)m * n;
+  int rc = upload(ct_in, F, mn, df, s);
+  if (rc) return rc;
+  T_HIP(hipMalloc(&dq.p, mn * csz(ct_out)));
+  T_HIP(hipMalloc(&dws.p, mn * 16));
+  T_HIP(hipMalloc(&dn.p, 256));
+  QrArgs args;
+  std::memset(&args, 0, sizeof(args));
+  QrGroup& g = args.g[0];
+  g.f = op_of(df.p, 0);
+  g.q = op_of(dq.p, 0);
+  g.ws = op_of(dws.p, 0);
+  g.nrm2 = op_of(dn.p, 0);
+  g.ids = nullptr;
+  g.m = m;
+  g.n = n;
+  g.mode = mode;
+  g.batch = 1;
+  g.blk_begin = 0;
+  args.ngroups = 1;
+  args.total_blocks = 1;
+  const size_t lds = mn * 16;
+  args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
+  T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+  std::vector<char> h(mn * csz(ct_out));
+  T_HIP(hipMemcpyAsync(h.data(), dq.p, h.size(), hipMemcpyDeviceToHost, s));
+  T_HIP(hipMemcpyAsync(nrm2_out, dn.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  T_HIP(hipStreamSynchronize(s));
+  unpack(ct_out, h, Q, mn);
+  return DCS_OK;
+}
+
+}  // extern "C"

@@ -10,10 +10,11 @@ from inputs import circuits as C
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "dcs.h")
+HEADER_TESTING = os.path.join(ROOT, "include", "dcs_testing.h")
 
 
-def _declared():
-    txt = open(HEADER).read()
+def _declared(path=HEADER):
+    txt = open(path).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(dcs_[a-z_0-9]+)\s*\(", txt)))
 
@@ -27,6 +28,10 @@ def test_header_declares_and_library_exports():
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(capi.EXPORTED) == names
+    tnames = _declared(HEADER_TESTING)
+    for name in tnames:
+        assert hasattr(lib, name), name
+    assert sorted(capi.EXPORTED_TESTING) == tnames
 
 
 def test_version():

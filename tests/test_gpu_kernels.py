@@ -1,0 +1,120 @@
+"""Kernel-level checks of the contraction, gate-operator and QR kernels
+against plain numpy references (FP64), through include/dcs_testing.h."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 0, 1
+OPN, OPT, OPC, OPJ = 0, 1, 2, 3
+
+
+@pytest.fixture(scope="module")
+def capi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_26516_amd import capi as c
+    return c
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+COMBOS = [
+    (F64, F64, F64, F64, OPN, OPN), (F64, F64, F64, F64, OPN, OPT),
+    (F64, F64, F64, F64, OPC, OPN), (F64, F64, F64, F64, OPJ, OPT),
+    (F32, F32, F32, F32, OPN, OPN), (F32, F32, F32, F32, OPN, OPT),
+    (F32, F32, F32, F32, OPC, OPN), (F32, F32, F32, F32, OPJ, OPT),
+    (F64, F32, F64, F64, OPN, OPN), (F32, F64, F64, F64, OPC, OPN),
+    (F32, F64, F64, F64, OPN, OPT), (F32, F64, F64, F64, OPJ, OPT),
+    (F32, F32, F64, F64, OPC, OPN), (F32, F32, F64, F64, OPJ, OPT),
+]
+
+
+@pytest.mark.parametrize("combo", COMBOS)
+@pytest.mark.parametrize("mnk", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 130, 37),
+                                 (200, 96, 257)])
+def test_gemm(capi, combo, mnk):
+    ta, tb, tc, tacc, opa, opb = combo
+    m, n, k = mnk
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    batch = 3
+    a = _rand(rng, batch, k, m) if opa == OPC else _rand(rng, batch, m, k)
+    b = _rand(rng, batch, n, k) if opb == OPT else _rand(rng, batch, k, n)
+    if ta == F32:
+        a = a.astype(np.complex64).astype(np.complex128)
+    if tb == F32:
+        b = b.astype(np.complex64).astype(np.complex128)
+    c = capi.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b)
+    A = {OPN: a, OPC: np.conj(np.swapaxes(a, 1, 2)), OPJ: np.conj(a)}[opa]
+    B = {OPN: b, OPT: np.swapaxes(b, 1, 2)}[opb]
+    ref = A @ B
+    # rounding bound ~ K u max|a||b|; inputs are O(1), so scale by K
+    u = 1.2e-16 if (tacc == F64 and tc == F64) else 6e-8
+    tol = 8 * u * k * 2
+    err = np.max(np.abs(c - ref))
+    assert err < tol, (err, tol)
+
+
+@pytest.mark.parametrize("ct", [F32, F64])
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("d0,d1,wl,wr", [(1, 2, 1, 4), (5, 7, 4, 4), (33, 300, 4, 1),
+                                         (9, 11, 16, 4), (3, 70, 2, 16)])
+def test_gate_operator(capi, ct, direction, d0, d1, wl, wr):
+    rng = np.random.default_rng(d0 * 31 + d1 + wl * 5 + wr)
+    w = _rand(rng, wl, 2, 2, wr)
+    if direction == 0:
+        x = _rand(rng, d0, wl, 2, d1)
+        ref = np.einsum("awty,wstv->asvy", x, w)
+    else:
+        x = _rand(rng, d0, 2, d1, wr)
+        ref = np.einsum("xtcv,wstv->wxsc", x, w)
+    if ct == F32:
+        x = x.astype(np.complex64).astype(np.complex128)
+        w = w.astype(np.complex64).astype(np.complex128)
+        ref = (np.einsum("awty,wstv->asvy", x, w) if direction == 0
+               else np.einsum("xtcv,wstv->wxsc", x, w))
+    out = capi.dcs_test_mpo(ct, direction, d0, d1, wl, wr, x.reshape(-1), w.reshape(-1))
+    tol = 1e-12 if ct == F64 else 1e-5
+    assert np.max(np.abs(out - ref.reshape(-1))) < tol * np.sqrt(wl * wr * 4)
+
+
+@pytest.mark.parametrize("use_lds", [0, 1])
+@pytest.mark.parametrize("m,n", [(2, 1), (4, 2), (8, 8), (32, 16), (64, 32), (130, 65),
+                                 (512, 256)])
+def test_qr_full_rank(capi, use_lds, m, n):
+    rng = np.random.default_rng(m + n)
+    f = _rand(rng, m, n)
+    q, nrm2 = capi.dcs_test_qr(F64, F64, m, n, 0, use_lds, f.reshape(-1))
+    q = q.reshape(m, n)
+    qn, _ = np.linalg.qr(f)
+    assert abs(nrm2 - np.sum(np.abs(f) ** 2)) < 1e-10 * nrm2
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(n), atol=1e-12)
+    # same Householder convention as LAPACK: Q agrees element-wise
+    assert np.max(np.abs(q - qn)) < 1e-10
+    # LQ mode on the conjugate transpose layout
+    g = f.conj().T.copy()                                  # n x m
+    ql, _ = capi.dcs_test_qr(F64, F64, m, n, 1, use_lds, g.reshape(-1))
+    ql = ql.reshape(n, m)
+    np.testing.assert_allclose(ql @ ql.conj().T, np.eye(n), atol=1e-12)
+    assert np.max(np.abs(ql - qn.conj().T)) < 1e-10
+
+
+def test_qr_rank_deficient_and_normalise(capi):
+    rng = np.random.default_rng(1)
+    m, n = 64, 32
+    f = _rand(rng, m, 3) @ _rand(rng, 3, n)                  # rank 3
+    f[:, 5] = 0
+    q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, 0, f.reshape(-1))
+    q = q.reshape(m, n)
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(q @ (q.conj().T @ f), f, atol=1e-11)
+    # mode 2: F / |F|
+    t, nrm2 = capi.dcs_test_qr(F32, F32, 10, 3, 2, 0, f[:10, :3].reshape(-1))
+    ref = f[:10, :3] / np.linalg.norm(f[:10, :3])
+    assert np.max(np.abs(t.reshape(10, 3) - ref)) < 1e-6
+    # exactly zero matrix: Q is the leading identity columns
+    z, _ = capi.dcs_test_qr(F64, F64, 6, 3, 0, 1, np.zeros(18, complex))
+    np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
