@@ -52,6 +52,62 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return scratch[0] + scratch[1] + scratch[2] + scratch[3];
 }
 
+// Running (scale, sum of squares) pair: the represented value is
+// scale^2 * ssq, accumulated without squaring anything tiny or huge.
+__device__ __forceinline__ void ssq_add(double& sc, double& q, double x) {
+  x = fabs(x);
+  if (x > 0.0) {
+    if (sc < x) {
+      const double r = sc / x;
+      q = 1.0 + q * r * r;
+      sc = x;
+    } else {
+      const double r = x / sc;
+      q += r * r;
+    }
+  }
+}
+
+__device__ __forceinline__ void ssq_merge(double& sc, double& q, double sc2, double q2) {
+  if (sc2 > sc) {
+    const double r = sc / sc2;
+    q = q2 + q * r * r;
+    sc = sc2;
+  } else if (sc2 > 0.0) {
+    const double r = sc2 / sc;
+    q += q2 * r * r;
+  }
+}
+
+// Block-wide merge of (scale, ssq); every thread gets the result.
+__device__ __forceinline__ void block_ssq(double& sc, double& q, double* scratch) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double s2 = __shfl_xor(sc, o, 64), q2 = __shfl_xor(q, o, 64);
+    ssq_merge(sc, q, s2, q2);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wave] = sc;
+    scratch[2 * wave + 1] = q;
+  }
+  __syncthreads();
+  sc = scratch[0];
+  q = scratch[1];
+  for (int w = 1; w < 4; ++w) ssq_merge(sc, q, scratch[2 * w], scratch[2 * w + 1]);
+}
+
+// 1 / d by Smith's scaling (no overflow or underflow of |d|^2).
+__device__ __forceinline__ double2 crecip(double2 d) {
+  if (fabs(d.x) >= fabs(d.y)) {
+    const double r = d.y / d.x, den = d.x + d.y * r;
+    return make_double2(1.0 / den, -r / den);
+  }
+  const double r = d.x / d.y, den = d.x * r + d.y;
+  return make_double2(r / den, -1.0 / den);
+}
+
 template <int GROUPS, typename G>
 __device__ __forceinline__ int find_group(const G* g, int ngroups, int blk) {
   int gi = 0;
@@ -195,7 +251,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
   using TO = typename St<CTO>::T;
   extern __shared__ double2 dyn_lds[];
   __shared__ double2 s_tau[1024];
-  __shared__ double s_red[4];
+  __shared__ double s_red[8];
   __shared__ double2 s_bc[2];
 
   const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
@@ -250,23 +306,29 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
   // factorisation
   for (int k = 0; k < n; ++k) {
     double2* colk = W + (long long)k * m;
-    double p = 0;
+    // scaled sum of squares of x = column k below the diagonal (no underflow
+    // for the tiny entries rank-deficient local tensors carry)
+    double sc = 0.0, q = 0.0;
     for (int i = k + 1 + tid; i < m; i += NT) {
       const double2 v = colk[i];
-      p += v.x * v.x + v.y * v.y;
+      ssq_add(sc, q, v.x);
+      ssq_add(sc, q, v.y);
     }
-    const double xn2 = block_sum(p, s_red);
+    block_ssq(sc, q, s_red);
     if (tid == 0) {
       const double2 alpha = colk[k];
       double2 tau = make_double2(0.0, 0.0), scal = make_double2(1.0, 0.0);
-      if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-        const double nrm_all = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
-        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        const double2 d = make_double2(alpha.x - beta, alpha.y);   // alpha - beta
-        const double dd = d.x * d.x + d.y * d.y;
-        scal = make_double2(d.x / dd, -d.y / dd);                    // 1 / (alpha - beta)
-        colk[k] = make_double2(beta, 0.0);
+      if (!(sc == 0.0 && alpha.y == 0.0)) {
+        double sa = sc, qa = q;
+        ssq_add(sa, qa, alpha.x);
+        ssq_add(sa, qa, alpha.y);
+        const double nrm_all = sa * sqrt(qa);
+        if (nrm_all > 1e-280) {
+          const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+          tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+          scal = crecip(make_double2(alpha.x - beta, alpha.y));   // 1 / (alpha - beta)
+          colk[k] = make_double2(beta, 0.0);
+        }
       }
       s_tau[k] = tau;
       s_bc[0] = tau;

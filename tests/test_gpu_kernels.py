@@ -118,3 +118,30 @@ def test_qr_rank_deficient_and_normalise(capi):
     # exactly zero matrix: Q is the leading identity columns
     z, _ = capi.dcs_test_qr(F64, F64, 6, 3, 0, 1, np.zeros(18, complex))
     np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tiny", [1e-120, 1e-170, 1e-250])
+def test_qr_tiny_noise_columns(capi, mode, tiny):
+    """Rank-deficient local tensors carry noise far below the FP64 square
+    range; the factorisation must stay finite and orthonormal."""
+    rng = np.random.default_rng(int(-np.log10(tiny)))
+    m, n = 256, 128
+    f = _rand(rng, m, 2) @ _rand(rng, 2, n) + tiny * _rand(rng, m, n)
+    f[:, 7] *= tiny
+    if mode == 0:
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, 0, f.reshape(-1))
+        q = q.reshape(m, n)
+        gram = q.conj().T @ q
+        rec = q @ (q.conj().T @ f)
+        target = f
+    else:
+        g = f.conj().T.copy()
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 1, 0, g.reshape(-1))
+        q = q.reshape(n, m)
+        gram = q @ q.conj().T
+        rec = (g @ q.conj().T) @ q
+        target = g
+    assert np.all(np.isfinite(q))
+    np.testing.assert_allclose(gram, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(rec, target, atol=1e-12)
