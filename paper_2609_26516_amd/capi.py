@@ -275,10 +275,10 @@ def dcs_test_mpo(ct, direction, d0, d1, wl, wr, x, w, stream=0) -> np.ndarray:
     return out
 
 
-def dcs_test_qr(ct_in, ct_out, m, n, mode, use_lds, f, stream=0):
+def dcs_test_qr(ct_in, ct_out, m, n, mode, variant, f, stream=0):
     f = _c128(f)
     q = np.zeros(m * n, dtype=np.complex128)
     nrm = np.zeros(1)
-    _check(_lib.dcs_test_qr(ct_in, ct_out, m, n, mode, 1 if use_lds else 0,
+    _check(_lib.dcs_test_qr(ct_in, ct_out, m, n, mode, int(variant),
                             _dp(f.view(np.float64)), _dp(q.view(np.float64)), _dp(nrm), stream))
     return q, float(nrm[0])

@@ -87,6 +87,11 @@ struct QrArgs {
 };
 hipError_t launch_qr(int ct_in, int ct_out, const QrArgs& args, size_t lds_bytes, hipStream_t s);
 size_t qr_lds_limit();
+// Blocked variant (16-column panels in LDS, FP64 MFMA updates) for m <=
+// qr_blocked_max_rows(); the workspace of each item holds m*n + 256*ceil(n/16)
+// complex128 values, row-major working matrix first.
+hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s);
+int qr_blocked_max_rows();
 
 // n_m = Re sum_{a,b} conj(A[a][m][b]) Z[a][m][b] for m = 0, 1 (FP64), one
 // workgroup per branch; Z = A when z.base is null.

@@ -424,6 +424,356 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
 }
 
 // ---------------------------------------------------------------------------
+// Blocked FP64 Householder QR with explicit thin Q (same reflectors as the
+// unblocked kernel above).  One workgroup per matrix; the m x n working
+// matrix is row-major in the branch's global workspace.  16-column panels are
+// factored in LDS (rows of the panel swizzled so column walks and MFMA operand
+// fetches are free of bank conflicts); each panel's reflectors are combined
+// into the compact WY form H_0 ... H_15 = I - V T V^H; the trailing columns
+// are updated with FP64 MFMA (v_mfma_f64_16x16x4) in 16-column sub-strips,
+// one sub-strip per wave: W = V^H A, W2 = T^H W (both kept in the MFMA result
+// registers, whose layout is the next product's B-operand layout),
+// A -= V W2.  Q is then accumulated backwards panel by panel in place.
+
+constexpr int QB = 16;
+
+__device__ __forceinline__ int pidx(int i, int c) { return i * QB + (c ^ (i & 15)); }
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d_t mfma64(double a, double b, v4d_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// complex accumulate (cr, ci) += (ar + i ai)(br + i bi) on one 16x16x4 step
+__device__ __forceinline__ void cmma(double ar, double ai, double br, double bi, v4d_t& cr,
+                                     v4d_t& ci) {
+  cr = mfma64(ar, br, cr);
+  cr = mfma64(-ai, bi, cr);
+  ci = mfma64(ar, bi, ci);
+  ci = mfma64(ai, br, ci);
+}
+
+// Reflector r of the panel at local row i: 0 above the diagonal, 1 on it.
+__device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, int nbk) {
+  if (r >= nbk || i < r || i >= mp) return make_double2(0.0, 0.0);
+  if (i == r) return make_double2(1.0, 0.0);
+  return P[pidx(i, r)];
+}
+
+__device__ __forceinline__ void zero4(v4d_t& a) {
+  a[0] = 0;
+  a[1] = 0;
+  a[2] = 0;
+  a[3] = 0;
+}
+
+// Apply (I - V X V^H) to the 16-column sub-strip at global column c0 of rows
+// p..m-1 of the row-major matrix A (leading dimension n), X = T^H (conjT) or
+// T.  Executed by one wave.
+__device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int nbk, int c0,
+                            const double2* P, const double2* sT, bool conjT, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  const bool col_ok = col < n;
+  v4d_t wr, wi;
+  zero4(wr);
+  zero4(wi);
+  // W = V^H A_sub  (16 x 16): k runs over the panel rows
+  for (int i0 = 0; i0 < mp; i0 += 4) {
+    const int i = i0 + lk;
+    const double2 v = vval(P, i, li, mp, nbk);
+    double2 b = make_double2(0.0, 0.0);
+    if (i < mp && col_ok) b = A[(long long)(p + i) * n + col];
+    cmma(v.x, -v.y, b.x, b.y, wr, wi);
+  }
+  // W2 = X W; W's result item t holds row lk + 4t = the B operand of k-step t
+  v4d_t xr, xi;
+  zero4(xr);
+  zero4(xi);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int s = 4 * t + lk;
+    double2 a;
+    if (conjT) {
+      const double2 tt = sT[s * QB + li];   // X[li][s] = conj(T[s][li])
+      a = make_double2(tt.x, -tt.y);
+    } else {
+      a = sT[li * QB + s];                  // X[li][s] = T[li][s]
+    }
+    cmma(a.x, a.y, wr[t], wi[t], xr, xi);
+  }
+  // A_sub -= V W2, 16 rows at a time
+  for (int rb = 0; rb < mp; rb += 16) {
+    v4d_t dr, di;
+    zero4(dr);
+    zero4(di);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double2 v = vval(P, rb + li, 4 * t + lk, mp, nbk);
+      cmma(v.x, v.y, xr[t], xi[t], dr, di);
+    }
+    if (col_ok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = rb + lk + 4 * t;
+        if (i < mp) {
+          double2* ptr = A + (long long)(p + i) * n + col;
+          const double2 o = *ptr;
+          *ptr = make_double2(o.x - dr[t], o.y - di[t]);
+        }
+      }
+    }
+  }
+}
+
+template <int CTI, int CTO>
+__global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
+  using TI = typename St<CTI>::T;
+  using TO = typename St<CTO>::T;
+  extern __shared__ double2 P[];          // panel, rows p..m-1, swizzled
+  __shared__ double2 sT[QB * QB];
+  __shared__ double2 sG[QB * QB];
+  __shared__ double2 s_tau[QB];
+  __shared__ double s_red[8];
+  __shared__ double2 s_bc[2];
+
+  const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const QrGroup& G = args.g[gi];
+  const int item = blockIdx.x - G.blk_begin;
+  const int m = G.m, n = G.n, mode = G.mode;
+  const TI* __restrict__ F = reinterpret_cast<const TI*>(item_ptr(G.f, G.ids, item));
+  TO* __restrict__ Q = reinterpret_cast<TO*>(const_cast<char*>(item_ptr(G.q, G.ids, item)));
+  double* nrm = reinterpret_cast<double*>(const_cast<char*>(item_ptr(G.nrm2, G.ids, item)));
+  double2* A = reinterpret_cast<double2*>(const_cast<char*>(item_ptr(G.ws, G.ids, item)));
+  double2* Tg = A + (long long)m * n;       // T factor of every panel
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long mn = (long long)m * n;
+
+  // load the row-major working matrix (T, or T^H in mode 1) and |F|^2
+  double part = 0;
+  if (mode == 0) {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+      A[idx] = v;
+    }
+  } else if (mode == 1) {
+    for (long long idx = tid; idx < mn; idx += NT) {   // F is n x m: F[j][i]
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+      const int j = (int)(idx / m), i = (int)(idx % m);
+      A[(long long)i * n + j] = cconj(v);
+    }
+  } else {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      part += v.x * v.x + v.y * v.y;
+    }
+  }
+  const double nu2 = block_sum(part, s_red);
+  if (tid == 0) *nrm = nu2;
+  if (mode == 2) {
+    const double sc = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0;
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = to_d2(F[idx]);
+      TO o;
+      o.x = v.x * sc;
+      o.y = v.y * sc;
+      Q[idx] = o;
+    }
+    return;
+  }
+  __syncthreads();
+
+  const int npan = (n + QB - 1) / QB;
+  for (int pi = 0; pi < npan; ++pi) {
+    const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
+    // panel -> LDS
+    for (int e = tid; e < mp * QB; e += NT) {
+      const int i = e / QB, c = e % QB;
+      P[pidx(i, c)] = (c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // unblocked factorisation of the panel
+    for (int kk = 0; kk < nbk; ++kk) {
+      double sc = 0.0, q = 0.0;
+      for (int i = kk + 1 + tid; i < mp; i += NT) {
+        const double2 v = P[pidx(i, kk)];
+        ssq_add(sc, q, v.x);
+        ssq_add(sc, q, v.y);
+      }
+      block_ssq(sc, q, s_red);
+      if (tid == 0) {
+        const double2 alpha = P[pidx(kk, kk)];
+        double2 tau = make_double2(0.0, 0.0), scal = make_double2(1.0, 0.0);
+        if (!(sc == 0.0 && alpha.y == 0.0)) {
+          double sa = sc, qa = q;
+          ssq_add(sa, qa, alpha.x);
+          ssq_add(sa, qa, alpha.y);
+          const double nrm_all = sa * sqrt(qa);
+          if (nrm_all > 1e-280) {
+            const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            scal = crecip(make_double2(alpha.x - beta, alpha.y));
+            P[pidx(kk, kk)] = make_double2(beta, 0.0);
+          }
+        }
+        s_tau[kk] = tau;
+        s_bc[0] = tau;
+        s_bc[1] = scal;
+      }
+      __syncthreads();
+      const double2 tau = s_bc[0], scal = s_bc[1];
+      if (tau.x == 0.0 && tau.y == 0.0) {
+        // H = I; below-diagonal entries (if any tiny ones) become an exact
+        // zero reflector so V stays consistent with tau = 0
+        for (int i = kk + 1 + tid; i < mp; i += NT) P[pidx(i, kk)] = make_double2(0.0, 0.0);
+        __syncthreads();
+        continue;
+      }
+      for (int i = kk + 1 + tid; i < mp; i += NT) P[pidx(i, kk)] = cmul(P[pidx(i, kk)], scal);
+      __syncthreads();
+      const double2 ctau = cconj(tau);
+      for (int c = kk + 1 + wave; c < nbk; c += 4) {
+        double sr = 0, si = 0;
+        for (int i = kk + lane; i < mp; i += 64) {
+          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : P[pidx(i, kk)];
+          const double2 w = cdotc(v, P[pidx(i, c)]);
+          sr += w.x;
+          si += w.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        const double2 cc = cmul(ctau, make_double2(sr, si));
+        for (int i = kk + lane; i < mp; i += 64) {
+          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : P[pidx(i, kk)];
+          const double2 u = cmul(v, cc);
+          const double2 o = P[pidx(i, c)];
+          P[pidx(i, c)] = make_double2(o.x - u.x, o.y - u.y);
+        }
+      }
+      __syncthreads();
+    }
+    // Gram matrix G = V^H V of the panel (wave 0, MFMA), then T (zlarft)
+    if (wave == 0) {
+      const int li = lane & 15, lk = lane >> 4;
+      v4d_t gr, gim;
+      zero4(gr);
+      zero4(gim);
+      for (int i0 = 0; i0 < mp; i0 += 4) {
+        const double2 a = vval(P, i0 + lk, li, mp, nbk);   // A = V^H: conj(V[i][li])
+        cmma(a.x, -a.y, a.x, a.y, gr, gim);                // B = V[i][li]
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) sG[(lk + 4 * t) * QB + li] = make_double2(gr[t], gim[t]);
+    }
+    sT[tid] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int k = 0; k < nbk; ++k) {
+      if (tid < k) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int t = tid; t < k; ++t) {
+          const double2 u = cmul(sT[tid * QB + t], sG[t * QB + k]);
+          acc.x += u.x;
+          acc.y += u.y;
+        }
+        const double2 tk = s_tau[k];
+        const double2 u = cmul(tk, acc);
+        sT[tid * QB + k] = make_double2(-u.x, -u.y);
+      } else if (tid == k) {
+        sT[k * QB + k] = s_tau[k];
+      }
+      __syncthreads();
+    }
+    Tg[(long long)pi * QB * QB + tid] = sT[tid];
+    // panel (R above, V below the diagonal) back to global
+    for (int e = tid; e < mp * QB; e += NT) {
+      const int i = e / QB, c = e % QB;
+      if (c < nbk) A[(long long)(p + i) * n + p + c] = P[pidx(i, c)];
+    }
+    // trailing columns: A -= V T^H V^H A, one 16-column sub-strip per wave
+    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 64)
+      apply_block(A, n, p, mp, nbk, c0, P, sT, true, lane);
+    __syncthreads();
+  }
+
+  // explicit thin Q, panels in reverse order (in place)
+  for (int pi = npan - 1; pi >= 0; --pi) {
+    const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
+    for (int e = tid; e < mp * QB; e += NT) {
+      const int i = e / QB, c = e % QB;
+      P[pidx(i, c)] = (c < nbk && i > c) ? A[(long long)(p + i) * n + p + c]
+                                         : make_double2(0.0, 0.0);
+    }
+    sT[tid] = Tg[(long long)pi * QB * QB + tid];
+    __syncthreads();
+    // columns already formed: A <- H A with H = I - V T V^H
+    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 64)
+      apply_block(A, n, p, mp, nbk, c0, P, sT, false, lane);
+    // the panel's own columns: [I; 0] - V (T V1^H), V1 the top nbk x nbk block
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      v4d_t sr, si;
+      zero4(sr);
+      zero4(si);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int s = 4 * t + lk;
+        const double2 a = sT[li * QB + s];                    // T[li][s]
+        const double2 b = vval(P, li, s, mp, nbk);            // V1[li][s] -> conj for B
+        cmma(a.x, a.y, b.x, -b.y, sr, si);
+      }
+      // S = T V1^H in registers (item t: row lk + 4t, col li)
+      for (int rb = wave * 16; rb < mp; rb += 64) {
+        v4d_t dr, di;
+        zero4(dr);
+        zero4(di);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double2 v = vval(P, rb + li, 4 * t + lk, mp, nbk);
+          cmma(v.x, v.y, sr[t], si[t], dr, di);
+        }
+        if (li < nbk) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = rb + lk + 4 * t;
+            if (i < mp)
+              A[(long long)(p + i) * n + p + li] =
+                  make_double2((i == li ? 1.0 : 0.0) - dr[t], -di[t]);
+          }
+        }
+      }
+    }
+    for (int e = tid; e < p * nbk; e += NT) {   // rows above the panel
+      const int i = e / nbk, c = e % nbk;
+      A[(long long)i * n + p + c] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+
+  // write Q (mode 0) or Q^H (mode 1)
+  if (mode == 0) {
+    for (long long idx = tid; idx < mn; idx += NT) {
+      const double2 v = A[idx];
+      TO o;
+      o.x = v.x;
+      o.y = v.y;
+      Q[idx] = o;
+    }
+  } else {
+    for (long long idx = tid; idx < mn; idx += NT) {   // out[j][i] = conj(A[i][j])
+      const int j = (int)(idx / m), i = (int)(idx % m);
+      const double2 v = A[(long long)i * n + j];
+      TO o;
+      o.x = v.x;
+      o.y = -v.y;
+      Q[idx] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Outcome norms n_m = Re sum conj(A[a][m][b]) Z[a][m][b], FP64 accumulation.
 
 template <int CTA, int CTZ>
@@ -532,6 +882,29 @@ size_t qr_lds_limit() {
   // dynamic LDS for the working matrix next to the static arrays (16.1 KB),
   // within the 64 KB a workgroup gets without an opt-in
   return 64 * 1024 - 17 * 1024;
+}
+
+size_t qr_blocked_lds(int m) { return (size_t)m * QB * sizeof(double2); }
+int qr_blocked_max_rows() { return 512; }
+
+hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
+  if (args.total_blocks <= 0) return hipSuccess;
+  const size_t lds = qr_blocked_lds(m_max);
+  const dim3 grid(args.total_blocks), blk(NT);
+#define DCS_QRB(I, O)                                                                       \
+  if (ct_in == I && ct_out == O) {                                                          \
+    static hipError_t attr = hipFuncSetAttribute(                                          \
+        reinterpret_cast<const void*>(&qr_blocked_kernel<I, O>),                            \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_blocked_lds(512));              \
+    if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
+    hipLaunchKernelGGL((qr_blocked_kernel<I, O>), grid, blk, lds, s, args);                 \
+    return hipGetLastError();                                                               \
+  }
+  DCS_QRB(CT_F32, CT_F32)
+  DCS_QRB(CT_F64, CT_F64)
+  DCS_QRB(CT_F64, CT_F32)
+#undef DCS_QRB
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_qr(int ct_in, int ct_out, const QrArgs& args, size_t lds_bytes, hipStream_t s) {

@@ -173,7 +173,7 @@ Layout make_layout(int precision, int n, int cap, int chi_max, int wmax, int n_i
   L.o_f = p;
   p += align_up(fmax * L.cs);
   L.o_ws = p;
-  p += align_up(fmax * 16);
+  p += align_up(fmax * 16 + (dmax / 16 + 2) * 256 * 16);
   L.o_e = p;
   p += align_up(dmax * dmax * 16);
   L.o_g = p;
@@ -427,9 +427,16 @@ int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& jobs, 
     if (ng == 0) continue;
     args.ngroups = ng;
     args.total_blocks = blocks;
-    args.use_lds = (lds > 0 && lds <= qr_lds_limit()) ? 1 : 0;
+    int m_max = 0;
+    for (int g = 0; g < ng; ++g) m_max = std::max(m_max, args.g[g].mode == 2 ? 0 : args.g[g].m);
     Timed t(ctx, s, CLS_QR, flops, bytes);
-    DCS_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+    if (m_max <= qr_blocked_max_rows()) {
+      args.use_lds = 1;
+      DCS_HIP(launch_qr_blocked(ct_in, ct_out, args, std::max(m_max, 1), s));
+    } else {
+      args.use_lds = (lds > 0 && lds <= qr_lds_limit()) ? 1 : 0;
+      DCS_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+    }
   }
   return DCS_OK;
 }
@@ -744,7 +751,8 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
   void* dws = nullptr;
   void* dnrm = nullptr;
   DCS_HIP(hipMalloc(&dg, total * 16));
-  hipError_t e = hipMalloc(&dws, emax * 16 * per_launch);
+  const size_t ws_item = emax * 16 + ((size_t)L.chi_max / 16 + 2) * 256 * 16;
+  hipError_t e = hipMalloc(&dws, ws_item * per_launch);
   if (e == hipSuccess) e = hipMalloc(&dnrm, 64 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(dg, gauss, total * 16, hipMemcpyHostToDevice, s);
   int rc = DCS_OK;
@@ -756,7 +764,7 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
       QrJob q;
       q.f = local_op(static_cast<char*>(dg) + goff[j] * 16, 0);
       q.q = local_op(ibase + L.site_off[j], 0);
-      q.ws = local_op(static_cast<char*>(dws) + (size_t)(j - j0) * emax * 16, 0);
+      q.ws = local_op(static_cast<char*>(dws) + (size_t)(j - j0) * ws_item, 0);
       q.nrm2 = local_op(static_cast<double*>(dnrm) + (j - j0), 0);
       q.ids = nullptr;
       q.batch = 1;

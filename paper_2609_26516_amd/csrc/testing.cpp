@@ -170,7 +170,7 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
   int rc = upload(ct_in, F, mn, df, s);
   if (rc) return rc;
   T_HIP(hipMalloc(&dq.p, mn * csz(ct_out)));
-  T_HIP(hipMalloc(&dws.p, mn * 16));
+  T_HIP(hipMalloc(&dws.p, mn * 16 + ((size_t)n / 16 + 2) * 256 * 16));
   T_HIP(hipMalloc(&dn.p, 256));
   QrArgs args;
   std::memset(&args, 0, sizeof(args));
@@ -188,8 +188,14 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
   args.ngroups = 1;
   args.total_blocks = 1;
   const size_t lds = mn * 16;
-  args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
-  T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+  if (use_lds == 2) {   // blocked variant
+    if (m > qr_blocked_max_rows()) return testing_fail(DCS_EINVAL, "too many rows for the blocked QR");
+    args.use_lds = 1;
+    T_HIP(launch_qr_blocked(ct_in, ct_out, args, m, s));
+  } else {
+    args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
+    T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+  }
   std::vector<char> h(mn * csz(ct_out));
   T_HIP(hipMemcpyAsync(h.data(), dq.p, h.size(), hipMemcpyDeviceToHost, s));
   T_HIP(hipMemcpyAsync(nrm2_out, dn.p, sizeof(double), hipMemcpyDeviceToHost, s));

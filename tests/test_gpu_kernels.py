@@ -81,9 +81,9 @@ def test_gate_operator(capi, ct, direction, d0, d1, wl, wr):
     assert np.max(np.abs(out - ref.reshape(-1))) < tol * np.sqrt(wl * wr * 4)
 
 
-@pytest.mark.parametrize("use_lds", [0, 1])
+@pytest.mark.parametrize("use_lds", [0, 1, 2])
 @pytest.mark.parametrize("m,n", [(2, 1), (4, 2), (8, 8), (32, 16), (64, 32), (130, 65),
-                                 (512, 256)])
+                                 (512, 256), (34, 17), (100, 100), (512, 512)])
 def test_qr_full_rank(capi, use_lds, m, n):
     rng = np.random.default_rng(m + n)
     f = _rand(rng, m, n)
@@ -102,12 +102,13 @@ def test_qr_full_rank(capi, use_lds, m, n):
     assert np.max(np.abs(ql - qn.conj().T)) < 1e-10
 
 
-def test_qr_rank_deficient_and_normalise(capi):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_qr_rank_deficient_and_normalise(capi, variant):
     rng = np.random.default_rng(1)
     m, n = 64, 32
     f = _rand(rng, m, 3) @ _rand(rng, 3, n)                  # rank 3
     f[:, 5] = 0
-    q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, 0, f.reshape(-1))
+    q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, variant, f.reshape(-1))
     q = q.reshape(m, n)
     np.testing.assert_allclose(q.conj().T @ q, np.eye(n), atol=1e-12)
     np.testing.assert_allclose(q @ (q.conj().T @ f), f, atol=1e-11)
@@ -116,13 +117,14 @@ def test_qr_rank_deficient_and_normalise(capi):
     ref = f[:10, :3] / np.linalg.norm(f[:10, :3])
     assert np.max(np.abs(t.reshape(10, 3) - ref)) < 1e-6
     # exactly zero matrix: Q is the leading identity columns
-    z, _ = capi.dcs_test_qr(F64, F64, 6, 3, 0, 1, np.zeros(18, complex))
+    z, _ = capi.dcs_test_qr(F64, F64, 6, 3, 0, variant, np.zeros(18, complex))
     np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
 
 
+@pytest.mark.parametrize("variant", [0, 2])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("tiny", [1e-120, 1e-170, 1e-250])
-def test_qr_tiny_noise_columns(capi, mode, tiny):
+def test_qr_tiny_noise_columns(capi, mode, tiny, variant):
     """Rank-deficient local tensors carry noise far below the FP64 square
     range; the factorisation must stay finite and orthonormal."""
     rng = np.random.default_rng(int(-np.log10(tiny)))
@@ -130,14 +132,14 @@ def test_qr_tiny_noise_columns(capi, mode, tiny):
     f = _rand(rng, m, 2) @ _rand(rng, 2, n) + tiny * _rand(rng, m, n)
     f[:, 7] *= tiny
     if mode == 0:
-        q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, 0, f.reshape(-1))
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, variant, f.reshape(-1))
         q = q.reshape(m, n)
         gram = q.conj().T @ q
         rec = q @ (q.conj().T @ f)
         target = f
     else:
         g = f.conj().T.copy()
-        q, _ = capi.dcs_test_qr(F64, F64, m, n, 1, 0, g.reshape(-1))
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 1, variant, g.reshape(-1))
         q = q.reshape(n, m)
         gram = q @ q.conj().T
         rec = (g @ q.conj().T) @ q
