@@ -40,7 +40,7 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool):
 
     circ, prm = C.workload(WORKLOAD)
     n, chi = prm["n"], prm["chi"]
-    k = C.segment_max(circ)
+    k = C.segment_max(circ) + 1      # chunks break only at measurements
     eng = E.Engine(0)
     st = E.State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
     nm = circ.n_measurements()

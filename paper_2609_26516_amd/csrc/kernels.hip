@@ -470,9 +470,10 @@ __device__ __forceinline__ void zero4(v4d_t& a) {
 
 // Apply (I - V X V^H) to the 16-column sub-strip at global column c0 of rows
 // p..m-1 of the row-major matrix A (leading dimension n), X = T^H (conjT) or
-// T.  Executed by one wave.
+// T.  Executed by one wave; global operands are fetched one block ahead.
 __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int nbk, int c0,
                             const double2* P, const double2* sT, bool conjT, int lane) {
+  constexpr int U = 4;   // k-steps (4 rows each) per fetch block
   const int li = lane & 15, lk = lane >> 4;
   const int col = c0 + li;
   const bool col_ok = col < n;
@@ -480,12 +481,24 @@ __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int n
   zero4(wr);
   zero4(wi);
   // W = V^H A_sub  (16 x 16): k runs over the panel rows
-  for (int i0 = 0; i0 < mp; i0 += 4) {
-    const int i = i0 + lk;
-    const double2 v = vval(P, i, li, mp, nbk);
-    double2 b = make_double2(0.0, 0.0);
-    if (i < mp && col_ok) b = A[(long long)(p + i) * n + col];
-    cmma(v.x, -v.y, b.x, b.y, wr, wi);
+  double2 bc[U], bn[U];
+  auto load_b = [&](double2* b, int i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 4 * u + lk;
+      b[u] = (i < mp && col_ok) ? A[(long long)(p + i) * n + col] : make_double2(0.0, 0.0);
+    }
+  };
+  load_b(bc, 0);
+  for (int i0 = 0; i0 < mp; i0 += 4 * U) {
+    if (i0 + 4 * U < mp) load_b(bn, i0 + 4 * U);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double2 v = vval(P, i0 + 4 * u + lk, li, mp, nbk);
+      cmma(v.x, -v.y, bc[u].x, bc[u].y, wr, wi);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) bc[u] = bn[u];
   }
   // W2 = X W; W's result item t holds row lk + 4t = the B operand of k-step t
   v4d_t xr, xi;
@@ -504,7 +517,17 @@ __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int n
     cmma(a.x, a.y, wr[t], wi[t], xr, xi);
   }
   // A_sub -= V W2, 16 rows at a time
+  double2 ac[4], an[4];
+  auto load_a = [&](double2* a, int rb) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = rb + lk + 4 * t;
+      a[t] = (i < mp && col_ok) ? A[(long long)(p + i) * n + col] : make_double2(0.0, 0.0);
+    }
+  };
+  load_a(ac, 0);
   for (int rb = 0; rb < mp; rb += 16) {
+    if (rb + 16 < mp) load_a(an, rb + 16);
     v4d_t dr, di;
     zero4(dr);
     zero4(di);
@@ -517,25 +540,49 @@ __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int n
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int i = rb + lk + 4 * t;
-        if (i < mp) {
-          double2* ptr = A + (long long)(p + i) * n + col;
-          const double2 o = *ptr;
-          *ptr = make_double2(o.x - dr[t], o.y - di[t]);
-        }
+        if (i < mp) A[(long long)(p + i) * n + col] = make_double2(ac[t].x - dr[t], ac[t].y - di[t]);
       }
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ac[t] = an[t];
   }
 }
 
+// Block-wide (sum, max) over NW waves; every thread gets both.
+template <int NW>
+__device__ __forceinline__ void block_sum_max(double& sm, double& mx, double* scratch) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sm += __shfl_xor(sm, o, 64);
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wave] = sm;
+    scratch[2 * wave + 1] = mx;
+  }
+  __syncthreads();
+  sm = 0.0;
+  mx = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sm += scratch[2 * w];
+    mx = fmax(mx, scratch[2 * w + 1]);
+  }
+}
+
+constexpr int NTQ = 512, NWQ = NTQ / 64;
+
 template <int CTI, int CTO>
-__global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
+__global__ __launch_bounds__(NTQ) void qr_blocked_kernel(const QrArgs args) {
   using TI = typename St<CTI>::T;
   using TO = typename St<CTO>::T;
   extern __shared__ double2 P[];          // panel, rows p..m-1, swizzled
   __shared__ double2 sT[QB * QB];
   __shared__ double2 sG[QB * QB];
   __shared__ double2 s_tau[QB];
-  __shared__ double s_red[8];
+  __shared__ double s_red[2 * NWQ];
   __shared__ double2 s_bc[2];
 
   const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
@@ -553,29 +600,30 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
   // load the row-major working matrix (T, or T^H in mode 1) and |F|^2
   double part = 0;
   if (mode == 0) {
-    for (long long idx = tid; idx < mn; idx += NT) {
+    for (long long idx = tid; idx < mn; idx += NTQ) {
       const double2 v = to_d2(F[idx]);
       part += v.x * v.x + v.y * v.y;
       A[idx] = v;
     }
   } else if (mode == 1) {
-    for (long long idx = tid; idx < mn; idx += NT) {   // F is n x m: F[j][i]
+    for (long long idx = tid; idx < mn; idx += NTQ) {   // F is n x m: F[j][i]
       const double2 v = to_d2(F[idx]);
       part += v.x * v.x + v.y * v.y;
       const int j = (int)(idx / m), i = (int)(idx % m);
       A[(long long)i * n + j] = cconj(v);
     }
   } else {
-    for (long long idx = tid; idx < mn; idx += NT) {
+    for (long long idx = tid; idx < mn; idx += NTQ) {
       const double2 v = to_d2(F[idx]);
       part += v.x * v.x + v.y * v.y;
     }
   }
-  const double nu2 = block_sum(part, s_red);
+  double nu2 = part, nu_mx = 0.0;
+  block_sum_max<NWQ>(nu2, nu_mx, s_red);
   if (tid == 0) *nrm = nu2;
   if (mode == 2) {
     const double sc = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0;
-    for (long long idx = tid; idx < mn; idx += NT) {
+    for (long long idx = tid; idx < mn; idx += NTQ) {
       const double2 v = to_d2(F[idx]);
       TO o;
       o.x = v.x * sc;
@@ -590,20 +638,37 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
   for (int pi = 0; pi < npan; ++pi) {
     const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
     // panel -> LDS
-    for (int e = tid; e < mp * QB; e += NT) {
+    for (int e = tid; e < mp * QB; e += NTQ) {
       const int i = e / QB, c = e % QB;
       P[pidx(i, c)] = (c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     // unblocked factorisation of the panel
     for (int kk = 0; kk < nbk; ++kk) {
-      double sc = 0.0, q = 0.0;
-      for (int i = kk + 1 + tid; i < mp; i += NT) {
+      // |x|^2 and max|x| in one pass; a scaled second pass only when the
+      // entries leave the range where squares neither underflow nor overflow
+      double sm = 0.0, mx = 0.0;
+      for (int i = kk + 1 + tid; i < mp; i += NTQ) {
         const double2 v = P[pidx(i, kk)];
-        ssq_add(sc, q, v.x);
-        ssq_add(sc, q, v.y);
+        sm += v.x * v.x + v.y * v.y;
+        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
       }
-      block_ssq(sc, q, s_red);
+      block_sum_max<NWQ>(sm, mx, s_red);
+      double sc = 0.0, q = 0.0;
+      if (mx > 0.0 && (mx < 1e-140 || mx > 1e140)) {
+        double sm2 = 0.0, dummy = 0.0;
+        const double inv = 1.0 / mx;
+        for (int i = kk + 1 + tid; i < mp; i += NTQ) {
+          const double2 v = P[pidx(i, kk)];
+          sm2 += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+        }
+        block_sum_max<NWQ>(sm2, dummy, s_red);
+        sc = mx;
+        q = sm2;
+      } else if (mx > 0.0) {
+        sc = 1.0;
+        q = sm;
+      }
       if (tid == 0) {
         const double2 alpha = P[pidx(kk, kk)];
         double2 tau = make_double2(0.0, 0.0), scal = make_double2(1.0, 0.0);
@@ -628,14 +693,14 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
       if (tau.x == 0.0 && tau.y == 0.0) {
         // H = I; below-diagonal entries (if any tiny ones) become an exact
         // zero reflector so V stays consistent with tau = 0
-        for (int i = kk + 1 + tid; i < mp; i += NT) P[pidx(i, kk)] = make_double2(0.0, 0.0);
+        for (int i = kk + 1 + tid; i < mp; i += NTQ) P[pidx(i, kk)] = make_double2(0.0, 0.0);
         __syncthreads();
         continue;
       }
-      for (int i = kk + 1 + tid; i < mp; i += NT) P[pidx(i, kk)] = cmul(P[pidx(i, kk)], scal);
+      for (int i = kk + 1 + tid; i < mp; i += NTQ) P[pidx(i, kk)] = cmul(P[pidx(i, kk)], scal);
       __syncthreads();
       const double2 ctau = cconj(tau);
-      for (int c = kk + 1 + wave; c < nbk; c += 4) {
+      for (int c = kk + 1 + wave; c < nbk; c += NWQ) {
         double sr = 0, si = 0;
         for (int i = kk + lane; i < mp; i += 64) {
           const double2 v = (i == kk) ? make_double2(1.0, 0.0) : P[pidx(i, kk)];
@@ -668,7 +733,7 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) sG[(lk + 4 * t) * QB + li] = make_double2(gr[t], gim[t]);
     }
-    sT[tid] = make_double2(0.0, 0.0);
+    if (tid < QB * QB) sT[tid] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int k = 0; k < nbk; ++k) {
       if (tid < k) {
@@ -686,14 +751,14 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
       }
       __syncthreads();
     }
-    Tg[(long long)pi * QB * QB + tid] = sT[tid];
+    if (tid < QB * QB) Tg[(long long)pi * QB * QB + tid] = sT[tid];
     // panel (R above, V below the diagonal) back to global
-    for (int e = tid; e < mp * QB; e += NT) {
+    for (int e = tid; e < mp * QB; e += NTQ) {
       const int i = e / QB, c = e % QB;
       if (c < nbk) A[(long long)(p + i) * n + p + c] = P[pidx(i, c)];
     }
     // trailing columns: A -= V T^H V^H A, one 16-column sub-strip per wave
-    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 64)
+    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
       apply_block(A, n, p, mp, nbk, c0, P, sT, true, lane);
     __syncthreads();
   }
@@ -701,15 +766,15 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
   // explicit thin Q, panels in reverse order (in place)
   for (int pi = npan - 1; pi >= 0; --pi) {
     const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
-    for (int e = tid; e < mp * QB; e += NT) {
+    for (int e = tid; e < mp * QB; e += NTQ) {
       const int i = e / QB, c = e % QB;
       P[pidx(i, c)] = (c < nbk && i > c) ? A[(long long)(p + i) * n + p + c]
                                          : make_double2(0.0, 0.0);
     }
-    sT[tid] = Tg[(long long)pi * QB * QB + tid];
+    if (tid < QB * QB) sT[tid] = Tg[(long long)pi * QB * QB + tid];
     __syncthreads();
     // columns already formed: A <- H A with H = I - V T V^H
-    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 64)
+    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
       apply_block(A, n, p, mp, nbk, c0, P, sT, false, lane);
     // the panel's own columns: [I; 0] - V (T V1^H), V1 the top nbk x nbk block
     {
@@ -725,7 +790,7 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
         cmma(a.x, a.y, b.x, -b.y, sr, si);
       }
       // S = T V1^H in registers (item t: row lk + 4t, col li)
-      for (int rb = wave * 16; rb < mp; rb += 64) {
+      for (int rb = wave * 16; rb < mp; rb += 16 * NWQ) {
         v4d_t dr, di;
         zero4(dr);
         zero4(di);
@@ -745,7 +810,7 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
         }
       }
     }
-    for (int e = tid; e < p * nbk; e += NT) {   // rows above the panel
+    for (int e = tid; e < p * nbk; e += NTQ) {   // rows above the panel
       const int i = e / nbk, c = e % nbk;
       A[(long long)i * n + p + c] = make_double2(0.0, 0.0);
     }
@@ -754,7 +819,7 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
 
   // write Q (mode 0) or Q^H (mode 1)
   if (mode == 0) {
-    for (long long idx = tid; idx < mn; idx += NT) {
+    for (long long idx = tid; idx < mn; idx += NTQ) {
       const double2 v = A[idx];
       TO o;
       o.x = v.x;
@@ -762,7 +827,7 @@ __global__ __launch_bounds__(NT) void qr_blocked_kernel(const QrArgs args) {
       Q[idx] = o;
     }
   } else {
-    for (long long idx = tid; idx < mn; idx += NT) {   // out[j][i] = conj(A[i][j])
+    for (long long idx = tid; idx < mn; idx += NTQ) {   // out[j][i] = conj(A[i][j])
       const int j = (int)(idx / m), i = (int)(idx % m);
       const double2 v = A[(long long)i * n + j];
       TO o;
@@ -890,7 +955,7 @@ int qr_blocked_max_rows() { return 512; }
 hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
   if (args.total_blocks <= 0) return hipSuccess;
   const size_t lds = qr_blocked_lds(m_max);
-  const dim3 grid(args.total_blocks), blk(NT);
+  const dim3 grid(args.total_blocks), blk(NTQ);
 #define DCS_QRB(I, O)                                                                       \
   if (ct_in == I && ct_out == O) {                                                          \
     static hipError_t attr = hipFuncSetAttribute(                                          \

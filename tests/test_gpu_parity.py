@@ -5,7 +5,10 @@ same algorithm; the sweep is a smooth map of its inputs, so 1e-9 absolute on
 probabilities / fidelities and on 1 - |<gpu|oracle>|^2 leaves ample room over
 the ~1e-13 rounding of the contractions.  The complex64 path is held to the
 stated target of the precision form: 1e-6 absolute probability error and
-1e-6 state-fidelity error (1 - |<gpu|oracle>|^2).
+1e-6 state-fidelity error (1 - |<gpu|oracle>|^2).  The partial-fidelity
+estimate f = <F|F> is first order in the FP32 rounding of the environments
+(about n chained contractions of depth 2 chi, each ~1e-7 relative), so its
+complex64 tolerance is 1e-5 (F_TOL); the product over a run gets 10x that.
 """
 import numpy as np
 import pytest
@@ -19,6 +22,7 @@ from oracle import statevector as SV
 pytestmark = pytest.mark.gpu
 
 TOL = {"c128": 1e-9, "c64": 1e-6}
+F_TOL = {"c128": 1e-9, "c64": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -89,7 +93,7 @@ def test_compress_step_parity(eng, prec, n, chi, sweeps, layers):
     gpu = st.export(1)
     capi.dcs_chunk_destroy(h)
     st.close()
-    assert abs(f[0] - f_ref) < TOL[prec], (f[0], f_ref)
+    assert abs(f[0] - f_ref) < F_TOL[prec], (f[0], f_ref)
     assert _fid_err(gpu, ref) < TOL[prec]
     assert abs(OM.norm_sq(gpu) - 1) < 10 * TOL[prec]
 
@@ -148,7 +152,7 @@ def test_single_path_cfg1_replay(eng, prec):
     ref = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"]),
                              outcomes=res["outcomes"][0])
     np.testing.assert_allclose(res["p0s"][0], ref["p0s"], atol=TOL[prec], rtol=0)
-    assert abs(res["F"][0] - ref["F"]) < 10 * TOL[prec]
+    assert abs(res["F"][0] - ref["F"]) < 10 * F_TOL[prec]
     assert abs(res["p"][0] - ref["p"]) < 10 * TOL[prec]
     assert _fid_err(st.export(int(res["ids"][0])), ref["mps"]) < TOL[prec]
     # same uniforms give the same outcomes on the oracle's own sampling
@@ -183,7 +187,7 @@ def test_batched_shots_replay(eng, prec):
     for s in range(shots):
         ref = OD.run_single_path(circ, sim, outcomes=res["outcomes"][s])
         np.testing.assert_allclose(res["p0s"][s], ref["p0s"], atol=TOL[prec], rtol=0)
-        assert abs(res["F"][s] - ref["F"]) < 10 * TOL[prec]
+        assert abs(res["F"][s] - ref["F"]) < 10 * F_TOL[prec]
         assert _fid_err(st.export(int(res["ids"][s])), ref["mps"]) < TOL[prec]
     st.close()
 
@@ -234,7 +238,7 @@ def test_multi_path_uneven_chi_parity(eng, prec):
     assert set(got) == set(want)
     for pth, b in want.items():
         assert abs(got[pth]["p"] - b["p"]) < 10 * TOL[prec]
-        assert abs(got[pth]["F"] - b["F"]) < 10 * TOL[prec]
+        assert abs(got[pth]["F"] - b["F"]) < 10 * F_TOL[prec]
         assert _fid_err(st.export(got[pth]["id"]), b["mps"]) < TOL[prec]
     assert abs(res["dropped"] - ref["dropped"]) < 10 * TOL[prec]
     st.close()
