@@ -29,7 +29,14 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "cfg2_n40_chi256"
 PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA")}
 HBM_PEAK_GBS = 8000.0
-CLASSES = ["gemm", "gate_operator", "qr", "measure", "other"]
+CLASSES = ["gemm_nn", "gemm_nt", "gemm_cn", "gemm_jt", "gate_operator", "qr", "measure",
+           "other"]
+# rocprofv3 kernel names of the timed classes (complex64 path)
+KERNEL_NAMES = {
+    "gemm_nn": "gemm_kernel<0, 0, 0, float, 0, 0>", "gemm_nt": "gemm_kernel<0, 0, 0, float, 0, 1>",
+    "gemm_cn": "gemm_kernel<0, 0, 0, float, 2, 0>", "gemm_jt": "gemm_kernel<0, 0, 0, float, 3, 1>",
+    "gate_operator": "mpo_right_kernel / mpo_left_kernel", "qr": "qr_blocked_kernel<0, 0>",
+}
 
 
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool):
@@ -76,7 +83,7 @@ def roofline(stats, prec):
     avg_ms = ms[dom] / max(1, launches[dom])
     per_launch_flops = flops[dom] / max(1, launches[dom])
     per_launch_bytes = byts[dom] / max(1, launches[dom])
-    if CLASSES[dom] in ("gemm", "measure") or (CLASSES[dom] == "qr" and False):
+    if CLASSES[dom].startswith("gemm") or CLASSES[dom] == "measure":
         peak, _ = PEAK[prec]
         ach = per_launch_flops / (avg_ms * 1e-3) / 1e12
         rl = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
@@ -89,11 +96,15 @@ def roofline(stats, prec):
         ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         rl = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
-    rl["kernel"] = CLASSES[dom]
+    rl["kernel"] = KERNEL_NAMES.get(CLASSES[dom], CLASSES[dom])
     rl["avg_launch_ms"] = round(avg_ms, 5)
     rl["launches"] = int(launches[dom])
     rl["time_share"] = round(ms[dom] / max(1e-12, sum(ms)), 4)
     rl["classes_ms"] = {c: round(v, 2) for c, v in zip(CLASSES, ms)}
+    tot_f = sum(flops[:4])
+    tot_ms = sum(ms[:4])
+    rl["all_contraction_gemms"] = {"achieved_tflops": round(tot_f / (tot_ms * 1e-3) / 1e12, 3),
+                                   "frac": round(tot_f / (tot_ms * 1e-3) / 1e12 / PEAK[prec][0], 4)}
     return rl
 
 
@@ -136,7 +147,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--shots", type=int, default=256)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--cpu-rounds", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")

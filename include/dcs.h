@@ -87,11 +87,13 @@ int dcs_ctx_create(dcs_ctx **out, int device);
 int dcs_ctx_destroy(dcs_ctx *ctx);
 
 /* Per-kernel-class launch timing with HIP events on the caller's stream
- * (off by default).  Classes: 0 contraction GEMMs of the compression step,
- * 1 gate-operator application, 2 QR/LQ gauge shift, 3 measurement
- * contractions, 4 other.  dcs_ctx_timing returns, per class, the number of
- * launches, their summed duration in ms, and the algorithmic flops and HBM
- * bytes (unpadded shapes) of those launches; arrays have 5 entries. */
+ * (off by default).  Classes (DCS_TIMING_CLASSES of them): 0-3 the
+ * contraction GEMMs of the compression step by operand form (0 A B, 1 A B^T,
+ * 2 A^H B, 3 conj(A) B^T), 4 gate-operator application, 5 QR/LQ gauge shift,
+ * 6 measurement contractions, 7 other.  dcs_ctx_timing returns, per class,
+ * the number of launches, their summed duration in ms, and the algorithmic
+ * flops and operand bytes (unpadded shapes) of those launches. */
+#define DCS_TIMING_CLASSES 8
 int dcs_ctx_set_timing(dcs_ctx *ctx, int enabled);
 int dcs_ctx_timing(dcs_ctx *ctx, long long *launches, double *ms, double *flops,
                    double *bytes, int reset);

@@ -123,9 +123,14 @@ def dcs_ctx_set_timing(ctx: int, enabled: bool) -> None:
     _check(_lib.dcs_ctx_set_timing(ctx, 1 if enabled else 0))
 
 
+TIMING_CLASSES = ["gemm_nn", "gemm_nt", "gemm_cn", "gemm_jt", "gate_operator", "qr", "measure",
+                  "other"]
+
+
 def dcs_ctx_timing(ctx: int, reset: bool = False):
-    launches = (c_longlong * 5)()
-    ms, flops, byts = (c_double * 5)(), (c_double * 5)(), (c_double * 5)()
+    k = len(TIMING_CLASSES)
+    launches = (c_longlong * k)()
+    ms, flops, byts = (c_double * k)(), (c_double * k)(), (c_double * k)()
     _check(_lib.dcs_ctx_timing(ctx, launches, ms, flops, byts, 1 if reset else 0))
     return list(launches), list(ms), list(flops), list(byts)
 

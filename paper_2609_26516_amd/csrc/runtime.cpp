@@ -85,10 +85,10 @@ struct dcs_ctx {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
-  long long launches[5] = {0, 0, 0, 0, 0};
-  double ms[5] = {0, 0, 0, 0, 0};
-  double flops[5] = {0, 0, 0, 0, 0};
-  double bytes[5] = {0, 0, 0, 0, 0};
+  long long launches[DCS_TIMING_CLASSES] = {};
+  double ms[DCS_TIMING_CLASSES] = {};
+  double flops[DCS_TIMING_CLASSES] = {};
+  double bytes[DCS_TIMING_CLASSES] = {};
 };
 
 struct dcs_chunk {
@@ -278,7 +278,16 @@ void resolve_timing(dcs_ctx* c) {
   c->pending.clear();
 }
 
-enum { CLS_GEMM = 0, CLS_MPO = 1, CLS_QR = 2, CLS_MEAS = 3, CLS_OTHER = 4 };
+// timing classes: contraction GEMMs of the compression step by operand form
+// (N N, N T, C N, J T), gate-operator application, QR, measurement, other
+enum { CLS_GEMM = 0, CLS_MPO = 4, CLS_QR = 5, CLS_MEAS = 6, CLS_OTHER = 7 };
+
+int gemm_class(int opa, int opb) {
+  if (opa == OP_N && opb == OP_N) return 0;
+  if (opa == OP_N && opb == OP_T) return 1;
+  if (opa == OP_C && opb == OP_N) return 2;
+  return 3;
+}
 
 // ---------------------------------------------------------------------------
 // Batched launch builders
@@ -340,7 +349,7 @@ int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
     if (ng == 0) continue;
     args.ngroups = ng;
     args.total_tiles = tiles;
-    Timed t(ctx, s, cls, flops, bytes);
+    Timed t(ctx, s, cls == CLS_GEMM ? gemm_class(opa, opb) : cls, flops, bytes);
     DCS_HIP(launch_gemm(ta, tb, tc, tacc, opa, opb, args, s));
   }
   return DCS_OK;
@@ -642,7 +651,7 @@ int dcs_ctx_timing(dcs_ctx* ctx, long long* launches, double* ms, double* flops,
                    int reset) {
   if (!ctx) return fail(DCS_EINVAL, "null context");
   resolve_timing(ctx);
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < DCS_TIMING_CLASSES; ++i) {
     if (launches) launches[i] = ctx->launches[i];
     if (ms) ms[i] = ctx->ms[i];
     if (flops) flops[i] = ctx->flops[i];
