@@ -27,6 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "cfg2_n40_chi256"
+# other workload shapes reachable with --workload (parity-test configurations,
+# not the headline line)
+SINGLE_PATH = {"sp40": "cfg2_n40_chi256", "sp24": "cfg4_n24_chi64_x1024",
+               "sp10": "cfg1_n10_chi16"}
+MULTI_PATH = {"mp32": "cfg3_n32_mp64"}
 PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA")}
 HBM_PEAK_GBS = 8000.0
 CLASSES = ["gemm_nn", "gemm_nt", "gemm_cn", "gemm_jt", "gate_operator", "qr", "measure",
@@ -39,13 +44,13 @@ KERNEL_NAMES = {
 }
 
 
-def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool):
+def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD):
     import torch
     from inputs import circuits as C
     from inputs.randomness import shot_uniforms
     from paper_2609_26516_amd import engine as E
 
-    circ, prm = C.workload(WORKLOAD)
+    circ, prm = C.workload(workload)
     n, chi = prm["n"], prm["chi"]
     k = C.segment_max(circ) + 1      # chunks break only at measurements
     eng = E.Engine(0)
@@ -75,6 +80,48 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool):
     st.close()
     eng.close()
     return dt, stats, fids
+
+
+def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload: str):
+    """Alg. 2 runs of the uneven-bond-cap multi-path workload; one step = one
+    run from |0...0> to the end with top-M retention after every measurement."""
+    import torch
+    from inputs import circuits as C
+    from inputs.randomness import branch_chi_draw
+    from paper_2609_26516_amd import engine as E
+
+    circ, prm = C.workload(workload)
+    n, chi, M = prm["n"], prm["chi"], prm["max_branches"]
+    choices = prm["chi_choices"]
+    k = C.segment_max(circ) + 1
+    chi_of = lambda path: branch_chi_draw(prm["seed"], path, choices)  # noqa: E731
+    eng = E.Engine(0)
+    st = E.State(eng, prec, n, 2 * M, chi, 4, list(choices) + [chi], prm["init_seed"])
+    info = {}
+
+    def one_run():
+        st.reset()
+        res = E.run_multi_path(eng, st, circ, chi, k, 2, max_branches=M, chi_of=chi_of)
+        info["branches"] = len(res["branches"])
+        info["dropped"] = res["dropped"]
+        info["F_mp"] = res["F_mp"]
+        return res
+
+    for _ in range(warmup):
+        one_run()
+    torch.cuda.synchronize()
+    eng.timing(timing)
+    eng.timing_stats(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = eng.timing_stats(reset=True) if timing else None
+    eng.timing(False)
+    st.close()
+    eng.close()
+    return dt, stats, info
 
 
 def roofline(stats, prec):
@@ -152,6 +199,7 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="sp40", choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -159,6 +207,38 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload in MULTI_PATH:
+        wl = MULTI_PATH[args.workload]
+        dt, stats, info = run_gpu_multipath("c64", args.steps, args.warmup, True, wl)
+        out = {"metric": "multi-path runs/s (grouped FP32-MFMA form, uneven chi 32..256, M=64)",
+               "value": round(args.steps / dt, 5), "unit": "runs/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": round(1e3 * dt / args.steps, 2), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+               "data": "synthetic: seeded Haar brickwork dynamic circuit",
+               "config": {"workload": wl, **info}, "roofline": roofline(stats, "c64")}
+        if not args.no_fp64:
+            dt64, _, _ = run_gpu_multipath("c128", 1, 0, False, wl)
+            out["fp64_path"] = {"value": round(1 / dt64, 5), "unit": "runs/s", "dtype": "c128"}
+        print(json.dumps(out))
+        return
+    if args.workload != "sp40":
+        wl = SINGLE_PATH[args.workload]
+        dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, True, wl)
+        out = {"metric": "shots/s (batched FP32-MFMA form)", "value": round(args.shots * args.steps / dt, 4),
+               "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": round(1e3 * dt / args.steps, 2), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+               "data": "synthetic: seeded Haar brickwork dynamic circuit",
+               "config": {"workload": wl, "shots_per_step": args.shots},
+               "roofline": roofline(stats, "c64"),
+               "mean_fidelity_estimate": round(float(np.mean(fids)), 6)}
+        if not args.no_fp64:
+            dt64, _, _ = run_gpu("c128", args.shots, args.fp64_steps, 0, False, wl)
+            out["fp64_path"] = {"value": round(args.shots * args.fp64_steps / dt64, 4),
+                                "unit": "shots/s", "dtype": "c128"}
+        print(json.dumps(out))
+        return
     dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, timing=True)
     value = args.shots * args.steps / dt
     out = {

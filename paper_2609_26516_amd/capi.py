@@ -11,6 +11,10 @@ import os
 from ctypes import POINTER, c_double, c_int, c_longlong, c_size_t, c_void_p
 
 import numpy as np
+# PyTorch provides the device memory and streams; loading it first makes
+# libdcs.so bind to the same HIP runtime (both carry libamdhip64.so.7), so the
+# process holds exactly one runtime whatever the caller imported first.
+import torch  # noqa: F401
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdcs.so")
 

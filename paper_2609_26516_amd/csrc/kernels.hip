@@ -471,9 +471,9 @@ __device__ __forceinline__ void zero4(v4d_t& a) {
 // Apply (I - V X V^H) to the 16-column sub-strip at global column c0 of rows
 // p..m-1 of the row-major matrix A (leading dimension n), X = T^H (conjT) or
 // T.  Executed by one wave; global operands are fetched one block ahead.
+template <int U>   // k-steps (4 rows each) per fetch block
 __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int nbk, int c0,
                             const double2* P, const double2* sT, bool conjT, int lane) {
-  constexpr int U = 4;   // k-steps (4 rows each) per fetch block
   const int li = lane & 15, lk = lane >> 4;
   const int col = c0 + li;
   const bool col_ok = col < n;
@@ -572,10 +572,17 @@ __device__ __forceinline__ void block_sum_max(double& sm, double& mx, double* sc
   }
 }
 
-constexpr int NTQ = 512, NWQ = NTQ / 64;
+// NTQ threads per workgroup: 512 (8 waves, one workgroup per CU) for the
+// large panels, 256 (4 waves, registers capped so two fit on a CU) for
+// matrices of at most 128 rows.
+template <int NTQ>
+struct QrWaves {
+  static constexpr int value = NTQ / 64;
+};
 
-template <int CTI, int CTO>
-__global__ __launch_bounds__(NTQ) void qr_blocked_kernel(const QrArgs args) {
+template <int CTI, int CTO, int NTQ>
+__global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(const QrArgs args) {
+  constexpr int NWQ = QrWaves<NTQ>::value;
   using TI = typename St<CTI>::T;
   using TO = typename St<CTO>::T;
   extern __shared__ double2 P[];          // panel, rows p..m-1, swizzled
@@ -759,7 +766,7 @@ __global__ __launch_bounds__(NTQ) void qr_blocked_kernel(const QrArgs args) {
     }
     // trailing columns: A -= V T^H V^H A, one 16-column sub-strip per wave
     for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
-      apply_block(A, n, p, mp, nbk, c0, P, sT, true, lane);
+      apply_block<NTQ == 256 ? 1 : 4>(A, n, p, mp, nbk, c0, P, sT, true, lane);
     __syncthreads();
   }
 
@@ -775,7 +782,7 @@ __global__ __launch_bounds__(NTQ) void qr_blocked_kernel(const QrArgs args) {
     __syncthreads();
     // columns already formed: A <- H A with H = I - V T V^H
     for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
-      apply_block(A, n, p, mp, nbk, c0, P, sT, false, lane);
+      apply_block<NTQ == 256 ? 1 : 4>(A, n, p, mp, nbk, c0, P, sT, false, lane);
     // the panel's own columns: [I; 0] - V (T V1^H), V1 the top nbk x nbk block
     {
       const int li = lane & 15, lk = lane >> 4;
@@ -955,19 +962,23 @@ int qr_blocked_max_rows() { return 512; }
 hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
   if (args.total_blocks <= 0) return hipSuccess;
   const size_t lds = qr_blocked_lds(m_max);
-  const dim3 grid(args.total_blocks), blk(NTQ);
-#define DCS_QRB(I, O)                                                                       \
-  if (ct_in == I && ct_out == O) {                                                          \
+  const bool small = m_max <= 128;
+  const dim3 grid(args.total_blocks), blk(small ? 256 : 512);
+#define DCS_QRB(I, O, T)                                                                    \
+  if (ct_in == I && ct_out == O && (T == 256) == small) {                                  \
     static hipError_t attr = hipFuncSetAttribute(                                          \
-        reinterpret_cast<const void*>(&qr_blocked_kernel<I, O>),                            \
+        reinterpret_cast<const void*>(&qr_blocked_kernel<I, O, T>),                         \
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_blocked_lds(512));              \
     if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
-    hipLaunchKernelGGL((qr_blocked_kernel<I, O>), grid, blk, lds, s, args);                 \
+    hipLaunchKernelGGL((qr_blocked_kernel<I, O, T>), grid, blk, lds, s, args);              \
     return hipGetLastError();                                                               \
   }
-  DCS_QRB(CT_F32, CT_F32)
-  DCS_QRB(CT_F64, CT_F64)
-  DCS_QRB(CT_F64, CT_F32)
+  DCS_QRB(CT_F32, CT_F32, 512)
+  DCS_QRB(CT_F64, CT_F64, 512)
+  DCS_QRB(CT_F64, CT_F32, 512)
+  DCS_QRB(CT_F32, CT_F32, 256)
+  DCS_QRB(CT_F64, CT_F64, 256)
+  DCS_QRB(CT_F64, CT_F32, 256)
 #undef DCS_QRB
   return hipErrorInvalidValue;
 }
