@@ -44,7 +44,8 @@ KERNEL_NAMES = {
 }
 
 
-def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD):
+def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
+            graphs: bool = False):
     import torch
     from inputs import circuits as C
     from inputs.randomness import shot_uniforms
@@ -54,6 +55,7 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, worklo
     n, chi = prm["n"], prm["chi"]
     k = C.segment_max(circ) + 1      # chunks break only at measurements
     eng = E.Engine(0)
+    eng.graphs(graphs)
     st = E.State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
     nm = circ.n_measurements()
 
@@ -200,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="sp40", choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH))
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay recurring compression steps from HIP graphs (no per-kernel timing)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -224,14 +228,15 @@ def main():
         return
     if args.workload != "sp40":
         wl = SINGLE_PATH[args.workload]
-        dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, True, wl)
+        dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, not args.graphs, wl,
+                                  graphs=args.graphs)
         out = {"metric": "shots/s (batched FP32-MFMA form)", "value": round(args.shots * args.steps / dt, 4),
                "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": round(1e3 * dt / args.steps, 2), "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "c64",
                "data": "synthetic: seeded Haar brickwork dynamic circuit",
-               "config": {"workload": wl, "shots_per_step": args.shots},
-               "roofline": roofline(stats, "c64"),
+               "config": {"workload": wl, "shots_per_step": args.shots, "graphs": args.graphs},
+               "roofline": roofline(stats, "c64") if stats else None,
                "mean_fidelity_estimate": round(float(np.mean(fids)), 6)}
         if not args.no_fp64:
             dt64, _, _ = run_gpu("c128", args.shots, args.fp64_steps, 0, False, wl)

@@ -86,6 +86,14 @@ int dcs_version(void);
 int dcs_ctx_create(dcs_ctx **out, int device);
 int dcs_ctx_destroy(dcs_ctx *ctx);
 
+/* Capture the launch sequence of dcs_compress_step into a HIP graph and
+ * replay it when the same signature recurs (same branch slots, shapes,
+ * operator bonds, sweeps and buffer parity), off by default.  A signature is
+ * run eagerly the first time, captured the second time, replayed afterwards;
+ * the per-call uploads (slot ids, gate operators) stay outside the graph.
+ * Ignored while launch timing is on.  Graphs are owned by the state. */
+int dcs_ctx_set_graphs(dcs_ctx *ctx, int enabled);
+
 /* Per-kernel-class launch timing with HIP events on the caller's stream
  * (off by default).  Classes (DCS_TIMING_CLASSES of them): 0-3 the
  * contraction GEMMs of the compression step by operand form (0 A B, 1 A B^T,

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "DCS_OK", -1: "DCS_EINVAL", -2: "DCS_ENONLOCAL", -3: "DCS_EZE
                 -8: "DCS_ENUMERIC"}
 EXPORTED = [
     "dcs_last_error", "dcs_version", "dcs_ctx_create", "dcs_ctx_destroy", "dcs_ctx_set_timing",
-    "dcs_ctx_timing", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
+    "dcs_ctx_timing", "dcs_ctx_set_graphs", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
     "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
@@ -55,6 +55,7 @@ _SIGS = {
     "dcs_ctx_create": (c_int, [POINTER(c_void_p), c_int]),
     "dcs_ctx_destroy": (c_int, [_P]),
     "dcs_ctx_set_timing": (c_int, [_P, c_int]),
+    "dcs_ctx_set_graphs": (c_int, [_P, c_int]),
     "dcs_ctx_timing": (c_int, [_P, POINTER(c_longlong), _DP, _DP, _DP, c_int]),
     "dcs_state_bytes": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
     "dcs_state_create": (c_int, [_P, POINTER(c_void_p), c_int, c_int, c_int, c_int, c_int, c_int,
@@ -121,6 +122,10 @@ def dcs_ctx_create(device: int) -> int:
 
 def dcs_ctx_destroy(ctx: int) -> None:
     _check(_lib.dcs_ctx_destroy(ctx))
+
+
+def dcs_ctx_set_graphs(ctx: int, enabled: bool) -> None:
+    _check(_lib.dcs_ctx_set_graphs(ctx, 1 if enabled else 0))
 
 
 def dcs_ctx_set_timing(ctx: int, enabled: bool) -> None:

@@ -74,6 +74,7 @@ struct Split {
 
 struct dcs_ctx {
   int device = 0;
+  bool graphs = false;
   std::unordered_map<std::string, Split> split_cache;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -219,6 +220,17 @@ struct dcs_state {
   std::vector<Slot> slots;
   std::vector<InitSlot> inits;
   std::vector<char> host_stage;  // pinned-equivalent staging (pageable)
+  // captured launch sequences of compression steps, keyed by their signature
+  // (group shapes, slot ids, buffer parity, sweeps); a signature is captured
+  // the second time it is seen and replayed afterwards
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::map<std::string, int> graph_seen;
+  hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's
+
+  ~dcs_state() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
 
   char* slot_base(int id) const { return base + L.o_slots + L.slot_stride * (size_t)id; }
   int init_index(int chi) const {
@@ -638,6 +650,12 @@ int dcs_ctx_destroy(dcs_ctx* ctx) {
   for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
+  return DCS_OK;
+}
+
+int dcs_ctx_set_graphs(dcs_ctx* ctx, int enabled) {
+  if (!ctx) return fail(DCS_EINVAL, "null context");
+  ctx->graphs = enabled != 0;
   return DCS_OK;
 }
 
@@ -1147,12 +1165,6 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
     return right_env_from(j, false);
   };
 
-  // right environments of the starting guess
-  for (int j = nq - 1; j >= 1; --j) {
-    DCS_TRY(left_prologue(j));
-    DCS_TRY(right_env_from(j, true));
-  }
-  // sweeps
   std::vector<int> visits;
   for (int t = 1; t <= n_sweeps; ++t) {
     if (t % 2 == 1)
@@ -1160,15 +1172,73 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
     else
       for (int j = nq - 2; j >= 0; --j) visits.push_back(j);
   }
-  for (size_t v = 0; v < visits.size(); ++v) {
-    const int j = visits[v];
-    if (v + 1 == visits.size()) {
-      DCS_TRY(right_site(j, 2));
-    } else if (visits[v + 1] == j + 1) {
-      DCS_TRY(right_site(j, 0));
-    } else {
-      DCS_TRY(left_site(j));
+  auto enqueue = [&]() -> int {
+    // right environments of the starting guess
+    for (int j = nq - 1; j >= 1; --j) {
+      DCS_TRY(left_prologue(j));
+      DCS_TRY(right_env_from(j, true));
     }
+    for (size_t v = 0; v < visits.size(); ++v) {
+      const int j = visits[v];
+      if (v + 1 == visits.size()) {
+        DCS_TRY(right_site(j, 2));
+      } else if (visits[v + 1] == j + 1) {
+        DCS_TRY(right_site(j, 0));
+      } else {
+        DCS_TRY(left_site(j));
+      }
+    }
+    return DCS_OK;
+  };
+  if (st->ctx->graphs && !st->ctx->timing) {
+    std::string sig;
+    auto put = [&](int v) { sig.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
+    put(n_sweeps);
+    for (auto& g : groups) {
+      put(-1);
+      put(g.chi_cap);
+      put(g.cur);
+      put(g.goff);
+      for (int v : g.Kb) put(v);
+      for (int v : g.w) put(v);
+      for (int i : g.members) put(ids[i]);
+    }
+    auto it = st->graphs.find(sig);
+    if (it == st->graphs.end() && st->graph_seen[sig]++ >= 1) {
+      if (st->graphs.size() >= 64) {
+        for (auto& kv : st->graphs) (void)hipGraphExecDestroy(kv.second);
+        st->graphs.clear();
+      }
+      // capture on the state's own stream (the caller's may be the legacy
+      // default stream, which cannot capture); the kernels only read data the
+      // caller's stream has produced, so the replay goes on the caller's stream
+      if (!st->capture_stream)
+        DCS_HIP(hipStreamCreateWithFlags(&st->capture_stream, hipStreamNonBlocking));
+      const hipStream_t caller = s;
+      s = st->capture_stream;
+      DCS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue();
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s, &graph);
+      s = caller;
+      if (rc != DCS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      DCS_HIP(ec);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      DCS_HIP(ei);
+      it = st->graphs.emplace(sig, exec).first;
+    }
+    if (it != st->graphs.end()) {
+      DCS_HIP(hipGraphLaunch(it->second, s));
+    } else {
+      DCS_TRY(enqueue());
+    }
+  } else {
+    DCS_TRY(enqueue());
   }
   std::vector<double> nrm(n);
   DCS_HIP(hipMemcpyAsync(nrm.data(), nrm_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));

@@ -69,6 +69,10 @@ class Engine:
             capi.dcs_chunk_destroy(h)
         self._chunks.clear()
 
+    def graphs(self, enabled: bool) -> None:
+        """Replay recurring compression steps from captured HIP graphs."""
+        capi.dcs_ctx_set_graphs(self.ctx, enabled)
+
     def timing(self, enabled: bool) -> None:
         capi.dcs_ctx_set_timing(self.ctx, enabled)
 
