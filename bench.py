@@ -44,6 +44,9 @@ KERNEL_NAMES = {
 }
 
 
+TUNE = {"enabled": True, "save": None}
+
+
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
             graphs: bool = False):
     import torch
@@ -56,6 +59,7 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, worklo
     k = C.segment_max(circ) + 1      # chunks break only at measurements
     eng = E.Engine(0)
     eng.graphs(graphs)
+    eng.tuning(TUNE["enabled"])
     st = E.State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
     nm = circ.n_measurements()
 
@@ -79,6 +83,8 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, worklo
     dt = time.perf_counter() - t0
     stats = eng.timing_stats(reset=True) if timing else None
     eng.timing(False)
+    if TUNE["save"] and prec == "c64":
+        eng.save_tuning(TUNE["save"])
     st.close()
     eng.close()
     return dt, stats, fids
@@ -98,6 +104,7 @@ def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload
     k = C.segment_max(circ) + 1
     chi_of = lambda path: branch_chi_draw(prm["seed"], path, choices)  # noqa: E731
     eng = E.Engine(0)
+    eng.tuning(TUNE["enabled"])
     st = E.State(eng, prec, n, 2 * M, chi, 4, list(choices) + [chi], prm["init_seed"])
     info = {}
 
@@ -204,7 +211,12 @@ def main():
     ap.add_argument("--workload", default="sp40", choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH))
     ap.add_argument("--graphs", action="store_true",
                     help="replay recurring compression steps from HIP graphs (no per-kernel timing)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="fixed 64x64 contraction tiles instead of the online autotuner")
+    ap.add_argument("--save-tiles", default=None, help="write the tuned tile table (JSON) here")
     args = ap.parse_args()
+    TUNE["enabled"] = not args.no_tune
+    TUNE["save"] = args.save_tiles
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(shots shard across GPUs without communication; see the design notes)",

@@ -86,6 +86,16 @@ int dcs_version(void);
 int dcs_ctx_create(dcs_ctx **out, int device);
 int dcs_ctx_destroy(dcs_ctx *ctx);
 
+/* Autotuning of the contraction tile shapes (64x64, 32x32, 128x64, 64x128
+ * output tiles per workgroup), on by default: for every shape class (operand
+ * types and forms, power-of-two buckets of M, N, K and batch) the first
+ * launches try each tile shape `reps` times, timed with HIP events, and the
+ * fastest is used from then on.  All shapes give bit-identical results.
+ * dcs_ctx_tuning_save / _load write and read the decided table as JSON. */
+int dcs_ctx_set_tuning(dcs_ctx *ctx, int enabled, int reps);
+int dcs_ctx_tuning_save(dcs_ctx *ctx, const char *path);
+int dcs_ctx_tuning_load(dcs_ctx *ctx, const char *path);
+
 /* Capture the launch sequence of dcs_compress_step into a HIP graph and
  * replay it when the same signature recurs (same branch slots, shapes,
  * operator bonds, sweeps and buffer parity), off by default.  A signature is

@@ -22,9 +22,11 @@ extern "C" {
  * A[b] at b * M * K, B[b] at b * K * N, C[b] at b * M * N.  ta/tb/tc are the
  * storage types of A, B, C and tacc the accumulation type (1 = FP64 MFMA,
  * 0 = FP32 MFMA); only the combinations the library uses are available
- * (DCS_EINVAL otherwise). */
+ * (DCS_EINVAL otherwise).  variant: output tile shape 0 64x64, 1 32x32,
+ * 2 128x64, 3 64x128. */
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
-                  int batch, const double *A, const double *B, double *C, void *stream);
+                  int batch, int variant, const double *A, const double *B, double *C,
+                  void *stream);
 
 /* Gate-operator application.  dir 0: in X1[d0][wl][2][d1] -> out
  * X2[d0][2][wr][d1]; dir 1: in Y1[d0][2][d1][wr] -> out Y2[wl][d0][2][d1];

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "DCS_OK", -1: "DCS_EINVAL", -2: "DCS_ENONLOCAL", -3: "DCS_EZE
                 -8: "DCS_ENUMERIC"}
 EXPORTED = [
     "dcs_last_error", "dcs_version", "dcs_ctx_create", "dcs_ctx_destroy", "dcs_ctx_set_timing",
-    "dcs_ctx_timing", "dcs_ctx_set_graphs", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
+    "dcs_ctx_timing", "dcs_ctx_set_graphs", "dcs_ctx_set_tuning", "dcs_ctx_tuning_save",
+    "dcs_ctx_tuning_load", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
     "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
@@ -56,6 +57,9 @@ _SIGS = {
     "dcs_ctx_destroy": (c_int, [_P]),
     "dcs_ctx_set_timing": (c_int, [_P, c_int]),
     "dcs_ctx_set_graphs": (c_int, [_P, c_int]),
+    "dcs_ctx_set_tuning": (c_int, [_P, c_int, c_int]),
+    "dcs_ctx_tuning_save": (c_int, [_P, ctypes.c_char_p]),
+    "dcs_ctx_tuning_load": (c_int, [_P, ctypes.c_char_p]),
     "dcs_ctx_timing": (c_int, [_P, POINTER(c_longlong), _DP, _DP, _DP, c_int]),
     "dcs_state_bytes": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t)]),
     "dcs_state_create": (c_int, [_P, POINTER(c_void_p), c_int, c_int, c_int, c_int, c_int, c_int,
@@ -75,7 +79,7 @@ _SIGS = {
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
-    "dcs_test_gemm": (c_int, [c_int] * 10 + [_DP, _DP, _DP, _P]),
+    "dcs_test_gemm": (c_int, [c_int] * 11 + [_DP, _DP, _DP, _P]),
     "dcs_test_mpo": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
 }
@@ -122,6 +126,18 @@ def dcs_ctx_create(device: int) -> int:
 
 def dcs_ctx_destroy(ctx: int) -> None:
     _check(_lib.dcs_ctx_destroy(ctx))
+
+
+def dcs_ctx_set_tuning(ctx: int, enabled: bool, reps: int = 3) -> None:
+    _check(_lib.dcs_ctx_set_tuning(ctx, 1 if enabled else 0, reps))
+
+
+def dcs_ctx_tuning_save(ctx: int, path: str) -> None:
+    _check(_lib.dcs_ctx_tuning_save(ctx, path.encode()))
+
+
+def dcs_ctx_tuning_load(ctx: int, path: str) -> None:
+    _check(_lib.dcs_ctx_tuning_load(ctx, path.encode()))
 
 
 def dcs_ctx_set_graphs(ctx: int, enabled: bool) -> None:
@@ -267,7 +283,7 @@ def _c128(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
 
 
-def dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b, stream=0) -> np.ndarray:
+def dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b, stream=0, variant=0) -> np.ndarray:
     """a: (batch, rows, cols) as stored; b likewise; returns (batch, M, N)."""
     a, b = _c128(a), _c128(b)
     batch = a.shape[0]
@@ -275,7 +291,7 @@ def dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b, stream=0) -> np.ndarray:
     k = a.shape[1] if opa == 2 else a.shape[2]
     n = b.shape[1] if opb == 1 else b.shape[2]
     c = np.zeros((batch, m, n), dtype=np.complex128)
-    _check(_lib.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, m, n, k, batch,
+    _check(_lib.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, m, n, k, batch, variant,
                               _dp(a.view(np.float64)), _dp(b.view(np.float64)),
                               _dp(c.view(np.float64)), stream))
     return c

@@ -42,7 +42,11 @@ struct GemmArgs {
   int total_tiles;
 };
 
-hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb,
+// Tile shapes of the GEMM kernel (output tile BM x BN per workgroup).
+enum GemmVariant { GEMM_64x64 = 0, GEMM_32x32 = 1, GEMM_128x64 = 2, GEMM_64x128 = 3 };
+constexpr int GEMM_VARIANTS = 4;
+void gemm_tile_shape(int variant, int* bm, int* bn);
+hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int variant,
                        const GemmArgs& args, hipStream_t s);
 
 // Gate-operator application (one batch item per branch).

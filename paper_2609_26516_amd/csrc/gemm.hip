@@ -7,13 +7,17 @@
 // v_mfma_f64_16x16x4_f64.  Mixed storage (e.g. complex64 site tensors against
 // a complex128 environment) is converted while staging into LDS.
 //
-// Tiling: one 256-thread workgroup (4 wave64) per 64x64 output tile, each
-// wave a 32x32 quadrant (2x2 MFMA blocks, real and imaginary accumulators);
-// K advances in steps of 16 complex columns through LDS held as split real /
-// imaginary planes in [k][m] order, so the 16 lanes of an MFMA operand row
-// read consecutive words.  The next K tile is fetched into registers while
-// the current one is multiplied.  Workgroup ids are remapped so consecutive
-// tiles (same batch item, shared operands) land on the same XCD / L2.
+// Tiling: one 256-thread workgroup (4 wave64 in a 2x2 grid) per BM x BN
+// output tile; each wave owns a (BM/2) x (BN/2) quadrant made of 16x16 MFMA
+// blocks with real and imaginary accumulators.  K advances in steps of 16
+// complex columns through LDS held as split real / imaginary planes in
+// [k][m] order, so the 16 lanes of an MFMA operand row read consecutive
+// words.  The next K tile is fetched into registers while the current one is
+// multiplied.  Workgroup ids are remapped so consecutive tiles (same batch
+// item, shared operands) land on the same XCD / L2.  Tile shapes: 64x64,
+// 32x32, 128x64, 64x128 (chosen per shape class by the runtime's autotuner);
+// every shape accumulates each output element over K in the same order, so
+// they give bit-identical results.
 //
 // Every group of a launch is a batch of equal-shape problems; item b of a
 // group addresses its operands through the slot-id table or its call-local
@@ -26,11 +30,11 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <typename R>
-struct Mfma;
 // Operand layout of both 16x16x4 forms: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16].  Result: lane l, item r holds D[row][l % 16] with
 // row = 4 (l / 16) + r for FP32 and row = l / 16 + 4 r for FP64.
+template <typename R>
+struct Mfma;
 template <>
 struct Mfma<float> {
   using V = v4f;
@@ -59,7 +63,7 @@ struct Store<CT_F64> {
   using T = double2;
 };
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 4;
+constexpr int BK = 16, NT = 256, PAD = 4;
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int q = total >> 3, r = total & 7;
@@ -72,12 +76,15 @@ __device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids
   return static_cast<const char*>(o.base) + idx * o.stride;
 }
 
-template <int TA, int TB, int TC, typename R, int OPA, int OPB>
+template <int TA, int TB, int TC, typename R, int OPA, int OPB, int BM, int BN>
 __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   using CA = typename Store<TA>::T;
   using CB = typename Store<TB>::T;
   using CC = typename Store<TC>::T;
   using V = typename Mfma<R>::V;
+  constexpr int EA = BM * BK / NT;   // A elements staged per thread
+  constexpr int EB = BN * BK / NT;   // B elements staged per thread
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
 
   __shared__ R sAr[BK][BM + PAD];
   __shared__ R sAi[BK][BM + PAD];
@@ -101,14 +108,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   CC* __restrict__ C = reinterpret_cast<CC*>(const_cast<char*>(item_ptr(G.c, G.ids, item)));
 
   const int tid = threadIdx.x;
-  R ar[4], ai[4], br[4], bi[4];
+  R ar[EA], ai[EA], br[EB], bi[EB];
 
   auto load_a = [&](int k0) {
-    if constexpr (OPA == OP_N || OPA == OP_J) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
+    if constexpr (OPA == OP_N || OPA == OP_J) {   // stored M x K: EA consecutive k
+      constexpr int TPR = BK / EA;
+      const int row = tid / TPR, kq = (tid % TPR) * EA;
       const int m = m0 + row;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EA; ++u) {
         const int k = k0 + kq + u;
         R re = 0, im = 0;
         if (m < M && k < K) {
@@ -119,11 +127,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
         ar[u] = re;
         ai[u] = (OPA == OP_J) ? -im : im;
       }
-    } else {  // OP_C: stored K x M, conjugated
-      const int kr = tid >> 4, mq = (tid & 15) * 4;
+    } else {  // OP_C: stored K x M, conjugated; EA consecutive m
+      const int kr = tid / 16, mq = (tid % 16) * EA;
       const int k = k0 + kr;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EA; ++u) {
         const int m = m0 + mq + u;
         R re = 0, im = 0;
         if (m < M && k < K) {
@@ -138,27 +146,28 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   };
   auto store_a = [&]() {
     if constexpr (OPA == OP_N || OPA == OP_J) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
+      constexpr int TPR = BK / EA;
+      const int row = tid / TPR, kq = (tid % TPR) * EA;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EA; ++u) {
         sAr[kq + u][row] = ar[u];
         sAi[kq + u][row] = ai[u];
       }
     } else {
-      const int kr = tid >> 4, mq = (tid & 15) * 4;
+      const int kr = tid / 16, mq = (tid % 16) * EA;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EA; ++u) {
         sAr[kr][mq + u] = ar[u];
         sAi[kr][mq + u] = ai[u];
       }
     }
   };
   auto load_b = [&](int k0) {
-    if constexpr (OPB == OP_N) {  // stored K x N
-      const int kr = tid >> 4, nq = (tid & 15) * 4;
+    if constexpr (OPB == OP_N) {  // stored K x N: EB consecutive n
+      const int kr = tid / 16, nq = (tid % 16) * EB;
       const int k = k0 + kr;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EB; ++u) {
         const int n = n0 + nq + u;
         R re = 0, im = 0;
         if (n < N && k < K) {
@@ -169,11 +178,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
         br[u] = re;
         bi[u] = im;
       }
-    } else {  // OP_T: stored N x K
-      const int nr = tid >> 2, kq = (tid & 3) * 4;
+    } else {  // OP_T: stored N x K: EB consecutive k
+      constexpr int TPR = BK / EB;
+      const int nr = tid / TPR, kq = (tid % TPR) * EB;
       const int n = n0 + nr;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EB; ++u) {
         const int k = k0 + kq + u;
         R re = 0, im = 0;
         if (n < N && k < K) {
@@ -188,16 +198,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   };
   auto store_b = [&]() {
     if constexpr (OPB == OP_N) {
-      const int kr = tid >> 4, nq = (tid & 15) * 4;
+      const int kr = tid / 16, nq = (tid % 16) * EB;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EB; ++u) {
         sBr[kr][nq + u] = br[u];
         sBi[kr][nq + u] = bi[u];
       }
     } else {
-      const int nr = tid >> 2, kq = (tid & 3) * 4;
+      constexpr int TPR = BK / EB;
+      const int nr = tid / TPR, kq = (tid % TPR) * EB;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < EB; ++u) {
         sBr[kq + u][nr] = br[u];
         sBi[kq + u][nr] = bi[u];
       }
@@ -205,14 +216,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   };
 
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  V cr[2][2], ci[2][2];
+  V cr[FM][FN], ci[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cr[i][j][r] = 0;
@@ -236,21 +247,21 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + lk;
-      R xr[2], xi[2], yr[2], yi[2];
+      R xr[FM], xi[FM], yr[FN], yi[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < FM; ++i) {
         xr[i] = sAr[kr][wm + i * 16 + li];
         xi[i] = sAi[kr][wm + i * 16 + li];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < FN; ++j) {
         yr[j] = sBr[kr][wn + j * 16 + li];
         yi[j] = sBi[kr][wn + j * 16 + li];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
           cr[i][j] = Mfma<R>::mma(xr[i], yr[j], cr[i][j]);
           cr[i][j] = Mfma<R>::mma(-xi[i], yi[j], cr[i][j]);
           ci[i][j] = Mfma<R>::mma(xr[i], yi[j], ci[i][j]);
@@ -260,9 +271,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   }
 
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FN; ++j) {
       const int col = n0 + wn + j * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -278,21 +289,56 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
 }
 
 template <int TA, int TB, int TC, typename R, int OPA, int OPB>
-hipError_t run(const GemmArgs& args, hipStream_t s) {
+hipError_t run(int variant, const GemmArgs& args, hipStream_t s) {
   if (args.total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB>), dim3(args.total_tiles), dim3(NT), 0,
-                     s, args);
+  const dim3 grid(args.total_tiles), blk(NT);
+  switch (variant) {
+    case GEMM_64x64:
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 64>), grid, blk, 0, s, args);
+      break;
+    case GEMM_32x32:
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 32, 32>), grid, blk, 0, s, args);
+      break;
+    case GEMM_128x64:
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 128, 64>), grid, blk, 0, s, args);
+      break;
+    case GEMM_64x128:
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 128>), grid, blk, 0, s, args);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, const GemmArgs& args,
-                       hipStream_t s) {
+void gemm_tile_shape(int variant, int* bm, int* bn) {
+  switch (variant) {
+    case GEMM_32x32:
+      *bm = 32;
+      *bn = 32;
+      return;
+    case GEMM_128x64:
+      *bm = 128;
+      *bn = 64;
+      return;
+    case GEMM_64x128:
+      *bm = 64;
+      *bn = 128;
+      return;
+    default:
+      *bm = 64;
+      *bn = 64;
+  }
+}
+
+hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int variant,
+                       const GemmArgs& args, hipStream_t s) {
 #define DCS_GEMM_CASE(TA, TB, TC, R, OA, OB)                                             \
   if (ta == TA && tb == TB && tc == TC && tacc == (sizeof(R) == 8 ? CT_F64 : CT_F32) && \
       opa == OA && opb == OB)                                                            \
-    return run<TA, TB, TC, R, OA, OB>(args, s);
+    return run<TA, TB, TC, R, OA, OB>(variant, args, s);
   // compression-step contractions in path precision
   DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_N, OP_N)
   DCS_GEMM_CASE(CT_F64, CT_F64, CT_F64, double, OP_N, OP_T)

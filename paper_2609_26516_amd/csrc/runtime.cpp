@@ -7,6 +7,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <array>
+#include <cstdio>
 #include <map>
 #include <string>
 #include <unordered_map>
@@ -72,9 +74,29 @@ struct Split {
   std::vector<cd> right;  // [w][s][t], r*2*2
 };
 
+struct TuneRec {
+  int best = -1;
+  double ms[GEMM_VARIANTS] = {};    // fastest trial of each tile shape
+  int cnt[GEMM_VARIANTS] = {};      // trials resolved
+  int issued[GEMM_VARIANTS] = {};   // trials launched
+};
+using TuneKey = std::array<int, 10>;
+
 struct dcs_ctx {
   int device = 0;
   bool graphs = false;
+  bool capturing = false;
+  // online autotuning of GEMM tile shapes: per shape class, the first launches
+  // try every tile shape (timed with events) and the fastest is kept
+  bool tuning = true;
+  int tune_reps = 3;
+  std::map<TuneKey, TuneRec> tune;
+  struct TunePending {
+    TuneKey key;
+    int variant;
+    hipEvent_t a, b;
+  };
+  std::vector<TunePending> tune_pending;
   std::unordered_map<std::string, Split> split_cache;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -327,16 +349,98 @@ struct GemmJob {
   int M, N, K, lda, ldb, ldc, batch;
 };
 
+int lg2_bucket(long long x) {
+  int b = 0;
+  while ((1LL << b) < x && b < 40) ++b;
+  return b;
+}
+
+hipEvent_t take_event(dcs_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Tile shape for a shape class; *timed set when this launch is a tuning trial.
+int tune_choose(dcs_ctx* c, const TuneKey& key, bool* timed) {
+  *timed = false;
+  auto it = c->tune.find(key);
+  if (it != c->tune.end() && it->second.best >= 0) return it->second.best;
+  const bool small = key[6] <= 5 && key[7] <= 5;   // M, N <= 32
+  const int fallback = small ? GEMM_32x32 : GEMM_64x64;
+  if (!c->tuning || c->capturing) return fallback;
+  TuneRec& r = c->tune[key];
+  int v = 0;
+  for (int i = 1; i < GEMM_VARIANTS; ++i)
+    if (r.issued[i] < r.issued[v]) v = i;
+  if (r.issued[v] >= c->tune_reps) return fallback;   // all trials in flight
+  r.issued[v] += 1;
+  *timed = true;
+  return v;
+}
+
+void tune_resolve(dcs_ctx* c) {
+  for (auto& p : c->tune_pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    TuneRec& r = c->tune[p.key];
+    r.ms[p.variant] = r.cnt[p.variant] ? std::min(r.ms[p.variant], (double)ms) : ms;
+    r.cnt[p.variant] += 1;
+    bool done = true;
+    for (int i = 0; i < GEMM_VARIANTS; ++i) done = done && r.cnt[i] >= c->tune_reps;
+    if (done && r.best < 0) {
+      int b = 0;
+      for (int i = 1; i < GEMM_VARIANTS; ++i)
+        if (r.ms[i] < r.ms[b]) b = i;
+      r.best = b;
+    }
+    c->free_events.push_back(p.a);
+    c->free_events.push_back(p.b);
+  }
+  c->tune_pending.clear();
+}
+
 int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
              const std::vector<GemmJob>& jobs, hipStream_t s, int cls) {
   size_t i = 0;
   while (i < jobs.size()) {
+    // jobs of this launch and the shape class of the largest one
+    size_t j_end = i;
+    int ng = 0;
+    long long big = -1;
+    TuneKey key{};
+    for (; j_end < jobs.size() && ng < GEMM_MAX_GROUPS; ++j_end) {
+      const GemmJob& j = jobs[j_end];
+      if (j.batch <= 0 || j.M <= 0 || j.N <= 0) continue;
+      ++ng;
+      const long long w = (long long)j.M * j.N * j.batch;
+      if (w > big) {
+        big = w;
+        key = {ta, tb, tc, tacc, opa, opb, lg2_bucket(j.M), lg2_bucket(j.N), lg2_bucket(j.K),
+               lg2_bucket(j.batch)};
+      }
+    }
+    if (ng == 0) {
+      i = j_end;
+      continue;
+    }
+    bool timed = false;
+    const int variant = tune_choose(ctx, key, &timed);
+    int bm = 64, bn = 64;
+    gemm_tile_shape(variant, &bm, &bn);
     GemmArgs args;
     std::memset(&args, 0, sizeof(args));
-    int ng = 0, tiles = 0;
+    ng = 0;
+    int tiles = 0;
     double flops = 0, bytes = 0;
     const double es = (ta == CT_F32 ? 8.0 : 16.0);
-    for (; i < jobs.size() && ng < GEMM_MAX_GROUPS; ++i) {
+    for (; i < j_end; ++i) {
       const GemmJob& j = jobs[i];
       if (j.batch <= 0 || j.M <= 0 || j.N <= 0) continue;
       GemmGroup& g = args.g[ng++];
@@ -351,18 +455,29 @@ int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
       g.ldb = j.ldb;
       g.ldc = j.ldc;
       g.batch = j.batch;
-      g.tiles_n = (j.N + 63) / 64;
-      g.tiles_per_item = ((j.M + 63) / 64) * g.tiles_n;
+      g.tiles_n = (j.N + bn - 1) / bn;
+      g.tiles_per_item = ((j.M + bm - 1) / bm) * g.tiles_n;
       g.tile_begin = tiles;
       tiles += g.tiles_per_item * j.batch;
       flops += 8.0 * j.M * j.N * (double)j.K * j.batch;
       bytes += es * ((double)j.M * j.K + (double)j.K * j.N + (double)j.M * j.N) * j.batch;
     }
-    if (ng == 0) continue;
     args.ngroups = ng;
     args.total_tiles = tiles;
-    Timed t(ctx, s, cls == CLS_GEMM ? gemm_class(opa, opb) : cls, flops, bytes);
-    DCS_HIP(launch_gemm(ta, tb, tc, tacc, opa, opb, args, s));
+    hipEvent_t ta_ev = nullptr, tb_ev = nullptr;
+    if (timed) {
+      ta_ev = take_event(ctx);
+      tb_ev = take_event(ctx);
+      (void)hipEventRecord(ta_ev, s);
+    }
+    {
+      Timed t(ctx, s, cls == CLS_GEMM ? gemm_class(opa, opb) : cls, flops, bytes);
+      DCS_HIP(launch_gemm(ta, tb, tc, tacc, opa, opb, variant, args, s));
+    }
+    if (timed) {
+      (void)hipEventRecord(tb_ev, s);
+      ctx->tune_pending.push_back({key, variant, ta_ev, tb_ev});
+    }
   }
   return DCS_OK;
 }
@@ -647,9 +762,70 @@ int dcs_ctx_create(dcs_ctx** out, int device) {
 int dcs_ctx_destroy(dcs_ctx* ctx) {
   if (!ctx) return DCS_OK;
   resolve_timing(ctx);
+  tune_resolve(ctx);
   for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
+  return DCS_OK;
+}
+
+int dcs_ctx_set_tuning(dcs_ctx* ctx, int enabled, int reps) {
+  if (!ctx) return fail(DCS_EINVAL, "null context");
+  if (reps < 1 || reps > 100) return fail(DCS_EINVAL, "reps must be in [1, 100]");
+  ctx->tuning = enabled != 0;
+  ctx->tune_reps = reps;
+  return DCS_OK;
+}
+
+int dcs_ctx_tuning_save(dcs_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
+  tune_resolve(ctx);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(DCS_EINVAL, std::string("cannot write ") + path);
+  std::fprintf(f, "{\"format\": \"dcs-gemm-tiles-1\", \"entries\": [");
+  bool first = true;
+  for (auto& kv : ctx->tune) {
+    if (kv.second.best < 0) continue;
+    std::fprintf(f, "%s\n  {\"key\": [", first ? "" : ",");
+    for (int i = 0; i < 10; ++i) std::fprintf(f, "%s%d", i ? ", " : "", kv.first[i]);
+    std::fprintf(f, "], \"best\": %d, \"ms\": [", kv.second.best);
+    for (int i = 0; i < GEMM_VARIANTS; ++i)
+      std::fprintf(f, "%s%.6g", i ? ", " : "", kv.second.cnt[i] ? kv.second.ms[i] : -1.0);
+    std::fprintf(f, "]}");
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return DCS_OK;
+}
+
+int dcs_ctx_tuning_load(dcs_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(DCS_EINVAL, std::string("cannot read ") + path);
+  std::string txt;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+  std::fclose(f);
+  if (txt.find("dcs-gemm-tiles-1") == std::string::npos)
+    return fail(DCS_EINVAL, "not a tile-shape table");
+  size_t pos = 0;
+  int loaded = 0;
+  while ((pos = txt.find("\"key\": [", pos)) != std::string::npos) {
+    pos += 8;
+    TuneKey k{};
+    int best = -1;
+    const char* c = txt.c_str() + pos;
+    int used = 0;
+    if (std::sscanf(c, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], \"best\": %d%n", &k[0], &k[1],
+                    &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9], &best, &used) != 11)
+      return fail(DCS_EINVAL, "malformed tile-shape entry");
+    if (best < 0 || best >= GEMM_VARIANTS) return fail(DCS_EINVAL, "bad tile shape id");
+    ctx->tune[k].best = best;
+    ++loaded;
+    pos += used;
+  }
   return DCS_OK;
 }
 
@@ -1217,7 +1393,9 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       const hipStream_t caller = s;
       s = st->capture_stream;
       DCS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      st->ctx->capturing = true;
       const int rc = enqueue();
+      st->ctx->capturing = false;
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(s, &graph);
       s = caller;
@@ -1243,6 +1421,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
   std::vector<double> nrm(n);
   DCS_HIP(hipMemcpyAsync(nrm.data(), nrm_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   DCS_HIP(hipStreamSynchronize(s));
+  tune_resolve(st->ctx);
   const int centre = visits.back();
   int k = 0;
   for (auto& g : groups) {
@@ -1404,6 +1583,7 @@ int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, do
   std::vector<double> nm(2 * n);
   DCS_HIP(hipMemcpyAsync(nm.data(), out_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
   DCS_HIP(hipStreamSynchronize(s));
+  tune_resolve(st->ctx);
   int k = 0;
   for (auto& g : groups)
     for (int i : g.members) {

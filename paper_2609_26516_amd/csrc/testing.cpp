@@ -80,11 +80,15 @@ Operand op_of(const void* p, long long stride) {
 extern "C" {
 
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
-                  int batch, const double* A, const double* B, double* C, void* stream) {
+                  int batch, int variant, const double* A, const double* B, double* C,
+                  void* stream) {
   if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C)
     return testing_fail(DCS_EINVAL, "bad gemm test arguments");
   if ((opa != OP_N && opa != OP_C && opa != OP_J) || (opb != OP_N && opb != OP_T))
     return testing_fail(DCS_EINVAL, "bad op");
+  if (variant < 0 || variant >= GEMM_VARIANTS) return testing_fail(DCS_EINVAL, "bad tile shape");
+  int bm = 64, bn = 64;
+  gemm_tile_shape(variant, &bm, &bn);
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevBuf da, db, dc;
   const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
@@ -107,12 +111,12 @@ int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int
   g.ldb = (opb == OP_T) ? K : N;
   g.ldc = N;
   g.batch = batch;
-  g.tiles_n = (N + 63) / 64;
-  g.tiles_per_item = ((M + 63) / 64) * g.tiles_n;
+  g.tiles_n = (N + bn - 1) / bn;
+  g.tiles_per_item = ((M + bm - 1) / bm) * g.tiles_n;
   g.tile_begin = 0;
   args.ngroups = 1;
   args.total_tiles = g.tiles_per_item * batch;
-  hipError_t e = launch_gemm(ta, tb, tc, tacc, opa, opb, args, s);
+  hipError_t e = launch_gemm(ta, tb, tc, tacc, opa, opb, variant, args, s);
   if (e == hipErrorInvalidValue) return testing_fail(DCS_EINVAL, "type/op combination not built");
   T_HIP(e);
   std::vector<char> h(nc * csz(tc));

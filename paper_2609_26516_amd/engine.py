@@ -69,6 +69,16 @@ class Engine:
             capi.dcs_chunk_destroy(h)
         self._chunks.clear()
 
+    def tuning(self, enabled: bool, reps: int = 3) -> None:
+        """Online autotuning of the contraction tile shapes (on by default)."""
+        capi.dcs_ctx_set_tuning(self.ctx, enabled, reps)
+
+    def save_tuning(self, path: str) -> None:
+        capi.dcs_ctx_tuning_save(self.ctx, path)
+
+    def load_tuning(self, path: str) -> None:
+        capi.dcs_ctx_tuning_load(self.ctx, path)
+
     def graphs(self, enabled: bool) -> None:
         """Replay recurring compression steps from captured HIP graphs."""
         capi.dcs_ctx_set_graphs(self.ctx, enabled)

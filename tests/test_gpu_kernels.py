@@ -33,10 +33,11 @@ COMBOS = [
 ]
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("combo", COMBOS)
 @pytest.mark.parametrize("mnk", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 130, 37),
                                  (200, 96, 257)])
-def test_gemm(capi, combo, mnk):
+def test_gemm(capi, combo, mnk, variant):
     ta, tb, tc, tacc, opa, opb = combo
     m, n, k = mnk
     rng = np.random.default_rng(m * 7 + n * 3 + k)
@@ -47,7 +48,7 @@ def test_gemm(capi, combo, mnk):
         a = a.astype(np.complex64).astype(np.complex128)
     if tb == F32:
         b = b.astype(np.complex64).astype(np.complex128)
-    c = capi.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b)
+    c = capi.dcs_test_gemm(ta, tb, tc, tacc, opa, opb, a, b, variant=variant)
     A = {OPN: a, OPC: np.conj(np.swapaxes(a, 1, 2)), OPJ: np.conj(a)}[opa]
     B = {OPN: b, OPT: np.swapaxes(b, 1, 2)}[opb]
     ref = A @ B
@@ -147,3 +148,14 @@ def test_qr_tiny_noise_columns(capi, mode, tiny, variant):
     assert np.all(np.isfinite(q))
     np.testing.assert_allclose(gram, np.eye(n), atol=1e-12)
     np.testing.assert_allclose(rec, target, atol=1e-12)
+
+
+def test_tile_shapes_bit_identical(capi):
+    """Every tile shape accumulates each output over K in the same order."""
+    rng = np.random.default_rng(5)
+    a = _rand(rng, 2, 150, 300).astype(np.complex64).astype(np.complex128)
+    b = _rand(rng, 2, 300, 90).astype(np.complex64).astype(np.complex128)
+    ref = capi.dcs_test_gemm(F32, F32, F32, F32, OPN, OPN, a, b, variant=0)
+    for v in (1, 2, 3):
+        np.testing.assert_array_equal(capi.dcs_test_gemm(F32, F32, F32, F32, OPN, OPN, a, b,
+                                                         variant=v), ref)
