@@ -47,6 +47,29 @@ KERNEL_NAMES = {
 TUNE = {"enabled": True, "save": None}
 
 
+# HBM bytes of the dominant kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch, averaged over the kernel's dispatches in
+# one default step), each scaled by what the counter reads for a plain copy
+# of known size.  Valid only for the kernel source they were taken on.
+TRAFFIC = {
+    "qr": {"src": "paper_2609_26516_amd/csrc/kernels.hip",
+           "sha256": "72fcbbeef27749ccf289d58ab592416a595b37ba7f6d69eeb6acac8716f52a43",
+           "fetch_kib": 4608106.9, "write_kib": 5568073.8,
+           "fetch_factor": 1048576 / 524298.0, "write_factor": 1048576 / 1048576.0},
+}
+
+
+def measured_traffic(cls):
+    import hashlib
+    t = TRAFFIC.get(cls)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None       # kernel changed since the counters were taken
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
+
+
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
             graphs: bool = False):
     import torch
@@ -133,7 +156,8 @@ def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload
     return dt, stats, info
 
 
-def roofline(stats, prec):
+def roofline(stats, prec, counters=False):
+    """counters: the HBM counters in TRAFFIC were taken on this workload."""
     launches, ms, flops, byts = stats
     dom = int(np.argmax(ms))
     avg_ms = ms[dom] / max(1, launches[dom])
@@ -152,6 +176,10 @@ def roofline(stats, prec):
         ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         rl = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    tr = measured_traffic(CLASSES[dom]) if counters else None
+    if tr is not None:
+        rl["traffic"] = round(tr)
+        rl["traffic_over_algorithmic"] = round(tr / max(1.0, per_launch_bytes), 2)
     rl["kernel"] = KERNEL_NAMES.get(CLASSES[dom], CLASSES[dom])
     rl["avg_launch_ms"] = round(avg_ms, 5)
     rl["launches"] = int(launches[dom])
@@ -198,6 +226,27 @@ def cpu_baseline(rounds: int):
                       f"each) of one shot, {dt:.1f} s, scaled by {rounds}/{total_rounds}"}
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain copy kernel of known size: `nbytes` read and written per launch."""
+    import torch
+    from paper_2609_26516_amd import capi
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    capi.dcs_test_copy(src.data_ptr(), dst.data_ptr(), nbytes, 1, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    capi.dcs_test_copy(src.data_ptr(), dst.data_ptr(), nbytes, reps, stream)
+    b.record()
+    torch.cuda.synchronize()
+    if not bool(torch.equal(src, dst)):
+        raise RuntimeError("copy kernel produced wrong data")
+    ms = a.elapsed_time(b) / reps
+    return {"copy_bytes_per_launch": nbytes, "launches": reps + 1, "avg_ms": round(ms, 4),
+            "GB_per_s_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +260,8 @@ def main():
     ap.add_argument("--workload", default="sp40", choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH))
     ap.add_argument("--graphs", action="store_true",
                     help="replay recurring compression steps from HIP graphs (no per-kernel timing)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="fixed 64x64 contraction tiles instead of the online autotuner")
     ap.add_argument("--save-tiles", default=None, help="write the tuned tile table (JSON) here")
@@ -223,6 +274,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()))
+        return
     if args.workload in MULTI_PATH:
         wl = MULTI_PATH[args.workload]
         dt, stats, info = run_gpu_multipath("c64", args.steps, args.warmup, True, wl)
@@ -267,7 +321,7 @@ def main():
         "config": {"workload": "n40_depth20_chi256_4meas_per_2layers_single_path",
                    "shots_per_step": args.shots, "n_qubits": 40, "depth": 20, "chi": 256,
                    "sweeps": 2, "precision": "complex64 contractions, FP64 QR/norms"},
-        "roofline": roofline(stats, "c64"),
+        "roofline": roofline(stats, "c64", counters=args.shots == 256),
         "mean_fidelity_estimate": round(float(np.mean(fids)), 6),
     }
     if not args.no_fp64:

@@ -42,6 +42,12 @@ int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double *
 int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int variant, const double *F,
                 double *Q, double *nrm2_out, void *stream);
 
+/* Device-to-device copy of `bytes` (a multiple of 16; both pointers device
+ * memory, 16-byte aligned) from src to dst, `reps` times, enqueued on the
+ * stream without synchronisation: `bytes` read and `bytes` written per launch.
+ * Reference point that converts the profiler's HBM byte counters. */
+int dcs_test_copy(const void *src, void *dst, size_t bytes, int reps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

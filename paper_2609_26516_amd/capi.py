@@ -33,7 +33,7 @@ EXPORTED = [
     "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
     "dcs_export_mps", "dcs_import_mps",
 ]
-EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr"]
+EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
 
 
 class DcsError(RuntimeError):
@@ -82,6 +82,7 @@ _SIGS = {
     "dcs_test_gemm": (c_int, [c_int] * 11 + [_DP, _DP, _DP, _P]),
     "dcs_test_mpo": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
+    "dcs_test_copy": (c_int, [_P, _P, ctypes.c_size_t, c_int, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -312,3 +313,7 @@ def dcs_test_qr(ct_in, ct_out, m, n, mode, variant, f, stream=0):
     _check(_lib.dcs_test_qr(ct_in, ct_out, m, n, mode, int(variant),
                             _dp(f.view(np.float64)), _dp(q.view(np.float64)), _dp(nrm), stream))
     return q, float(nrm[0])
+
+
+def dcs_test_copy(src: int, dst: int, nbytes: int, reps: int = 1, stream: int = 0) -> None:
+    _check(_lib.dcs_test_copy(src, dst, nbytes, reps, stream))

@@ -1,6 +1,8 @@
 // Kernel-level test entry points (include/dcs_testing.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -75,9 +77,34 @@ Operand op_of(const void* p, long long stride) {
   return o;
 }
 
+// Plain device-to-device copy: one 16-byte load and store per thread and
+// iteration, grid-stride.  Reference point for the HBM byte counters.
+__global__ void __launch_bounds__(256) copy16_kernel(const int4* __restrict__ src,
+                                                     int4* __restrict__ dst, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
 }  // namespace
 
 extern "C" {
+
+int dcs_test_copy(const void* src, void* dst, size_t bytes, int reps, void* stream) {
+  if (!src || !dst || bytes % 16 != 0 || reps < 1 || reps > 1000)
+    return testing_fail(DCS_EINVAL, "bad copy test arguments");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return testing_fail(DCS_EINVAL, "copy buffers must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n16 = bytes / 16;
+  const int blocks = (int)std::min<size_t>(8192, (n16 + 255) / 256 + (n16 == 0));
+  for (int r = 0; r < reps; ++r) {
+    hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s,
+                       static_cast<const int4*>(src), static_cast<int4*>(dst), n16);
+    T_HIP(hipGetLastError());
+  }
+  return DCS_OK;
+}
 
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
                   int batch, int variant, const double* A, const double* B, double* C,

@@ -159,3 +159,13 @@ def test_tile_shapes_bit_identical(capi):
     for v in (1, 2, 3):
         np.testing.assert_array_equal(capi.dcs_test_gemm(F32, F32, F32, F32, OPN, OPN, a, b,
                                                          variant=v), ref)
+
+
+def test_copy_kernel(capi):
+    import torch
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    capi.dcs_test_copy(src.data_ptr(), dst.data_ptr(), 4 << 20, 2,
+                       torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
