@@ -66,9 +66,15 @@ enum dcs_status {
 
 enum dcs_precision {
   DCS_C128 = 0,         /* complex128 storage and contractions (FP64 MFMA)  */
-  DCS_C64 = 1           /* complex64 storage, contractions on FP32 MFMA with
+  DCS_C64 = 1,          /* complex64 storage, contractions on FP32 MFMA with
                            FP32 accumulation; QR, norms, probabilities and
                            renormalisation stay in FP64                      */
+  DCS_BF16X3 = 2        /* complex64 storage; the compression-step
+                           contractions run as split-BF16 products (each FP32
+                           component = bf16 hi + bf16 lo, three BF16 MFMA
+                           products per real product, FP32 accumulation);
+                           gate operators in FP32; QR, norms, probabilities
+                           and renormalisation in FP64                       */
 };
 
 typedef struct dcs_ctx dcs_ctx;

@@ -21,7 +21,8 @@ extern "C" {
  * opb: 0 N (B stored K x N), 1 T (B stored N x K).  Items are contiguous:
  * A[b] at b * M * K, B[b] at b * K * N, C[b] at b * M * N.  ta/tb/tc are the
  * storage types of A, B, C and tacc the accumulation type (1 = FP64 MFMA,
- * 0 = FP32 MFMA); only the combinations the library uses are available
+ * 0 = FP32 MFMA, 2 = split-BF16 products on BF16 MFMA with FP32 accumulation,
+ * complex64 storage only); only the combinations the library uses are available
  * (DCS_EINVAL otherwise).  variant: output tile shape 0 64x64, 1 32x32,
  * 2 128x64, 3 64x128. */
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,

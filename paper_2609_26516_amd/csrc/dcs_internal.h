@@ -46,6 +46,11 @@ struct GemmArgs {
 enum GemmVariant { GEMM_64x64 = 0, GEMM_32x32 = 1, GEMM_128x64 = 2, GEMM_64x128 = 3 };
 constexpr int GEMM_VARIANTS = 4;
 void gemm_tile_shape(int variant, int* bm, int* bn);
+// Accumulation mode of a GEMM besides the storage types: split-BF16 products
+// (three BF16 MFMA products per real product, FP32 accumulation) over
+// complex64 operands.
+constexpr int ACC_BF16X3 = 2;
+hipError_t launch_gemm_bf16x3(int opa, int opb, int variant, const GemmArgs& args, hipStream_t s);
 hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int variant,
                        const GemmArgs& args, hipStream_t s);
 

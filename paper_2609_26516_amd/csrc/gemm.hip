@@ -335,6 +335,10 @@ void gemm_tile_shape(int variant, int* bm, int* bn) {
 
 hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int variant,
                        const GemmArgs& args, hipStream_t s) {
+  if (tacc == ACC_BF16X3)
+    return (ta == CT_F32 && tb == CT_F32 && tc == CT_F32)
+               ? launch_gemm_bf16x3(opa, opb, variant, args, s)
+               : hipErrorInvalidValue;
 #define DCS_GEMM_CASE(TA, TB, TC, R, OA, OB)                                             \
   if (ta == TA && tb == TB && tc == TC && tacc == (sizeof(R) == 8 ? CT_F64 : CT_F32) && \
       opa == OA && opb == OB)                                                            \

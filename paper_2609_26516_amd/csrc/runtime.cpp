@@ -56,7 +56,7 @@ std::vector<int> bond_dims(int n, int chi) {
   return d;
 }
 
-int ctype_of(int precision) { return precision == DCS_C64 ? CT_F32 : CT_F64; }
+int ctype_of(int precision) { return precision == DCS_C128 ? CT_F64 : CT_F32; }
 size_t csize_of(int ct) { return ct == CT_F32 ? 8 : 16; }
 
 }  // namespace
@@ -859,7 +859,8 @@ int dcs_ctx_timing(dcs_ctx* ctx, long long* launches, double* ms, double* flops,
 }
 
 static int check_state_args(int precision, int n, int cap, int chi_max, int wmax, int n_init) {
-  if (precision != DCS_C128 && precision != DCS_C64) return fail(DCS_EINVAL, "unknown precision");
+  if (precision != DCS_C128 && precision != DCS_C64 && precision != DCS_BF16X3)
+    return fail(DCS_EINVAL, "unknown precision");
   if (n < 1 || n > 4096) return fail(DCS_EINVAL, "n_qubits out of range");
   if (cap < 1) return fail(DCS_EINVAL, "capacity must be positive");
   if (chi_max < 1 || chi_max > 1024) return fail(DCS_EINVAL, "chi_max must be in [1, 1024]");
@@ -1230,6 +1231,9 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
   for (auto& g : groups) g.ids_dev = ids_dev + g.goff;
 
   const int ct = L.ct;
+  // contractions of the compression step: path precision, or split-BF16
+  // products over the complex64 tensors
+  const int acc = st->precision == DCS_BF16X3 ? ACC_BF16X3 : ct;
   const size_t cs = L.cs;
   double* nrm_dev = reinterpret_cast<double*>(st->base + L.o_out);
   auto ket_site = [&](const Group& g, int j) { return slot_op(st, L.o_mps[g.cur], L.site_off[j]); };
@@ -1262,7 +1266,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
                     dr * wr, bsz});
       mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, kl, dr, wl, wr, bsz});
     }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_T, gj, s, CLS_GEMM));
+    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, gj, s, CLS_GEMM));
     return run_mpo(st->ctx, ct, 1, mj, s);
   };
   auto right_env_from = [&](int j, bool from_init) -> int {
@@ -1273,7 +1277,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       gj.push_back({from_init ? init_site(g, j) : new_site(g, j), x2(), env(j), g.ids_dev, dl,
                     wl * kl, 2 * dr, 2 * dr, 2 * dr, wl * kl, bsz});
     }
-    return run_gemm(st->ctx, ct, ct, ct, ct, OP_J, OP_T, gj, s, CLS_GEMM);
+    return run_gemm(st->ctx, ct, ct, ct, acc, OP_J, OP_T, gj, s, CLS_GEMM);
   };
   // moving right at site j: X1 = L_j K_j, X2 = W X1, F = X2 R_{j+1}^T
   auto right_site = [&](int j, int qr_mode) -> int {
@@ -1301,9 +1305,9 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       q.batch = bsz;
       qj.push_back(q);
     }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_N, g1, s, CLS_GEMM));
+    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, g1, s, CLS_GEMM));
     DCS_TRY(run_mpo(st->ctx, ct, 0, mj, s));
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_T, g2, s, CLS_GEMM));
+    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, g2, s, CLS_GEMM));
     DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
     if (qr_mode == 2) return DCS_OK;
     std::vector<GemmJob> g3;
@@ -1313,7 +1317,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       g3.push_back({new_site(g, j), x2(), env(j + 1), g.ids_dev, dr, wr * kr, 2 * dl, dr,
                     wr * kr, wr * kr, bsz});
     }
-    return run_gemm(st->ctx, ct, ct, ct, ct, OP_C, OP_N, g3, s, CLS_GEMM);
+    return run_gemm(st->ctx, ct, ct, ct, acc, OP_C, OP_N, g3, s, CLS_GEMM);
   };
   auto left_site = [&](int j) -> int {
     DCS_TRY(left_prologue(j));
@@ -1336,7 +1340,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       q.batch = bsz;
       qj.push_back(q);
     }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_N, gj, s, CLS_GEMM));
+    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, gj, s, CLS_GEMM));
     DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
     return right_env_from(j, false);
   };

@@ -20,7 +20,7 @@ from inputs.circuits import CGate, Circuit, Gate, Measure
 from . import capi
 
 EPS_BRANCH = 1e-10
-PRECISIONS = {"c128": capi.DCS_C128, "c64": capi.DCS_C64}
+PRECISIONS = {"c128": capi.DCS_C128, "c64": capi.DCS_C64, "bf16x3": capi.DCS_BF16X3}
 
 
 def _cond_true(cond, regs: np.ndarray) -> np.ndarray:

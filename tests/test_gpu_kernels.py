@@ -59,6 +59,51 @@ def test_gemm(capi, combo, mnk, variant):
     assert err < tol, (err, tol)
 
 
+BF16X3 = 2
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("ops", [(OPN, OPN), (OPN, OPT), (OPC, OPN), (OPJ, OPT)])
+@pytest.mark.parametrize("mnk", [(1, 1, 1), (16, 16, 32), (64, 64, 64), (70, 130, 37),
+                                 (200, 96, 257), (33, 150, 1000)])
+def test_gemm_bf16x3(capi, ops, mnk, variant):
+    """Split-BF16 products: x = hi + lo + d with |x - hi| <= 2^-9 |x| and
+    |d| <= 2^-18 |x|, so each real product carries at most ~3 * 2^-18 |x y|
+    (the dropped lo*lo term and the two d terms), plus FP32 accumulation.
+    Plain BF16 (error ~2^-9) fails this bound by orders of magnitude."""
+    opa, opb = ops
+    m, n, k = mnk
+    rng = np.random.default_rng(m * 5 + n * 11 + k)
+    batch = 2
+    a = _rand(rng, batch, k, m) if opa == OPC else _rand(rng, batch, m, k)
+    b = _rand(rng, batch, n, k) if opb == OPT else _rand(rng, batch, k, n)
+    a = a.astype(np.complex64).astype(np.complex128)
+    b = b.astype(np.complex64).astype(np.complex128)
+    c = capi.dcs_test_gemm(F32, F32, F32, BF16X3, opa, opb, a, b, variant=variant)
+    A = {OPN: a, OPC: np.conj(np.swapaxes(a, 1, 2)), OPJ: np.conj(a)}[opa]
+    B = {OPN: b, OPT: np.swapaxes(b, 1, 2)}[opb]
+    ref = A @ B
+    absA = np.abs(A.real) + np.abs(A.imag)
+    absB = np.abs(B.real) + np.abs(B.imag)
+    S = absA @ absB                       # sum_k of |real products|
+    bound = (4 * 2.0 ** -18 + 2 * (k + 2) * 2.0 ** -24) * S + 1e-30
+    err = np.abs(c - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    if k >= 32:
+        # far more accurate than single BF16 rounding of the operands
+        assert np.max(err / S) < 2.0 ** -14
+
+
+def test_bf16x3_tile_shapes_bit_identical(capi):
+    rng = np.random.default_rng(9)
+    a = _rand(rng, 2, 150, 300).astype(np.complex64).astype(np.complex128)
+    b = _rand(rng, 2, 300, 90).astype(np.complex64).astype(np.complex128)
+    ref = capi.dcs_test_gemm(F32, F32, F32, BF16X3, OPN, OPN, a, b, variant=0)
+    for v in (1, 2, 3):
+        np.testing.assert_array_equal(
+            capi.dcs_test_gemm(F32, F32, F32, BF16X3, OPN, OPN, a, b, variant=v), ref)
+
+
 @pytest.mark.parametrize("ct", [F32, F64])
 @pytest.mark.parametrize("direction", [0, 1])
 @pytest.mark.parametrize("d0,d1,wl,wr", [(1, 2, 1, 4), (5, 7, 4, 4), (33, 300, 4, 1),

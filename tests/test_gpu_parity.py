@@ -9,6 +9,10 @@ stated target of the precision form: 1e-6 absolute probability error and
 estimate f = <F|F> is first order in the FP32 rounding of the environments
 (about n chained contractions of depth 2 chi, each ~1e-7 relative), so its
 complex64 tolerance is 1e-5 (F_TOL); the product over a run gets 10x that.
+The split-BF16 form (complex64 storage, bf16x3 contractions) carries a
+per-product error of at most 3 * 2^-18 ~ 1.1e-5 relative instead of FP32's
+6e-8, so its first-order quantities (probabilities, f) get 1e-4 and the
+second-order state-fidelity error 1e-6.
 """
 import numpy as np
 import pytest
@@ -21,8 +25,9 @@ from oracle import statevector as SV
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-9, "c64": 1e-6}
-F_TOL = {"c128": 1e-9, "c64": 1e-5}
+TOL = {"c128": 1e-9, "c64": 1e-6, "bf16x3": 1e-4}
+F_TOL = {"c128": 1e-9, "c64": 1e-5, "bf16x3": 1e-4}
+FE_TOL = {"c128": 1e-9, "c64": 1e-6, "bf16x3": 1e-6}   # 1 - |<gpu|oracle>|^2
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +73,7 @@ def _fid_err(a, b):
     return abs(1 - abs(OM.overlap(a, b)) ** 2 / (OM.norm_sq(a) * OM.norm_sq(b)))
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 @pytest.mark.parametrize("n,chi,sweeps,layers", [
     (6, 8, 2, 3),       # exact regime
     (9, 16, 1, 2),      # exact regime, odd sweeps
@@ -93,12 +98,14 @@ def test_compress_step_parity(eng, prec, n, chi, sweeps, layers):
     gpu = st.export(1)
     capi.dcs_chunk_destroy(h)
     st.close()
+    print(f"{prec} n={n} chi={chi} sweeps={sweeps}: |df| = {abs(f[0] - f_ref):.2e}, "
+          f"state fidelity error = {_fid_err(gpu, ref):.2e}")
     assert abs(f[0] - f_ref) < F_TOL[prec], (f[0], f_ref)
-    assert _fid_err(gpu, ref) < TOL[prec]
-    assert abs(OM.norm_sq(gpu) - 1) < 10 * TOL[prec]
+    assert _fid_err(gpu, ref) < FE_TOL[prec]
+    assert abs(OM.norm_sq(gpu) - 1) < 10 * FE_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 def test_measure_and_collapse_parity(eng, prec):
     capi = _capi()
     n, chi = 11, 24
@@ -118,8 +125,8 @@ def test_measure_and_collapse_parity(eng, prec):
         assert abs(pm[0] - (n0, n1)[m] / (n0 + n1)) < TOL[prec]
         other = OM.collapse(psi, q, 1 - m, (n0, n1)[1 - m])
         psi = OM.collapse(psi, q, m, (n0, n1)[m])
-        assert _fid_err(st.export(0), psi) < TOL[prec]
-        assert _fid_err(st.export(1), other) < TOL[prec]
+        assert _fid_err(st.export(0), psi) < FE_TOL[prec]
+        assert _fid_err(st.export(1), other) < FE_TOL[prec]
         capi.dcs_branch_release(st.h, [1])
     st.close()
 
@@ -139,7 +146,7 @@ def test_zero_probability_collapse_is_refused(eng):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 def test_single_path_cfg1_replay(eng, prec):
     """Whole single-path run of the 10-qubit chi=16 workload against the
     oracle replaying the GPU's sampled outcomes."""
@@ -154,7 +161,7 @@ def test_single_path_cfg1_replay(eng, prec):
     np.testing.assert_allclose(res["p0s"][0], ref["p0s"], atol=TOL[prec], rtol=0)
     assert abs(res["F"][0] - ref["F"]) < 10 * F_TOL[prec]
     assert abs(res["p"][0] - ref["p"]) < 10 * TOL[prec]
-    assert _fid_err(st.export(int(res["ids"][0])), ref["mps"]) < TOL[prec]
+    assert _fid_err(st.export(int(res["ids"][0])), ref["mps"]) < FE_TOL[prec]
     # same uniforms give the same outcomes on the oracle's own sampling
     ref2 = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"]), uniforms=u[0])
     assert ref2["outcomes"] == list(res["outcomes"][0])
@@ -174,7 +181,7 @@ def test_exact_regime_run_matches_statevector(eng):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 def test_batched_shots_replay(eng, prec):
     """Several shots in lockstep (chunks differ through the feed-forward)."""
     circ, prm = C.workload("cfg4_n24_chi64_x1024", n=12, depth=6, chi=16)
@@ -188,7 +195,7 @@ def test_batched_shots_replay(eng, prec):
         ref = OD.run_single_path(circ, sim, outcomes=res["outcomes"][s])
         np.testing.assert_allclose(res["p0s"][s], ref["p0s"], atol=TOL[prec], rtol=0)
         assert abs(res["F"][s] - ref["F"]) < 10 * F_TOL[prec]
-        assert _fid_err(st.export(int(res["ids"][s])), ref["mps"]) < TOL[prec]
+        assert _fid_err(st.export(int(res["ids"][s])), ref["mps"]) < FE_TOL[prec]
     st.close()
 
 
@@ -221,7 +228,7 @@ def test_teleport_and_ghz_multi_path(eng):
     st.close()
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 def test_multi_path_uneven_chi_parity(eng, prec):
     """Multi-path with per-child bond caps and top-M against the oracle."""
     circ, prm = C.workload("cfg3_n32_mp64", n=10, depth=6, chi=24)
@@ -239,6 +246,6 @@ def test_multi_path_uneven_chi_parity(eng, prec):
     for pth, b in want.items():
         assert abs(got[pth]["p"] - b["p"]) < 10 * TOL[prec]
         assert abs(got[pth]["F"] - b["F"]) < 10 * F_TOL[prec]
-        assert _fid_err(st.export(got[pth]["id"]), b["mps"]) < TOL[prec]
+        assert _fid_err(st.export(got[pth]["id"]), b["mps"]) < FE_TOL[prec]
     assert abs(res["dropped"] - ref["dropped"]) < 10 * TOL[prec]
     st.close()
