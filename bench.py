@@ -32,7 +32,9 @@ WORKLOAD = "cfg2_n40_chi256"
 SINGLE_PATH = {"sp40": "cfg2_n40_chi256", "sp24": "cfg4_n24_chi64_x1024",
                "sp10": "cfg1_n10_chi16"}
 MULTI_PATH = {"mp32": "cfg3_n32_mp64"}
-PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA")}
+LARGE_CHI = {"sp60": "cfg5_n60_chi1024"}
+PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA"),
+        "bf16x3": (2500.0 / 3.0, "bf16 dense MFMA / 3 products per real product")}
 HBM_PEAK_GBS = 8000.0
 CLASSES = ["gemm_nn", "gemm_nt", "gemm_cn", "gemm_jt", "gate_operator", "qr", "measure",
            "other"]
@@ -70,6 +72,12 @@ def measured_traffic(cls):
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
 
 
+def mpo_bond_max(prm) -> int:
+    """Operator bond of a chunk of L Haar brickwork layers: a bond is
+    straddled by ceil(L / 2) two-qubit gates of operator-Schmidt rank 4."""
+    return 4 ** ((prm["layers_per_round"] + 1) // 2)
+
+
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
             graphs: bool = False):
     import torch
@@ -83,7 +91,7 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, worklo
     eng = E.Engine(0)
     eng.graphs(graphs)
     eng.tuning(TUNE["enabled"])
-    st = E.State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
+    st = E.State(eng, prec, n, shots, chi, mpo_bond_max(prm), [chi], prm["init_seed"])
     nm = circ.n_measurements()
 
     def one_step(step):
@@ -192,6 +200,62 @@ def roofline(stats, prec, counters=False):
     return rl
 
 
+def run_large_chi(workload: str, steps: int, warmup: int, timing: bool):
+    """Single-path shots of the large-chi workload in the split-BF16 form,
+    then the FP64 path replaying the first shot's outcomes; the two final
+    states are compared by the FP64 overlap in one complex128 state."""
+    import torch
+    from inputs import circuits as C
+    from inputs.randomness import shot_uniforms
+    from paper_2609_26516_amd import capi
+    from paper_2609_26516_amd import engine as E
+
+    circ, prm = C.workload(workload)
+    n, chi = prm["n"], prm["chi"]
+    k = C.segment_max(circ) + 1
+    w = mpo_bond_max(prm)
+    nm = circ.n_measurements()
+    u = lambda shot: shot_uniforms(prm["seed"], shot, nm)[None, :]  # noqa: E731
+    eng = E.Engine(0)
+    st = E.State(eng, "bf16x3", n, 1, chi, w, [chi], prm["init_seed"])
+    for i in range(warmup):
+        st.release(E.run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u(10_000 + i))["ids"])
+    torch.cuda.synchronize()
+    eng.timing(timing)
+    eng.timing_stats(reset=True)
+    t0 = time.perf_counter()
+    first = None
+    for i in range(steps):
+        r = E.run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u(i))
+        if first is None:
+            first = (r, st.export(int(r["ids"][0])))
+        st.release(r["ids"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = eng.timing_stats(reset=True) if timing else None
+    eng.timing(False)
+    st.close()
+    r_bf, mps_bf = first
+    st64 = E.State(eng, "c128", n, 2, chi, w, [chi], prm["init_seed"])
+    t1 = time.perf_counter()
+    r64 = E.run_single_path(eng, st64, circ, 1, chi, k, 2, outcomes=r_bf["outcomes"])
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t1
+    i64 = int(r64["ids"][0])
+    other = st64.alloc(1)[0]
+    capi.dcs_import_mps(st64.h, other, chi, mps_bf, eng.stream())
+    ov = capi.dcs_overlap(st64.h, i64, other, eng.stream())
+    na = capi.dcs_overlap(st64.h, i64, i64, eng.stream()).real
+    nb = capi.dcs_overlap(st64.h, other, other, eng.stream()).real
+    st64.close()
+    eng.close()
+    cmp = {"reference": "GPU FP64 path (complex128, FP64 MFMA) replaying the outcomes",
+           "state_fidelity_error": float(abs(1 - abs(ov) ** 2 / (na * nb))),
+           "max_abs_probability_error": float(np.max(np.abs(r_bf["p0s"][0] - r64["p0s"][0]))),
+           "fidelity_estimate": float(r_bf["F"][0]), "fidelity_estimate_fp64": float(r64["F"][0])}
+    return dt, dt64, stats, cmp
+
+
 def cpu_baseline(rounds: int):
     """The FP64 oracle on the first `rounds` measurement rounds of one shot of
     the same workload, scaled to shots/s by the fraction of rounds done."""
@@ -257,7 +321,8 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="sp40", choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH))
+    ap.add_argument("--workload", default="sp40",
+                    choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH) + sorted(LARGE_CHI))
     ap.add_argument("--graphs", action="store_true",
                     help="replay recurring compression steps from HIP graphs (no per-kernel timing)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -276,6 +341,21 @@ def main():
 
     if args.copy_calibration:
         print(json.dumps(copy_calibration()))
+        return
+    if args.workload in LARGE_CHI:
+        wl = LARGE_CHI[args.workload]
+        dt, dt64, stats, cmp = run_large_chi(wl, args.steps, args.warmup, True)
+        out = {"metric": "shots/s (split-BF16 form, chi=1024), FP64 path beside it",
+               "value": round(args.steps / dt, 5), "unit": "shots/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+               "data": "synthetic: seeded Haar brickwork dynamic circuit",
+               "config": {"workload": wl, "shots_per_step": 1},
+               "roofline": roofline(stats, "bf16x3"),
+               "fp64_path": {"value": round(1 / dt64, 5), "unit": "shots/s", "dtype": "c128"},
+               "precision_vs_fp64": cmp}
+        print(json.dumps(out))
         return
     if args.workload in MULTI_PATH:
         wl = MULTI_PATH[args.workload]

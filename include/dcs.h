@@ -215,6 +215,15 @@ int dcs_collapse(dcs_state *st, int n, const int *src_ids, const int *qubits,
 int dcs_topk_by_weight(int n, const double *weights, int k, int *keep_idx_out,
                        int *n_keep_out, double *discarded_out);
 
+/* <a|b> = sum over all indices of conj(A) B for branches id_a (bra) and id_b
+ * (ket) of one state, by the FP64 left-transfer contraction E_{j+1} =
+ * A_j^H (E_j B_j) on the contraction kernels (Sec. III-B state overlap; the
+ * fidelity |<a|b>|^2 / (<a|a><b|b>) compares two states).  The branches may
+ * have different bond caps.  out: host, 2 doubles (re, im).  Uses the
+ * measurement scratch of id_a.  Synchronises the stream.  Errors: EINVAL,
+ * ECAPACITY, ESTATE (branch not live), EHIP. */
+int dcs_overlap(dcs_state *st, int id_a, int id_b, double *out, void *stream);
+
 /* FP64 host copy of branch `id`'s MPS: sites concatenated, each row-major
  * [chi_j][2][chi_{j+1}] complex128 interleaved (2 * sum chi_j*2*chi_{j+1}
  * doubles, at most cap_doubles); dims_out gets chi_0..chi_n. */

@@ -31,7 +31,7 @@ EXPORTED = [
     "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
-    "dcs_export_mps", "dcs_import_mps",
+    "dcs_overlap", "dcs_export_mps", "dcs_import_mps",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
 
@@ -77,6 +77,7 @@ _SIGS = {
     "dcs_measure_prob": (c_int, [_P, c_int, _IP, _IP, _DP, _P]),
     "dcs_collapse": (c_int, [_P, c_int, _IP, _IP, _IP, _IP, c_double, _DP, _P]),
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
+    "dcs_overlap": (c_int, [_P, c_int, c_int, _DP, _P]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
     "dcs_test_gemm": (c_int, [c_int] * 11 + [_DP, _DP, _DP, _P]),
@@ -254,6 +255,12 @@ def dcs_topk_by_weight(weights, k):
     _check(_lib.dcs_topk_by_weight(len(w), _dp(w), k, _ip(keep), ctypes.byref(nk),
                                    ctypes.byref(disc)))
     return keep[:nk.value].copy(), disc.value
+
+
+def dcs_overlap(st: int, id_a: int, id_b: int, stream: int = 0) -> complex:
+    out = np.zeros(2)
+    _check(_lib.dcs_overlap(st, id_a, id_b, _dp(out), stream))
+    return complex(out[0], out[1])
 
 
 def dcs_export_mps(st, bid, n_qubits, chi_max, stream):

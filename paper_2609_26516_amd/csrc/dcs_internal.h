@@ -101,6 +101,13 @@ size_t qr_lds_limit();
 // complex128 values, row-major working matrix first.
 hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s);
 int qr_blocked_max_rows();
+// Multi-kernel variant for qr_blocked_max_rows() < m <= qr_large_max_rows()
+// (modes 0 and 1): panels factored by one workgroup per matrix, trailing
+// updates and the backward Q accumulation spread over 16-column strips.  The
+// workspace of each item holds qr_large_ws_elems(m, n) complex128 values.
+hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args, hipStream_t s);
+int qr_large_max_rows();
+size_t qr_large_ws_elems(int m, int n);
 
 // n_m = Re sum_{a,b} conj(A[a][m][b]) Z[a][m][b] for m = 0, 1 (FP64), one
 // workgroup per branch; Z = A when z.base is null.

@@ -3,117 +3,12 @@
 // tensor (gauge shift), outcome norms for the measurement probability, and
 // the collapse of a site tensor.
 #include "dcs_internal.h"
+#include "kernel_util.h"
 
 namespace dcs {
 namespace {
 
 constexpr int NT = 256;
-
-template <int CT>
-struct St;
-template <>
-struct St<CT_F32> {
-  using T = float2;
-  using R = float;
-};
-template <>
-struct St<CT_F64> {
-  using T = double2;
-  using R = double;
-};
-
-__device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids, int b) {
-  const long long idx = o.by_slot ? ids[b] : b;
-  return static_cast<const char*>(o.base) + idx * o.stride;
-}
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-// conj(a) * b
-__device__ __forceinline__ double2 cdotc(double2 a, double2 b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over the 256-thread block; every thread gets the result.
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
-  v = wave_sum(v);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) scratch[wave] = v;
-  __syncthreads();
-  return scratch[0] + scratch[1] + scratch[2] + scratch[3];
-}
-
-// Running (scale, sum of squares) pair: the represented value is
-// scale^2 * ssq, accumulated without squaring anything tiny or huge.
-__device__ __forceinline__ void ssq_add(double& sc, double& q, double x) {
-  x = fabs(x);
-  if (x > 0.0) {
-    if (sc < x) {
-      const double r = sc / x;
-      q = 1.0 + q * r * r;
-      sc = x;
-    } else {
-      const double r = x / sc;
-      q += r * r;
-    }
-  }
-}
-
-__device__ __forceinline__ void ssq_merge(double& sc, double& q, double sc2, double q2) {
-  if (sc2 > sc) {
-    const double r = sc / sc2;
-    q = q2 + q * r * r;
-    sc = sc2;
-  } else if (sc2 > 0.0) {
-    const double r = sc2 / sc;
-    q += q2 * r * r;
-  }
-}
-
-// Block-wide merge of (scale, ssq); every thread gets the result.
-__device__ __forceinline__ void block_ssq(double& sc, double& q, double* scratch) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double s2 = __shfl_xor(sc, o, 64), q2 = __shfl_xor(q, o, 64);
-    ssq_merge(sc, q, s2, q2);
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) {
-    scratch[2 * wave] = sc;
-    scratch[2 * wave + 1] = q;
-  }
-  __syncthreads();
-  sc = scratch[0];
-  q = scratch[1];
-  for (int w = 1; w < 4; ++w) ssq_merge(sc, q, scratch[2 * w], scratch[2 * w + 1]);
-}
-
-// 1 / d by Smith's scaling (no overflow or underflow of |d|^2).
-__device__ __forceinline__ double2 crecip(double2 d) {
-  if (fabs(d.x) >= fabs(d.y)) {
-    const double r = d.y / d.x, den = d.x + d.y * r;
-    return make_double2(1.0 / den, -r / den);
-  }
-  const double r = d.x / d.y, den = d.x * r + d.y;
-  return make_double2(r / den, -1.0 / den);
-}
-
-template <int GROUPS, typename G>
-__device__ __forceinline__ int find_group(const G* g, int ngroups, int blk) {
-  int gi = 0;
-  while (gi + 1 < ngroups && blk >= g[gi + 1].blk_begin) ++gi;
-  return gi;
-}
 
 // ---------------------------------------------------------------------------
 // Gate-operator application.  WMAX bounds the operator bond dims so the
@@ -240,10 +135,6 @@ __global__ __launch_bounds__(NT) void mpo_left_kernel(const MpoArgs args) {
 // [I; 0] accumulated backwards (zung2r).  The m x n working matrix is held
 // column-major either in LDS or in the branch's global workspace.
 
-template <typename TI>
-__device__ __forceinline__ double2 to_d2(TI v) {
-  return make_double2((double)v.x, (double)v.y);
-}
 
 template <int CTI, int CTO>
 __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
@@ -439,20 +330,6 @@ constexpr int QB = 16;
 
 __device__ __forceinline__ int pidx(int i, int c) { return i * QB + (c ^ (i & 15)); }
 
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4d_t mfma64(double a, double b, v4d_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// complex accumulate (cr, ci) += (ar + i ai)(br + i bi) on one 16x16x4 step
-__device__ __forceinline__ void cmma(double ar, double ai, double br, double bi, v4d_t& cr,
-                                     v4d_t& ci) {
-  cr = mfma64(ar, br, cr);
-  cr = mfma64(-ai, bi, cr);
-  ci = mfma64(ar, bi, ci);
-  ci = mfma64(ai, br, ci);
-}
 
 // Reflector r of the panel at local row i: 0 above the diagonal, 1 on it.
 __device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, int nbk) {
@@ -461,12 +338,6 @@ __device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, 
   return P[pidx(i, r)];
 }
 
-__device__ __forceinline__ void zero4(v4d_t& a) {
-  a[0] = 0;
-  a[1] = 0;
-  a[2] = 0;
-  a[3] = 0;
-}
 
 // Apply (I - V X V^H) to the 16-column sub-strip at global column c0 of rows
 // p..m-1 of the row-major matrix A (leading dimension n), X = T^H (conjT) or
@@ -548,29 +419,6 @@ __device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int n
   }
 }
 
-// Block-wide (sum, max) over NW waves; every thread gets both.
-template <int NW>
-__device__ __forceinline__ void block_sum_max(double& sm, double& mx, double* scratch) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    sm += __shfl_xor(sm, o, 64);
-    mx = fmax(mx, __shfl_xor(mx, o, 64));
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) {
-    scratch[2 * wave] = sm;
-    scratch[2 * wave + 1] = mx;
-  }
-  __syncthreads();
-  sm = 0.0;
-  mx = 0.0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    sm += scratch[2 * w];
-    mx = fmax(mx, scratch[2 * w + 1]);
-  }
-}
 
 // NTQ threads per workgroup: 512 (8 waves, one workgroup per CU) for the
 // large panels, 256 (4 waves, registers capped so two fit on a CU) for

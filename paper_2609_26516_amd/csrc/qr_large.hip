@@ -1,0 +1,461 @@
+// FP64 Householder QR with explicit thin Q for local matrices of more than
+// 512 rows (bond caps above 256), where one workgroup per matrix would leave
+// the chip idle and the panel no longer fits in LDS.  Same reflectors as the
+// other QR kernels (LAPACK convention: v_k = 1, beta = -sign(Re alpha) |x|,
+// tau = ((beta - Re alpha) / beta, -Im alpha / beta), tau = 0 for a zero
+// column), blocked in panels of NB columns with the compact WY form
+// H_p ... H_{p+NB-1} = I - V T V^H:
+//   qrl_load   F (mode 0) or F^H (mode 1) -> FP64 working matrix A (m x n,
+//              row-major), |F|^2 partial sums per chunk
+//   qrl_panel  one 512-thread workgroup per matrix factors A[p:, p:p+NB]
+//              with the panel in registers (RP rows per thread), reducing
+//              norms and inner products over the workgroup; writes the
+//              explicit V (unit diagonal) and T (zlarft recurrence, Gram
+//              entries v_j^H v_k reduced together with the panel updates)
+//   qrl_apply  A[p:, c:] -= V X (V^H A[p:, c:]) with X = T^H, one 4-wave
+//              workgroup per 16-column strip on FP64 MFMA; the partial
+//              W = V^H A of each wave is summed through LDS
+// After the last panel A is reset to [I; 0] and the panels are applied in
+// reverse order with X = T, which leaves the thin Q = H_0 ... H_{n-1} [I; 0]
+// in A; qrl_store writes Q (mode 0) or Q^H (mode 1) in the output precision.
+#include <utility>
+
+#include "dcs_internal.h"
+#include "kernel_util.h"
+
+namespace dcs {
+namespace {
+
+// f(std::integral_constant<int, k>) for k = 0 .. N-1, expanded at compile time
+template <typename Fn, int... K>
+__device__ __forceinline__ void static_for_impl(Fn&& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int QRL_CHUNKS = 64;   // load / store / fill work units per matrix
+constexpr int QRL_NT = 512;      // panel workgroup
+constexpr int QRL_NW = QRL_NT / 64;
+
+struct QrlItem {
+  const QrGroup* g;
+  int item;
+};
+
+__device__ __forceinline__ QrlItem qrl_item(const QrArgs& args, int flat) {
+  const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, flat);
+  return {&args.g[gi], flat - args.g[gi].blk_begin};
+}
+
+__device__ __forceinline__ double2* qrl_ws(const QrlItem& it) {
+  return reinterpret_cast<double2*>(const_cast<char*>(item_ptr(it.g->ws, it.g->ids, it.item)));
+}
+
+// workspace: A (m n), V (m n), T factors (16 (n + 16)), chunk partials
+__device__ __forceinline__ double* qrl_partials(double2* ws, int m, int n) {
+  return reinterpret_cast<double*>(ws + 2LL * m * n + 16LL * (n + 16));
+}
+
+template <int CTI>
+__global__ __launch_bounds__(256) void qrl_load_kernel(const QrArgs args) {
+  using TI = typename St<CTI>::T;
+  __shared__ double s_red[4];
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  const int m = it.g->m, n = it.g->n, mode = it.g->mode;
+  const TI* __restrict__ F = reinterpret_cast<const TI*>(item_ptr(it.g->f, it.g->ids, it.item));
+  double2* A = qrl_ws(it);
+  const long long mn = (long long)m * n;
+  const long long per = (mn + QRL_CHUNKS - 1) / QRL_CHUNKS;
+  const long long e0 = per * blockIdx.x, e1 = min(mn, e0 + per);
+  double part = 0.0;
+  for (long long idx = e0 + threadIdx.x; idx < e1; idx += 256) {
+    double2 v;
+    if (mode == 0) {
+      v = to_d2(F[idx]);
+    } else {   // A[i][j] = conj(F[j][i]), F stored n x m
+      const long long i = idx / n, j = idx % n;
+      v = cconj(to_d2(F[j * m + i]));
+    }
+    part += v.x * v.x + v.y * v.y;
+    A[idx] = v;
+  }
+  part = block_sum(part, s_red);
+  if (threadIdx.x == 0) qrl_partials(A, m, n)[blockIdx.x] = part;
+}
+
+// Panel factorisation.  RP rows per thread (rows tid + r QRL_NT), NB panel
+// columns; every loop over columns is unrolled so the panel stays in
+// registers.
+template <int RP, int NB>
+__global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, int p) {
+  __shared__ double s_red[2 * QRL_NW];
+  __shared__ double2 s_dot[QRL_NW][NB];
+  __shared__ double2 s_T[NB * NB];
+  __shared__ double2 s_alpha;
+  const QrlItem it = qrl_item(args, blockIdx.x);
+  const int m = it.g->m, n = it.g->n;
+  if (p >= n) return;
+  double2* A = qrl_ws(it);
+  double2* V = A + (long long)m * n;
+  double2* Tg = V + (long long)m * n;
+  const int mp = m - p, nbk = min(NB, n - p);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
+    const double* part = qrl_partials(A, m, n);
+    double s = 0.0;
+    for (int c = 0; c < QRL_CHUNKS; ++c) s += part[c];
+    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
+  }
+
+  double2 a[RP][NB];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int i = tid + r * QRL_NT;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      a[r][c] = (i < mp && c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
+  }
+  if (tid < NB * NB) s_T[tid] = make_double2(0.0, 0.0);
+
+  static_for<NB>([&](auto kc) {
+    constexpr int kk = decltype(kc)::value;
+    if (kk >= nbk) return;   // uniform over the workgroup
+    // |x|^2 and max|x| of the column below the diagonal (row kk is thread kk)
+    double sm = 0.0, mx = 0.0;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + r * QRL_NT;
+      if (i > kk && i < mp) {
+        const double2 v = a[r][kk];
+        sm += v.x * v.x + v.y * v.y;
+        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+      }
+    }
+    if (tid == kk) s_alpha = a[0][kk];
+    block_sum_max_dpp<QRL_NW>(sm, mx, s_red);
+    double sc = 0.0, q = 0.0;
+    if (mx > 0.0 && (mx < 1e-140 || mx > 1e140)) {
+      double sm2 = 0.0, dummy = 0.0;
+      const double inv = 1.0 / mx;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int i = tid + r * QRL_NT;
+        if (i > kk && i < mp) {
+          const double2 v = a[r][kk];
+          sm2 += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+        }
+      }
+      block_sum_max_dpp<QRL_NW>(sm2, dummy, s_red);
+      sc = mx;
+      q = sm2;
+    } else if (mx > 0.0) {
+      sc = 1.0;
+      q = sm;
+    }
+    const double2 alpha = s_alpha;
+    double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+    if (!(sc == 0.0 && alpha.y == 0.0)) {
+      double sa = sc, qa = q;
+      ssq_add(sa, qa, alpha.x);
+      ssq_add(sa, qa, alpha.y);
+      const double nrm_all = sa * sqrt(qa);
+      if (nrm_all > 1e-280) {
+        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        scal = crecip(make_double2(alpha.x - beta, alpha.y));
+      }
+    }
+    // v below the diagonal (an exact zero reflector when tau = 0)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + r * QRL_NT;
+      if (i > kk && i < mp) a[r][kk] = cmul(a[r][kk], scal);
+    }
+    // s_dot[.][c] = v^H a_c for the panel columns c > kk and v_c^H v for the
+    // earlier reflectors c < kk (Gram column of the T recurrence), one wave
+    // partial per entry
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c == kk || c >= nbk) continue;
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int i = tid + r * QRL_NT;
+        if (i >= kk && i < mp) {
+          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : a[r][kk];
+          // row i >= kk > c: a[r][c] holds v_c for c < kk
+          const double2 w = (c > kk) ? cdotc(v, a[r][c]) : cdotc(a[r][c], v);
+          acc.x += w.x;
+          acc.y += w.y;
+        }
+      }
+      acc.x = wave_sum_dpp(acc.x);
+      acc.y = wave_sum_dpp(acc.y);
+      if (lane == 0) s_dot[wave][c] = acc;
+    }
+    __syncthreads();
+    auto dot = [&](int c) {
+      double2 acc = s_dot[0][c];
+#pragma unroll
+      for (int w = 1; w < QRL_NW; ++w) {
+        acc.x += s_dot[w][c].x;
+        acc.y += s_dot[w][c].y;
+      }
+      return acc;
+    };
+    // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk], T[kk][kk] = tau
+    if (tid < kk) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        if (t >= tid && t < kk) {
+          const double2 u = cmul(s_T[tid * NB + t], dot(t));
+          acc.x += u.x;
+          acc.y += u.y;
+        }
+      }
+      const double2 u = cmul(tau, acc);
+      s_T[tid * NB + kk] = make_double2(-u.x, -u.y);
+    } else if (tid == kk) {
+      s_T[kk * NB + kk] = tau;
+    }
+    // a_c -= v conj(tau) d[c] for the remaining panel columns
+    const double2 ctau = cconj(tau);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c > kk && c < nbk) {
+        const double2 cc = cmul(ctau, dot(c));
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const int i = tid + r * QRL_NT;
+          if (i >= kk && i < mp) {
+            const double2 v = (i == kk) ? make_double2(1.0, 0.0) : a[r][kk];
+            const double2 u = cmul(v, cc);
+            a[r][c] = make_double2(a[r][c].x - u.x, a[r][c].y - u.y);
+          }
+        }
+      }
+    }
+  });
+  __syncthreads();
+  // explicit V of the panel (zero above, one on the diagonal) and T
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int i = tid + r * QRL_NT;
+    if (i < mp) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c < nbk) {
+          const double2 v = (i < c) ? make_double2(0.0, 0.0)
+                                    : (i == c ? make_double2(1.0, 0.0) : a[r][c]);
+          V[(long long)(p + i) * n + p + c] = v;
+        }
+      }
+    }
+  }
+  if (tid < NB * NB) Tg[(long long)(p / NB) * NB * NB + tid] = s_T[tid];
+}
+
+// A[p:, c0:c0+16] -= V X (V^H A[p:, c0:c0+16]), X = T^H (conj_t) or T.
+// QRA_NW waves split the rows; global operands are fetched eight k-steps
+// (W) or two row blocks (update) at a time.
+constexpr int QRA_NW = 8;
+
+template <int NB>
+__global__ __launch_bounds__(64 * QRA_NW) void qrl_apply_kernel(const QrArgs args, int p,
+                                                                int c_off, int conj_t) {
+  __shared__ double2 sW[QRA_NW][256];
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  const int m = it.g->m, n = it.g->n;
+  const int c0 = p + c_off + 16 * blockIdx.x;
+  if (p >= n || c0 >= n) return;
+  double2* A = qrl_ws(it);
+  const double2* V = A + (long long)m * n;
+  const double2* T = V + (long long)m * n + (long long)(p / NB) * NB * NB;
+  const int mp = m - p, nbk = min(NB, n - p);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  const bool col_ok = col < n;
+  const int rw = ((mp + 16 * QRA_NW - 1) / (16 * QRA_NW)) * 16;   // rows per wave
+  const int r0 = wave * rw, r1 = min(mp, r0 + rw);
+  const double2 zero = make_double2(0.0, 0.0);
+
+  // partial W = V^H A over this wave's rows
+  v4d_t wr, wi;
+  zero4(wr);
+  zero4(wi);
+  for (int i0 = r0; i0 < r1; i0 += 32) {
+    double2 vv[8], bb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 4 * u + lk;
+      const bool ok = i < r1;
+      vv[u] = (ok && li < nbk) ? V[(long long)(p + i) * n + p + li] : zero;
+      bb[u] = (ok && col_ok) ? A[(long long)(p + i) * n + col] : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cmma(vv[u].x, -vv[u].y, bb[u].x, bb[u].y, wr, wi);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sW[wave][(lk + 4 * t) * 16 + li] = make_double2(wr[t], wi[t]);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = (lk + 4 * t) * 16 + li;
+    double2 sum = sW[0][e];
+#pragma unroll
+    for (int w = 1; w < QRA_NW; ++w) {
+      sum.x += sW[w][e].x;
+      sum.y += sW[w][e].y;
+    }
+    wr[t] = sum.x;
+    wi[t] = sum.y;
+  }
+  // W2 = X W (result item t = row lk + 4t = the B operand of k-step t)
+  v4d_t xr, xi;
+  zero4(xr);
+  zero4(xi);
+#pragma unroll
+  for (int t = 0; t < NB / 4; ++t) {
+    const int s = 4 * t + lk;
+    double2 x = zero;
+    if (li < nbk && s < nbk) {
+      if (conj_t) {
+        const double2 tt = T[s * NB + li];
+        x = make_double2(tt.x, -tt.y);
+      } else {
+        x = T[li * NB + s];
+      }
+    }
+    cmma(x.x, x.y, wr[t], wi[t], xr, xi);
+  }
+  // A -= V W2, two 16-row blocks at a time
+  for (int rb0 = r0; rb0 < r1; rb0 += 32) {
+    v4d_t dr[2], di[2];
+    double2 vv[2][NB / 4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rb = rb0 + 16 * h;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = rb + lk + 4 * t;
+        const double2 v = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
+        dr[h][t] = v.x;
+        di[h][t] = v.y;
+      }
+#pragma unroll
+      for (int t = 0; t < NB / 4; ++t) {
+        const int i = rb + li, sref = 4 * t + lk;
+        vv[h][t] = (i < r1 && sref < nbk) ? V[(long long)(p + i) * n + p + sref] : zero;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int t = 0; t < NB / 4; ++t) cmma(vv[h][t].x, vv[h][t].y, -xr[t], -xi[t], dr[h], di[h]);
+      if (col_ok) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = rb0 + 16 * h + lk + 4 * t;
+          if (i < r1) A[(long long)(p + i) * n + col] = make_double2(dr[h][t], di[h][t]);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void qrl_fill_kernel(const QrArgs args) {
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  const int m = it.g->m, n = it.g->n;
+  double2* A = qrl_ws(it);
+  const long long mn = (long long)m * n;
+  const long long per = (mn + QRL_CHUNKS - 1) / QRL_CHUNKS;
+  const long long e0 = per * blockIdx.x, e1 = min(mn, e0 + per);
+  for (long long idx = e0 + threadIdx.x; idx < e1; idx += 256)
+    A[idx] = make_double2((idx / n == idx % n) ? 1.0 : 0.0, 0.0);
+}
+
+template <int CTO>
+__global__ __launch_bounds__(256) void qrl_store_kernel(const QrArgs args) {
+  using TO = typename St<CTO>::T;
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  const int m = it.g->m, n = it.g->n, mode = it.g->mode;
+  const double2* A = qrl_ws(it);
+  TO* Q = reinterpret_cast<TO*>(const_cast<char*>(item_ptr(it.g->q, it.g->ids, it.item)));
+  const long long mn = (long long)m * n;
+  const long long per = (mn + QRL_CHUNKS - 1) / QRL_CHUNKS;
+  const long long e0 = per * blockIdx.x, e1 = min(mn, e0 + per);
+  for (long long idx = e0 + threadIdx.x; idx < e1; idx += 256) {
+    double2 v;
+    if (mode == 0) {
+      v = A[idx];
+    } else {   // Q^H: out[j][i] = conj(A[i][j]), out stored n x m
+      const long long j = idx / m, i = idx % m;
+      v = cconj(A[i * n + j]);
+    }
+    TO o;
+    o.x = v.x;
+    o.y = v.y;
+    Q[idx] = o;
+  }
+}
+
+template <int RP, int NB, int CTI, int CTO>
+hipError_t run_large(QrArgs args, int items, int n_max, hipStream_t s) {
+  const dim3 chunks(QRL_CHUNKS, items);
+  hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
+  for (int p = 0; p < n_max; p += NB) {
+    hipLaunchKernelGGL((qrl_panel_kernel<RP, NB>), dim3(items), dim3(QRL_NT), 0, s, args, p);
+    const int strips = (n_max - p - NB + 15) / 16;
+    if (strips > 0)
+      hipLaunchKernelGGL((qrl_apply_kernel<NB>), dim3(strips, items), dim3(64 * QRA_NW), 0, s,
+                         args, p, NB, 1);
+  }
+  hipLaunchKernelGGL(qrl_fill_kernel, chunks, dim3(256), 0, s, args);
+  for (int p = ((n_max - 1) / NB) * NB; p >= 0; p -= NB) {
+    const int strips = (n_max - p + 15) / 16;
+    hipLaunchKernelGGL((qrl_apply_kernel<NB>), dim3(strips, items), dim3(64 * QRA_NW), 0, s, args,
+                       p, 0, 0);
+  }
+  hipLaunchKernelGGL((qrl_store_kernel<CTO>), chunks, dim3(256), 0, s, args);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int qr_large_max_rows() { return 2048; }
+
+size_t qr_large_ws_elems(int m, int n) {
+  return 2 * (size_t)m * n + 16 * ((size_t)n + 16) + QRL_CHUNKS / 2 + 1;
+}
+
+hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStream_t s) {
+  QrArgs args = args_in;
+  int items = 0, m_max = 0, n_max = 0;
+  for (int g = 0; g < args.ngroups; ++g) {
+    if (args.g[g].mode == 2 || args.g[g].m < args.g[g].n) return hipErrorInvalidValue;
+    args.g[g].blk_begin = items;
+    items += args.g[g].batch;
+    m_max = max(m_max, args.g[g].m);
+    n_max = max(n_max, args.g[g].n);
+  }
+  if (items == 0) return hipSuccess;
+  if (m_max > qr_large_max_rows()) return hipErrorInvalidValue;
+  const bool wide = m_max <= 1024;   // 2 rows per thread and 16-column panels, else 4 and 8
+#define DCS_QRL(I, O)                                                     \
+  if (ct_in == I && ct_out == O)                                          \
+    return wide ? run_large<2, 16, I, O>(args, items, n_max, s)           \
+                : run_large<4, 8, I, O>(args, items, n_max, s);
+  DCS_QRL(CT_F32, CT_F32)
+  DCS_QRL(CT_F64, CT_F64)
+  DCS_QRL(CT_F64, CT_F32)
+#undef DCS_QRL
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dcs

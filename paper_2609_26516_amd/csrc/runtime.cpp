@@ -56,6 +56,15 @@ std::vector<int> bond_dims(int n, int chi) {
   return d;
 }
 
+// Complex128 workspace elements of one QR item with at most `emax` matrix
+// elements and at most `dmax` columns (rows <= 2 dmax).
+size_t qr_ws_elems(size_t emax, size_t dmax) {
+  size_t w = emax + (dmax / 16 + 2) * 256;
+  if (2 * dmax > (size_t)qr_blocked_max_rows())
+    w = std::max(w, 2 * emax + 16 * (dmax + 16) + 64);
+  return w;
+}
+
 int ctype_of(int precision) { return precision == DCS_C128 ? CT_F64 : CT_F32; }
 size_t csize_of(int ct) { return ct == CT_F32 ? 8 : 16; }
 
@@ -196,7 +205,7 @@ Layout make_layout(int precision, int n, int cap, int chi_max, int wmax, int n_i
   L.o_f = p;
   p += align_up(fmax * L.cs);
   L.o_ws = p;
-  p += align_up(fmax * 16 + (dmax / 16 + 2) * 256 * 16);
+  p += align_up(qr_ws_elems(fmax, dmax) * 16);
   L.o_e = p;
   p += align_up(dmax * dmax * 16);
   L.o_g = p;
@@ -531,47 +540,59 @@ struct QrJob {
   int m, n, mode, batch;
 };
 
-int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& jobs, hipStream_t s) {
-  size_t i = 0;
-  while (i < jobs.size()) {
-    QrArgs args;
-    std::memset(&args, 0, sizeof(args));
-    int ng = 0, blocks = 0;
-    size_t lds = 0;
-    double flops = 0, bytes = 0;
-    for (; i < jobs.size() && ng < QR_MAX_GROUPS; ++i) {
-      const QrJob& j = jobs[i];
-      if (j.batch <= 0) continue;
-      QrGroup& g = args.g[ng++];
-      g.f = j.f;
-      g.q = j.q;
-      g.ws = j.ws;
-      g.nrm2 = j.nrm2;
-      g.ids = j.ids;
-      g.m = j.m;
-      g.n = j.n;
-      g.mode = j.mode;
-      g.batch = j.batch;
-      g.blk_begin = blocks;
-      blocks += j.batch;
-      if (j.mode != 2) lds = std::max(lds, (size_t)j.m * j.n * 16);
-      const double m = j.m, n = j.n;
-      // Householder factorisation + explicit thin Q (complex flops x 8)
-      if (j.mode != 2) flops += 8.0 * (2.0 * m * n * n - 2.0 * n * n * n / 3.0) * j.batch;
-      bytes += (m * n * (csize_of(ct_in) + csize_of(ct_out))) * j.batch;
-    }
-    if (ng == 0) continue;
-    args.ngroups = ng;
-    args.total_blocks = blocks;
-    int m_max = 0;
-    for (int g = 0; g < ng; ++g) m_max = std::max(m_max, args.g[g].mode == 2 ? 0 : args.g[g].m);
-    Timed t(ctx, s, CLS_QR, flops, bytes);
-    if (m_max <= qr_blocked_max_rows()) {
-      args.use_lds = 1;
-      DCS_HIP(launch_qr_blocked(ct_in, ct_out, args, std::max(m_max, 1), s));
-    } else {
-      args.use_lds = (lds > 0 && lds <= qr_lds_limit()) ? 1 : 0;
-      DCS_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+// Path of a QR job: 0 blocked single-workgroup kernel (m <= 512 or mode 2),
+// 1 multi-kernel large-matrix path, 2 unblocked kernel (beyond both).
+int qr_path(const QrJob& j) {
+  if (j.mode == 2 || j.m <= qr_blocked_max_rows()) return 0;
+  return j.m <= qr_large_max_rows() ? 1 : 2;
+}
+
+int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, hipStream_t s) {
+  for (int path = 0; path < 3; ++path) {
+    std::vector<QrJob> jobs;
+    for (const QrJob& j : all)
+      if (j.batch > 0 && qr_path(j) == path) jobs.push_back(j);
+    size_t i = 0;
+    while (i < jobs.size()) {
+      QrArgs args;
+      std::memset(&args, 0, sizeof(args));
+      int ng = 0, blocks = 0;
+      size_t lds = 0;
+      double flops = 0, bytes = 0;
+      for (; i < jobs.size() && ng < QR_MAX_GROUPS; ++i) {
+        const QrJob& j = jobs[i];
+        QrGroup& g = args.g[ng++];
+        g.f = j.f;
+        g.q = j.q;
+        g.ws = j.ws;
+        g.nrm2 = j.nrm2;
+        g.ids = j.ids;
+        g.m = j.m;
+        g.n = j.n;
+        g.mode = j.mode;
+        g.batch = j.batch;
+        g.blk_begin = blocks;
+        blocks += j.batch;
+        if (j.mode != 2) lds = std::max(lds, (size_t)j.m * j.n * 16);
+        const double m = j.m, n = j.n;
+        // Householder factorisation + explicit thin Q (complex flops x 8)
+        if (j.mode != 2) flops += 8.0 * (2.0 * m * n * n - 2.0 * n * n * n / 3.0) * j.batch;
+        bytes += (m * n * (csize_of(ct_in) + csize_of(ct_out))) * j.batch;
+      }
+      args.ngroups = ng;
+      args.total_blocks = blocks;
+      int m_max = 0;
+      for (int g = 0; g < ng; ++g) m_max = std::max(m_max, args.g[g].mode == 2 ? 0 : args.g[g].m);
+      Timed t(ctx, s, CLS_QR, flops, bytes);
+      if (path == 0) {
+        args.use_lds = 1;
+        DCS_HIP(launch_qr_blocked(ct_in, ct_out, args, std::max(m_max, 1), s));
+      } else if (path == 1) {
+        DCS_HIP(launch_qr_large(ct_in, ct_out, args, s));
+      } else {
+        args.use_lds = (lds > 0 && lds <= qr_lds_limit()) ? 1 : 0;
+        DCS_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+      }
     }
   }
   return DCS_OK;
@@ -955,7 +976,7 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
   void* dws = nullptr;
   void* dnrm = nullptr;
   DCS_HIP(hipMalloc(&dg, total * 16));
-  const size_t ws_item = emax * 16 + ((size_t)L.chi_max / 16 + 2) * 256 * 16;
+  const size_t ws_item = align_up(qr_ws_elems(emax, (size_t)chi_cap) * 16);
   hipError_t e = hipMalloc(&dws, ws_item * per_launch);
   if (e == hipSuccess) e = hipMalloc(&dnrm, 64 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(dg, gauss, total * 16, hipMemcpyHostToDevice, s);
@@ -1709,6 +1730,47 @@ int dcs_topk_by_weight(int n, const double* weights, int k, int* keep_idx_out, i
   for (int i = 0; i < keep; ++i) keep_idx_out[i] = order[i];
   *n_keep_out = keep;
   if (discarded_out) *discarded_out = dropped;
+  return DCS_OK;
+}
+
+int dcs_overlap(dcs_state* st, int id_a, int id_b, double* out, void* stream) {
+  if (!st || !out) return fail(DCS_EINVAL, "null argument");
+  const int pair[2] = {id_a, id_b};
+  DCS_TRY(check_ids(st, id_a == id_b ? 1 : 2, pair, true));
+  const Layout& L = st->L;
+  const int ct = L.ct;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Slot& A = st->slots[id_a];
+  const Slot& B = st->slots[id_b];
+  auto site = [&](int id, const Slot& sl, int j) {
+    return local_op(st->slot_base(id) + L.o_mps[sl.cur] + L.site_off[j], 0);
+  };
+  // left transfer E_j[a][b] over bonds j (bra a, ket b), FP64, in slot a's
+  // measurement scratch (its cached left transfer becomes invalid)
+  const Operand E = local_op(st->slot_base(id_a) + L.o_e, 0);
+  const Operand TX = local_op(st->slot_base(id_a) + L.o_tx, 0);
+  for (int j = 0; j < L.n; ++j) {
+    const int dla = A.dims[j], dra = A.dims[j + 1], dlb = B.dims[j], drb = B.dims[j + 1];
+    if (j == 0) {   // E_1 = A_0^H B_0 (left bond of dimension 1)
+      std::vector<GemmJob> g{{site(id_a, A, 0), site(id_b, B, 0), E, nullptr, dra, drb, 2 * dla,
+                              dra, drb, drb, 1}};
+      DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, g, s, CLS_OTHER));
+    } else {        // TX = E_j B_j, E_{j+1} = A_j^H TX over (a, s)
+      std::vector<GemmJob> g1{{E, site(id_b, B, j), TX, nullptr, dla, 2 * drb, dlb, dlb, 2 * drb,
+                               2 * drb, 1}};
+      DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, g1, s, CLS_OTHER));
+      std::vector<GemmJob> g2{{site(id_a, A, j), TX, E, nullptr, dra, drb, 2 * dla, dra, drb, drb,
+                               1}};
+      DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, g2, s, CLS_OTHER));
+    }
+  }
+  double v[2];
+  DCS_HIP(hipMemcpyAsync(v, st->slot_base(id_a) + L.o_e, sizeof(v), hipMemcpyDeviceToHost, s));
+  DCS_HIP(hipStreamSynchronize(s));
+  tune_resolve(st->ctx);
+  st->slots[id_a].ecache_bond = -1;
+  out[0] = v[0];
+  out[1] = v[1];
   return DCS_OK;
 }
 

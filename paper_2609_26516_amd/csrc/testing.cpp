@@ -201,7 +201,7 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
   int rc = upload(ct_in, F, mn, df, s);
   if (rc) return rc;
   T_HIP(hipMalloc(&dq.p, mn * csz(ct_out)));
-  T_HIP(hipMalloc(&dws.p, mn * 16 + ((size_t)n / 16 + 2) * 256 * 16));
+  T_HIP(hipMalloc(&dws.p, std::max(mn + ((size_t)n / 16 + 2) * 256, qr_large_ws_elems(m, n)) * 16));
   T_HIP(hipMalloc(&dn.p, 256));
   QrArgs args;
   std::memset(&args, 0, sizeof(args));
@@ -219,7 +219,11 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
   args.ngroups = 1;
   args.total_blocks = 1;
   const size_t lds = mn * 16;
-  if (use_lds == 2) {   // blocked variant
+  if (use_lds == 3) {   // large-matrix variant
+    if (mode == 2 || m > qr_large_max_rows())
+      return testing_fail(DCS_EINVAL, "the large-matrix QR takes modes 0/1 and m <= 2048");
+    T_HIP(launch_qr_large(ct_in, ct_out, args, s));
+  } else if (use_lds == 2) {   // blocked variant
     if (m > qr_blocked_max_rows()) return testing_fail(DCS_EINVAL, "too many rows for the blocked QR");
     args.use_lds = 1;
     T_HIP(launch_qr_blocked(ct_in, ct_out, args, m, s));

@@ -148,7 +148,7 @@ def test_qr_full_rank(capi, use_lds, m, n):
     assert np.max(np.abs(ql - qn.conj().T)) < 1e-10
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_qr_rank_deficient_and_normalise(capi, variant):
     rng = np.random.default_rng(1)
     m, n = 64, 32
@@ -167,7 +167,7 @@ def test_qr_rank_deficient_and_normalise(capi, variant):
     np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("tiny", [1e-120, 1e-170, 1e-250])
 def test_qr_tiny_noise_columns(capi, mode, tiny, variant):
@@ -193,6 +193,28 @@ def test_qr_tiny_noise_columns(capi, mode, tiny, variant):
     assert np.all(np.isfinite(q))
     np.testing.assert_allclose(gram, np.eye(n), atol=1e-12)
     np.testing.assert_allclose(rec, target, atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n", [(64, 32), (513, 200), (600, 300), (1024, 512), (1030, 515),
+                                 (1500, 700), (2048, 37), (2048, 1024)])
+def test_qr_large_matches_lapack(capi, m, n):
+    """Multi-kernel path for more than 512 rows (16-column panels up to 1024
+    rows, 8-column panels above): same reflectors as LAPACK, so Q agrees
+    element-wise, in both the QR and the LQ layout."""
+    rng = np.random.default_rng(m * 3 + n)
+    f = _rand(rng, m, n)
+    qn, _ = np.linalg.qr(f)
+    q, nrm2 = capi.dcs_test_qr(F64, F64, m, n, 0, 3, f.reshape(-1))
+    q = q.reshape(m, n)
+    assert abs(nrm2 - np.sum(np.abs(f) ** 2)) < 1e-10 * nrm2
+    assert np.max(np.abs(q.conj().T @ q - np.eye(n))) < 1e-12
+    assert np.max(np.abs(q - qn)) < 1e-10
+    g = f.conj().T.copy()
+    ql, _ = capi.dcs_test_qr(F64, F64, m, n, 1, 3, g.reshape(-1))
+    assert np.max(np.abs(ql.reshape(n, m) - qn.conj().T)) < 1e-10
+    # complex64 storage in and out, FP64 inside
+    q32, _ = capi.dcs_test_qr(F32, F32, m, n, 0, 3, f.astype(np.complex64).reshape(-1))
+    assert np.max(np.abs(q32.reshape(m, n) - qn)) < 1e-5
 
 
 def test_tile_shapes_bit_identical(capi):

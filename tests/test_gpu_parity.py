@@ -80,6 +80,7 @@ def _fid_err(a, b):
     (12, 16, 2, 2),     # truncated
     (14, 96, 2, 2),     # several 64-row tiles with a ragged tail
     (17, 130, 2, 2),    # chi not a multiple of the tile, 260-row panels
+    (18, 264, 2, 2),    # 528-row gauge shift on the large-matrix QR path
     (8, 4, 3, 3),       # three sweeps
 ])
 def test_compress_step_parity(eng, prec, n, chi, sweeps, layers):
@@ -128,6 +129,27 @@ def test_measure_and_collapse_parity(eng, prec):
         assert _fid_err(st.export(0), psi) < FE_TOL[prec]
         assert _fid_err(st.export(1), other) < FE_TOL[prec]
         capi.dcs_branch_release(st.h, [1])
+    st.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_overlap_matches_oracle(eng, prec):
+    """<a|b> of two branches with different bond caps by the FP64 transfer
+    contraction, against the oracle's overlap."""
+    capi = _capi()
+    n = 9
+    rng = np.random.default_rng(17)
+    a, _, _ = OM.compress(OM.zero_state(n, 12), OM.chunk_mpo(n, _random_ops(rng, n, 3)),
+                          OM.generic_bra(bra_init_gaussians(n, 12, 3)), 2)
+    b, _, _ = OM.compress(OM.zero_state(n, 8), OM.chunk_mpo(n, _random_ops(rng, n, 3)),
+                          OM.generic_bra(bra_init_gaussians(n, 8, 3)), 2)
+    st = _E().State(eng, prec, n, 2, 12, 4, [12], 3)
+    capi.dcs_import_mps(st.h, 0, 12, a, eng.stream())
+    capi.dcs_import_mps(st.h, 1, 8, b, eng.stream())
+    tol = 1e-12 if prec == "c128" else 1e-6
+    assert abs(capi.dcs_overlap(st.h, 0, 1, eng.stream()) - OM.overlap(a, b)) < tol
+    assert abs(capi.dcs_overlap(st.h, 1, 0, eng.stream()) - OM.overlap(b, a)) < tol
+    assert abs(capi.dcs_overlap(st.h, 0, 0, eng.stream()) - OM.norm_sq(a)) < tol
     st.close()
 
 
