@@ -172,6 +172,23 @@ __device__ __forceinline__ double wave_max_dpp(double v) {
   return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
+// Wave sums of N independent doubles, the DPP stages interleaved across the
+// values; every lane gets every total (same order as wave_sum_dpp).
+template <int N>
+__device__ __forceinline__ void wave_sums_dpp(double (&v)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_d<0xB1>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_d<0x4E>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_d<0x141>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_d<0x140>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    v[q] = (readlane_d(v[q], 0) + readlane_d(v[q], 16)) + (readlane_d(v[q], 32) + readlane_d(v[q], 48));
+}
+
 // (sum, max) over NW waves with the DPP wave reduction; every thread gets
 // both, summed over the waves in a fixed order.
 template <int NW>

@@ -12,9 +12,9 @@
 //              norms and inner products over the workgroup; writes the
 //              explicit V (unit diagonal) and T (zlarft recurrence, Gram
 //              entries v_j^H v_k reduced together with the panel updates)
-//   qrl_apply  A[p:, c:] -= V X (V^H A[p:, c:]) with X = T^H, one 4-wave
-//              workgroup per 16-column strip on FP64 MFMA; the partial
-//              W = V^H A of each wave is summed through LDS
+//   qrl_wpart  W = V^H A[p:, c:] in parts over (16-column strip, 256-row
+//   qrl_update chunk) tiles on FP64 MFMA, then A[p:, c:] -= V X W with
+//              X = T^H, every chunk summing its strip's parts in one order
 // After the last panel A is reset to [I; 0] and the panels are applied in
 // reverse order with X = T, which leaves the thin Q = H_0 ... H_{n-1} [I; 0]
 // in A; qrl_store writes Q (mode 0) or Q^H (mode 1) in the output precision.
@@ -54,7 +54,8 @@ __device__ __forceinline__ double2* qrl_ws(const QrlItem& it) {
   return reinterpret_cast<double2*>(const_cast<char*>(item_ptr(it.g->ws, it.g->ids, it.item)));
 }
 
-// workspace: A (m n), V (m n), T factors (16 (n + 16)), chunk partials
+// workspace: A (m n), V (m n), T factors (16 (n + 16)), |F|^2 chunk partials,
+// then the W parts of the strip updates
 __device__ __forceinline__ double* qrl_partials(double2* ws, int m, int n) {
   return reinterpret_cast<double*>(ws + 2LL * m * n + 16LL * (n + 16));
 }
@@ -88,13 +89,23 @@ __global__ __launch_bounds__(256) void qrl_load_kernel(const QrArgs args) {
 
 // Panel factorisation.  RP rows per thread (rows tid + r QRL_NT), NB panel
 // columns; every loop over columns is unrolled so the panel stays in
-// registers.
+// registers.  Column kk takes one reduction round: with x the entries below
+// the diagonal and v = [1; scal x],
+//   |x|^2, max|x|,  p_c = x^H a_c (c > kk),  q_c = v_c^H x (c < kk)
+// are reduced together, and after the round every thread forms
+//   v^H a_c = a_kk,c + conj(scal) p_c   and   v_c^H v = conj(v_c[kk]) + scal q_c
+// (row kk broadcast through LDS).  The reduction: DPP sums over lane quads,
+// quad partials to LDS, 16 lanes per value sum them and finish with DPP.
 template <int RP, int NB>
 __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, int p) {
+  constexpr int NV = 2 * NB;           // reduced values: |x|^2, p_c / q_c (re, im), spare
+  constexpr int NQ = QRL_NW * 16;      // quad partials per value
+  __shared__ double s_q[NV][NQ];
+  __shared__ double s_fin[NV];
+  __shared__ double s_mx[QRL_NW];
   __shared__ double s_red[2 * QRL_NW];
-  __shared__ double2 s_dot[QRL_NW][NB];
+  __shared__ double2 s_row[NB];
   __shared__ double2 s_T[NB * NB];
-  __shared__ double2 s_alpha;
   const QrlItem it = qrl_item(args, blockIdx.x);
   const int m = it.g->m, n = it.g->n;
   if (p >= n) return;
@@ -124,23 +135,67 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
   static_for<NB>([&](auto kc) {
     constexpr int kk = decltype(kc)::value;
     if (kk >= nbk) return;   // uniform over the workgroup
-    // |x|^2 and max|x| of the column below the diagonal (row kk is thread kk)
-    double sm = 0.0, mx = 0.0;
+    // partial sums over this thread's rows below the diagonal
+    double x[NV];
+    double mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) x[q] = 0.0;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       const int i = tid + r * QRL_NT;
       if (i > kk && i < mp) {
-        const double2 v = a[r][kk];
-        sm += v.x * v.x + v.y * v.y;
-        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+        const double2 xi = a[r][kk];
+        x[0] += xi.x * xi.x + xi.y * xi.y;
+        mx = fmax(mx, fmax(fabs(xi.x), fabs(xi.y)));
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c == kk) continue;
+          // value slots: c > kk -> p_c = x^H a_c, c < kk -> q_c = v_c^H x
+          const double2 w = (c > kk) ? cdotc(xi, a[r][c]) : cdotc(a[r][c], xi);
+          const int slot = 1 + 2 * (c < kk ? c : c - 1);
+          x[slot] += w.x;
+          x[slot + 1] += w.y;
+        }
       }
     }
-    if (tid == kk) s_alpha = a[0][kk];
-    block_sum_max_dpp<QRL_NW>(sm, mx, s_red);
-    double sc = 0.0, q = 0.0;
-    if (mx > 0.0 && (mx < 1e-140 || mx > 1e140)) {
+    // stage 1: lane quads (DPP), quad partials to LDS; max over the wave
+#pragma unroll
+    for (int q = 0; q < NV; ++q) x[q] += dpp_d<0xB1>(x[q]);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) x[q] += dpp_d<0x4E>(x[q]);
+    mx = wave_max_dpp(mx);
+    __syncthreads();   // readers of the previous round (s_row, s_q, s_fin) are done
+    if (tid == kk) {   // row kk: alpha, R entries (c > kk) and v_c[kk] (c < kk)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) s_row[c] = a[0][c];
+    }
+    if ((lane & 3) == 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) s_q[q][wave * 16 + (lane >> 2)] = x[q];
+    }
+    if (lane == 0) s_mx[wave] = mx;
+    __syncthreads();
+    // stage 2: 16 lanes per value, eight quad partials each, then DPP
+    if (tid < NV * 16) {
+      const int q = tid >> 4, sub = tid & 15;
+      double v = 0.0;
+#pragma unroll
+      for (int u = 0; u < NQ / 16; ++u) v += s_q[q][sub * (NQ / 16) + u];
+      v += dpp_d<0xB1>(v);
+      v += dpp_d<0x4E>(v);
+      v += dpp_d<0x141>(v);
+      v += dpp_d<0x140>(v);
+      if (sub == 0) s_fin[q] = v;
+    }
+    __syncthreads();
+    double mxa = 0.0;
+#pragma unroll
+    for (int w = 0; w < QRL_NW; ++w) mxa = fmax(mxa, s_mx[w]);
+    double sc = 0.0, qn = 0.0;
+    if (mxa > 0.0 && (mxa < 1e-140 || mxa > 1e140)) {
+      // squares leave the safe range: scaled second pass (rare, uniform)
       double sm2 = 0.0, dummy = 0.0;
-      const double inv = 1.0 / mx;
+      const double inv = 1.0 / mxa;
 #pragma unroll
       for (int r = 0; r < RP; ++r) {
         const int i = tid + r * QRL_NT;
@@ -150,16 +205,16 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
         }
       }
       block_sum_max_dpp<QRL_NW>(sm2, dummy, s_red);
-      sc = mx;
-      q = sm2;
-    } else if (mx > 0.0) {
+      sc = mxa;
+      qn = sm2;
+    } else if (mxa > 0.0) {
       sc = 1.0;
-      q = sm;
+      qn = s_fin[0];
     }
-    const double2 alpha = s_alpha;
+    const double2 alpha = s_row[kk];
     double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
     if (!(sc == 0.0 && alpha.y == 0.0)) {
-      double sa = sc, qa = q;
+      double sa = sc, qa = qn;
       ssq_add(sa, qa, alpha.x);
       ssq_add(sa, qa, alpha.y);
       const double nrm_all = sa * sqrt(qa);
@@ -169,51 +224,31 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
         scal = crecip(make_double2(alpha.x - beta, alpha.y));
       }
     }
+    // inner products with v = [1; scal x]: v^H a_c (c > kk), v_c^H v (c < kk)
+    auto dval = [&](int c) {
+      const int slot = 1 + 2 * (c < kk ? c : c - 1);
+      const double2 pq = make_double2(s_fin[slot], s_fin[slot + 1]);
+      const double2 rc = s_row[c];
+      if (c > kk) {
+        const double2 u = cmul(cconj(scal), pq);
+        return make_double2(rc.x + u.x, rc.y + u.y);
+      }
+      const double2 u = cmul(scal, pq);
+      return make_double2(rc.x + u.x, -rc.y + u.y);
+    };
     // v below the diagonal (an exact zero reflector when tau = 0)
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       const int i = tid + r * QRL_NT;
       if (i > kk && i < mp) a[r][kk] = cmul(a[r][kk], scal);
     }
-    // s_dot[.][c] = v^H a_c for the panel columns c > kk and v_c^H v for the
-    // earlier reflectors c < kk (Gram column of the T recurrence), one wave
-    // partial per entry
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c == kk || c >= nbk) continue;
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < RP; ++r) {
-        const int i = tid + r * QRL_NT;
-        if (i >= kk && i < mp) {
-          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : a[r][kk];
-          // row i >= kk > c: a[r][c] holds v_c for c < kk
-          const double2 w = (c > kk) ? cdotc(v, a[r][c]) : cdotc(a[r][c], v);
-          acc.x += w.x;
-          acc.y += w.y;
-        }
-      }
-      acc.x = wave_sum_dpp(acc.x);
-      acc.y = wave_sum_dpp(acc.y);
-      if (lane == 0) s_dot[wave][c] = acc;
-    }
-    __syncthreads();
-    auto dot = [&](int c) {
-      double2 acc = s_dot[0][c];
-#pragma unroll
-      for (int w = 1; w < QRL_NW; ++w) {
-        acc.x += s_dot[w][c].x;
-        acc.y += s_dot[w][c].y;
-      }
-      return acc;
-    };
     // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk], T[kk][kk] = tau
     if (tid < kk) {
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         if (t >= tid && t < kk) {
-          const double2 u = cmul(s_T[tid * NB + t], dot(t));
+          const double2 u = cmul(s_T[tid * NB + t], dval(t));
           acc.x += u.x;
           acc.y += u.y;
         }
@@ -223,12 +258,12 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
     } else if (tid == kk) {
       s_T[kk * NB + kk] = tau;
     }
-    // a_c -= v conj(tau) d[c] for the remaining panel columns
+    // a_c -= v conj(tau) (v^H a_c) for the remaining panel columns
     const double2 ctau = cconj(tau);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       if (c > kk && c < nbk) {
-        const double2 cc = cmul(ctau, dot(c));
+        const double2 cc = cmul(ctau, dval(c));
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
           const int i = tid + r * QRL_NT;
@@ -260,61 +295,97 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
   if (tid < NB * NB) Tg[(long long)(p / NB) * NB * NB + tid] = s_T[tid];
 }
 
-// A[p:, c0:c0+16] -= V X (V^H A[p:, c0:c0+16]), X = T^H (conj_t) or T.
-// QRA_NW waves split the rows; global operands are fetched eight k-steps
-// (W) or two row blocks (update) at a time.
-constexpr int QRA_NW = 8;
+// A[p:, c0:c0+16] -= V X (V^H A[p:, c0:c0+16]) with X = T^H (conj_t) or T,
+// in two launches over (16-column strip, QRL_CH-row chunk) tiles so the chip
+// has many waves in flight: qrl_wpart writes each chunk's W = V^H A part,
+// qrl_update sums the parts of its strip in chunk order (the same sum in
+// every chunk of the strip), forms X W and updates its rows.
+constexpr int QRL_CH = 256;   // rows per chunk (four waves of 64)
+
+__device__ __forceinline__ double2* qrl_wparts(double2* ws, int m, int n) {
+  return reinterpret_cast<double2*>(qrl_partials(ws, m, n) + QRL_CHUNKS);
+}
 
 template <int NB>
-__global__ __launch_bounds__(64 * QRA_NW) void qrl_apply_kernel(const QrArgs args, int p,
-                                                                int c_off, int conj_t) {
-  __shared__ double2 sW[QRA_NW][256];
-  const QrlItem it = qrl_item(args, blockIdx.y);
+__global__ __launch_bounds__(256) void qrl_wpart_kernel(const QrArgs args, int p, int c_off) {
+  __shared__ double2 sW[4][256];
+  const QrlItem it = qrl_item(args, blockIdx.z);
   const int m = it.g->m, n = it.g->n;
   const int c0 = p + c_off + 16 * blockIdx.x;
-  if (p >= n || c0 >= n) return;
+  const int mp = m - p;
+  if (p >= n || c0 >= n || (int)blockIdx.y * QRL_CH >= mp) return;
   double2* A = qrl_ws(it);
   const double2* V = A + (long long)m * n;
-  const double2* T = V + (long long)m * n + (long long)(p / NB) * NB * NB;
-  const int mp = m - p, nbk = min(NB, n - p);
+  const int nbk = min(NB, n - p);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int col = c0 + li;
   const bool col_ok = col < n;
-  const int rw = ((mp + 16 * QRA_NW - 1) / (16 * QRA_NW)) * 16;   // rows per wave
-  const int r0 = wave * rw, r1 = min(mp, r0 + rw);
+  const int r0 = blockIdx.y * QRL_CH + wave * 64, r1 = min(mp, r0 + 64);
   const double2 zero = make_double2(0.0, 0.0);
-
-  // partial W = V^H A over this wave's rows
   v4d_t wr, wi;
   zero4(wr);
   zero4(wi);
-  for (int i0 = r0; i0 < r1; i0 += 32) {
-    double2 vv[8], bb[8];
+  double2 vv[16], bb[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + 4 * u + lk;
-      const bool ok = i < r1;
-      vv[u] = (ok && li < nbk) ? V[(long long)(p + i) * n + p + li] : zero;
-      bb[u] = (ok && col_ok) ? A[(long long)(p + i) * n + col] : zero;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cmma(vv[u].x, -vv[u].y, bb[u].x, bb[u].y, wr, wi);
+  for (int u = 0; u < 16; ++u) {
+    const int i = r0 + 4 * u + lk;
+    const bool ok = i < r1;
+    vv[u] = (ok && li < nbk) ? V[(long long)(p + i) * n + p + li] : zero;
+    bb[u] = (ok && col_ok) ? A[(long long)(p + i) * n + col] : zero;
   }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) cmma(vv[u].x, -vv[u].y, bb[u].x, bb[u].y, wr, wi);
 #pragma unroll
   for (int t = 0; t < 4; ++t) sW[wave][(lk + 4 * t) * 16 + li] = make_double2(wr[t], wi[t]);
   __syncthreads();
+  const int e = threadIdx.x;
+  double2 sum = sW[0][e];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    sum.x += sW[w][e].x;
+    sum.y += sW[w][e].y;
+  }
+  const int nchunk = (mp + QRL_CH - 1) / QRL_CH;
+  qrl_wparts(A, m, n)[((long long)blockIdx.x * nchunk + blockIdx.y) * 256 + e] = sum;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int p, int c_off,
+                                                         int conj_t) {
+  __shared__ double2 sW[256];
+  const QrlItem it = qrl_item(args, blockIdx.z);
+  const int m = it.g->m, n = it.g->n;
+  const int c0 = p + c_off + 16 * blockIdx.x;
+  const int mp = m - p;
+  if (p >= n || c0 >= n || (int)blockIdx.y * QRL_CH >= mp) return;
+  double2* A = qrl_ws(it);
+  const double2* V = A + (long long)m * n;
+  const double2* T = V + (long long)m * n + (long long)(p / NB) * NB * NB;
+  const int nbk = min(NB, n - p);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  const bool col_ok = col < n;
+  const double2 zero = make_double2(0.0, 0.0);
+  {
+    const int nchunk = (mp + QRL_CH - 1) / QRL_CH;
+    const double2* parts = qrl_wparts(A, m, n) + (long long)blockIdx.x * nchunk * 256;
+    const int e = threadIdx.x;
+    double2 sum = parts[e];
+    for (int c = 1; c < nchunk; ++c) {
+      sum.x += parts[c * 256 + e].x;
+      sum.y += parts[c * 256 + e].y;
+    }
+    sW[e] = sum;
+  }
+  __syncthreads();
+  v4d_t wr, wi;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int e = (lk + 4 * t) * 16 + li;
-    double2 sum = sW[0][e];
-#pragma unroll
-    for (int w = 1; w < QRA_NW; ++w) {
-      sum.x += sW[w][e].x;
-      sum.y += sW[w][e].y;
-    }
-    wr[t] = sum.x;
-    wi[t] = sum.y;
+    const double2 w = sW[(lk + 4 * t) * 16 + li];
+    wr[t] = w.x;
+    wi[t] = w.y;
   }
   // W2 = X W (result item t = row lk + 4t = the B operand of k-step t)
   v4d_t xr, xi;
@@ -334,36 +405,35 @@ __global__ __launch_bounds__(64 * QRA_NW) void qrl_apply_kernel(const QrArgs arg
     }
     cmma(x.x, x.y, wr[t], wi[t], xr, xi);
   }
-  // A -= V W2, two 16-row blocks at a time
-  for (int rb0 = r0; rb0 < r1; rb0 += 32) {
-    v4d_t dr[2], di[2];
-    double2 vv[2][NB / 4];
+  // this wave's 64 rows: A -= V W2, four 16-row blocks
+  const int r0 = blockIdx.y * QRL_CH + wave * 64, r1 = min(mp, r0 + 64);
+  v4d_t dr[4], di[4];
+  double2 vv[4][NB / 4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int rb = rb0 + 16 * h;
+  for (int h = 0; h < 4; ++h) {
+    const int rb = r0 + 16 * h;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int i = rb + lk + 4 * t;
-        const double2 v = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
-        dr[h][t] = v.x;
-        di[h][t] = v.y;
-      }
-#pragma unroll
-      for (int t = 0; t < NB / 4; ++t) {
-        const int i = rb + li, sref = 4 * t + lk;
-        vv[h][t] = (i < r1 && sref < nbk) ? V[(long long)(p + i) * n + p + sref] : zero;
-      }
+    for (int t = 0; t < 4; ++t) {
+      const int i = rb + lk + 4 * t;
+      const double2 v = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
+      dr[h][t] = v.x;
+      di[h][t] = v.y;
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int t = 0; t < NB / 4; ++t) {
+      const int i = rb + li, sref = 4 * t + lk;
+      vv[h][t] = (i < r1 && sref < nbk) ? V[(long long)(p + i) * n + p + sref] : zero;
+    }
+  }
 #pragma unroll
-      for (int t = 0; t < NB / 4; ++t) cmma(vv[h][t].x, vv[h][t].y, -xr[t], -xi[t], dr[h], di[h]);
-      if (col_ok) {
+  for (int h = 0; h < 4; ++h) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = rb0 + 16 * h + lk + 4 * t;
-          if (i < r1) A[(long long)(p + i) * n + col] = make_double2(dr[h][t], di[h][t]);
-        }
+    for (int t = 0; t < NB / 4; ++t) cmma(vv[h][t].x, vv[h][t].y, -xr[t], -xi[t], dr[h], di[h]);
+    if (col_ok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = r0 + 16 * h + lk + 4 * t;
+        if (i < r1) A[(long long)(p + i) * n + col] = make_double2(dr[h][t], di[h][t]);
       }
     }
   }
@@ -406,22 +476,22 @@ __global__ __launch_bounds__(256) void qrl_store_kernel(const QrArgs args) {
 }
 
 template <int RP, int NB, int CTI, int CTO>
-hipError_t run_large(QrArgs args, int items, int n_max, hipStream_t s) {
+hipError_t run_large(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
   const dim3 chunks(QRL_CHUNKS, items);
   hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
+  auto apply = [&](int p, int c_off, int conj_t) {
+    const int strips = (n_max - p - c_off + 15) / 16;
+    if (strips <= 0) return;
+    const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
+    hipLaunchKernelGGL((qrl_wpart_kernel<NB>), grid, dim3(256), 0, s, args, p, c_off);
+    hipLaunchKernelGGL((qrl_update_kernel<NB>), grid, dim3(256), 0, s, args, p, c_off, conj_t);
+  };
   for (int p = 0; p < n_max; p += NB) {
     hipLaunchKernelGGL((qrl_panel_kernel<RP, NB>), dim3(items), dim3(QRL_NT), 0, s, args, p);
-    const int strips = (n_max - p - NB + 15) / 16;
-    if (strips > 0)
-      hipLaunchKernelGGL((qrl_apply_kernel<NB>), dim3(strips, items), dim3(64 * QRA_NW), 0, s,
-                         args, p, NB, 1);
+    apply(p, NB, 1);
   }
   hipLaunchKernelGGL(qrl_fill_kernel, chunks, dim3(256), 0, s, args);
-  for (int p = ((n_max - 1) / NB) * NB; p >= 0; p -= NB) {
-    const int strips = (n_max - p + 15) / 16;
-    hipLaunchKernelGGL((qrl_apply_kernel<NB>), dim3(strips, items), dim3(64 * QRA_NW), 0, s, args,
-                       p, 0, 0);
-  }
+  for (int p = ((n_max - 1) / NB) * NB; p >= 0; p -= NB) apply(p, 0, 0);
   hipLaunchKernelGGL((qrl_store_kernel<CTO>), chunks, dim3(256), 0, s, args);
   return hipGetLastError();
 }
@@ -431,7 +501,8 @@ hipError_t run_large(QrArgs args, int items, int n_max, hipStream_t s) {
 int qr_large_max_rows() { return 2048; }
 
 size_t qr_large_ws_elems(int m, int n) {
-  return 2 * (size_t)m * n + 16 * ((size_t)n + 16) + QRL_CHUNKS / 2 + 1;
+  const size_t parts = (((size_t)n + 15) / 16) * (((size_t)m + QRL_CH - 1) / QRL_CH) * 256;
+  return 2 * (size_t)m * n + 16 * ((size_t)n + 16) + QRL_CHUNKS / 2 + parts + 1;
 }
 
 hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStream_t s) {
@@ -446,11 +517,11 @@ hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStre
   }
   if (items == 0) return hipSuccess;
   if (m_max > qr_large_max_rows()) return hipErrorInvalidValue;
-  const bool wide = m_max <= 1024;   // 2 rows per thread and 16-column panels, else 4 and 8
+  const bool wide = m_max <= 1024;   // 2 rows per thread and 12-column panels, else 4 and 8
 #define DCS_QRL(I, O)                                                     \
   if (ct_in == I && ct_out == O)                                          \
-    return wide ? run_large<2, 16, I, O>(args, items, n_max, s)           \
-                : run_large<4, 8, I, O>(args, items, n_max, s);
+    return wide ? run_large<2, 12, I, O>(args, items, m_max, n_max, s)    \
+                : run_large<4, 8, I, O>(args, items, m_max, n_max, s);
   DCS_QRL(CT_F32, CT_F32)
   DCS_QRL(CT_F64, CT_F64)
   DCS_QRL(CT_F64, CT_F32)

@@ -61,7 +61,7 @@ std::vector<int> bond_dims(int n, int chi) {
 size_t qr_ws_elems(size_t emax, size_t dmax) {
   size_t w = emax + (dmax / 16 + 2) * 256;
   if (2 * dmax > (size_t)qr_blocked_max_rows())
-    w = std::max(w, 2 * emax + 16 * (dmax + 16) + 64);
+    w = std::max(w, qr_large_ws_elems((int)(2 * dmax), (int)dmax));
   return w;
 }
 
