@@ -208,6 +208,21 @@ int dcs_collapse(dcs_state *st, int n, const int *src_ids, const int *qubits,
                  const int *outcomes, const int *dst_ids, double eps, double *pm_out,
                  void *stream);
 
+/* Measurement, sampling and collapse without a host round trip (Alg. 1 with
+ * the outcome drawn on the device; Sec. IV-B1 probabilities and projection).
+ * For each i: p_0 of branch ids[i] at qubits[i] as in dcs_measure_prob, then
+ * outcome m = 0 if u_dev[i] < p_0 else 1; if p_m <= eps the other outcome
+ * is taken (an event of probability at most eps); the branch is collapsed in
+ * place (slice 1-m zeroed, slice m scaled by 1/sqrt(n_m) in FP64).
+ * u_dev (double[n]), outcome_dev (int[n]) and pm_dev (double[n], p_m) are
+ * device memory.  Enqueued on the stream without host synchronisation; the
+ * caller reads the outcomes when it needs them (e.g. for classical control).
+ * A branch whose norm vanished gets outcome -1, p_m NaN and is left as is.
+ * Errors (checked on the host, before any work): EINVAL, ECAPACITY, ESTATE. */
+int dcs_measure_sample_collapse(dcs_state *st, int n, const int *ids, const int *qubits,
+                                const double *u_dev, double eps, int *outcome_dev,
+                                double *pm_dev, void *stream);
+
 /* Top-M retention (Alg. 2, after a measurement): indices of the k largest of
  * weights[0..n) in descending order, ties in index order (stable), into
  * keep_idx_out (capacity >= min(n, k)); *n_keep_out = min(n, k);

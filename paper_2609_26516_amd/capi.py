@@ -30,7 +30,7 @@ EXPORTED = [
     "dcs_ctx_tuning_load", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
     "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
-    "dcs_compress_step", "dcs_measure_prob", "dcs_collapse", "dcs_topk_by_weight",
+    "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight",
     "dcs_overlap", "dcs_export_mps", "dcs_import_mps",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
@@ -75,6 +75,7 @@ _SIGS = {
     "dcs_chunk_destroy": (c_int, [_P]),
     "dcs_compress_step": (c_int, [_P, c_int, _IP, POINTER(c_void_p), c_int, _DP, _P]),
     "dcs_measure_prob": (c_int, [_P, c_int, _IP, _IP, _DP, _P]),
+    "dcs_measure_sample_collapse": (c_int, [_P, c_int, _IP, _IP, _P, c_double, _P, _P, _P]),
     "dcs_collapse": (c_int, [_P, c_int, _IP, _IP, _IP, _IP, c_double, _DP, _P]),
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
     "dcs_overlap": (c_int, [_P, c_int, c_int, _DP, _P]),
@@ -238,6 +239,15 @@ def dcs_measure_prob(st, ids, qubits, stream) -> np.ndarray:
     p0 = np.zeros(len(i), dtype=np.float64)
     _check(_lib.dcs_measure_prob(st, len(i), _ip(i), _ip(q), _dp(p0), stream))
     return p0
+
+
+def dcs_measure_sample_collapse(st, ids, qubits, u_dev: int, eps: float, outcome_dev: int,
+                                pm_dev: int, stream) -> None:
+    """Device pointers: u_dev (float64[n]), outcome_dev (int32[n]), pm_dev
+    (float64[n]); nothing is synchronised."""
+    i, q = _ints(ids), _ints(qubits)
+    _check(_lib.dcs_measure_sample_collapse(st, len(i), _ip(i), _ip(q), u_dev, eps, outcome_dev,
+                                            pm_dev, stream))
 
 
 def dcs_collapse(st, src_ids, qubits, outcomes, dst_ids, eps, stream) -> np.ndarray:

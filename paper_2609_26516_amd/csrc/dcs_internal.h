@@ -137,6 +137,19 @@ struct CollapseItem {
 hipError_t launch_collapse(int ct, const CollapseItem* items_dev, int n_items, int max_elems,
                            hipStream_t s);
 
+// Device-side sampling and collapse of site tensor A[dl][2][dr]: with
+// (n_0, n_1) = norms[2k], [2k + 1] and u = u[idx], outcome m = (u >= p_0),
+// switched to the other outcome if p_m <= eps; slice 1-m zeroed, slice m
+// scaled by 1/sqrt(n_m) (FP64); outcome[idx] = m, pm[idx] = p_m (pm NaN and
+// outcome -1, tensor untouched, when n_0 + n_1 is not positive and finite).
+struct SampleItem {
+  void* a;
+  int dl, dr, k, idx;
+};
+hipError_t launch_sample_collapse(int ct, const SampleItem* items_dev, int n_items, int max_elems,
+                                  const double* norms, const double* u, double eps, int* outcome,
+                                  double* pm, hipStream_t s);
+
 // Writes (1, 0), (0, 0) as two complex words at each listed address.
 hipError_t launch_fill_unit(int ct, void* const* ptrs_dev, int n, hipStream_t s);
 

@@ -753,6 +753,43 @@ __global__ __launch_bounds__(NT) void collapse_kernel(const CollapseItem* items)
   drop = z;
 }
 
+// Sampling and collapse on the device: every block derives the outcome from
+// the same FP64 norms and uniform, so all blocks of an item agree.
+template <int CT>
+__global__ __launch_bounds__(NT) void sample_collapse_kernel(const SampleItem* items,
+                                                             const double* norms, const double* u,
+                                                             double eps, int* outcome, double* pm) {
+  using T = typename St<CT>::T;
+  const SampleItem it = items[blockIdx.y];
+  const double n0 = norms[2 * it.k], n1 = norms[2 * it.k + 1];
+  const double tot = n0 + n1;
+  const bool ok = tot > 0.0 && isfinite(tot);
+  int m = (ok && u[it.idx] >= n0 / tot) ? 1 : 0;
+  if (ok && !((m ? n1 : n0) / tot > eps)) m = 1 - m;
+  const double nm = m ? n1 : n0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    outcome[it.idx] = ok ? m : -1;
+    pm[it.idx] = ok ? nm / tot : __builtin_nan("");
+  }
+  if (!ok) return;
+  const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
+  const long long total = (long long)it.dl * it.dr;
+  if (idx >= total) return;
+  const int a = (int)(idx / it.dr), b = (int)(idx % it.dr);
+  T* A = reinterpret_cast<T*>(it.a);
+  const double sc = 1.0 / sqrt(nm);
+  T& keep = A[((long long)a * 2 + m) * it.dr + b];
+  T& drop = A[((long long)a * 2 + (1 - m)) * it.dr + b];
+  T k = keep;
+  k.x = (double)k.x * sc;
+  k.y = (double)k.y * sc;
+  keep = k;
+  T z;
+  z.x = 0;
+  z.y = 0;
+  drop = z;
+}
+
 // Writes the complex pair (1, 0) at each listed address: the 1 x 2 x 1 site
 // tensor of |0>, or a 1 x 1 x 1 boundary environment (its second word is
 // alignment padding).
@@ -873,6 +910,20 @@ hipError_t launch_collapse(int ct, const CollapseItem* items_dev, int n_items, i
     hipLaunchKernelGGL((collapse_kernel<CT_F32>), grid, blk, 0, s, items_dev);
   else
     hipLaunchKernelGGL((collapse_kernel<CT_F64>), grid, blk, 0, s, items_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_collapse(int ct, const SampleItem* items_dev, int n_items, int max_elems,
+                                  const double* norms, const double* u, double eps, int* outcome,
+                                  double* pm, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const dim3 grid((max(max_elems, 1) + NT - 1) / NT, n_items), blk(NT);
+  if (ct == CT_F32)
+    hipLaunchKernelGGL((sample_collapse_kernel<CT_F32>), grid, blk, 0, s, items_dev, norms, u, eps,
+                       outcome, pm);
+  else
+    hipLaunchKernelGGL((sample_collapse_kernel<CT_F64>), grid, blk, 0, s, items_dev, norms, u, eps,
+                       outcome, pm);
   return hipGetLastError();
 }
 

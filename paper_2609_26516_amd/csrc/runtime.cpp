@@ -257,10 +257,24 @@ struct dcs_state {
   std::map<std::string, hipGraphExec_t> graphs;
   std::map<std::string, int> graph_seen;
   hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's
+  // pinned host staging for uploads of calls that return without
+  // synchronising: a ring of buffers, each reused once its last copy is done
+  static constexpr int PIN_RING = 4;
+  void* pin_buf[PIN_RING] = {};
+  size_t pin_bytes[PIN_RING] = {};
+  hipEvent_t pin_done[PIN_RING] = {};
+  int pin_next = 0;
 
   ~dcs_state() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (int k = 0; k < PIN_RING; ++k) {
+      if (pin_done[k]) {
+        (void)hipEventSynchronize(pin_done[k]);
+        (void)hipEventDestroy(pin_done[k]);
+      }
+      if (pin_buf[k]) (void)hipHostFree(pin_buf[k]);
+    }
   }
 
   char* slot_base(int id) const { return base + L.o_slots + L.slot_stride * (size_t)id; }
@@ -1471,17 +1485,38 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
 // ---------------------------------------------------------------------------
 // Measurement probability
 
-int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, double* p0_out,
-                     void* stream) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  DCS_TRY(check_ids(st, n, ids, true));
-  if (n == 0) return DCS_OK;
-  if (!qubits || !p0_out) return fail(DCS_EINVAL, "null qubits or p0_out");
+namespace {
+
+// Host -> device copy through the state's pinned ring, ordered on stream s;
+// the source may be released as soon as this returns.
+int stage_h2d(dcs_state* st, hipStream_t s, void* dst, const void* src, size_t bytes) {
+  const int k = st->pin_next;
+  st->pin_next = (k + 1) % dcs_state::PIN_RING;
+  if (st->pin_done[k]) {
+    DCS_HIP(hipEventSynchronize(st->pin_done[k]));
+  } else {
+    DCS_HIP(hipEventCreateWithFlags(&st->pin_done[k], hipEventDisableTiming));
+  }
+  if (st->pin_bytes[k] < bytes) {
+    if (st->pin_buf[k]) DCS_HIP(hipHostFree(st->pin_buf[k]));
+    st->pin_buf[k] = nullptr;
+    st->pin_bytes[k] = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    DCS_HIP(hipHostMalloc(&st->pin_buf[k], want, hipHostMallocDefault));
+    st->pin_bytes[k] = want;
+  }
+  std::memcpy(st->pin_buf[k], src, bytes);
+  DCS_HIP(hipMemcpyAsync(dst, st->pin_buf[k], bytes, hipMemcpyHostToDevice, s));
+  DCS_HIP(hipEventRecord(st->pin_done[k], s));
+  return DCS_OK;
+}
+
+// Enqueues the outcome norms (n_0, n_1) of branch ids[i] at qubits[i] into
+// the state's output area, FP64, at position pos[i] (branches grouped by
+// shape).  Arguments are checked by the caller.
+int enqueue_norms(dcs_state* st, int n, const int* ids, const int* qubits, hipStream_t s,
+                  std::vector<int>& pos) {
   const Layout& L = st->L;
-  const int nq = L.n;
-  for (int i = 0; i < n; ++i)
-    if (qubits[i] < 0 || qubits[i] >= nq) return fail(DCS_EINVAL, "qubit out of range");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int ct = L.ct;
 
   struct MGroup {
@@ -1525,7 +1560,7 @@ int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, do
     for (int i : g.members) ids_host.push_back(ids[i]);
   }
   int* ids_dev = reinterpret_cast<int*>(st->base + L.o_ids);
-  DCS_HIP(hipMemcpyAsync(ids_dev, ids_host.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  DCS_TRY(stage_h2d(st, s, ids_dev, ids_host.data(), sizeof(int) * n));
   for (auto& g : groups) g.ids_dev = ids_dev + g.goff;
   double* out_dev = reinterpret_cast<double*>(st->base + L.o_out);
 
@@ -1605,25 +1640,92 @@ int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, do
       if (e_nontrivial) sl.ecache_bond = q;
     }
   }
+  pos.assign(n, 0);
+  int k = 0;
+  for (auto& g : groups)
+    for (int i : g.members) pos[i] = k++;
+  return DCS_OK;
+}
+
+int check_measure_args(dcs_state* st, int n, const int* ids, const int* qubits) {
+  if (!st) return fail(DCS_EINVAL, "null state");
+  DCS_TRY(check_ids(st, n, ids, true));
+  if (n > 0 && !qubits) return fail(DCS_EINVAL, "null qubits");
+  for (int i = 0; i < n; ++i)
+    if (qubits[i] < 0 || qubits[i] >= st->L.n) return fail(DCS_EINVAL, "qubit out of range");
+  return DCS_OK;
+}
+
+}  // namespace
+
+int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, double* p0_out,
+                     void* stream) {
+  DCS_TRY(check_measure_args(st, n, ids, qubits));
+  if (n == 0) return DCS_OK;
+  if (!p0_out) return fail(DCS_EINVAL, "null p0_out");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int> pos;
+  DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
+  const double* out_dev = reinterpret_cast<const double*>(st->base + st->L.o_out);
   std::vector<double> nm(2 * n);
   DCS_HIP(hipMemcpyAsync(nm.data(), out_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
   DCS_HIP(hipStreamSynchronize(s));
   tune_resolve(st->ctx);
-  int k = 0;
-  for (auto& g : groups)
-    for (int i : g.members) {
-      Slot& sl = st->slots[ids[i]];
-      sl.n0 = nm[2 * k];
-      sl.n1 = nm[2 * k + 1];
-      sl.measured_q = qubits[i];
-      ++k;
-      const double tot = sl.n0 + sl.n1;
-      if (!(tot > 0.0) || !std::isfinite(tot)) {
-        sl.measured_q = -1;
-        return fail(DCS_ENUMERIC, "state norm vanished or is not finite");
-      }
-      p0_out[i] = sl.n0 / tot;
+  for (int i = 0; i < n; ++i) {
+    Slot& sl = st->slots[ids[i]];
+    sl.n0 = nm[2 * pos[i]];
+    sl.n1 = nm[2 * pos[i] + 1];
+    sl.measured_q = qubits[i];
+    const double tot = sl.n0 + sl.n1;
+    if (!(tot > 0.0) || !std::isfinite(tot)) {
+      sl.measured_q = -1;
+      return fail(DCS_ENUMERIC, "state norm vanished or is not finite");
     }
+    p0_out[i] = sl.n0 / tot;
+  }
+  return DCS_OK;
+}
+
+int dcs_measure_sample_collapse(dcs_state* st, int n, const int* ids, const int* qubits,
+                                const double* u_dev, double eps, int* outcome_dev,
+                                double* pm_dev, void* stream) {
+  DCS_TRY(check_measure_args(st, n, ids, qubits));
+  if (n == 0) return DCS_OK;
+  if (!u_dev || !outcome_dev || !pm_dev) return fail(DCS_EINVAL, "null device array");
+  if (!(eps >= 0.0 && eps < 0.5)) return fail(DCS_EINVAL, "eps must be in [0, 0.5)");
+  const Layout& L = st->L;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int> pos;
+  DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
+  std::vector<SampleItem> items(n);
+  int max_elems = 0;
+  for (int i = 0; i < n; ++i) {
+    const Slot& sl = st->slots[ids[i]];
+    const int q = qubits[i];
+    items[i].a = st->slot_base(ids[i]) + L.o_mps[sl.cur] + L.site_off[q];
+    items[i].dl = sl.dims[q];
+    items[i].dr = sl.dims[q + 1];
+    items[i].k = pos[i];
+    items[i].idx = i;
+    max_elems = std::max(max_elems, sl.dims[q] * sl.dims[q + 1]);
+  }
+  SampleItem* items_dev = reinterpret_cast<SampleItem*>(st->base + L.o_items);
+  DCS_TRY(stage_h2d(st, s, items_dev, items.data(), sizeof(SampleItem) * n));
+  {
+    Timed t(st->ctx, s, CLS_MEAS, 0, 0);
+    DCS_HIP(launch_sample_collapse(L.ct, items_dev, n, max_elems,
+                                   reinterpret_cast<const double*>(st->base + L.o_out), u_dev, eps,
+                                   outcome_dev, pm_dev, s));
+  }
+  // the collapsed site breaks the canonical forms around it, whatever the outcome
+  for (int i = 0; i < n; ++i) {
+    Slot& sl = st->slots[ids[i]];
+    const int q = qubits[i];
+    sl.lc_end = std::min(sl.lc_end, q);
+    sl.rc_start = std::max(sl.rc_start, q + 1);
+    if (sl.ecache_bond > q) sl.ecache_bond = -1;
+    sl.measured_q = -1;
+  }
   return DCS_OK;
 }
 

@@ -148,13 +148,24 @@ class State:
 
 def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int, k: int,
                     n_sweeps: int = 2, uniforms: Optional[np.ndarray] = None,
-                    outcomes: Optional[np.ndarray] = None) -> Dict:
+                    outcomes: Optional[np.ndarray] = None, device_sampling: bool = False) -> Dict:
     """Alg. 1 for `shots` independent trajectories advanced in lockstep.
 
     Outcome of measurement i of shot s: outcomes[s, i] when given (replay),
     else 0 if uniforms[s, i] < p_0 and 1 otherwise.  Chunks of all shots that
-    are due at the same operation are compressed in one batched call."""
+    are due at the same operation are compressed in one batched call.  With
+    device_sampling the draw and the collapse happen on the GPU
+    (dcs_measure_sample_collapse); only the outcomes come back, for the
+    classical register (p_0 is then not reported: NaN)."""
     stream = eng.stream()
+    if device_sampling:
+        if uniforms is None:
+            raise ValueError("device sampling draws from given uniforms")
+        dev = torch.device("cuda", eng.device)
+        u_dev = torch.tensor(np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).T),
+                             device=dev)
+        m_dev = torch.empty(u_dev.shape, dtype=torch.int32, device=dev)
+        pm_dev = torch.empty(u_dev.shape, dtype=torch.float64, device=dev)
     ids = np.array(st.alloc(shots), dtype=np.int32)
     capi.dcs_branch_init_zero(st.h, ids, np.full(shots, chi), stream)
     regs = np.zeros((shots, max(circ.n_bits, 1)), dtype=np.int8)
@@ -181,12 +192,22 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
             if isinstance(op, Measure):
                 compress(np.array([s for s in range(shots) if chunk[s]], dtype=np.int64))
                 q = np.full(shots, op.qubit)
-                p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
-                if outcomes is not None:
-                    m = np.asarray(outcomes[:, i_meas], dtype=np.int32)
+                if device_sampling:
+                    capi.dcs_measure_sample_collapse(st.h, ids, q, u_dev[i_meas].data_ptr(),
+                                                     EPS_BRANCH, m_dev[i_meas].data_ptr(),
+                                                     pm_dev[i_meas].data_ptr(), stream)
+                    m = m_dev[i_meas].cpu().numpy()
+                    pm = pm_dev[i_meas].cpu().numpy()
+                    if np.any(m < 0):
+                        raise capi.DcsError(capi.DCS_ENUMERIC, "state norm vanished")
+                    p0 = np.full(shots, np.nan)
                 else:
-                    m = (uniforms[:, i_meas] >= p0).astype(np.int32)
-                pm = capi.dcs_collapse(st.h, ids, q, m, ids, EPS_BRANCH, stream)
+                    p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+                    if outcomes is not None:
+                        m = np.asarray(outcomes[:, i_meas], dtype=np.int32)
+                    else:
+                        m = (uniforms[:, i_meas] >= p0).astype(np.int32)
+                    pm = capi.dcs_collapse(st.h, ids, q, m, ids, EPS_BRANCH, stream)
                 p *= pm
                 regs[:, op.bit] = m
                 rec_out.append(m.copy())

@@ -221,6 +221,48 @@ def test_batched_shots_replay(eng, prec):
     st.close()
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_device_sampling_matches_host(eng, prec):
+    """Outcome drawn and collapse applied on the GPU from the same uniforms:
+    same outcomes, branch weights and final states as the host-side draw."""
+    circ, prm = C.workload("cfg4_n24_chi64_x1024", n=12, depth=6, chi=16)
+    n, chi, shots = 12, 16, 6
+    k = C.segment_max(circ)
+    u = np.stack([shot_uniforms(prm["seed"], s, circ.n_measurements()) for s in range(shots)])
+    runs = []
+    for dev in (False, True):
+        st = _E().State(eng, prec, n, shots, chi, 4, [chi], prm["init_seed"])
+        r = _E().run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u, device_sampling=dev)
+        runs.append((r, [st.export(int(i)) for i in r["ids"]]))
+        st.close()
+    (rh, mh), (rd, md) = runs
+    np.testing.assert_array_equal(rd["outcomes"], rh["outcomes"])
+    np.testing.assert_allclose(rd["p"], rh["p"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(rd["F"], rh["F"], rtol=1e-12, atol=0)
+    for a, b in zip(md, mh):
+        assert _fid_err(a, b) < 1e-12
+
+
+def test_device_sampling_refuses_impossible_outcome(eng):
+    """p_1 = 0 on |0...0>: a uniform of 1.0 would pick outcome 1; the device
+    draw takes the only possible outcome instead."""
+    import torch
+    capi = _capi()
+    st = _E().State(eng, "c128", 4, 1, 4, 4, [4], 1)
+    capi.dcs_branch_init_zero(st.h, [0], [4], eng.stream())
+    u = torch.ones(1, dtype=torch.float64, device="cuda")
+    m = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    pm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    capi.dcs_measure_sample_collapse(st.h, [0], [2], u.data_ptr(), 1e-10, m.data_ptr(),
+                                     pm.data_ptr(), eng.stream())
+    assert int(m.item()) == 0 and float(pm.item()) == 1.0
+    with pytest.raises(capi.DcsError) as e:
+        capi.dcs_measure_sample_collapse(st.h, [0], [2], u.data_ptr(), 0.7, m.data_ptr(),
+                                         pm.data_ptr(), eng.stream())
+    assert e.value.code == capi.DCS_EINVAL
+    st.close()
+
+
 def test_teleport_and_ghz_multi_path(eng):
     E = _E()
     st = E.State(eng, "c128", 3, 16, 2, 4, [2], 7)
