@@ -2,10 +2,22 @@
 // addressing, complex arithmetic, scaled sums of squares and reductions.
 #pragma once
 
+#include <utility>
+
 #include "dcs_internal.h"
 
 namespace dcs {
 namespace {
+
+// f(std::integral_constant<int, k>) for k = 0 .. N-1, expanded at compile time
+template <typename Fn, int... K>
+__device__ __forceinline__ void static_for_impl(Fn&& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <int CT>
 struct St;

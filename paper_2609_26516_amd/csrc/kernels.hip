@@ -4,6 +4,7 @@
 // the collapse of a site tensor.
 #include "dcs_internal.h"
 #include "kernel_util.h"
+#include "qr_panel.h"
 
 namespace dcs {
 namespace {
@@ -316,20 +317,28 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
 
 // ---------------------------------------------------------------------------
 // Blocked FP64 Householder QR with explicit thin Q (same reflectors as the
-// unblocked kernel above).  One workgroup per matrix; the m x n working
-// matrix is row-major in the branch's global workspace.  16-column panels are
-// factored in LDS (rows of the panel swizzled so column walks and MFMA operand
-// fetches are free of bank conflicts); each panel's reflectors are combined
-// into the compact WY form H_0 ... H_15 = I - V T V^H; the trailing columns
-// are updated with FP64 MFMA (v_mfma_f64_16x16x4) in 16-column sub-strips,
-// one sub-strip per wave: W = V^H A, W2 = T^H W (both kept in the MFMA result
-// registers, whose layout is the next product's B-operand layout),
-// A -= V W2.  Q is then accumulated backwards panel by panel in place.
+// unblocked kernel above), one workgroup per matrix of at most 512 rows; the
+// m x n working matrix is row-major in the branch's global workspace.  Per
+// 16-column panel:
+//   * the panel rows go to registers, one row per thread, and are factored
+//     there (factor_panel: one workgroup reduction round per column; the T
+//     factor of the compact WY form H_p ... H_{p+15} = I - V T V^H from the
+//     Gram entries gathered in the same rounds);
+//   * V goes to LDS (rows swizzled against bank conflicts) and every wave
+//     copies the rows it owns into registers in the two MFMA operand layouts
+//     it needs;
+//   * the trailing columns are updated 16 at a time by the whole workgroup:
+//     each wave loads its rows of the strip once, forms its part of
+//     W = V^H A on FP64 MFMA (v_mfma_f64_16x16x4), the parts are summed
+//     through LDS in a fixed order, W2 = T^H W, and each wave writes its rows
+//     of A - V W2 from the same registers: one read and one write of the
+//     trailing matrix per panel.
+// Q is then accumulated backwards panel by panel in place, the same way with
+// X = T, after the panel's own columns [I; 0] - V (T V1^H).
 
 constexpr int QB = 16;
 
 __device__ __forceinline__ int pidx(int i, int c) { return i * QB + (c ^ (i & 15)); }
-
 
 // Reflector r of the panel at local row i: 0 above the diagonal, 1 on it.
 __device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, int nbk) {
@@ -338,107 +347,121 @@ __device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, 
   return P[pidx(i, r)];
 }
 
+// NTQ threads per workgroup: 512 (8 waves, one workgroup per CU) for up to
+// 512 rows, 256 (4 waves, two per CU) for up to 128 rows; wave w owns rows
+// [w rw, (w + 1) rw) below the panel top, at most MAXB blocks of 16.
+// Dynamic LDS: the panel's V for up to PROWS rows (also holding the panel
+// factorisation scratch before V is written), then one W part per wave
+// (also holding T while the panel is factored).
+template <int NTQ>
+struct QrShape {
+  static constexpr int NW = NTQ / 64;
+  static constexpr int MAXB = NTQ == 512 ? 4 : 2;
+  static constexpr int PROWS = NTQ == 512 ? 512 : 128;
+  static constexpr size_t P_BYTES = (size_t)PROWS * QB * sizeof(double2);
+  static constexpr size_t LDS_BYTES = P_BYTES + (size_t)NW * 256 * sizeof(double2);
+  static_assert(sizeof(PanelSmem<NW, QB>) <= P_BYTES, "factorisation scratch fits the panel area");
+};
 
-// Apply (I - V X V^H) to the 16-column sub-strip at global column c0 of rows
-// p..m-1 of the row-major matrix A (leading dimension n), X = T^H (conjT) or
-// T.  Executed by one wave; global operands are fetched one block ahead.
-template <int U>   // k-steps (4 rows each) per fetch block
-__device__ void apply_block(double2* __restrict__ A, int n, int p, int mp, int nbk, int c0,
-                            const double2* P, const double2* sT, bool conjT, int lane) {
+// Columns c_begin..n-1 of rows p + [r0, r1) of A: A -= V X (V^H A) with
+// X[li][4t + lk] = xv[t] (T^H or T), strips of 16 columns.  Both V operands
+// come from the panel in LDS; the waves' W parts are summed through Wp in a
+// fixed order.  Every thread of the workgroup takes part.
+template <int NTQ>
+__device__ __forceinline__ void update_strips(double2* __restrict__ A, int n, int p, int mp,
+                                              int nbk, int r0, int r1, int c_begin,
+                                              const double2* P, const double2 (&xv)[4],
+                                              double2* Wp) {
+  constexpr int NW = QrShape<NTQ>::NW, MAXB = QrShape<NTQ>::MAXB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int col = c0 + li;
-  const bool col_ok = col < n;
-  v4d_t wr, wi;
-  zero4(wr);
-  zero4(wi);
-  // W = V^H A_sub  (16 x 16): k runs over the panel rows
-  double2 bc[U], bn[U];
-  auto load_b = [&](double2* b, int i0) {
+  const double2 zero = make_double2(0.0, 0.0);
+  for (int c0 = c_begin; c0 < n; c0 += 16) {
+    const int col = c0 + li;
+    const bool ok = col < n;
+    // row r0 + lk of the strip; the other rows are wave-uniform offsets
+    double2* __restrict__ Arow = A + (long long)(p + r0 + lk) * n + col;
+    double2 a[MAXB][4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + 4 * u + lk;
-      b[u] = (i < mp && col_ok) ? A[(long long)(p + i) * n + col] : make_double2(0.0, 0.0);
-    }
-  };
-  load_b(bc, 0);
-  for (int i0 = 0; i0 < mp; i0 += 4 * U) {
-    if (i0 + 4 * U < mp) load_b(bn, i0 + 4 * U);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double2 v = vval(P, i0 + 4 * u + lk, li, mp, nbk);
-      cmma(v.x, -v.y, bc[u].x, bc[u].y, wr, wi);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) bc[u] = bn[u];
-  }
-  // W2 = X W; W's result item t holds row lk + 4t = the B operand of k-step t
-  v4d_t xr, xi;
-  zero4(xr);
-  zero4(xi);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int s = 4 * t + lk;
-    double2 a;
-    if (conjT) {
-      const double2 tt = sT[s * QB + li];   // X[li][s] = conj(T[s][li])
-      a = make_double2(tt.x, -tt.y);
-    } else {
-      a = sT[li * QB + s];                  // X[li][s] = T[li][s]
-    }
-    cmma(a.x, a.y, wr[t], wi[t], xr, xi);
-  }
-  // A_sub -= V W2, 16 rows at a time
-  double2 ac[4], an[4];
-  auto load_a = [&](double2* a, int rb) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i = rb + lk + 4 * t;
-      a[t] = (i < mp && col_ok) ? A[(long long)(p + i) * n + col] : make_double2(0.0, 0.0);
-    }
-  };
-  load_a(ac, 0);
-  for (int rb = 0; rb < mp; rb += 16) {
-    if (rb + 16 < mp) load_a(an, rb + 16);
-    v4d_t dr, di;
-    zero4(dr);
-    zero4(di);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double2 v = vval(P, rb + li, 4 * t + lk, mp, nbk);
-      cmma(v.x, v.y, xr[t], xi[t], dr, di);
-    }
-    if (col_ok) {
+    for (int b = 0; b < MAXB; ++b)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int i = rb + lk + 4 * t;
-        if (i < mp) A[(long long)(p + i) * n + col] = make_double2(ac[t].x - dr[t], ac[t].y - di[t]);
+        const int i = r0 + 16 * b + lk + 4 * t;
+        a[b][t] = (i < r1 && ok) ? Arow[(16 * b + 4 * t) * n] : zero;
       }
+    v4d_t wr, wi;
+    zero4(wr);
+    zero4(wi);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = r0 + 16 * b + 4 * t + lk;
+        const double2 v = i < r1 ? vval(P, i, li, mp, nbk) : zero;   // A operand conj(V[i][li])
+        cmma(v.x, -v.y, a[b][t].x, a[b][t].y, wr, wi);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the LDS operand reads block by block
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) ac[t] = an[t];
+    for (int r = 0; r < 4; ++r) Wp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(wr[r], wi[r]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = (lk + 4 * r) * 16 + li;
+      double2 sum = Wp[e];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        sum.x += Wp[w * 256 + e].x;
+        sum.y += Wp[w * 256 + e].y;
+      }
+      wr[r] = sum.x;
+      wi[r] = sum.y;
+    }
+    __syncthreads();   // every wave has its W before the next strip's parts
+    // W2 = X W (result item t = row lk + 4t = the B operand of k-step t)
+    v4d_t xr, xi;
+    zero4(xr);
+    zero4(xi);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cmma(xv[t].x, xv[t].y, wr[t], wi[t], xr, xi);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      v4d_t dr, di;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        dr[t] = a[b][t].x;
+        di[t] = a[b][t].y;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = r0 + 16 * b + li;   // A operand V[i][4t + lk]
+        const double2 v = i < r1 ? vval(P, i, 4 * t + lk, mp, nbk) : zero;
+        cmma(v.x, v.y, -xr[t], -xi[t], dr, di);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (ok) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = r0 + 16 * b + lk + 4 * t;
+          if (i < r1) Arow[(16 * b + 4 * t) * n] = make_double2(dr[t], di[t]);
+        }
+      }
+    }
   }
 }
 
-
-// NTQ threads per workgroup: 512 (8 waves, one workgroup per CU) for the
-// large panels, 256 (4 waves, registers capped so two fit on a CU) for
-// matrices of at most 128 rows.
-template <int NTQ>
-struct QrWaves {
-  static constexpr int value = NTQ / 64;
-};
-
 template <int CTI, int CTO, int NTQ>
 __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(const QrArgs args) {
-  constexpr int NWQ = QrWaves<NTQ>::value;
+  using Shape = QrShape<NTQ>;
+  constexpr int NW = Shape::NW;
   using TI = typename St<CTI>::T;
   using TO = typename St<CTO>::T;
-  extern __shared__ double2 P[];          // panel, rows p..m-1, swizzled
-  __shared__ double2 sT[QB * QB];
-  __shared__ double2 sG[QB * QB];
-  __shared__ double2 s_tau[QB];
-  __shared__ double s_red[2 * NWQ];
-  __shared__ double2 s_bc[2];
+  extern __shared__ __attribute__((aligned(16))) double2 dyn[];
+  PanelSmem<NW, QB>& psm = *reinterpret_cast<PanelSmem<NW, QB>*>(dyn);
+  double* s_red = reinterpret_cast<double*>(dyn);       // start of the kernel only
+  double2* P = dyn;
+  double2* Wp = dyn + Shape::P_BYTES / sizeof(double2);
+  double2* sT = Wp;                                     // while a panel is factored
 
   const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
   const QrGroup& G = args.g[gi];
@@ -474,7 +497,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
     }
   }
   double nu2 = part, nu_mx = 0.0;
-  block_sum_max<NWQ>(nu2, nu_mx, s_red);
+  block_sum_max<NW>(nu2, nu_mx, s_red);
   if (tid == 0) *nrm = nu2;
   if (mode == 2) {
     const double sc = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0;
@@ -489,163 +512,62 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
   }
   __syncthreads();
 
+  const int li = lane & 15, lk = lane >> 4;
   const int npan = (n + QB - 1) / QB;
   for (int pi = 0; pi < npan; ++pi) {
     const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
-    // panel -> LDS
-    for (int e = tid; e < mp * QB; e += NTQ) {
-      const int i = e / QB, c = e % QB;
-      P[pidx(i, c)] = (c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    // unblocked factorisation of the panel
-    for (int kk = 0; kk < nbk; ++kk) {
-      // |x|^2 and max|x| in one pass; a scaled second pass only when the
-      // entries leave the range where squares neither underflow nor overflow
-      double sm = 0.0, mx = 0.0;
-      for (int i = kk + 1 + tid; i < mp; i += NTQ) {
-        const double2 v = P[pidx(i, kk)];
-        sm += v.x * v.x + v.y * v.y;
-        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-      }
-      block_sum_max<NWQ>(sm, mx, s_red);
-      double sc = 0.0, q = 0.0;
-      if (mx > 0.0 && (mx < 1e-140 || mx > 1e140)) {
-        double sm2 = 0.0, dummy = 0.0;
-        const double inv = 1.0 / mx;
-        for (int i = kk + 1 + tid; i < mp; i += NTQ) {
-          const double2 v = P[pidx(i, kk)];
-          sm2 += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
-        }
-        block_sum_max<NWQ>(sm2, dummy, s_red);
-        sc = mx;
-        q = sm2;
-      } else if (mx > 0.0) {
-        sc = 1.0;
-        q = sm;
-      }
-      if (tid == 0) {
-        const double2 alpha = P[pidx(kk, kk)];
-        double2 tau = make_double2(0.0, 0.0), scal = make_double2(1.0, 0.0);
-        if (!(sc == 0.0 && alpha.y == 0.0)) {
-          double sa = sc, qa = q;
-          ssq_add(sa, qa, alpha.x);
-          ssq_add(sa, qa, alpha.y);
-          const double nrm_all = sa * sqrt(qa);
-          if (nrm_all > 1e-280) {
-            const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
-            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-            scal = crecip(make_double2(alpha.x - beta, alpha.y));
-            P[pidx(kk, kk)] = make_double2(beta, 0.0);
-          }
-        }
-        s_tau[kk] = tau;
-        s_bc[0] = tau;
-        s_bc[1] = scal;
-      }
-      __syncthreads();
-      const double2 tau = s_bc[0], scal = s_bc[1];
-      if (tau.x == 0.0 && tau.y == 0.0) {
-        // H = I; below-diagonal entries (if any tiny ones) become an exact
-        // zero reflector so V stays consistent with tau = 0
-        for (int i = kk + 1 + tid; i < mp; i += NTQ) P[pidx(i, kk)] = make_double2(0.0, 0.0);
-        __syncthreads();
-        continue;
-      }
-      for (int i = kk + 1 + tid; i < mp; i += NTQ) P[pidx(i, kk)] = cmul(P[pidx(i, kk)], scal);
-      __syncthreads();
-      const double2 ctau = cconj(tau);
-      for (int c = kk + 1 + wave; c < nbk; c += NWQ) {
-        double sr = 0, si = 0;
-        for (int i = kk + lane; i < mp; i += 64) {
-          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : P[pidx(i, kk)];
-          const double2 w = cdotc(v, P[pidx(i, c)]);
-          sr += w.x;
-          si += w.y;
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        const double2 cc = cmul(ctau, make_double2(sr, si));
-        for (int i = kk + lane; i < mp; i += 64) {
-          const double2 v = (i == kk) ? make_double2(1.0, 0.0) : P[pidx(i, kk)];
-          const double2 u = cmul(v, cc);
-          const double2 o = P[pidx(i, c)];
-          P[pidx(i, c)] = make_double2(o.x - u.x, o.y - u.y);
-        }
-      }
-      __syncthreads();
-    }
-    // Gram matrix G = V^H V of the panel (wave 0, MFMA), then T (zlarft)
-    if (wave == 0) {
-      const int li = lane & 15, lk = lane >> 4;
-      v4d_t gr, gim;
-      zero4(gr);
-      zero4(gim);
-      for (int i0 = 0; i0 < mp; i0 += 4) {
-        const double2 a = vval(P, i0 + lk, li, mp, nbk);   // A = V^H: conj(V[i][li])
-        cmma(a.x, -a.y, a.x, a.y, gr, gim);                // B = V[i][li]
-      }
+    const int rw = ((mp + 16 * NW - 1) / (16 * NW)) * 16;
+    const int r0 = wave * rw, r1 = min(mp, r0 + rw);
+    double2 a[1][QB];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) sG[(lk + 4 * t) * QB + li] = make_double2(gr[t], gim[t]);
-    }
-    if (tid < QB * QB) sT[tid] = make_double2(0.0, 0.0);
-    __syncthreads();
-    for (int k = 0; k < nbk; ++k) {
-      if (tid < k) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int t = tid; t < k; ++t) {
-          const double2 u = cmul(sT[tid * QB + t], sG[t * QB + k]);
-          acc.x += u.x;
-          acc.y += u.y;
-        }
-        const double2 tk = s_tau[k];
-        const double2 u = cmul(tk, acc);
-        sT[tid * QB + k] = make_double2(-u.x, -u.y);
-      } else if (tid == k) {
-        sT[k * QB + k] = s_tau[k];
+    for (int c = 0; c < QB; ++c)
+      a[0][c] = (tid < mp && c < nbk) ? A[(long long)(p + tid) * n + p + c] : make_double2(0.0, 0.0);
+    factor_panel<1, QB, NTQ>(a, mp, nbk, psm, sT);
+    // V to LDS (over the factorisation scratch), the panel to the workspace
+    // for the Q accumulation, T to the workspace and X = T^H to registers
+    if (tid < mp) {
+#pragma unroll
+      for (int c = 0; c < QB; ++c) {
+        P[pidx(tid, c)] = a[0][c];
+        if (c < nbk) A[(long long)(p + tid) * n + p + c] = a[0][c];
       }
-      __syncthreads();
     }
     if (tid < QB * QB) Tg[(long long)pi * QB * QB + tid] = sT[tid];
-    // panel (R above, V below the diagonal) back to global
-    for (int e = tid; e < mp * QB; e += NTQ) {
-      const int i = e / QB, c = e % QB;
-      if (c < nbk) A[(long long)(p + i) * n + p + c] = P[pidx(i, c)];
-    }
-    // trailing columns: A -= V T^H V^H A, one 16-column sub-strip per wave
-    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
-      apply_block<NTQ == 256 ? 1 : 4>(A, n, p, mp, nbk, c0, P, sT, true, lane);
+    double2 xv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xv[t] = cconj(sT[(4 * t + lk) * QB + li]);
+    __syncthreads();
+    update_strips<NTQ>(A, n, p, mp, nbk, r0, r1, p + nbk, P, xv, Wp);
     __syncthreads();
   }
 
   // explicit thin Q, panels in reverse order (in place)
   for (int pi = npan - 1; pi >= 0; --pi) {
     const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
+    const int rw = ((mp + 16 * NW - 1) / (16 * NW)) * 16;
+    const int r0 = wave * rw, r1 = min(mp, r0 + rw);
     for (int e = tid; e < mp * QB; e += NTQ) {
       const int i = e / QB, c = e % QB;
       P[pidx(i, c)] = (c < nbk && i > c) ? A[(long long)(p + i) * n + p + c]
                                          : make_double2(0.0, 0.0);
     }
-    if (tid < QB * QB) sT[tid] = Tg[(long long)pi * QB * QB + tid];
+    double2 xv[4];   // X = T: xv[t] = T[li][4t + lk]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xv[t] = Tg[(long long)pi * QB * QB + li * QB + 4 * t + lk];
     __syncthreads();
-    // columns already formed: A <- H A with H = I - V T V^H
-    for (int c0 = p + nbk + wave * 16; c0 < n; c0 += 16 * NWQ)
-      apply_block<NTQ == 256 ? 1 : 4>(A, n, p, mp, nbk, c0, P, sT, false, lane);
     // the panel's own columns: [I; 0] - V (T V1^H), V1 the top nbk x nbk block
     {
-      const int li = lane & 15, lk = lane >> 4;
       v4d_t sr, si;
       zero4(sr);
       zero4(si);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int s = 4 * t + lk;
-        const double2 a = sT[li * QB + s];                    // T[li][s]
-        const double2 b = vval(P, li, s, mp, nbk);            // V1[li][s] -> conj for B
-        cmma(a.x, a.y, b.x, -b.y, sr, si);
+        const int s2 = 4 * t + lk;
+        const double2 b = vval(P, li, s2, mp, nbk);   // V1[li][s2] -> conj for B
+        cmma(xv[t].x, xv[t].y, b.x, -b.y, sr, si);
       }
       // S = T V1^H in registers (item t: row lk + 4t, col li)
-      for (int rb = wave * 16; rb < mp; rb += 16 * NWQ) {
+      for (int rb = wave * 16; rb < mp; rb += 16 * NW) {
         v4d_t dr, di;
         zero4(dr);
         zero4(di);
@@ -669,6 +591,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
       const int i = e / nbk, c = e % nbk;
       A[(long long)i * n + p + c] = make_double2(0.0, 0.0);
     }
+    update_strips<NTQ>(A, n, p, mp, nbk, r0, r1, p + nbk, P, xv, Wp);
     __syncthreads();
   }
 
@@ -841,7 +764,9 @@ size_t qr_lds_limit() {
   return 64 * 1024 - 17 * 1024;
 }
 
-size_t qr_blocked_lds(int m) { return (size_t)m * QB * sizeof(double2); }
+size_t qr_blocked_lds(int m) {
+  return m <= 128 ? QrShape<256>::LDS_BYTES : QrShape<512>::LDS_BYTES;
+}
 int qr_blocked_max_rows() { return 512; }
 
 hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {

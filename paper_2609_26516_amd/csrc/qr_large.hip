@@ -18,23 +18,13 @@
 // After the last panel A is reset to [I; 0] and the panels are applied in
 // reverse order with X = T, which leaves the thin Q = H_0 ... H_{n-1} [I; 0]
 // in A; qrl_store writes Q (mode 0) or Q^H (mode 1) in the output precision.
-#include <utility>
-
 #include "dcs_internal.h"
 #include "kernel_util.h"
+#include "qr_panel.h"
 
 namespace dcs {
 namespace {
 
-// f(std::integral_constant<int, k>) for k = 0 .. N-1, expanded at compile time
-template <typename Fn, int... K>
-__device__ __forceinline__ void static_for_impl(Fn&& f, std::integer_sequence<int, K...>) {
-  (f(std::integral_constant<int, K>{}), ...);
-}
-template <int N, typename Fn>
-__device__ __forceinline__ void static_for(Fn&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
 
 constexpr int QRL_CHUNKS = 64;   // load / store / fill work units per matrix
 constexpr int QRL_NT = 512;      // panel workgroup
@@ -87,24 +77,11 @@ __global__ __launch_bounds__(256) void qrl_load_kernel(const QrArgs args) {
   if (threadIdx.x == 0) qrl_partials(A, m, n)[blockIdx.x] = part;
 }
 
-// Panel factorisation.  RP rows per thread (rows tid + r QRL_NT), NB panel
-// columns; every loop over columns is unrolled so the panel stays in
-// registers.  Column kk takes one reduction round: with x the entries below
-// the diagonal and v = [1; scal x],
-//   |x|^2, max|x|,  p_c = x^H a_c (c > kk),  q_c = v_c^H x (c < kk)
-// are reduced together, and after the round every thread forms
-//   v^H a_c = a_kk,c + conj(scal) p_c   and   v_c^H v = conj(v_c[kk]) + scal q_c
-// (row kk broadcast through LDS).  The reduction: DPP sums over lane quads,
-// quad partials to LDS, 16 lanes per value sum them and finish with DPP.
+// Panel factorisation: RP rows per thread (rows tid + r QRL_NT), NB columns
+// in registers (factor_panel).
 template <int RP, int NB>
 __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, int p) {
-  constexpr int NV = 2 * NB;           // reduced values: |x|^2, p_c / q_c (re, im), spare
-  constexpr int NQ = QRL_NW * 16;      // quad partials per value
-  __shared__ double s_q[NV][NQ];
-  __shared__ double s_fin[NV];
-  __shared__ double s_mx[QRL_NW];
-  __shared__ double s_red[2 * QRL_NW];
-  __shared__ double2 s_row[NB];
+  __shared__ PanelSmem<QRL_NW, NB> sm;
   __shared__ double2 s_T[NB * NB];
   const QrlItem it = qrl_item(args, blockIdx.x);
   const int m = it.g->m, n = it.g->n;
@@ -113,7 +90,7 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
   double2* V = A + (long long)m * n;
   double2* Tg = V + (long long)m * n;
   const int mp = m - p, nbk = min(NB, n - p);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x;
 
   if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
     const double* part = qrl_partials(A, m, n);
@@ -130,153 +107,7 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
     for (int c = 0; c < NB; ++c)
       a[r][c] = (i < mp && c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
   }
-  if (tid < NB * NB) s_T[tid] = make_double2(0.0, 0.0);
-
-  static_for<NB>([&](auto kc) {
-    constexpr int kk = decltype(kc)::value;
-    if (kk >= nbk) return;   // uniform over the workgroup
-    // partial sums over this thread's rows below the diagonal
-    double x[NV];
-    double mx = 0.0;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) x[q] = 0.0;
-#pragma unroll
-    for (int r = 0; r < RP; ++r) {
-      const int i = tid + r * QRL_NT;
-      if (i > kk && i < mp) {
-        const double2 xi = a[r][kk];
-        x[0] += xi.x * xi.x + xi.y * xi.y;
-        mx = fmax(mx, fmax(fabs(xi.x), fabs(xi.y)));
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          if (c == kk) continue;
-          // value slots: c > kk -> p_c = x^H a_c, c < kk -> q_c = v_c^H x
-          const double2 w = (c > kk) ? cdotc(xi, a[r][c]) : cdotc(a[r][c], xi);
-          const int slot = 1 + 2 * (c < kk ? c : c - 1);
-          x[slot] += w.x;
-          x[slot + 1] += w.y;
-        }
-      }
-    }
-    // stage 1: lane quads (DPP), quad partials to LDS; max over the wave
-#pragma unroll
-    for (int q = 0; q < NV; ++q) x[q] += dpp_d<0xB1>(x[q]);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) x[q] += dpp_d<0x4E>(x[q]);
-    mx = wave_max_dpp(mx);
-    __syncthreads();   // readers of the previous round (s_row, s_q, s_fin) are done
-    if (tid == kk) {   // row kk: alpha, R entries (c > kk) and v_c[kk] (c < kk)
-#pragma unroll
-      for (int c = 0; c < NB; ++c) s_row[c] = a[0][c];
-    }
-    if ((lane & 3) == 0) {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) s_q[q][wave * 16 + (lane >> 2)] = x[q];
-    }
-    if (lane == 0) s_mx[wave] = mx;
-    __syncthreads();
-    // stage 2: 16 lanes per value, eight quad partials each, then DPP
-    if (tid < NV * 16) {
-      const int q = tid >> 4, sub = tid & 15;
-      double v = 0.0;
-#pragma unroll
-      for (int u = 0; u < NQ / 16; ++u) v += s_q[q][sub * (NQ / 16) + u];
-      v += dpp_d<0xB1>(v);
-      v += dpp_d<0x4E>(v);
-      v += dpp_d<0x141>(v);
-      v += dpp_d<0x140>(v);
-      if (sub == 0) s_fin[q] = v;
-    }
-    __syncthreads();
-    double mxa = 0.0;
-#pragma unroll
-    for (int w = 0; w < QRL_NW; ++w) mxa = fmax(mxa, s_mx[w]);
-    double sc = 0.0, qn = 0.0;
-    if (mxa > 0.0 && (mxa < 1e-140 || mxa > 1e140)) {
-      // squares leave the safe range: scaled second pass (rare, uniform)
-      double sm2 = 0.0, dummy = 0.0;
-      const double inv = 1.0 / mxa;
-#pragma unroll
-      for (int r = 0; r < RP; ++r) {
-        const int i = tid + r * QRL_NT;
-        if (i > kk && i < mp) {
-          const double2 v = a[r][kk];
-          sm2 += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
-        }
-      }
-      block_sum_max_dpp<QRL_NW>(sm2, dummy, s_red);
-      sc = mxa;
-      qn = sm2;
-    } else if (mxa > 0.0) {
-      sc = 1.0;
-      qn = s_fin[0];
-    }
-    const double2 alpha = s_row[kk];
-    double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
-    if (!(sc == 0.0 && alpha.y == 0.0)) {
-      double sa = sc, qa = qn;
-      ssq_add(sa, qa, alpha.x);
-      ssq_add(sa, qa, alpha.y);
-      const double nrm_all = sa * sqrt(qa);
-      if (nrm_all > 1e-280) {
-        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
-        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        scal = crecip(make_double2(alpha.x - beta, alpha.y));
-      }
-    }
-    // inner products with v = [1; scal x]: v^H a_c (c > kk), v_c^H v (c < kk)
-    auto dval = [&](int c) {
-      const int slot = 1 + 2 * (c < kk ? c : c - 1);
-      const double2 pq = make_double2(s_fin[slot], s_fin[slot + 1]);
-      const double2 rc = s_row[c];
-      if (c > kk) {
-        const double2 u = cmul(cconj(scal), pq);
-        return make_double2(rc.x + u.x, rc.y + u.y);
-      }
-      const double2 u = cmul(scal, pq);
-      return make_double2(rc.x + u.x, -rc.y + u.y);
-    };
-    // v below the diagonal (an exact zero reflector when tau = 0)
-#pragma unroll
-    for (int r = 0; r < RP; ++r) {
-      const int i = tid + r * QRL_NT;
-      if (i > kk && i < mp) a[r][kk] = cmul(a[r][kk], scal);
-    }
-    // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk], T[kk][kk] = tau
-    if (tid < kk) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t >= tid && t < kk) {
-          const double2 u = cmul(s_T[tid * NB + t], dval(t));
-          acc.x += u.x;
-          acc.y += u.y;
-        }
-      }
-      const double2 u = cmul(tau, acc);
-      s_T[tid * NB + kk] = make_double2(-u.x, -u.y);
-    } else if (tid == kk) {
-      s_T[kk * NB + kk] = tau;
-    }
-    // a_c -= v conj(tau) (v^H a_c) for the remaining panel columns
-    const double2 ctau = cconj(tau);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c > kk && c < nbk) {
-        const double2 cc = cmul(ctau, dval(c));
-#pragma unroll
-        for (int r = 0; r < RP; ++r) {
-          const int i = tid + r * QRL_NT;
-          if (i >= kk && i < mp) {
-            const double2 v = (i == kk) ? make_double2(1.0, 0.0) : a[r][kk];
-            const double2 u = cmul(v, cc);
-            a[r][c] = make_double2(a[r][c].x - u.x, a[r][c].y - u.y);
-          }
-        }
-      }
-    }
-  });
-  __syncthreads();
+  factor_panel<RP, NB, QRL_NT>(a, mp, nbk, sm, s_T);
   // explicit V of the panel (zero above, one on the diagonal) and T
 #pragma unroll
   for (int r = 0; r < RP; ++r) {

@@ -44,28 +44,32 @@ class Engine:
         self.device = device
         torch.cuda.set_device(device)
         self.ctx = capi.dcs_ctx_create(device)
-        self._chunks: Dict[tuple, int] = {}
+        self._chunks: Dict[tuple, tuple] = {}
 
     def stream(self) -> int:
         return torch.cuda.current_stream(self.device).cuda_stream
 
     def chunk(self, circ: Circuit, op_ids: Sequence[int]) -> int:
-        """Compiled chunk of the listed operations (cached by op indices)."""
+        """Compiled chunk of the listed operations (cached by circuit and op
+        indices; the cache holds the circuit, so its id is not reused)."""
         key = (id(circ), tuple(op_ids))
-        h = self._chunks.get(key)
-        if h is None:
-            q0, q1, mats = [], [], []
-            for i in op_ids:
-                g = _gate_of(circ.ops[i])
-                q0.append(g.qubits[0])
-                q1.append(g.qubits[1] if len(g.qubits) == 2 else -1)
-                mats.append(np.asarray(g.mat, dtype=np.complex128).reshape(-1))
-            h = capi.dcs_chunk_compile(self.ctx, circ.n_qubits, q0, q1, np.concatenate(mats))
-            self._chunks[key] = h
+        hit = self._chunks.get(key)
+        if hit is not None and hit[0] is circ:
+            return hit[1]
+        if hit is not None:
+            capi.dcs_chunk_destroy(hit[1])
+        q0, q1, mats = [], [], []
+        for i in op_ids:
+            g = _gate_of(circ.ops[i])
+            q0.append(g.qubits[0])
+            q1.append(g.qubits[1] if len(g.qubits) == 2 else -1)
+            mats.append(np.asarray(g.mat, dtype=np.complex128).reshape(-1))
+        h = capi.dcs_chunk_compile(self.ctx, circ.n_qubits, q0, q1, np.concatenate(mats))
+        self._chunks[key] = (circ, h)
         return h
 
     def clear_chunks(self) -> None:
-        for h in self._chunks.values():
+        for _, h in self._chunks.values():
             capi.dcs_chunk_destroy(h)
         self._chunks.clear()
 
