@@ -145,6 +145,29 @@ __device__ __forceinline__ void cmma(double ar, double ai, double br, double bi,
   ci = mfma64(ai, br, ci);
 }
 
+// Complex accumulation with three real MFMA products per step (Gauss):
+// p1 += ar br, p2 += ai bi, p3 += (ar + ai)(br + bi); then re = p1 - p2,
+// im = p3 - p1 - p2.  One product fewer than cmma per step, normwise error
+// of the same order in FP64.
+struct CAcc3 {
+  v4d_t p1, p2, p3;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      p1[r] = 0.0;
+      p2[r] = 0.0;
+      p3[r] = 0.0;
+    }
+  }
+  __device__ __forceinline__ void add(double ar, double ai, double br, double bi) {
+    p1 = mfma64(ar, br, p1);
+    p2 = mfma64(ai, bi, p2);
+    p3 = mfma64(ar + ai, br + bi, p3);
+  }
+  __device__ __forceinline__ double re(int r) const { return p1[r] - p2[r]; }
+  __device__ __forceinline__ double im(int r) const { return p3[r] - p1[r] - p2[r]; }
+};
+
 __device__ __forceinline__ void zero4(v4d_t& a) {
   a[0] = 0;
   a[1] = 0;

@@ -340,12 +340,9 @@ constexpr int QB = 16;
 
 __device__ __forceinline__ int pidx(int i, int c) { return i * QB + (c ^ (i & 15)); }
 
-// Reflector r of the panel at local row i: 0 above the diagonal, 1 on it.
-__device__ __forceinline__ double2 vval(const double2* P, int i, int r, int mp, int nbk) {
-  if (r >= nbk || i < r || i >= mp) return make_double2(0.0, 0.0);
-  if (i == r) return make_double2(1.0, 0.0);
-  return P[pidx(i, r)];
-}
+// Reflector r of the panel at local row i; the panel in LDS is explicit (0
+// above the diagonal, 1 on it, 0 in unused columns and rows).
+__device__ __forceinline__ double2 pv(const double2* P, int i, int r) { return P[pidx(i, r)]; }
 
 // NTQ threads per workgroup: 512 (8 waves, one workgroup per CU) for up to
 // 512 rows, 256 (4 waves, two per CU) for up to 128 rows; wave w owns rows
@@ -389,21 +386,20 @@ __device__ __forceinline__ void update_strips(double2* __restrict__ A, int n, in
         const int i = r0 + 16 * b + lk + 4 * t;
         a[b][t] = (i < r1 && ok) ? Arow[(16 * b + 4 * t) * n] : zero;
       }
-    v4d_t wr, wi;
-    zero4(wr);
-    zero4(wi);
+    CAcc3 w;
+    w.zero();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int i = r0 + 16 * b + 4 * t + lk;
-        const double2 v = i < r1 ? vval(P, i, li, mp, nbk) : zero;   // A operand conj(V[i][li])
-        cmma(v.x, -v.y, a[b][t].x, a[b][t].y, wr, wi);
+        const double2 v = pv(P, r0 + 16 * b + 4 * t + lk, li);   // A operand conj(V[i][li])
+        w.add(v.x, -v.y, a[b][t].x, a[b][t].y);
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the LDS operand reads block by block
     }
+    v4d_t wr, wi;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Wp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(wr[r], wi[r]);
+    for (int r = 0; r < 4; ++r) Wp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(w.re(r), w.im(r));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -419,31 +415,32 @@ __device__ __forceinline__ void update_strips(double2* __restrict__ A, int n, in
     }
     __syncthreads();   // every wave has its W before the next strip's parts
     // W2 = X W (result item t = row lk + 4t = the B operand of k-step t)
-    v4d_t xr, xi;
-    zero4(xr);
-    zero4(xi);
+    CAcc3 x2;
+    x2.zero();
 #pragma unroll
-    for (int t = 0; t < 4; ++t) cmma(xv[t].x, xv[t].y, wr[t], wi[t], xr, xi);
+    for (int t = 0; t < 4; ++t) x2.add(xv[t].x, xv[t].y, wr[t], wi[t]);
+    double x2r[4], x2i[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      x2r[t] = x2.re(t);
+      x2i[t] = x2.im(t);
+    }
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-      v4d_t dr, di;
+      CAcc3 e;   // V W2 for this block
+      e.zero();
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        dr[t] = a[b][t].x;
-        di[t] = a[b][t].y;
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int i = r0 + 16 * b + li;   // A operand V[i][4t + lk]
-        const double2 v = i < r1 ? vval(P, i, 4 * t + lk, mp, nbk) : zero;
-        cmma(v.x, v.y, -xr[t], -xi[t], dr, di);
+        const double2 v = pv(P, r0 + 16 * b + li, 4 * t + lk);   // A operand V[i][4t + lk]
+        e.add(v.x, v.y, x2r[t], x2i[t]);
       }
       __builtin_amdgcn_sched_barrier(0);
       if (ok) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int i = r0 + 16 * b + lk + 4 * t;
-          if (i < r1) Arow[(16 * b + 4 * t) * n] = make_double2(dr[t], di[t]);
+          if (i < r1)
+            Arow[(16 * b + 4 * t) * n] = make_double2(a[b][t].x - e.re(t), a[b][t].y - e.im(t));
         }
       }
     }
@@ -523,13 +520,17 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
     for (int c = 0; c < QB; ++c)
       a[0][c] = (tid < mp && c < nbk) ? A[(long long)(p + tid) * n + p + c] : make_double2(0.0, 0.0);
     factor_panel<1, QB, NTQ>(a, mp, nbk, psm, sT);
-    // V to LDS (over the factorisation scratch), the panel to the workspace
-    // for the Q accumulation, T to the workspace and X = T^H to registers
-    if (tid < mp) {
+    // explicit V to LDS (over the factorisation scratch), the panel to the
+    // workspace for the Q accumulation, T to the workspace and X = T^H to
+    // registers
+    if (tid < Shape::PROWS) {
 #pragma unroll
       for (int c = 0; c < QB; ++c) {
-        P[pidx(tid, c)] = a[0][c];
-        if (c < nbk) A[(long long)(p + tid) * n + p + c] = a[0][c];
+        const bool in = tid < mp && c < nbk;
+        P[pidx(tid, c)] = !in ? make_double2(0.0, 0.0)
+                              : (tid < c ? make_double2(0.0, 0.0)
+                                         : (tid == c ? make_double2(1.0, 0.0) : a[0][c]));
+        if (in) A[(long long)(p + tid) * n + p + c] = a[0][c];
       }
     }
     if (tid < QB * QB) Tg[(long long)pi * QB * QB + tid] = sT[tid];
@@ -546,10 +547,12 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
     const int p = pi * QB, nbk = min(QB, n - p), mp = m - p;
     const int rw = ((mp + 16 * NW - 1) / (16 * NW)) * 16;
     const int r0 = wave * rw, r1 = min(mp, r0 + rw);
-    for (int e = tid; e < mp * QB; e += NTQ) {
+    for (int e = tid; e < Shape::PROWS * QB; e += NTQ) {   // explicit V
       const int i = e / QB, c = e % QB;
-      P[pidx(i, c)] = (c < nbk && i > c) ? A[(long long)(p + i) * n + p + c]
-                                         : make_double2(0.0, 0.0);
+      double2 v = make_double2(0.0, 0.0);
+      if (i < mp && c < nbk)
+        v = i > c ? A[(long long)(p + i) * n + p + c] : make_double2(i == c ? 1.0 : 0.0, 0.0);
+      P[pidx(i, c)] = v;
     }
     double2 xv[4];   // X = T: xv[t] = T[li][4t + lk]
 #pragma unroll
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int s2 = 4 * t + lk;
-        const double2 b = vval(P, li, s2, mp, nbk);   // V1[li][s2] -> conj for B
+        const double2 b = pv(P, li, s2);   // V1[li][s2] -> conj for B
         cmma(xv[t].x, xv[t].y, b.x, -b.y, sr, si);
       }
       // S = T V1^H in registers (item t: row lk + 4t, col li)
@@ -573,7 +576,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
         zero4(di);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const double2 v = vval(P, rb + li, 4 * t + lk, mp, nbk);
+          const double2 v = pv(P, rb + li, 4 * t + lk);
           cmma(v.x, v.y, sr[t], si[t], dr, di);
         }
         if (li < nbk) {

@@ -154,9 +154,8 @@ __global__ __launch_bounds__(256) void qrl_wpart_kernel(const QrArgs args, int p
   const bool col_ok = col < n;
   const int r0 = blockIdx.y * QRL_CH + wave * 64, r1 = min(mp, r0 + 64);
   const double2 zero = make_double2(0.0, 0.0);
-  v4d_t wr, wi;
-  zero4(wr);
-  zero4(wi);
+  CAcc3 w;
+  w.zero();
   double2 vv[16], bb[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -166,9 +165,9 @@ __global__ __launch_bounds__(256) void qrl_wpart_kernel(const QrArgs args, int p
     bb[u] = (ok && col_ok) ? A[(long long)(p + i) * n + col] : zero;
   }
 #pragma unroll
-  for (int u = 0; u < 16; ++u) cmma(vv[u].x, -vv[u].y, bb[u].x, bb[u].y, wr, wi);
+  for (int u = 0; u < 16; ++u) w.add(vv[u].x, -vv[u].y, bb[u].x, bb[u].y);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) sW[wave][(lk + 4 * t) * 16 + li] = make_double2(wr[t], wi[t]);
+  for (int t = 0; t < 4; ++t) sW[wave][(lk + 4 * t) * 16 + li] = make_double2(w.re(t), w.im(t));
   __syncthreads();
   const int e = threadIdx.x;
   double2 sum = sW[0][e];
@@ -219,9 +218,8 @@ __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int 
     wi[t] = w.y;
   }
   // W2 = X W (result item t = row lk + 4t = the B operand of k-step t)
-  v4d_t xr, xi;
-  zero4(xr);
-  zero4(xi);
+  CAcc3 x2;
+  x2.zero();
 #pragma unroll
   for (int t = 0; t < NB / 4; ++t) {
     const int s = 4 * t + lk;
@@ -234,11 +232,17 @@ __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int 
         x = T[li * NB + s];
       }
     }
-    cmma(x.x, x.y, wr[t], wi[t], xr, xi);
+    x2.add(x.x, x.y, wr[t], wi[t]);
+  }
+  double xr[4], xi[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    xr[t] = x2.re(t);
+    xi[t] = x2.im(t);
   }
   // this wave's 64 rows: A -= V W2, four 16-row blocks
   const int r0 = blockIdx.y * QRL_CH + wave * 64, r1 = min(mp, r0 + 64);
-  v4d_t dr[4], di[4];
+  double2 av[4][4];
   double2 vv[4][NB / 4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
@@ -246,9 +250,7 @@ __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int i = rb + lk + 4 * t;
-      const double2 v = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
-      dr[h][t] = v.x;
-      di[h][t] = v.y;
+      av[h][t] = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
     }
 #pragma unroll
     for (int t = 0; t < NB / 4; ++t) {
@@ -258,13 +260,16 @@ __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int 
   }
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
+    CAcc3 e;   // V W2 for this block
+    e.zero();
 #pragma unroll
-    for (int t = 0; t < NB / 4; ++t) cmma(vv[h][t].x, vv[h][t].y, -xr[t], -xi[t], dr[h], di[h]);
+    for (int t = 0; t < NB / 4; ++t) e.add(vv[h][t].x, vv[h][t].y, xr[t], xi[t]);
     if (col_ok) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int i = r0 + 16 * h + lk + 4 * t;
-        if (i < r1) A[(long long)(p + i) * n + col] = make_double2(dr[h][t], di[h][t]);
+        if (i < r1)
+          A[(long long)(p + i) * n + col] = make_double2(av[h][t].x - e.re(t), av[h][t].y - e.im(t));
       }
     }
   }
