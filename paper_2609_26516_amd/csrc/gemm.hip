@@ -1,8 +1,9 @@
 // Batched / grouped complex GEMM on CDNA4 matrix cores.
 //
 // C = op(A) op(B) for complex operands stored interleaved (re, im), with the
-// complex product split into four real MFMA products per 16x16 block
-// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  FP32 operands use
+// complex product taken as three real MFMA products per 16x16 block (Gauss:
+// P1 += Ar Br, P2 += Ai Bi, P3 += (Ar + Ai)(Br + Bi), then Cr = P1 - P2,
+// Ci = P3 - P1 - P2; normwise error of the same order as four products).  FP32 operands use
 // v_mfma_f32_16x16x4_f32 (FP32 accumulation), FP64 operands
 // v_mfma_f64_16x16x4_f64.  Mixed storage (e.g. complex64 site tensors against
 // a complex128 environment) is converted while staging into LDS.
@@ -219,15 +220,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  V cr[FM][FN], ci[FM][FN];
+  // three real products per complex block (Gauss): p1 = Ar Br, p2 = Ai Bi,
+  // p3 = (Ar + Ai)(Br + Bi); Cr = p1 - p2, Ci = p3 - p1 - p2
+  V p1[FM][FN], p2[FM][FN], p3[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        cr[i][j][r] = 0;
-        ci[i][j][r] = 0;
+        p1[i][j][r] = 0;
+        p2[i][j][r] = 0;
+        p3[i][j][r] = 0;
       }
 
   const int nk = (K + BK - 1) / BK;
@@ -247,25 +251,26 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + lk;
-      R xr[FM], xi[FM], yr[FN], yi[FN];
+      R xr[FM], xi[FM], xs[FM], yr[FN], yi[FN], ys[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         xr[i] = sAr[kr][wm + i * 16 + li];
         xi[i] = sAi[kr][wm + i * 16 + li];
+        xs[i] = xr[i] + xi[i];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         yr[j] = sBr[kr][wn + j * 16 + li];
         yi[j] = sBi[kr][wn + j * 16 + li];
+        ys[j] = yr[j] + yi[j];
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-          cr[i][j] = Mfma<R>::mma(xr[i], yr[j], cr[i][j]);
-          cr[i][j] = Mfma<R>::mma(-xi[i], yi[j], cr[i][j]);
-          ci[i][j] = Mfma<R>::mma(xr[i], yi[j], ci[i][j]);
-          ci[i][j] = Mfma<R>::mma(xi[i], yr[j], ci[i][j]);
+          p1[i][j] = Mfma<R>::mma(xr[i], yr[j], p1[i][j]);
+          p2[i][j] = Mfma<R>::mma(xi[i], yi[j], p2[i][j]);
+          p3[i][j] = Mfma<R>::mma(xs[i], ys[j], p3[i][j]);
         }
     }
   }
@@ -280,8 +285,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
         const int row = m0 + wm + i * 16 + Mfma<R>::row(lk, r);
         if (row < M && col < N) {
           CC v;
-          v.x = cr[i][j][r];
-          v.y = ci[i][j][r];
+          v.x = p1[i][j][r] - p2[i][j][r];
+          v.y = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
           C[(long long)row * ldc + col] = v;
         }
       }
