@@ -10,10 +10,11 @@
 // diagonal and v = [1; scal x],
 //   |x|^2, max|x|,  p_c = x^H a_c (c > kk),  q_c = v_c^H x (c < kk)
 // are reduced together (DPP within lane quads, quad partials through LDS, a
-// group of lanes per value, DPP again), and after the round every thread
-// forms v^H a_c = a[kk][c] + conj(scal) p_c and the Gram entry
+// group of lanes per value, DPP again); then one wave forms the reflector,
+// v^H a_c = a[kk][c] + conj(scal) p_c, the Gram entry
 // v_c^H v = conj(v_c[kk]) + scal q_c of the zlarft recurrence
-// T[j][kk] = -tau_kk T[j][j:kk] G[j:kk][kk], T[kk][kk] = tau_kk.  Squares
+// T[j][kk] = -tau_kk T[j][j:kk] G[j:kk][kk], T[kk][kk] = tau_kk, and the
+// update coefficients, which every thread then applies to its rows.  Squares
 // are summed directly unless max|x| leaves [1e-140, 1e140], where a scaled
 // second pass keeps them representable.
 #pragma once
@@ -30,6 +31,8 @@ struct PanelSmem {
   double mx[NW];
   double red[2 * NW];
   double2 row[NB];             // row kk of the panel
+  double2 cc[NB];              // conj(tau) v^H a_c of the columns c > kk
+  double2 scal;                // v = [1; scal x]
 };
 
 // On return a holds R on and above the diagonal (the diagonal entry itself is
@@ -120,6 +123,7 @@ __device__ __forceinline__ void factor_panel(double2 (&a)[RP][NB], int mp, int n
     for (int w = 0; w < NW; ++w) mxa = fmax(mxa, sm.mx[w]);
     double sc = 0.0, qn = 0.0;
     if (mxa > 0.0 && (mxa < 1e-140 || mxa > 1e140)) {
+      // squares leave the safe range: scaled second pass (rare, uniform)
       double sm2 = 0.0, dummy = 0.0;
       const double inv = 1.0 / mxa;
 #pragma unroll
@@ -137,56 +141,63 @@ __device__ __forceinline__ void factor_panel(double2 (&a)[RP][NB], int mp, int n
       sc = 1.0;
       qn = sm.fin[2 * NB - 2];
     }
-    const double2 alpha = sm.row[kk];
-    double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
-    if (!(sc == 0.0 && alpha.y == 0.0)) {
-      double sa = sc, qa = qn;
-      ssq_add(sa, qa, alpha.x);
-      ssq_add(sa, qa, alpha.y);
-      const double nrm_all = sa * sqrt(qa);
-      if (nrm_all > 1e-280) {
-        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
-        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        scal = crecip(make_double2(alpha.x - beta, alpha.y));
+    // the reflector, the update coefficients and the T column: wave 0 only
+    if (wave == 0) {
+      const double2 alpha = sm.row[kk];
+      double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+      if (!(sc == 0.0 && alpha.y == 0.0)) {
+        double sa = sc, qa = qn;
+        ssq_add(sa, qa, alpha.x);
+        ssq_add(sa, qa, alpha.y);
+        const double nrm_all = sa * sqrt(qa);
+        if (nrm_all > 1e-280) {
+          const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+          tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+          scal = crecip(make_double2(alpha.x - beta, alpha.y));
+        }
+      }
+      // v^H a_c (c > kk) and the Gram entry v_c^H v (c < kk)
+      auto dval = [&](int c) {
+        const int slot = 2 * (c < kk ? c : c - 1);
+        const double2 pq = make_double2(sm.fin[slot], sm.fin[slot + 1]);
+        const double2 rc = sm.row[c];
+        if (c > kk) {
+          const double2 u = cmul(cconj(scal), pq);
+          return make_double2(rc.x + u.x, rc.y + u.y);
+        }
+        const double2 u = cmul(scal, pq);
+        return make_double2(rc.x + u.x, -rc.y + u.y);
+      };
+      if (lane < NB && lane > kk && lane < nbk) sm.cc[lane] = cmul(cconj(tau), dval(lane));
+      if (lane < kk) {   // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk]
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          if (t >= lane && t < kk) {
+            const double2 u = cmul(sT[lane * NB + t], dval(t));
+            acc.x += u.x;
+            acc.y += u.y;
+          }
+        }
+        const double2 u = cmul(tau, acc);
+        sT[lane * NB + kk] = make_double2(-u.x, -u.y);
+      } else if (lane == kk) {
+        sT[kk * NB + kk] = tau;
+        sm.scal = scal;
       }
     }
-    // v^H a_c (c > kk) and v_c^H v (c < kk)
-    auto dval = [&](int c) {
-      const int slot = 2 * (c < kk ? c : c - 1);
-      const double2 pq = make_double2(sm.fin[slot], sm.fin[slot + 1]);
-      const double2 rc = sm.row[c];
-      if (c > kk) {
-        const double2 u = cmul(cconj(scal), pq);
-        return make_double2(rc.x + u.x, rc.y + u.y);
-      }
-      const double2 u = cmul(scal, pq);
-      return make_double2(rc.x + u.x, -rc.y + u.y);
-    };
+    __syncthreads();
+    const double2 scal = sm.scal;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
       const int i = tid + r * NT;
       if (i > kk && i < mp) a[r][kk] = cmul(a[r][kk], scal);
     }
-    if (tid < kk) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t >= tid && t < kk) {
-          const double2 u = cmul(sT[tid * NB + t], dval(t));
-          acc.x += u.x;
-          acc.y += u.y;
-        }
-      }
-      const double2 u = cmul(tau, acc);
-      sT[tid * NB + kk] = make_double2(-u.x, -u.y);
-    } else if (tid == kk) {
-      sT[kk * NB + kk] = tau;
-    }
-    const double2 ctau = cconj(tau);
+    // a_c -= v conj(tau) (v^H a_c) for the remaining panel columns
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       if (c > kk && c < nbk) {
-        const double2 cc = cmul(ctau, dval(c));
+        const double2 cc = sm.cc[c];
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
           const int i = tid + r * NT;
