@@ -54,10 +54,11 @@ TUNE = {"enabled": True, "save": None}
 # one default step), each scaled by what the counter reads for a plain copy
 # of known size.  Valid only for the kernel source they were taken on.
 TRAFFIC = {
-    "qr": {"src": "paper_2609_26516_amd/csrc/kernels.hip",
-           "sha256": "72fcbbeef27749ccf289d58ab592416a595b37ba7f6d69eeb6acac8716f52a43",
-           "fetch_kib": 4608106.9, "write_kib": 5568073.8,
-           "fetch_factor": 1048576 / 524298.0, "write_factor": 1048576 / 1048576.0},
+    "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
+                   "paper_2609_26516_amd/csrc/kernel_util.h"],
+           "sha256": "318872ff4aee68337db0f996f2d8758d8a3eb271201a616cbcef1e8c02954cff",
+           "fetch_kib": 2618004.8, "write_kib": 5828996.2,
+           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
 }
 
 
@@ -66,16 +67,13 @@ def measured_traffic(cls):
     t = TRAFFIC.get(cls)
     if t is None:
         return None
-    with open(os.path.join(ROOT, t["src"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None       # kernel changed since the counters were taken
+    h = hashlib.sha256()
+    for src in t["src"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sha256"]:
+        return None       # kernel changed since the counters were taken
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
-
-
-def mpo_bond_max(prm) -> int:
-    """Operator bond of a chunk of L Haar brickwork layers: a bond is
-    straddled by ceil(L / 2) two-qubit gates of operator-Schmidt rank 4."""
-    return 4 ** ((prm["layers_per_round"] + 1) // 2)
 
 
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
