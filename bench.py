@@ -76,6 +76,12 @@ def measured_traffic(cls):
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
 
 
+def mpo_bond_max(prm) -> int:
+    """Operator bond of a chunk of L Haar brickwork layers: a bond is
+    straddled by ceil(L / 2) two-qubit gates of operator-Schmidt rank 4."""
+    return 4 ** ((prm["layers_per_round"] + 1) // 2)
+
+
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
             graphs: bool = False):
     import torch
