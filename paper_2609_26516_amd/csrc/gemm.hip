@@ -14,7 +14,8 @@
 // complex columns through LDS held as split real / imaginary planes in
 // [k][m] order, so the 16 lanes of an MFMA operand row read consecutive
 // words.  The next K tile is fetched into registers while the current one is
-// multiplied.  Workgroup ids are remapped so consecutive tiles (same batch
+// multiplied and then stored into the second of two LDS stages, one barrier
+// per K step.  Workgroup ids are remapped so consecutive tiles (same batch
 // item, shared operands) land on the same XCD / L2.  Tile shapes: 64x64,
 // 32x32, 128x64, 64x128 (chosen per shape class by the runtime's autotuner);
 // every shape accumulates each output element over K in the same order, so
@@ -87,10 +88,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   constexpr int EB = BN * BK / NT;   // B elements staged per thread
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
 
-  __shared__ R sAr[BK][BM + PAD];
-  __shared__ R sAi[BK][BM + PAD];
-  __shared__ R sBr[BK][BN + PAD];
-  __shared__ R sBi[BK][BN + PAD];
+  // two LDS stages: the next K tile is stored while the current one is read
+  __shared__ R sA_r[2][BK][BM + PAD];
+  __shared__ R sA_i[2][BK][BM + PAD];
+  __shared__ R sB_r[2][BK][BN + PAD];
+  __shared__ R sB_i[2][BK][BN + PAD];
+  int stage = 0;
 
   const int tile = xcd_remap(blockIdx.x, args.total_tiles);
   int gi = 0;
@@ -151,15 +154,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
       const int row = tid / TPR, kq = (tid % TPR) * EA;
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
-        sAr[kq + u][row] = ar[u];
-        sAi[kq + u][row] = ai[u];
+        sA_r[stage][kq + u][row] = ar[u];
+        sA_i[stage][kq + u][row] = ai[u];
       }
     } else {
       const int kr = tid / 16, mq = (tid % 16) * EA;
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
-        sAr[kr][mq + u] = ar[u];
-        sAi[kr][mq + u] = ai[u];
+        sA_r[stage][kr][mq + u] = ar[u];
+        sA_i[stage][kr][mq + u] = ai[u];
       }
     }
   };
@@ -202,16 +205,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
       const int kr = tid / 16, nq = (tid % 16) * EB;
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
-        sBr[kr][nq + u] = br[u];
-        sBi[kr][nq + u] = bi[u];
+        sB_r[stage][kr][nq + u] = br[u];
+        sB_i[stage][kr][nq + u] = bi[u];
       }
     } else {
       constexpr int TPR = BK / EB;
       const int nr = tid / TPR, kq = (tid % TPR) * EB;
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
-        sBr[kq + u][nr] = br[u];
-        sBi[kq + u][nr] = bi[u];
+        sB_r[stage][kq + u][nr] = br[u];
+        sB_i[stage][kq + u][nr] = bi[u];
       }
     }
   };
@@ -238,12 +241,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
   if (nk > 0) {
     load_a(0);
     load_b(0);
-  }
-  for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
     store_a();
     store_b();
     __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) {
       load_a((kt + 1) * BK);
       load_b((kt + 1) * BK);
@@ -254,14 +256,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
       R xr[FM], xi[FM], xs[FM], yr[FN], yi[FN], ys[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        xr[i] = sAr[kr][wm + i * 16 + li];
-        xi[i] = sAi[kr][wm + i * 16 + li];
+        xr[i] = sA_r[stage][kr][wm + i * 16 + li];
+        xi[i] = sA_i[stage][kr][wm + i * 16 + li];
         xs[i] = xr[i] + xi[i];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        yr[j] = sBr[kr][wn + j * 16 + li];
-        yi[j] = sBi[kr][wn + j * 16 + li];
+        yr[j] = sB_r[stage][kr][wn + j * 16 + li];
+        yi[j] = sB_i[stage][kr][wn + j * 16 + li];
         ys[j] = yr[j] + yi[j];
       }
 #pragma unroll
@@ -273,6 +275,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
           p3[i][j] = Mfma<R>::mma(xs[i], ys[j], p3[i][j]);
         }
     }
+    if (kt + 1 < nk) {
+      stage ^= 1;   // the other stage was last read before the previous barrier
+      store_a();
+      store_b();
+    }
+    __syncthreads();
   }
 
 #pragma unroll
