@@ -358,6 +358,10 @@ struct QrShape {
   static constexpr size_t P_BYTES = (size_t)PROWS * QB * sizeof(double2);
   static constexpr size_t LDS_BYTES = P_BYTES + (size_t)NW * 256 * sizeof(double2);
   static_assert(sizeof(PanelSmem<NW, QB>) <= P_BYTES, "factorisation scratch fits the panel area");
+  // left-looking variant: 16-row blocks per wave, V_j^T areas in the panel area
+  static constexpr int QLB = (NTQ == 512 ? 32 : 8) / NW;
+  static_assert((size_t)NW * QLB * 256 * sizeof(double2) <= P_BYTES, "V_j^T areas fit");
+  static_assert(sizeof(PanelSmem2<NW, QB>) <= P_BYTES, "factorisation scratch fits");
 };
 
 // Columns c_begin..n-1 of rows p + [r0, r1) of A: A -= V X (V^H A) with
@@ -620,6 +624,323 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_blocked_kernel(con
 }
 
 // ---------------------------------------------------------------------------
+// Left-looking variant of the blocked QR (same reflectors, same LDS budget).
+// Only Q is wanted, so the working matrix is never kept: panel k is read
+// from F, brought up to date by applying H_0^H, ..., H_{k-1}^H (the block
+// reflectors of the panels before it) and factored; then block k of Q,
+// H_0 H_1 ... H_k [0; I; 0], is formed from its identity columns by applying
+// H_k, ..., H_0 and written out.  Both loops apply one panel's reflector to
+// 16 columns held in registers, and each such step streams only that panel's
+// explicit V (rows p_j .. m-1) from the workspace: HBM traffic per step is a
+// read of V_j, where the right-looking form reads and writes the trailing
+// matrix once per panel in both the factorisation and the Q accumulation.
+// The next step's V is loaded while the current step runs.
+//
+// Rows are dealt to the waves in 16-row blocks, block beta to wave beta mod NW,
+// so the rows below a panel top stay spread over every wave.  Each wave keeps
+// V_j of its blocks in registers in the layout of the W = V^H a product and a
+// transposed copy in its own LDS area for E = V W2 (the panel area of the
+// factorisation, which is idle while the steps run).
+
+// Raw buffer accesses: an offset at or past the end of the range reads zero
+// and writes nothing, so guarded loads need no branches (which would make the
+// compiler wait for every load in flight before using any of them).
+typedef unsigned int qrl_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int qrl_u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t qrl_rsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+// Byte offset = voff + soff; callers keep soff = 0 so that the whole offset
+// takes part in the bounds check, and a lane that must not access memory
+// passes voff = the range size.
+__device__ __forceinline__ double2 qrl_load(__amdgpu_buffer_rsrc_t r, int voff, int soff,
+                                            const double2*) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ double2 qrl_load(__amdgpu_buffer_rsrc_t r, int voff, int soff,
+                                            const float2*) {
+  const float2 f =
+      __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return make_double2(f.x, f.y);
+}
+__device__ __forceinline__ void qrl_store(__amdgpu_buffer_rsrc_t r, int voff, int soff, double2 v,
+                                          double2*) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qrl_u4, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void qrl_store(__amdgpu_buffer_rsrc_t r, int voff, int soff, double2 v,
+                                          float2*) {
+  const float2 f = make_float2((float)v.x, (float)v.y);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qrl_u2, f), r, voff, soff, 0);
+}
+
+// One step on the 16 columns in a: FACT: a <- H_j^H a (X = T^H), otherwise
+// a <- H_j a (X = T), H_j = I - V_j T_j V_j^H.  On entry v holds V_j; on exit it
+// holds V_jn (zero if jn < 0).  In FACT mode block j of a is not updated:
+// after this step those rows only hold R, which is not wanted.  The waves'
+// parts of W = V_j^H a are summed in two stages: wave w adds up entries
+// [w E, (w + 1) E) of all parts (E = 256 / NW) and leaves the sums in place
+// in its own part, from where every wave then reads its entries.
+template <int NTQ, bool FACT>
+__device__ __forceinline__ void qrl_step(double2 (&a)[QrShape<NTQ>::QLB][4],
+                                         double2 (&v)[QrShape<NTQ>::QLB][4],
+                                         __amdgpu_buffer_rsrc_t rV,
+                                         const double2* __restrict__ Tg, int m, int n, int j,
+                                         int jn, bool first, double2* VT, double2* Wp) {
+  constexpr int NW = QrShape<NTQ>::NW, MAXB = QrShape<NTQ>::QLB, EPW = 256 / NW;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  // X of this step (needed after the W sum)
+  double2 xv[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    xv[t] = FACT ? cconj(Tg[(long long)j * 256 + (4 * t + lk) * 16 + li])
+                 : Tg[(long long)j * 256 + li * 16 + 4 * t + lk];
+  // this wave's part of W = V_j^H a (first step of a Q block: a = [0; I; 0]
+  // is zero outside block j)
+  CAcc3 w;
+  w.zero();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int beta = wave + NW * b;
+    if (beta >= j && 16 * beta < m && (!first || beta == j)) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w.add(v[b][t].x, -v[b][t].y, a[b][t].x, a[b][t].y);
+    }
+  }
+  __syncthreads();   // every wave has read the sums of the previous step
+  double2* Wq = Wp + wave * 256;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Wq[(lk + 4 * r) * 16 + li] = make_double2(w.re(r), w.im(r));
+  double2* Vt = VT + wave * (MAXB * 256);
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int beta = wave + NW * b;
+    if (beta >= j && 16 * beta < m) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Vt[b * 256 + pidx(4 * t + lk, li)] = v[b][t];
+    }
+  }
+  {   // V of the next step, in flight during the rest of this one; rows at
+      // or past m fall outside the range and read zero
+    const int oob = m * n * 16, loff = (lk * n + li) * 16;
+    const bool cok = jn >= 0 && 16 * jn + li < n;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+      const bool bact = beta >= jn && 16 * beta < m;   // uniform
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r0 = 16 * beta + 4 * t;
+        // branch-free select of the offset (branches around the loads would
+        // make the compiler wait for all of them before the W sum)
+        const int msk = -(int)(bact && cok);
+        v[b][t] = qrl_load(rV, oob + ((loff + (r0 * n + 16 * jn) * 16 - oob) & msk), 0,
+                           (const double2*)nullptr);
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < EPW) {
+    const int e = wave * EPW + lane;
+    double2 x[NW];
+#pragma unroll
+    for (int u = 0; u < NW; ++u) x[u] = Wp[u * 256 + e];
+    double2 sum = x[0];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) {
+      sum.x += x[u].x;
+      sum.y += x[u].y;
+    }
+    Wp[wave * 256 + e] = sum;
+  }
+  __syncthreads();
+  double wr[4], wi[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = (lk + 4 * r) * 16 + li;
+    const double2 x = Wp[(e / EPW) * 256 + e];
+    wr[r] = x.x;
+    wi[r] = x.y;
+  }
+  CAcc3 x2;   // W2 = X W
+  x2.zero();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) x2.add(xv[t].x, xv[t].y, wr[t], wi[t]);
+  double x2r[4], x2i[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    x2r[t] = x2.re(t);
+    x2i[t] = x2.im(t);
+  }
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int beta = wave + NW * b;
+    if (beta >= j + (FACT ? 1 : 0) && 16 * beta < m) {
+      CAcc3 e;   // rows of this block of V_j W2
+      e.zero();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double2 vt = Vt[b * 256 + pidx(li, 4 * t + lk)];   // V_j[16 beta + li][4t + lk]
+        e.add(vt.x, vt.y, x2r[t], x2i[t]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        a[b][r] = make_double2(a[b][r].x - e.re(r), a[b][r].y - e.im(r));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int CTI, int CTO, int NTQ>
+__global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const QrArgs args) {
+  using Shape = QrShape<NTQ>;
+  constexpr int NW = Shape::NW, MAXB = Shape::QLB;
+  using TI = typename St<CTI>::T;
+  using TO = typename St<CTO>::T;
+  extern __shared__ __attribute__((aligned(16))) double2 dyn[];
+  PanelSmem2<NW, QB>& psm = *reinterpret_cast<PanelSmem2<NW, QB>*>(dyn);
+  double* s_red = reinterpret_cast<double*>(dyn);
+  double2* P = dyn;   // panel rows to factor, or the waves' V_j^T areas
+  double2* Wp = dyn + Shape::P_BYTES / sizeof(double2);
+  double2* sT = Wp;   // while a panel is factored
+
+  const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
+  const QrGroup& G = args.g[gi];
+  const int item = blockIdx.x - G.blk_begin;
+  const int m = G.m, n = G.n, mode = G.mode;
+  const TI* __restrict__ F = reinterpret_cast<const TI*>(item_ptr(G.f, G.ids, item));
+  TO* __restrict__ Q = reinterpret_cast<TO*>(const_cast<char*>(item_ptr(G.q, G.ids, item)));
+  double* nrm = reinterpret_cast<double*>(const_cast<char*>(item_ptr(G.nrm2, G.ids, item)));
+  double2* Vw = reinterpret_cast<double2*>(const_cast<char*>(item_ptr(G.ws, G.ids, item)));
+  double2* Tg = Vw + (long long)m * n;   // T factor of every panel
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform block ownership
+  const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+  const long long mn = (long long)m * n;
+
+  if (mode == 2) {   // T = F / |F|
+    double part = 0;
+    for (long long idx = tid; idx < mn; idx += NTQ) {
+      const double2 u = to_d2(F[idx]);
+      part += u.x * u.x + u.y * u.y;
+    }
+    double nu2 = part, nu_mx = 0.0;
+    block_sum_max<NW>(nu2, nu_mx, s_red);
+    if (tid == 0) *nrm = nu2;
+    const double sc = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0;
+    for (long long idx = tid; idx < mn; idx += NTQ) {
+      const double2 u = to_d2(F[idx]);
+      TO o;
+      o.x = u.x * sc;
+      o.y = u.y * sc;
+      Q[idx] = o;
+    }
+    return;
+  }
+
+  const __amdgpu_buffer_rsrc_t rF = qrl_rsrc(F, mn * (long long)sizeof(TI));
+  const __amdgpu_buffer_rsrc_t rQ = qrl_rsrc(Q, mn * (long long)sizeof(TO));
+  const __amdgpu_buffer_rsrc_t rV = qrl_rsrc(Vw, mn * 16);
+  const int oobF = (int)(mn * sizeof(TI)), oobQ = (int)(mn * sizeof(TO));
+  // per-lane parts of the byte offsets of row r0 + lk, column c0 + li (r0, c0 uniform)
+  const int loffF = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TI);
+  const int loffQ = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TO);
+  double part = 0;   // |F|^2, each entry is read once
+  double2 a[MAXB][4], v[MAXB][4];
+  const int npan = (n + QB - 1) / QB;
+#pragma unroll 1
+  for (int k = 0; k < npan; ++k) {
+    const int p = k * QB, nbk = min(QB, n - p), mp = m - p;
+    // columns p .. p+15 of A (= F, or F^H in mode 1), and V_0
+    // (v holds V_0 here for k > 0, loaded by the last step of the previous Q block)
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r0 = 16 * beta + 4 * t;
+        const bool in = lk < m - r0 && li < nbk;
+        const int sF = (mode == 0 ? r0 * n + p : p * m + r0) * (int)sizeof(TI);
+        double2 u = qrl_load(rF, in ? loffF + sF : oobF, 0, (const TI*)nullptr);
+        if (mode != 0) u.y = -u.y;
+        part += u.x * u.x + u.y * u.y;
+        a[b][t] = u;
+      }
+    }
+#pragma unroll 1
+    for (int j = 0; j < k; ++j)
+      qrl_step<NTQ, true>(a, v, rV, Tg, m, n, j, j + 1 < k ? j + 1 : -1, false, P, Wp);
+
+    // factor the panel: rows p.. to LDS, one row per thread
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+      if (beta >= k && 16 * beta < m) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[pidx(16 * (beta - k) + 4 * t + lk, li)] = a[b][t];
+      }
+    }
+    __syncthreads();
+    double2 ar[1][QB];
+#pragma unroll
+    for (int c = 0; c < QB; ++c) ar[0][c] = tid < mp ? P[pidx(tid, c)] : zero;
+    factor_panel2<1, QB, NTQ>(ar, mp, nbk, psm, sT);
+    // explicit V_k to the workspace and (rows p.., zero past m) to LDS, T_k to
+    // the workspace
+    if (tid < Shape::PROWS) {
+#pragma unroll
+      for (int c = 0; c < QB; ++c) {
+        const bool in = tid < mp && c < nbk;
+        const double2 u = !in ? zero : (tid > c ? ar[0][c] : make_double2(tid == c ? 1.0 : 0.0, 0.0));
+        if (in) Vw[(long long)(p + tid) * n + p + c] = u;
+        P[pidx(tid, c)] = u;
+      }
+    }
+    if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sT[tid];
+    __threadfence_block();
+    __syncthreads();
+
+    // block k of Q
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int row = 16 * beta + 4 * t + lk;
+        a[b][t] = make_double2(row == p + li && li < nbk ? 1.0 : 0.0, 0.0);
+        v[b][t] = beta >= k && 16 * beta < m ? P[pidx(16 * (beta - k) + 4 * t + lk, li)] : zero;
+      }
+    }
+    // nothing in flight on entry to the loop, so the compiler can count the
+    // loads of each step exactly (the last step loads V_0 for the next
+    // panel's updates)
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll 1
+    for (int j = k; j >= 0; --j)
+      qrl_step<NTQ, false>(a, v, rV, Tg, m, n, j, j > 0 ? j - 1 : (k + 1 < npan ? 0 : -1), j == k,
+                           P, Wp);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r0 = 16 * beta + 4 * t;
+        const bool in = lk < m - r0 && li < nbk;
+        const int sQ = (mode == 0 ? r0 * n + p : p * m + r0) * (int)sizeof(TO);
+        const double2 o = make_double2(a[b][t].x, mode == 0 ? a[b][t].y : -a[b][t].y);
+        qrl_store(rQ, in ? loffQ + sQ : oobQ, 0, o, (TO*)nullptr);
+      }
+    }
+  }
+  double nu2 = part, nu_mx = 0.0;
+  block_sum_max<NW>(nu2, nu_mx, s_red);
+  if (tid == 0) *nrm = nu2;
+}
+
+// ---------------------------------------------------------------------------
 // Outcome norms n_m = Re sum conj(A[a][m][b]) Z[a][m][b], FP64 accumulation.
 
 template <int CTA, int CTZ>
@@ -793,6 +1114,30 @@ hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_ma
   DCS_QRB(CT_F64, CT_F64, 256)
   DCS_QRB(CT_F64, CT_F32, 256)
 #undef DCS_QRB
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
+  if (args.total_blocks <= 0) return hipSuccess;
+  const size_t lds = qr_blocked_lds(m_max);
+  const bool small = m_max <= 128;
+  const dim3 grid(args.total_blocks), blk(small ? 256 : 512);
+#define DCS_QRL(I, O, T)                                                                    \
+  if (ct_in == I && ct_out == O && (T == 256) == small) {                                  \
+    static hipError_t attr = hipFuncSetAttribute(                                          \
+        reinterpret_cast<const void*>(&qr_left_kernel<I, O, T>),                            \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_blocked_lds(512));              \
+    if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
+    hipLaunchKernelGGL((qr_left_kernel<I, O, T>), grid, blk, lds, s, args);                 \
+    return hipGetLastError();                                                               \
+  }
+  DCS_QRL(CT_F32, CT_F32, 512)
+  DCS_QRL(CT_F64, CT_F64, 512)
+  DCS_QRL(CT_F64, CT_F32, 512)
+  DCS_QRL(CT_F32, CT_F32, 256)
+  DCS_QRL(CT_F64, CT_F64, 256)
+  DCS_QRL(CT_F64, CT_F32, 256)
+#undef DCS_QRL
   return hipErrorInvalidValue;
 }
 

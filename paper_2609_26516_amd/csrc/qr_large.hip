@@ -78,10 +78,10 @@ __global__ __launch_bounds__(256) void qrl_load_kernel(const QrArgs args) {
 }
 
 // Panel factorisation: RP rows per thread (rows tid + r QRL_NT), NB columns
-// in registers (factor_panel).
+// in registers (factor_panel2).
 template <int RP, int NB>
 __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, int p) {
-  __shared__ PanelSmem<QRL_NW, NB> sm;
+  __shared__ PanelSmem2<QRL_NW, NB> sm;
   __shared__ double2 s_T[NB * NB];
   const QrlItem it = qrl_item(args, blockIdx.x);
   const int m = it.g->m, n = it.g->n;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, in
     for (int c = 0; c < NB; ++c)
       a[r][c] = (i < mp && c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
   }
-  factor_panel<RP, NB, QRL_NT>(a, mp, nbk, sm, s_T);
+  factor_panel2<RP, NB, QRL_NT>(a, mp, nbk, sm, s_T);
   // explicit V of the panel (zero above, one on the diagonal) and T
 #pragma unroll
   for (int r = 0; r < RP; ++r) {

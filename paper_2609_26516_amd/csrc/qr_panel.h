@@ -35,6 +35,60 @@ struct PanelSmem {
   double2 scal;                // v = [1; scal x]
 };
 
+// Column kk's reflector from the reduced values fin (slots as in factor_panel)
+// and the squared norm sc^2 qn of the entries below the diagonal: tau, the
+// scaling of v, the update coefficients cc[c] = conj(tau) v^H a_c (c > kk) and
+// column kk of T.  Executed by one wave; lane c handles column c.
+template <int NB>
+__device__ __forceinline__ void panel_reflector(int kk, int nbk, double sc, double qn,
+                                                const double* fin, const double2* row,
+                                                double2* cc_out, double2* scal_out,
+                                                double2* sT) {
+  const int lane = threadIdx.x & 63;
+  const double2 alpha = row[kk];
+  double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+  if (!(sc == 0.0 && alpha.y == 0.0)) {
+    double sa = sc, qa = qn;
+    ssq_add(sa, qa, alpha.x);
+    ssq_add(sa, qa, alpha.y);
+    const double nrm_all = sa * sqrt(qa);
+    if (nrm_all > 1e-280) {
+      const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      scal = crecip(make_double2(alpha.x - beta, alpha.y));
+    }
+  }
+  // v^H a_c (c > kk) and the Gram entry v_c^H v (c < kk)
+  auto dval = [&](int c) {
+    const int slot = 2 * (c < kk ? c : c - 1);
+    const double2 pq = make_double2(fin[slot], fin[slot + 1]);
+    const double2 rc = row[c];
+    if (c > kk) {
+      const double2 u = cmul(cconj(scal), pq);
+      return make_double2(rc.x + u.x, rc.y + u.y);
+    }
+    const double2 u = cmul(scal, pq);
+    return make_double2(rc.x + u.x, -rc.y + u.y);
+  };
+  if (lane < NB && lane > kk && lane < nbk) cc_out[lane] = cmul(cconj(tau), dval(lane));
+  if (lane < kk) {   // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk]
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      if (t >= lane && t < kk) {
+        const double2 u = cmul(sT[lane * NB + t], dval(t));
+        acc.x += u.x;
+        acc.y += u.y;
+      }
+    }
+    const double2 u = cmul(tau, acc);
+    sT[lane * NB + kk] = make_double2(-u.x, -u.y);
+  } else if (lane == kk) {
+    sT[kk * NB + kk] = tau;
+    *scal_out = scal;
+  }
+}
+
 // On return a holds R on and above the diagonal (the diagonal entry itself is
 // not needed and left as is) and v below it; sT (NB x NB, row-major, LDS)
 // holds T.  Every thread of the workgroup must call it; ends with a barrier.
@@ -142,49 +196,186 @@ __device__ __forceinline__ void factor_panel(double2 (&a)[RP][NB], int mp, int n
       qn = sm.fin[2 * NB - 2];
     }
     // the reflector, the update coefficients and the T column: wave 0 only
-    if (wave == 0) {
-      const double2 alpha = sm.row[kk];
-      double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
-      if (!(sc == 0.0 && alpha.y == 0.0)) {
-        double sa = sc, qa = qn;
-        ssq_add(sa, qa, alpha.x);
-        ssq_add(sa, qa, alpha.y);
-        const double nrm_all = sa * sqrt(qa);
-        if (nrm_all > 1e-280) {
-          const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
-          tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-          scal = crecip(make_double2(alpha.x - beta, alpha.y));
-        }
-      }
-      // v^H a_c (c > kk) and the Gram entry v_c^H v (c < kk)
-      auto dval = [&](int c) {
-        const int slot = 2 * (c < kk ? c : c - 1);
-        const double2 pq = make_double2(sm.fin[slot], sm.fin[slot + 1]);
-        const double2 rc = sm.row[c];
-        if (c > kk) {
-          const double2 u = cmul(cconj(scal), pq);
-          return make_double2(rc.x + u.x, rc.y + u.y);
-        }
-        const double2 u = cmul(scal, pq);
-        return make_double2(rc.x + u.x, -rc.y + u.y);
-      };
-      if (lane < NB && lane > kk && lane < nbk) sm.cc[lane] = cmul(cconj(tau), dval(lane));
-      if (lane < kk) {   // T[j][kk] = -tau T[j][j:kk] G[j:kk][kk]
-        double2 acc = make_double2(0.0, 0.0);
+    if (wave == 0) panel_reflector<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sT);
+    __syncthreads();
+    const double2 scal = sm.scal;
 #pragma unroll
-        for (int t = 0; t < NB; ++t) {
-          if (t >= lane && t < kk) {
-            const double2 u = cmul(sT[lane * NB + t], dval(t));
-            acc.x += u.x;
-            acc.y += u.y;
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + r * NT;
+      if (i > kk && i < mp) a[r][kk] = cmul(a[r][kk], scal);
+    }
+    // a_c -= v conj(tau) (v^H a_c) for the remaining panel columns
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c > kk && c < nbk) {
+        const double2 cc = sm.cc[c];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const int i = tid + r * NT;
+          if (i >= kk && i < mp) {
+            const double2 v = (i == kk) ? make_double2(1.0, 0.0) : a[r][kk];
+            const double2 u = cmul(v, cc);
+            a[r][c] = make_double2(a[r][c].x - u.x, a[r][c].y - u.y);
           }
         }
-        const double2 u = cmul(tau, acc);
-        sT[lane * NB + kk] = make_double2(-u.x, -u.y);
-      } else if (lane == kk) {
-        sT[kk * NB + kk] = tau;
-        sm.scal = scal;
       }
+    }
+  });
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Variant with two workgroup barriers per column instead of four.  Each wave
+// reduces its 32 partial values (the slots of factor_panel, padded to 32) with
+// a halving exchange: at lane distances 32 and 16 the permlane swaps hand each
+// half of the wave the other half's partials of the values it keeps, at 8, 4
+// and 2 lane shuffles do the same, and a DPP step at distance 1 completes the
+// wave sum of value s in lanes 2s and 2s + 1.  The waves' sums go to LDS, one
+// barrier, wave 0 adds them up and forms the reflector, a second barrier, and
+// every thread applies it.  The next column's LDS writes cannot disturb the
+// readers of this one: those all read before the second barrier.
+
+template <int NW, int NB>
+struct PanelSmem2 {
+  double part[NW][32];   // per-wave sums of the reduced values
+  double fin[32];        // the reduced values (written and read by wave 0)
+  double mx[NW];
+  double red[2 * NW];
+  double2 row[NB];       // row kk of the panel
+  double2 cc[NB];        // conj(tau) v^H a_c of the columns c > kk
+  double2 scal;          // v = [1; scal x]
+};
+
+// Exchanges a (lanes of one half) with b (lanes of the other half) so that
+// afterwards a + b is, in every lane, the sum over the lane pair of the value
+// that lane's half keeps: the lower half (by lane distance D = 32 or 16)
+// keeps the value of a, the upper half that of b.
+template <int D>
+__device__ __forceinline__ void half_swap(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32);
+  const unsigned blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+  unsigned r0lo, r1lo, r0hi, r1hi;
+  if (D == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    r0lo = lo[0]; r1lo = lo[1]; r0hi = hi[0]; r1hi = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    r0lo = lo[0]; r1lo = lo[1]; r0hi = hi[0]; r1hi = hi[1];
+  }
+  a = __longlong_as_double((long long)(((unsigned long long)r0hi << 32) | r0lo));
+  b = __longlong_as_double((long long)(((unsigned long long)r1hi << 32) | r1lo));
+}
+
+// Halving step at lane distance M over K value pairs (s, s + K): lanes with
+// the M bit set keep s + K, the others s.
+template <int M, int K>
+__device__ __forceinline__ void halve_shfl(double (&x)[32], int lane) {
+  const bool up = (lane & M) != 0;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const double send = up ? x[s] : x[s + K];
+    const double keep = up ? x[s + K] : x[s];
+    x[s] = keep + __shfl_xor(send, M, 64);
+  }
+}
+
+// Wave sums of 32 values; value s ends in lanes 2s and 2s + 1 (returned).
+__device__ __forceinline__ double wave_scatter_sum32(double (&x)[32]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    half_swap<32>(x[s], x[s + 16]);
+    x[s] += x[s + 16];
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    half_swap<16>(x[s], x[s + 8]);
+    x[s] += x[s + 8];
+  }
+  halve_shfl<8, 4>(x, lane);
+  halve_shfl<4, 2>(x, lane);
+  halve_shfl<2, 1>(x, lane);
+  return x[0] + dpp_d<0xB1>(x[0]);
+}
+
+template <int RP, int NB, int NT>
+__device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int nbk,
+                                              PanelSmem2<NT / 64, NB>& sm, double2* sT) {
+  static_assert(NB <= 16, "at most 32 reduced values");
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < NB * NB) sT[tid] = make_double2(0.0, 0.0);
+  __syncthreads();   // the caller's reads of this LDS are done
+
+  static_for<NB>([&](auto kc) {
+    constexpr int kk = decltype(kc)::value;
+    if (kk >= nbk) return;   // uniform over the workgroup
+    double x[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) x[q] = 0.0;
+    double mx = 0.0;
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int i = tid + r * NT;
+      if (i > kk && i < mp) {
+        const double2 xi = a[r][kk];
+        mx = fmax(mx, fmax(fabs(xi.x), fabs(xi.y)));
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c == kk) continue;
+          const int j = c < kk ? c : c - 1;
+          const double2 w = (c > kk) ? cdotc(xi, a[r][c]) : cdotc(a[r][c], xi);
+          x[2 * j] += w.x;
+          x[2 * j + 1] += w.y;
+        }
+        x[2 * NB - 2] += xi.x * xi.x + xi.y * xi.y;
+      }
+    }
+    if (tid == kk) {   // row kk: alpha, R entries (c > kk) and v_c[kk] (c < kk)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) sm.row[c] = a[0][c];
+    }
+    const double xs = wave_scatter_sum32(x);
+    mx = wave_max_dpp(mx);
+    if ((lane & 1) == 0) sm.part[wave][lane >> 1] = xs;
+    if (lane == 0) sm.mx[wave] = mx;
+    __syncthreads();
+    double mxa = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mxa = fmax(mxa, sm.mx[w]);
+    double sc = 0.0, qn = 0.0;
+    const bool scaled = mxa > 0.0 && (mxa < 1e-140 || mxa > 1e140);
+    if (scaled) {
+      // squares leave the safe range: scaled second pass (rare, uniform)
+      double sm2 = 0.0, dummy = 0.0;
+      const double inv = 1.0 / mxa;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int i = tid + r * NT;
+        if (i > kk && i < mp) {
+          const double2 v = a[r][kk];
+          sm2 += (v.x * inv) * (v.x * inv) + (v.y * inv) * (v.y * inv);
+        }
+      }
+      block_sum_max_dpp<NW>(sm2, dummy, sm.red);
+      sc = mxa;
+      qn = sm2;
+    }
+    if (wave == 0) {
+      if (lane < 32) {
+        double f = sm.part[0][lane];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) f += sm.part[w][lane];
+        sm.fin[lane] = f;
+      }
+      if (!scaled && mxa > 0.0) {
+        sc = 1.0;
+        qn = sm.fin[2 * NB - 2];
+      }
+      panel_reflector<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sT);
     }
     __syncthreads();
     const double2 scal = sm.scal;

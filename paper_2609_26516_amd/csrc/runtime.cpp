@@ -554,7 +554,8 @@ struct QrJob {
   int m, n, mode, batch;
 };
 
-// Path of a QR job: 0 blocked single-workgroup kernel (m <= 512 or mode 2),
+// Path of a QR job: 0 blocked single-workgroup kernel, left-looking form
+// (m <= 512 or mode 2),
 // 1 multi-kernel large-matrix path, 2 unblocked kernel (beyond both).
 int qr_path(const QrJob& j) {
   if (j.mode == 2 || j.m <= qr_blocked_max_rows()) return 0;
@@ -600,7 +601,7 @@ int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, h
       Timed t(ctx, s, CLS_QR, flops, bytes);
       if (path == 0) {
         args.use_lds = 1;
-        DCS_HIP(launch_qr_blocked(ct_in, ct_out, args, std::max(m_max, 1), s));
+        DCS_HIP(launch_qr_left(ct_in, ct_out, args, std::max(m_max, 1), s));
       } else if (path == 1) {
         DCS_HIP(launch_qr_large(ct_in, ct_out, args, s));
       } else {
