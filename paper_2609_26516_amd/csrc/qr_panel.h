@@ -47,7 +47,24 @@ __device__ __forceinline__ void panel_reflector(int kk, int nbk, double sc, doub
   const int lane = threadIdx.x & 63;
   const double2 alpha = row[kk];
   double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
-  if (!(sc == 0.0 && alpha.y == 0.0)) {
+  const double amax = fmax(fabs(alpha.x), fabs(alpha.y));
+  // every square representable (the sum of squares of x is in range or zero,
+  // |alpha| is in range or zero): direct formulas, one square root and two
+  // divisions; otherwise the scaled sums and Smith's reciprocal
+  const bool direct = amax < 1e140 && (sc == 1.0 ? true : (sc == 0.0 && (amax == 0.0 || amax > 1e-140)));
+  if (direct) {
+    if (!(sc == 0.0 && alpha.y == 0.0)) {
+      const double nrm_all = sqrt((sc == 1.0 ? qn : 0.0) + alpha.x * alpha.x + alpha.y * alpha.y);
+      if (nrm_all > 1e-280) {
+        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+        const double rb = 1.0 / beta;
+        tau = make_double2((beta - alpha.x) * rb, -alpha.y * rb);
+        const double dx = alpha.x - beta, dy = alpha.y;
+        const double id = 1.0 / (dx * dx + dy * dy);   // |alpha - beta| in [|beta|, 2 |beta|]
+        scal = make_double2(dx * id, -dy * id);
+      }
+    }
+  } else if (!(sc == 0.0 && alpha.y == 0.0)) {
     double sa = sc, qa = qn;
     ssq_add(sa, qa, alpha.x);
     ssq_add(sa, qa, alpha.y);
@@ -235,10 +252,91 @@ __device__ __forceinline__ void factor_panel(double2 (&a)[RP][NB], int mp, int n
 // every thread applies it.  The next column's LDS writes cannot disturb the
 // readers of this one: those all read before the second barrier.
 
+// panel_reflector with the T column spread over the whole wave: lane c
+// forms d_c (v^H a_c for c > kk, the Gram entry v_c^H v for c < kk) once, the
+// Gram entries go through LDS (dv, wave-local), and lanes 4j .. 4j + 3 add up
+// the four interleaved quarters of T[j][j:kk] d[j:kk] and combine them with
+// two DPP steps.  qn is taken as given (read by the caller from a lane).
+template <int NB>
+__device__ __forceinline__ void panel_reflector2(int kk, int nbk, double sc, double qn,
+                                                 const double* fin, const double2* row,
+                                                 double2* cc_out, double2* scal_out,
+                                                 double2* dv, double2* sT) {
+  const int lane = threadIdx.x & 63;
+  const double2 alpha = row[kk];
+  double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+  const double amax = fmax(fabs(alpha.x), fabs(alpha.y));
+  const bool direct = amax < 1e140 && (sc == 1.0 ? true : (sc == 0.0 && (amax == 0.0 || amax > 1e-140)));
+  if (direct) {
+    if (!(sc == 0.0 && alpha.y == 0.0)) {
+      const double nrm_all = sqrt((sc == 1.0 ? qn : 0.0) + alpha.x * alpha.x + alpha.y * alpha.y);
+      if (nrm_all > 1e-280) {
+        const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+        const double rb = 1.0 / beta;
+        tau = make_double2((beta - alpha.x) * rb, -alpha.y * rb);
+        const double dx = alpha.x - beta, dy = alpha.y;
+        const double id = 1.0 / (dx * dx + dy * dy);   // |alpha - beta| in [|beta|, 2 |beta|]
+        scal = make_double2(dx * id, -dy * id);
+      }
+    }
+  } else if (!(sc == 0.0 && alpha.y == 0.0)) {
+    double sa = sc, qa = qn;
+    ssq_add(sa, qa, alpha.x);
+    ssq_add(sa, qa, alpha.y);
+    const double nrm_all = sa * sqrt(qa);
+    if (nrm_all > 1e-280) {
+      const double beta = alpha.x >= 0.0 ? -nrm_all : nrm_all;
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      scal = crecip(make_double2(alpha.x - beta, alpha.y));
+    }
+  }
+  if (lane < NB && lane != kk) {
+    const int c = lane;
+    const int slot = 2 * (c < kk ? c : c - 1);
+    const double2 pq = make_double2(fin[slot], fin[slot + 1]);
+    const double2 rc = row[c];
+    if (c > kk) {
+      if (c < nbk) {
+        const double2 u = cmul(cconj(scal), pq);
+        cc_out[c] = cmul(cconj(tau), make_double2(rc.x + u.x, rc.y + u.y));
+      }
+    } else {
+      const double2 u = cmul(scal, pq);
+      dv[c] = make_double2(rc.x + u.x, -rc.y + u.y);
+    }
+  }
+  if (kk > 0) {   // T[j][kk] = -tau T[j][j:kk] d[j:kk]
+    const int j = lane >> 2, q = lane & 3;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < (NB + 3) / 4; ++u) {
+      const int t = q + 4 * u;
+      if (t >= j && t < kk) {
+        const double2 w = cmul(sT[j * NB + t], dv[t]);
+        acc.x += w.x;
+        acc.y += w.y;
+      }
+    }
+    acc.x += dpp_d<0xB1>(acc.x);
+    acc.y += dpp_d<0xB1>(acc.y);
+    acc.x += dpp_d<0x4E>(acc.x);
+    acc.y += dpp_d<0x4E>(acc.y);
+    if (q == 0 && j < kk) {
+      const double2 w = cmul(tau, acc);
+      sT[j * NB + kk] = make_double2(-w.x, -w.y);
+    }
+  }
+  if (lane == 0) {
+    sT[kk * NB + kk] = tau;
+    *scal_out = scal;
+  }
+}
+
 template <int NW, int NB>
 struct PanelSmem2 {
   double part[NW][32];   // per-wave sums of the reduced values
   double fin[32];        // the reduced values (written and read by wave 0)
+  double2 dv[NB];        // Gram entries of the T column (wave 0)
   double mx[NW];
   double red[2 * NW];
   double2 row[NB];       // row kk of the panel
@@ -343,6 +441,13 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
     if ((lane & 1) == 0) sm.part[wave][lane >> 1] = xs;
     if (lane == 0) sm.mx[wave] = mx;
     __syncthreads();
+    double f = 0.0;   // wave 0, lane s < 32: reduced value s
+    if (wave == 0 && lane < 32) {
+      f = sm.part[0][lane];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) f += sm.part[w][lane];
+      sm.fin[lane] = f;
+    }
     double mxa = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) mxa = fmax(mxa, sm.mx[w]);
@@ -365,17 +470,11 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
       qn = sm2;
     }
     if (wave == 0) {
-      if (lane < 32) {
-        double f = sm.part[0][lane];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) f += sm.part[w][lane];
-        sm.fin[lane] = f;
-      }
       if (!scaled && mxa > 0.0) {
         sc = 1.0;
-        qn = sm.fin[2 * NB - 2];
+        qn = readlane_d(f, 2 * NB - 2);
       }
-      panel_reflector<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sT);
+      panel_reflector2<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sm.dv, sT);
     }
     __syncthreads();
     const double2 scal = sm.scal;
