@@ -103,8 +103,13 @@ hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_ma
 int qr_blocked_max_rows();
 // Left-looking form of the blocked variant (modes 0-2, m >= n, same limits and
 // workspace): each panel is updated from the stored V of the earlier panels
-// just before it is factored, and Q is formed 16 columns at a time.
-hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s);
+// just before it is factored, and Q is formed 16 columns at a time.  split:
+// two launches, the factorisations, then one workgroup per 16-column block of
+// each Q (for batches too small to fill the chip).
+hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
+                          hipStream_t s);
+// Largest number of matrices for which the runtime splits the left-looking QR.
+int qr_split_max_items();
 // Multi-kernel variant for qr_blocked_max_rows() < m <= qr_large_max_rows()
 // (modes 0 and 1): panels factored by one workgroup per matrix, trailing
 // updates and the backward Q accumulation spread over 16-column strips.  The

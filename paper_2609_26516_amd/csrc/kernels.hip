@@ -3,6 +3,7 @@
 // tensor (gauge shift), outcome norms for the measurement probability, and
 // the collapse of a site tensor.
 #include "dcs_internal.h"
+#include <cstring>
 #include "kernel_util.h"
 #include "qr_panel.h"
 
@@ -793,7 +794,7 @@ __device__ __forceinline__ void qrl_step(double2 (&a)[QrShape<NTQ>::QLB][4],
 }
 
 template <int CTI, int CTO, int NTQ>
-__global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const QrArgs args) {
+__global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const QrArgs args, int part) {
   using Shape = QrShape<NTQ>;
   constexpr int NW = Shape::NW, MAXB = Shape::QLB;
   using TI = typename St<CTI>::T;
@@ -807,7 +808,11 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
 
   const int gi = find_group<QR_MAX_GROUPS>(args.g, args.ngroups, blockIdx.x);
   const QrGroup& G = args.g[gi];
-  const int item = blockIdx.x - G.blk_begin;
+  // part 0: whole QR; part 1: factorisation only (V, T to the workspace);
+  // part 2: one block of Q per workgroup from the stored V, T
+  const int npan = (G.n + QB - 1) / QB;
+  const int local = blockIdx.x - G.blk_begin;
+  const int item = part == 2 ? local / npan : local;
   const int m = G.m, n = G.n, mode = G.mode;
   const TI* __restrict__ F = reinterpret_cast<const TI*>(item_ptr(G.f, G.ids, item));
   TO* __restrict__ Q = reinterpret_cast<TO*>(const_cast<char*>(item_ptr(G.q, G.ids, item)));
@@ -819,6 +824,44 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
   const int li = lane & 15, lk = lane >> 4;
   const double2 zero = make_double2(0.0, 0.0);
   const long long mn = (long long)m * n;
+
+  if (part == 2) {   // block kq of Q: H_0 ... H_kq applied to its identity columns
+    const int k = local - item * npan, p = k * QB, nbk = min(QB, n - p);
+    const __amdgpu_buffer_rsrc_t rQ = qrl_rsrc(Q, mn * (long long)sizeof(TO));
+    const __amdgpu_buffer_rsrc_t rV = qrl_rsrc(Vw, mn * 16);
+    const int oobQ = (int)(mn * sizeof(TO)), oobV = (int)(mn * 16);
+    const int loffQ = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TO);
+    const int loffV = (lk * n + li) * 16;
+    double2 a[MAXB][4], v[MAXB][4];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r0 = 16 * beta + 4 * t;
+        a[b][t] = make_double2(r0 + lk == p + li && li < nbk ? 1.0 : 0.0, 0.0);
+        const int msk = -(int)(beta >= k && 16 * beta < m && li < nbk);   // rows past m: out of range
+        v[b][t] = qrl_load(rV, oobV + ((loffV + (r0 * n + p) * 16 - oobV) & msk), 0,
+                           (const double2*)nullptr);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll 1
+    for (int j = k; j >= 0; --j) qrl_step<NTQ, false>(a, v, rV, Tg, m, n, j, j - 1, j == k, P, Wp);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int beta = wave + NW * b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r0 = 16 * beta + 4 * t;
+        const bool in = lk < m - r0 && li < nbk;
+        const int sQ = (mode == 0 ? r0 * n + p : p * m + r0) * (int)sizeof(TO);
+        const double2 o = make_double2(a[b][t].x, mode == 0 ? a[b][t].y : -a[b][t].y);
+        qrl_store(rQ, in ? loffQ + sQ : oobQ, 0, o, (TO*)nullptr);
+      }
+    }
+    return;
+  }
 
   if (mode == 2) {   // T = F / |F|
     double part = 0;
@@ -843,18 +886,19 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
   const __amdgpu_buffer_rsrc_t rF = qrl_rsrc(F, mn * (long long)sizeof(TI));
   const __amdgpu_buffer_rsrc_t rQ = qrl_rsrc(Q, mn * (long long)sizeof(TO));
   const __amdgpu_buffer_rsrc_t rV = qrl_rsrc(Vw, mn * 16);
-  const int oobF = (int)(mn * sizeof(TI)), oobQ = (int)(mn * sizeof(TO));
+  const int oobF = (int)(mn * sizeof(TI)), oobQ = (int)(mn * sizeof(TO)), oobV = (int)(mn * 16);
+  const int loffV = (lk * n + li) * 16;
   // per-lane parts of the byte offsets of row r0 + lk, column c0 + li (r0, c0 uniform)
   const int loffF = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TI);
   const int loffQ = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TO);
-  double part = 0;   // |F|^2, each entry is read once
+  double nsq = 0;   // |F|^2, each entry is read once
   double2 a[MAXB][4], v[MAXB][4];
-  const int npan = (n + QB - 1) / QB;
 #pragma unroll 1
   for (int k = 0; k < npan; ++k) {
     const int p = k * QB, nbk = min(QB, n - p), mp = m - p;
     // columns p .. p+15 of A (= F, or F^H in mode 1), and V_0
-    // (v holds V_0 here for k > 0, loaded by the last step of the previous Q block)
+    // (for k > 0 in the whole QR, v holds V_0 here, loaded by the last step
+    // of the previous Q block)
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
       const int beta = wave + NW * b;
@@ -865,8 +909,13 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
         const int sF = (mode == 0 ? r0 * n + p : p * m + r0) * (int)sizeof(TI);
         double2 u = qrl_load(rF, in ? loffF + sF : oobF, 0, (const TI*)nullptr);
         if (mode != 0) u.y = -u.y;
-        part += u.x * u.x + u.y * u.y;
+        nsq += u.x * u.x + u.y * u.y;
         a[b][t] = u;
+        if (part == 1 && k > 0) {   // V_0 (rows past m: out of range)
+          const int msk = -(int)(16 * beta < m && li < n);
+          v[b][t] = qrl_load(rV, oobV + ((loffV + r0 * n * 16 - oobV) & msk), 0,
+                             (const double2*)nullptr);
+        }
       }
     }
 #pragma unroll 1
@@ -902,6 +951,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
     if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sT[tid];
     __threadfence_block();
     __syncthreads();
+    if (part == 1) continue;
 
     // block k of Q
 #pragma unroll
@@ -935,7 +985,7 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
       }
     }
   }
-  double nu2 = part, nu_mx = 0.0;
+  double nu2 = nsq, nu_mx = 0.0;
   block_sum_max<NW>(nu2, nu_mx, s_red);
   if (tid == 0) *nrm = nu2;
 }
@@ -1092,6 +1142,8 @@ size_t qr_blocked_lds(int m) {
   return m <= 128 ? QrShape<256>::LDS_BYTES : QrShape<512>::LDS_BYTES;
 }
 int qr_blocked_max_rows() { return 512; }
+// about 5/8 of the MI355X's 256 CUs
+int qr_split_max_items() { return 160; }
 
 hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
   if (args.total_blocks <= 0) return hipSuccess;
@@ -1117,18 +1169,35 @@ hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_ma
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
+hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
+                          hipStream_t s) {
   if (args.total_blocks <= 0) return hipSuccess;
   const size_t lds = qr_blocked_lds(m_max);
   const bool small = m_max <= 128;
-  const dim3 grid(args.total_blocks), blk(small ? 256 : 512);
+  const dim3 blk(small ? 256 : 512);
+  // split: the factorisations first (one workgroup per matrix), then every
+  // 16-column block of every Q in its own workgroup
+  QrArgs qa;
+  std::memset(&qa, 0, sizeof(qa));
+  if (split) {
+    for (int g = 0; g < args.ngroups; ++g) {
+      if (args.g[g].mode == 2) continue;
+      QrGroup& d = qa.g[qa.ngroups++];
+      d = args.g[g];
+      d.blk_begin = qa.total_blocks;
+      qa.total_blocks += d.batch * ((d.n + QB - 1) / QB);
+    }
+  }
 #define DCS_QRL(I, O, T)                                                                    \
   if (ct_in == I && ct_out == O && (T == 256) == small) {                                  \
     static hipError_t attr = hipFuncSetAttribute(                                          \
         reinterpret_cast<const void*>(&qr_left_kernel<I, O, T>),                            \
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_blocked_lds(512));              \
     if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
-    hipLaunchKernelGGL((qr_left_kernel<I, O, T>), grid, blk, lds, s, args);                 \
+    hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(args.total_blocks), blk, lds, s, args, \
+                       split ? 1 : 0);                                                      \
+    if (split && qa.total_blocks > 0)                                                       \
+      hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(qa.total_blocks), blk, lds, s, qa, 2); \
     return hipGetLastError();                                                               \
   }
   DCS_QRL(CT_F32, CT_F32, 512)

@@ -601,7 +601,10 @@ int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, h
       Timed t(ctx, s, CLS_QR, flops, bytes);
       if (path == 0) {
         args.use_lds = 1;
-        DCS_HIP(launch_qr_left(ct_in, ct_out, args, std::max(m_max, 1), s));
+        // fewer matrices than about 5/8 of the CUs: factorisations and Q blocks
+        // in separate launches so the Q blocks spread over the chip
+        DCS_HIP(launch_qr_left(ct_in, ct_out, args, std::max(m_max, 1),
+                               args.total_blocks <= qr_split_max_items(), s));
       } else if (path == 1) {
         DCS_HIP(launch_qr_large(ct_in, ct_out, args, s));
       } else {

@@ -127,7 +127,7 @@ def test_gate_operator(capi, ct, direction, d0, d1, wl, wr):
     assert np.max(np.abs(out - ref.reshape(-1))) < tol * np.sqrt(wl * wr * 4)
 
 
-@pytest.mark.parametrize("use_lds", [0, 1, 2, 4])
+@pytest.mark.parametrize("use_lds", [0, 1, 2, 4, 5])
 @pytest.mark.parametrize("m,n", [(2, 1), (4, 2), (8, 8), (32, 16), (64, 32), (130, 65),
                                  (512, 256), (34, 17), (100, 100), (512, 512), (511, 257),
                                  (129, 17), (300, 300)])
@@ -149,7 +149,7 @@ def test_qr_full_rank(capi, use_lds, m, n):
     assert np.max(np.abs(ql - qn.conj().T)) < 1e-10
 
 
-@pytest.mark.parametrize("variant", [0, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5])
 def test_qr_rank_deficient_and_normalise(capi, variant):
     rng = np.random.default_rng(1)
     m, n = 64, 32
@@ -160,7 +160,7 @@ def test_qr_rank_deficient_and_normalise(capi, variant):
     np.testing.assert_allclose(q.conj().T @ q, np.eye(n), atol=1e-12)
     np.testing.assert_allclose(q @ (q.conj().T @ f), f, atol=1e-11)
     # mode 2: F / |F|
-    t, nrm2 = capi.dcs_test_qr(F32, F32, 10, 3, 2, variant if variant in (2, 4) else 0,
+    t, nrm2 = capi.dcs_test_qr(F32, F32, 10, 3, 2, variant if variant in (2, 4, 5) else 0,
                                f[:10, :3].reshape(-1))
     ref = f[:10, :3] / np.linalg.norm(f[:10, :3])
     assert np.max(np.abs(t.reshape(10, 3) - ref)) < 1e-6
@@ -169,7 +169,7 @@ def test_qr_rank_deficient_and_normalise(capi, variant):
     np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
 
 
-@pytest.mark.parametrize("variant", [0, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("tiny", [1e-120, 1e-170, 1e-250])
 def test_qr_tiny_noise_columns(capi, mode, tiny, variant):
