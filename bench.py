@@ -56,9 +56,9 @@ TUNE = {"enabled": True, "save": None}
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
                    "paper_2609_26516_amd/csrc/kernel_util.h"],
-           "sha256": "318872ff4aee68337db0f996f2d8758d8a3eb271201a616cbcef1e8c02954cff",
-           "fetch_kib": 2618004.8, "write_kib": 5828996.2,
-           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
+           "sha256": "b8b19ab939a4e4e481d9cbbaa63800ea6f53c5e5c1fdd8d033e906bca5166ab7",
+           "fetch_kib": 2847584.7, "write_kib": 965448.4,
+           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.2},
 }
 
 
@@ -168,8 +168,9 @@ def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload
     return dt, stats, info
 
 
-def roofline(stats, prec, counters=False):
-    """counters: the HBM counters in TRAFFIC were taken on this workload."""
+def roofline(stats, prec, counters=False, names=None):
+    """counters: the HBM counters in TRAFFIC were taken on this workload;
+    names: kernel names of the classes where they differ from KERNEL_NAMES."""
     launches, ms, flops, byts = stats
     dom = int(np.argmax(ms))
     avg_ms = ms[dom] / max(1, launches[dom])
@@ -192,7 +193,7 @@ def roofline(stats, prec, counters=False):
     if tr is not None:
         rl["traffic"] = round(tr)
         rl["traffic_over_algorithmic"] = round(tr / max(1.0, per_launch_bytes), 2)
-    rl["kernel"] = KERNEL_NAMES.get(CLASSES[dom], CLASSES[dom])
+    rl["kernel"] = {**KERNEL_NAMES, **(names or {})}.get(CLASSES[dom], CLASSES[dom])
     rl["avg_launch_ms"] = round(avg_ms, 5)
     rl["launches"] = int(launches[dom])
     rl["time_share"] = round(ms[dom] / max(1e-12, sum(ms)), 4)
@@ -356,7 +357,11 @@ def main():
                "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
                "data": "synthetic: seeded Haar brickwork dynamic circuit",
                "config": {"workload": wl, "shots_per_step": 1},
-               "roofline": roofline(stats, "bf16x3"),
+               "roofline": roofline(stats, "bf16x3", names={
+                   "qr": "qrl_panel_kernel + qrl_wpart_kernel + qrl_update_kernel (m > 512), "
+                         "qr_left_kernel (m <= 512)",
+                   "gemm_nn": "gemm_bf16x3_kernel<0, 0>", "gemm_nt": "gemm_bf16x3_kernel<0, 1>",
+                   "gemm_cn": "gemm_bf16x3_kernel<2, 0>", "gemm_jt": "gemm_bf16x3_kernel<3, 1>"}),
                "fp64_path": {"value": round(1 / dt64, 5), "unit": "shots/s", "dtype": "c128"},
                "precision_vs_fp64": cmp}
         print(json.dumps(out))
