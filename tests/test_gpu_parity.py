@@ -82,6 +82,8 @@ def _fid_err(a, b):
     (17, 130, 2, 2),    # chi not a multiple of the tile, 260-row panels
     (18, 264, 2, 2),    # 528-row gauge shift on the large-matrix QR path
     (8, 4, 3, 3),       # three sweeps
+    (10, 8, 4, 3),      # more sweeps than the paper's two
+    (9, 6, 8, 2),
 ])
 def test_compress_step_parity(eng, prec, n, chi, sweeps, layers):
     capi = _capi()
@@ -104,6 +106,37 @@ def test_compress_step_parity(eng, prec, n, chi, sweeps, layers):
     assert abs(f[0] - f_ref) < F_TOL[prec], (f[0], f_ref)
     assert _fid_err(gpu, ref) < FE_TOL[prec]
     assert abs(OM.norm_sq(gpu) - 1) < 10 * FE_TOL[prec]
+
+
+def test_sweeps_reach_eckart_young_bound(eng):
+    """One truncated bond: with more sweeps the GPU's f rises to the sum of
+    the kept squared Schmidt coefficients of the exact post-gate state and
+    never exceeds it (complex128)."""
+    capi = _capi()
+    n, chi = 4, 2
+    rng = np.random.default_rng(42)
+    start = [((0,), C.H), ((0, 1), C.CNOT_01), ((2,), C.H), ((2, 3), C.CNOT_01)]
+    init = OM.generic_bra(bra_init_gaussians(n, chi, 5))
+    psi, _, _ = OM.compress(OM.zero_state(n, chi), OM.chunk_mpo(n, start), init, 2)
+    gate = [((1, 2), C.haar_unitary(rng, 4))]
+    target = SV.apply_gate(OM.to_statevector(psi), n, (1, 2), gate[0][1])
+    sv = np.linalg.svd(target.reshape(4, 4), compute_uv=False)
+    bound = float(np.sum(sv[:chi] ** 2))
+    st = _E().State(eng, "c128", n, 2, chi, 4, [chi], 5)
+    h = _compile(eng, n, gate)
+    prev = 0.0
+    for s_ in (1, 2, 4, 8, 16, 40):
+        capi.dcs_import_mps(st.h, 1, chi, psi, eng.stream())
+        f = float(capi.dcs_compress_step(st.h, [1], [h], s_, eng.stream())[0])
+        _, f_ref, _ = OM.compress(psi, OM.chunk_mpo(n, gate), init, s_)
+        assert abs(f - f_ref) < 1e-12
+        assert f <= bound + 1e-12
+        if s_ >= 4:
+            assert f >= prev - 1e-14
+        prev = f
+    assert abs(prev - bound) < 1e-12
+    capi.dcs_chunk_destroy(h)
+    st.close()
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
