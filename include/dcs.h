@@ -188,6 +188,17 @@ int dcs_compress_step(dcs_state *st, int n, const int *ids,
                       const dcs_chunk *const *chunks, int n_sweeps, double *fid_out,
                       void *stream);
 
+/* Starting guess of the compression steps of this state (the paper leaves
+ * the initial state of the variational compression open, Sec. III-C).
+ * enabled = 0 (default): the generic guess registered for the branch's bond
+ * cap.  enabled != 0: warm start from the ket, B = right-canonical form of
+ * (ket embedded in the bra's bond dims) + eta * (generic guess), the second
+ * term filling the directions the ket lacks with seeded ones; built on the
+ * GPU by an LQ chain from the right (B_j = Q_j of M_j = L_j Q_j, L_j absorbed
+ * into site j-1).  Branches whose ket has a bond wider than the bra's keep
+ * the generic guess.  eta in [0, 1e6], else DCS_EINVAL.  Host-only. */
+int dcs_state_set_warm_start(dcs_state *st, int enabled, double eta);
+
 /* Measurement probability (Sec. IV-B1) of qubit qubits[i] of branch ids[i]:
  * n_m = <psi|P_m|psi> (m = 0, 1) contracted in FP64 from the network,
  * p0_out[i] = n_0 / (n_0 + n_1) (host).  The norms are kept for the next

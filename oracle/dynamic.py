@@ -43,8 +43,10 @@ class Simulator:
     """Parameters shared by both strategies: bond cap chi, chunk size k,
     sweeps s, the seed of the starting guess."""
 
-    def __init__(self, n: int, chi: int, k: int, n_sweeps: int = 2, init_seed: int = 7):
+    def __init__(self, n: int, chi: int, k: int, n_sweeps: int = 2, init_seed: int = 7,
+                 warm_eta: Optional[float] = None):
         self.n, self.chi, self.k, self.s, self.init_seed = n, chi, k, n_sweeps, init_seed
+        self.warm_eta = warm_eta   # None: generic guess; else warm start (M.warm_bra)
         self._bra = {}
 
     def bra_init(self, chi: int) -> List[np.ndarray]:
@@ -54,7 +56,11 @@ class Simulator:
 
     def compress(self, state, chunk, chi: int):
         mpo = M.chunk_mpo(self.n, chunk)
-        new, f, centre = M.compress(state, mpo, self.bra_init(chi), self.s)
+        bra = self.bra_init(chi)
+        if self.warm_eta is not None and all(
+                k.shape[0] <= b.shape[0] and k.shape[2] <= b.shape[2] for k, b in zip(state, bra)):
+            bra = M.warm_bra(state, bra, self.warm_eta)
+        new, f, centre = M.compress(state, mpo, bra, self.s)
         return new, f
 
 

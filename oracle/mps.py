@@ -93,6 +93,35 @@ def generic_bra(gauss: Sequence[np.ndarray]) -> List[np.ndarray]:
     return out
 
 
+def warm_bra(ket: Sequence[np.ndarray], generic: Sequence[np.ndarray],
+             eta: float) -> List[np.ndarray]:
+    """Warm-start guess (a reading: the paper does not fix the starting state
+    of the variational compression): M_j = the ket's site embedded in the
+    bond dims of ``generic`` (zero outside the ket's block) plus eta times
+    the generic site, then, from the right, M_j = L_j Q_j by LQ, B_j = Q_j and
+    L_j absorbed into M_{j-1}; site 0 keeps what is left.  The result
+    represents the same state as the MPS M, with every site but 0
+    right-canonical."""
+    n = len(generic)
+    m = []
+    for j in range(n):
+        dl, _, dr = generic[j].shape
+        kl, _, kr = ket[j].shape
+        if kl > dl or kr > dr:
+            raise ValueError("ket bond wider than the starting guess")
+        t = eta * np.asarray(generic[j], dtype=np.complex128)
+        t[:kl, :, :kr] += ket[j]
+        m.append(t)
+    for j in range(n - 1, 0, -1):
+        dl, _, dr = m[j].shape
+        mj = m[j].reshape(dl, 2 * dr)
+        q = lq_q(mj)
+        lf = mj @ q.conj().T
+        m[j] = q.reshape(dl, 2, dr)
+        m[j - 1] = np.einsum("asb,bc->asc", m[j - 1], lf)
+    return m
+
+
 # ---------------------------------------------------------------------------
 # Chunk -> one layered operator per site
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "dcs_last_error", "dcs_version", "dcs_ctx_create", "dcs_ctx_destroy", "dcs_ctx_set_timing",
     "dcs_ctx_timing", "dcs_ctx_set_graphs", "dcs_ctx_set_tuning", "dcs_ctx_tuning_save",
     "dcs_ctx_tuning_load", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
-    "dcs_state_set_init", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
+    "dcs_state_set_init", "dcs_state_set_warm_start", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight",
     "dcs_overlap", "dcs_export_mps", "dcs_import_mps",
@@ -73,6 +73,7 @@ _SIGS = {
     "dcs_chunk_compile": (c_int, [_P, POINTER(c_void_p), c_int, c_int, _IP, _IP, _DP]),
     "dcs_chunk_bonds": (c_int, [_P, _IP]),
     "dcs_chunk_destroy": (c_int, [_P]),
+    "dcs_state_set_warm_start": (c_int, [_P, c_int, c_double]),
     "dcs_compress_step": (c_int, [_P, c_int, _IP, POINTER(c_void_p), c_int, _DP, _P]),
     "dcs_measure_prob": (c_int, [_P, c_int, _IP, _IP, _DP, _P]),
     "dcs_measure_sample_collapse": (c_int, [_P, c_int, _IP, _IP, _P, c_double, _P, _P, _P]),
@@ -224,6 +225,10 @@ def dcs_chunk_bonds(ch, n_qubits) -> np.ndarray:
 
 def dcs_chunk_destroy(ch) -> None:
     _check(_lib.dcs_chunk_destroy(ch))
+
+
+def dcs_state_set_warm_start(st, enabled: bool, eta: float = 0.0) -> None:
+    _check(_lib.dcs_state_set_warm_start(st, 1 if enabled else 0, float(eta)))
 
 
 def dcs_compress_step(st, ids, chunks, n_sweeps, stream) -> np.ndarray:

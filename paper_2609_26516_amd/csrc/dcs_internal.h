@@ -137,6 +137,19 @@ hipError_t launch_norms(int ct_a, int ct_z, const NormArgs& args, hipStream_t s)
 
 // Collapse site tensor A[dl][2][dr]: slice 1-m zeroed, slice m scaled by the
 // FP64 factor `scale` (= 1/sqrt(n_m)).
+// dst[a][s][b] (dl x 2 x dr) = src[a][s][b] where a < kl and b < kr (src is
+// kl x 2 x kr), else 0, plus eta * init[a][s][b] when init.base is set: the
+// ket embedded in the bra's bond dims with seeded completion, or (eta = 0,
+// equal dims) a batched copy.  One launch per site, item b at slot ids[b].
+struct EmbedArgs {
+  Operand dst, src, init;
+  const int* ids;
+  int dl, dr, kl, kr;
+  int batch;
+  double eta;
+};
+hipError_t launch_embed(int ct, const EmbedArgs& args, hipStream_t s);
+
 struct CollapseItem {
   void* a;
   double scale;

@@ -256,6 +256,9 @@ struct dcs_state {
   // the second time it is seen and replayed afterwards
   std::map<std::string, hipGraphExec_t> graphs;
   std::map<std::string, int> graph_seen;
+  // starting guess of compression steps: < 0 the registered generic guess;
+  // >= 0 warm start, the ket itself plus this multiple of the generic guess
+  double warm_eta = -1.0;
   hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's
   // pinned host staging for uploads of calls that return without
   // synchronising: a ring of buffers, each reused once its last copy is done
@@ -1200,9 +1203,17 @@ struct Group {
   std::vector<int> Db, Kb, w;
   int goff = 0;  // first call-local index of the group
   const int* ids_dev = nullptr;
+  bool warm = false;   // starting guess built from the ket (every ket bond <= the bra's)
 };
 
 }  // namespace
+
+int dcs_state_set_warm_start(dcs_state* st, int enabled, double eta) {
+  if (!st) return fail(DCS_EINVAL, "null state");
+  if (enabled && !(eta >= 0.0 && eta <= 1e6)) return fail(DCS_EINVAL, "eta must be in [0, 1e6]");
+  st->warm_eta = enabled ? eta : -1.0;
+  return DCS_OK;
+}
 
 int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* const* chunks,
                       int n_sweeps, double* fid_out, void* stream) {
@@ -1244,6 +1255,9 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       g.Db = bond_dims(nq, sl.chi_cap);
       g.Kb = sl.dims;
       g.w = chunks[i]->w;
+      g.warm = st->warm_eta >= 0.0;
+      for (int b = 0; b <= nq; ++b)
+        if (g.Kb[b] > g.Db[b]) g.warm = false;
       groups.push_back(g);
       it = key2g.emplace(key, (int)groups.size() - 1).first;
     }
@@ -1313,10 +1327,76 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
     for (auto& g : groups) {
       const int bsz = (int)g.members.size();
       const int kl = g.Kb[j], dl = g.Db[j], dr = g.Db[j + 1], wl = g.w[j];
-      gj.push_back({from_init ? init_site(g, j) : new_site(g, j), x2(), env(j), g.ids_dev, dl,
-                    wl * kl, 2 * dr, 2 * dr, 2 * dr, wl * kl, bsz});
+      gj.push_back({from_init && !g.warm ? init_site(g, j) : new_site(g, j), x2(), env(j),
+                    g.ids_dev, dl, wl * kl, 2 * dr, 2 * dr, 2 * dr, wl * kl, bsz});
     }
     return run_gemm(st->ctx, ct, ct, ct, acc, OP_J, OP_T, gj, s, CLS_GEMM);
+  };
+  // warm start: the ket embedded in the bra's bond dims plus eta times the
+  // generic guess (seeded completion of the directions the ket lacks),
+  // brought to right-canonical form from the right: M_j = L_j Q_j by LQ,
+  // B_j = Q_j, M_{j-1} <- M_{j-1} L_j (L_j^T = conj(Q_j) M_j^T).  B_0 is never
+  // read (the first visit forms site 0 from the environments).
+  auto warm_bra = [&]() -> int {
+    bool any = false;
+    for (auto& g : groups) any = any || g.warm;
+    if (!any) return DCS_OK;
+    auto embed = [&](const Group& g, Operand dst, Operand src, Operand ini, int dl, int dr,
+                     int kl, int kr, double eta) -> int {
+      EmbedArgs a;
+      a.dst = dst;
+      a.src = src;
+      a.init = ini;
+      a.ids = g.ids_dev;
+      a.dl = dl;
+      a.dr = dr;
+      a.kl = kl;
+      a.kr = kr;
+      a.batch = (int)g.members.size();
+      a.eta = eta;
+      DCS_HIP(launch_embed(ct, a, s));
+      return DCS_OK;
+    };
+    const Operand none = local_op(nullptr, 0);
+    for (auto& g : groups) {
+      if (!g.warm) continue;
+      for (int j = 0; j < nq; ++j)
+        DCS_TRY(embed(g, new_site(g, j), ket_site(g, j), init_site(g, j), g.Db[j], g.Db[j + 1],
+                      g.Kb[j], g.Kb[j + 1], st->warm_eta));
+    }
+    for (int j = nq - 1; j >= 1; --j) {
+      std::vector<QrJob> qj;
+      std::vector<GemmJob> gl, gm;
+      for (auto& g : groups) {
+        if (!g.warm) continue;
+        const int bsz = (int)g.members.size();
+        const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
+        QrJob q;
+        q.f = new_site(g, j);
+        q.q = fbuf();
+        q.ws = slot_op(st, L.o_ws, 0);
+        q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
+        q.ids = g.ids_dev;
+        q.m = 2 * dr;
+        q.n = dl;
+        q.mode = 1;
+        q.batch = bsz;
+        qj.push_back(q);
+        gl.push_back({fbuf(), new_site(g, j), x2(), g.ids_dev, dl, dl, 2 * dr, 2 * dr, 2 * dr, dl,
+                      bsz});
+        gm.push_back({new_site(g, j - 1), x2(), x1(), g.ids_dev, 2 * dp, dl, dl, dl, dl, dl, bsz});
+      }
+      DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_J, OP_T, gl, s, CLS_GEMM));
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_T, gm, s, CLS_GEMM));
+      for (auto& g : groups) {
+        if (!g.warm) continue;
+        const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
+        DCS_TRY(embed(g, new_site(g, j), fbuf(), none, dl, dr, dl, dr, 0.0));
+        DCS_TRY(embed(g, new_site(g, j - 1), x1(), none, dp, dl, dp, dl, 0.0));
+      }
+    }
+    return DCS_OK;
   };
   // moving right at site j: X1 = L_j K_j, X2 = W X1, F = X2 R_{j+1}^T
   auto right_site = [&](int j, int qr_mode) -> int {
@@ -1392,6 +1472,7 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
       for (int j = nq - 2; j >= 0; --j) visits.push_back(j);
   }
   auto enqueue = [&]() -> int {
+    DCS_TRY(warm_bra());
     // right environments of the starting guess
     for (int j = nq - 1; j >= 1; --j) {
       DCS_TRY(left_prologue(j));
@@ -1415,6 +1496,8 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
     put(n_sweeps);
     for (auto& g : groups) {
       put(-1);
+      put(g.warm ? 1 : 0);
+      if (g.warm) sig.append(reinterpret_cast<const char*>(&st->warm_eta), sizeof(double));
       put(g.chi_cap);
       put(g.cur);
       put(g.goff);

@@ -126,6 +126,11 @@ class State:
             capi.dcs_state_set_init(self.h, chi, flat, eng.stream())
         self.free = list(range(capacity - 1, -1, -1))
 
+    def warm_start(self, eta: Optional[float]) -> None:
+        """Starting guess of later compression steps: None the generic guess,
+        else the ket plus eta times the generic guess (dcs_state_set_warm_start)."""
+        capi.dcs_state_set_warm_start(self.h, eta is not None, 0.0 if eta is None else eta)
+
     def alloc(self, k: int = 1) -> List[int]:
         if len(self.free) < k:
             raise capi.DcsError(capi.DCS_ECAPACITY, "no free branch slot")

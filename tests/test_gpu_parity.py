@@ -223,6 +223,63 @@ def test_single_path_cfg1_replay(eng, prec):
     st.close()
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
+@pytest.mark.parametrize("n,chi_ket,chi,sweeps,eta", [
+    (10, 16, 16, 2, 0.0),     # warm start from a ket of the same bonds
+    (12, 16, 16, 2, 0.02),    # truncated, seeded completion
+    (11, 8, 16, 2, 0.05),     # narrower ket padded into the bra's bonds
+    (9, 6, 12, 1, 0.1),       # one sweep
+    (17, 64, 130, 2, 0.01),   # several tiles and a ragged tail in the LQ chain
+])
+def test_warm_start_compress_parity(eng, prec, n, chi_ket, chi, sweeps, eta):
+    """Compression from the warm-start guess (dcs_state_set_warm_start)
+    against the oracle's compress with warm_bra of the same ket."""
+    capi = _capi()
+    rng = np.random.default_rng(100 * n + chi + chi_ket)
+    init_ket = OM.generic_bra(bra_init_gaussians(n, chi_ket, 5))
+    psi, _, _ = OM.compress(OM.zero_state(n, chi_ket),
+                            OM.chunk_mpo(n, _random_ops(rng, n, 3)), init_ket, 2)
+    ops = _random_ops(rng, n, 2)
+    gen = OM.generic_bra(bra_init_gaussians(n, chi, 5))
+    ref, f_ref, _ = OM.compress(psi, OM.chunk_mpo(n, ops), OM.warm_bra(psi, gen, eta), sweeps)
+    st = _E().State(eng, prec, n, 2, chi, 16, [chi], 5)
+    st.warm_start(eta)
+    capi.dcs_import_mps(st.h, 1, chi_ket, psi, eng.stream())
+    if chi_ket != chi:
+        capi.dcs_branch_set_chi(st.h, [1], [chi])
+    h = _compile(eng, n, ops)
+    f = capi.dcs_compress_step(st.h, [1], [h], sweeps, eng.stream())
+    gpu = st.export(1)
+    capi.dcs_chunk_destroy(h)
+    st.close()
+    print(f"{prec} warm n={n} chi={chi_ket}->{chi} eta={eta}: |df| = {abs(f[0] - f_ref):.2e}, "
+          f"state fidelity error = {_fid_err(gpu, ref):.2e}")
+    assert abs(f[0] - f_ref) < F_TOL[prec], (f[0], f_ref)
+    assert _fid_err(gpu, ref) < FE_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_warm_start_single_path_replay(eng, prec):
+    """A whole single-path run with the warm-start guess against the oracle
+    replaying the GPU's outcomes with the same guess."""
+    circ, prm = C.workload("cfg1_n10_chi16")
+    n, chi = prm["n"], prm["chi"]
+    k = C.segment_max(circ)
+    eta = 0.03
+    u = shot_uniforms(prm["seed"], 0, circ.n_measurements())[None, :]
+    st = _E().State(eng, prec, n, 1, chi, 4, [chi], prm["init_seed"])
+    st.warm_start(eta)
+    res = _E().run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u)
+    ref = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"], warm_eta=eta),
+                             outcomes=res["outcomes"][0])
+    np.testing.assert_allclose(res["p0s"][0], ref["p0s"], atol=TOL[prec], rtol=0)
+    assert abs(res["F"][0] - ref["F"]) < 10 * F_TOL[prec]
+    assert _fid_err(st.export(int(res["ids"][0])), ref["mps"]) < FE_TOL[prec]
+    with pytest.raises(_capi().DcsError):
+        _capi().dcs_state_set_warm_start(st.h, True, -1.0)
+    st.close()
+
+
 def test_exact_regime_run_matches_statevector(eng):
     circ, prm = C.workload("cfg1_n10_chi16", n=8, depth=8, chi=16)
     u = shot_uniforms(5, 0, circ.n_measurements())[None, :]

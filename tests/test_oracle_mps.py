@@ -204,3 +204,67 @@ def test_topk_stable_and_mass():
     assert abs(dropped - 0.15) < 1e-15
     keep, dropped = D.topk_by_weight([0.2] * 5, 2)
     assert keep == [0, 1] and abs(dropped - 0.6) < 1e-15
+
+
+def _random_mps(rng, n, chi):
+    """A normalised MPS with every bond at min(chi, 2^b, 2^(n-b)) and generic
+    (full-rank) bonds."""
+    dims = M.bond_dims(n, chi)
+    t = [rng.normal(size=(dims[j], 2, dims[j + 1])) + 1j * rng.normal(size=(dims[j], 2, dims[j + 1]))
+         for j in range(n)]
+    v = M.to_statevector(t)
+    t[0] = t[0] / np.linalg.norm(v)
+    return t
+
+
+def test_warm_bra_keeps_the_state_and_is_right_canonical():
+    """eta = 0: the LQ chain with absorbed L factors represents the ket
+    exactly; eta > 0: it represents the site-wise sum M_j = ket_j + eta G_j;
+    sites 1..n-1 have orthonormal rows in both cases."""
+    rng = np.random.default_rng(8)
+    n, chi = 7, 6
+    ket = _random_mps(rng, n, chi)
+    gen = M.generic_bra(bra_init_gaussians(n, chi, 3))
+    for eta in (0.0, 0.3):
+        b = M.warm_bra(ket, gen, eta)
+        msum = [k + eta * g for k, g in zip(ket, gen)]
+        np.testing.assert_allclose(M.to_statevector(b), M.to_statevector(msum), atol=1e-12)
+        for j in range(1, n):
+            dl, _, dr = b[j].shape
+            q = b[j].reshape(dl, 2 * dr)
+            np.testing.assert_allclose(q @ q.conj().T, np.eye(dl), atol=1e-12)
+
+
+def test_warm_bra_pads_a_narrower_ket():
+    """A ket of smaller bonds sits in the top-left block of each site; the
+    rest is eta G (seeded completion); the chain keeps that state."""
+    rng = np.random.default_rng(9)
+    n = 6
+    ket = _random_mps(rng, n, 2)
+    gen = M.generic_bra(bra_init_gaussians(n, 4, 3))
+    eta = 0.05
+    b = M.warm_bra(ket, gen, eta)
+    assert [t.shape for t in b] == [t.shape for t in gen]
+    msum = []
+    for k, g in zip(ket, gen):
+        t = eta * g.copy()
+        t[:k.shape[0], :, :k.shape[2]] += k
+        msum.append(t)
+    np.testing.assert_allclose(M.to_statevector(b), M.to_statevector(msum), atol=1e-12)
+    with pytest.raises(ValueError):
+        M.warm_bra(_random_mps(rng, n, 8), gen, eta)
+
+
+def test_warm_start_one_sweep_reproduces_the_ket():
+    """Identity chunk, warm start with eta = 0 from a ket of full-rank bonds:
+    the bra spans the ket's right subspaces, so one left-to-right sweep
+    returns the ket with f = 1."""
+    rng = np.random.default_rng(10)
+    n, chi = 6, 4
+    ket = _random_mps(rng, n, chi)
+    gen = M.generic_bra(bra_init_gaussians(n, chi, 3))
+    ident = M.chunk_mpo(n, [((0,), np.eye(2, dtype=complex))])
+    new, f, _ = M.compress(ket, ident, M.warm_bra(ket, gen, 0.0), 1)
+    assert abs(f - 1) < 1e-12
+    ov = np.vdot(M.to_statevector(new), M.to_statevector(ket))
+    assert abs(abs(ov) ** 2 - 1) < 1e-12
