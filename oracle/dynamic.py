@@ -70,23 +70,33 @@ def _unitary(op):
 
 
 def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[float]] = None,
-                    outcomes: Optional[Sequence[int]] = None) -> Dict:
+                    outcomes: Optional[Sequence[int]] = None,
+                    chi_ladder: Optional[Sequence[int]] = None, f_target: float = 0.0) -> Dict:
     """Alg. 1.  Outcomes come from ``outcomes`` when given (replay), else from
     ``uniforms`` (m = 0 iff u < p_0).  Returns the fidelity estimate, path
-    probability, register, final MPS and the per-measurement records."""
+    probability, register, final MPS and the per-measurement records.
+    Adaptive bond cap (a reading; the paper fixes chi per run): with
+    ``chi_ladder`` (ascending from sim.chi), a compression whose partial
+    fidelity is below ``f_target`` moves the run one rung up for the next
+    compressions; "chis" records the cap of every compression."""
     state = M.zero_state(circ.n_qubits, sim.chi)
     c = [0] * circ.n_bits
     p, fid = 1.0, 1.0
     chunk: List = []
-    rec = {"outcomes": [], "pms": [], "p0s": [], "fids": []}
+    rec = {"outcomes": [], "pms": [], "p0s": [], "fids": [], "chis": []}
     i_meas = 0
+    rung = 0
+    ladder = list(chi_ladder) if chi_ladder is not None else [sim.chi]
 
     def flush():
-        nonlocal state, fid, chunk
-        state, f = sim.compress(state, chunk, sim.chi)
+        nonlocal state, fid, chunk, rung
+        state, f = sim.compress(state, chunk, ladder[rung])
         fid *= f
         rec["fids"].append(f)
+        rec["chis"].append(ladder[rung])
         chunk = []
+        if f < f_target and rung + 1 < len(ladder):
+            rung += 1
 
     for op in circ.ops:
         if isinstance(op, CGate) and not holds(op.cond, c):
@@ -131,14 +141,33 @@ def topk_by_weight(weights: Sequence[float], k: int):
 
 def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = None,
                    chi_of: Optional[Callable[[tuple], int]] = None,
-                   eps: float = EPS_BRANCH) -> Dict:
+                   eps: float = EPS_BRANCH, chi_ladder: Optional[Sequence[int]] = None,
+                   f_target: float = 0.0) -> Dict:
     """Alg. 2.  ``chi_of(path)`` gives a child's bond cap (default: sim.chi).
+    With ``chi_ladder`` (ascending from sim.chi; a reading, the paper fixes
+    chi per run) a branch whose compression fidelity falls below ``f_target``
+    takes the next rung for its later compressions and passes its rung to
+    its children; "chis" records each branch's caps along its path.
     Returns the live branches (path, p, c, F, mps, chi), the dropped mass and
     the probability-weighted fidelity."""
+    ladder = list(chi_ladder) if chi_ladder is not None else [sim.chi]
     live = [{"path": (), "p": 1.0, "c": [0] * circ.n_bits, "F": 1.0, "chunk": [],
-             "mps": M.zero_state(circ.n_qubits, sim.chi), "chi": sim.chi}]
+             "mps": M.zero_state(circ.n_qubits, sim.chi), "chi": sim.chi, "rung": 0,
+             "chis": []}]
     dropped = 0.0
     n_compress = 0
+
+    def flush(b):
+        nonlocal n_compress
+        b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
+        b["F"] *= f
+        b["chunk"] = []
+        b["chis"].append(b["chi"])
+        n_compress += 1
+        if chi_ladder is not None and f < f_target and b["rung"] + 1 < len(ladder):
+            b["rung"] += 1
+            b["chi"] = ladder[b["rung"]]
+
     for op in circ.ops:
         nxt = []
         for b in live:
@@ -147,10 +176,7 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
                 continue
             if isinstance(op, Measure):
                 if b["chunk"]:
-                    b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
-                    b["F"] *= f
-                    b["chunk"] = []
-                    n_compress += 1
+                    flush(b)
                 n0, n1 = M.outcome_norms(b["mps"], op.qubit)
                 for m, nm in ((0, n0), (1, n1)):
                     pm = nm / (n0 + n1)
@@ -160,14 +186,12 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
                         path = b["path"] + (m,)
                         nxt.append({"path": path, "p": b["p"] * pm, "c": c, "F": b["F"],
                                     "chunk": [], "mps": M.collapse(b["mps"], op.qubit, m, nm),
-                                    "chi": chi_of(path) if chi_of else b["chi"]})
+                                    "chi": chi_of(path) if chi_of else b["chi"],
+                                    "rung": b["rung"], "chis": list(b["chis"])})
             else:
                 b["chunk"].append(_unitary(op))
                 if len(b["chunk"]) == sim.k:
-                    b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
-                    b["F"] *= f
-                    b["chunk"] = []
-                    n_compress += 1
+                    flush(b)
                 nxt.append(b)
         live = nxt
         if isinstance(op, Measure) and max_branches is not None and len(live) > max_branches:
@@ -176,10 +200,7 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
             live = [live[i] for i in keep]
     for b in live:
         if b["chunk"]:
-            b["mps"], f = sim.compress(b["mps"], b["chunk"], b["chi"])
-            b["F"] *= f
-            b["chunk"] = []
-            n_compress += 1
+            flush(b)
     ptot = sum(b["p"] for b in live)
     fmp = sum(b["p"] * b["F"] for b in live) / ptot if ptot > 0 else float("nan")
     return {"branches": live, "dropped": dropped, "F_mp": fmp, "n_compress": n_compress}

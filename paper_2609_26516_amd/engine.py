@@ -157,7 +157,8 @@ class State:
 
 def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int, k: int,
                     n_sweeps: int = 2, uniforms: Optional[np.ndarray] = None,
-                    outcomes: Optional[np.ndarray] = None, device_sampling: bool = False) -> Dict:
+                    outcomes: Optional[np.ndarray] = None, device_sampling: bool = False,
+                    chi_ladder: Optional[Sequence[int]] = None, f_target: float = 0.0) -> Dict:
     """Alg. 1 for `shots` independent trajectories advanced in lockstep.
 
     Outcome of measurement i of shot s: outcomes[s, i] when given (replay),
@@ -165,8 +166,19 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
     are due at the same operation are compressed in one batched call.  With
     device_sampling the draw and the collapse happen on the GPU
     (dcs_measure_sample_collapse); only the outcomes come back, for the
-    classical register (p_0 is then not reported: NaN)."""
+    classical register (p_0 is then not reported: NaN).
+
+    Adaptive bond cap: with `chi_ladder` (ascending, chi its first rung, every
+    rung registered in the state), a run whose compression returns a partial
+    fidelity below `f_target` compresses with the next rung from then on;
+    "chis" lists each run's caps, one per compression."""
     stream = eng.stream()
+    if chi_ladder is not None:
+        chi_ladder = [int(c) for c in chi_ladder]
+        if chi_ladder[0] != chi or any(a >= b for a, b in zip(chi_ladder, chi_ladder[1:])):
+            raise ValueError("chi_ladder must ascend from chi")
+    rung = np.zeros(shots, dtype=np.int64)
+    chis: List[List[int]] = [[] for _ in range(shots)]
     if device_sampling:
         if uniforms is None:
             raise ValueError("device sampling draws from given uniforms")
@@ -195,6 +207,12 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
         rec_f.append(f_all)
         for s in sel:
             chunk[s] = []
+            chis[s].append(chi_ladder[rung[s]] if chi_ladder else chi)
+        if chi_ladder is not None:
+            up = [s for s, fv in zip(sel, f) if fv < f_target and rung[s] + 1 < len(chi_ladder)]
+            if up:
+                rung[up] += 1
+                capi.dcs_branch_set_chi(st.h, ids[up], [chi_ladder[rung[s]] for s in up])
 
     try:
         for li, op in enumerate(circ.ops):
@@ -240,22 +258,34 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
     return {"ids": ids, "F": fid, "p": p, "regs": regs,
             "outcomes": np.array(rec_out).T if rec_out else np.zeros((shots, 0), np.int32),
             "p0s": np.array(rec_p0).T if rec_p0 else np.zeros((shots, 0)),
-            "fids": rec_f}
+            "fids": rec_f, "chis": chis}
 
 
 def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sweeps: int = 2,
                    max_branches: Optional[int] = None, chi_of=None,
-                   eps: float = EPS_BRANCH) -> Dict:
+                   eps: float = EPS_BRANCH, chi_ladder: Optional[Sequence[int]] = None,
+                   f_target: float = 0.0) -> Dict:
     """Alg. 2: every measurement splits each live branch into its outcomes with
     p_m > eps (m = 0 kept in place, m = 1 copied to a new slot); after the
     measurement at most `max_branches` branches with the largest p are kept.
     `chi_of(path)` gives a new child's bond cap.  Chunks of all branches due
-    at the same operation are compressed in one batched call."""
+    at the same operation are compressed in one batched call.
+
+    Adaptive bond cap: with `chi_ladder` (ascending from chi), a branch whose
+    compression returns a partial fidelity below `f_target` moves one rung up
+    for its later compressions, and its children start on its rung; each
+    branch's "chis" lists the caps of the compressions on its path."""
+    if chi_ladder is not None:
+        chi_ladder = [int(c) for c in chi_ladder]
+        if chi_of is not None:
+            raise ValueError("chi_ladder and chi_of are exclusive")
+        if chi_ladder[0] != chi or any(a >= b for a, b in zip(chi_ladder, chi_ladder[1:])):
+            raise ValueError("chi_ladder must ascend from chi")
     stream = eng.stream()
     first = st.alloc(1)[0]
     capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
-           "F": 1.0, "chunk": []}]
+           "F": 1.0, "chunk": [], "rung": 0, "chis": []}]
     dropped = 0.0
 
     def compress(sel: List[dict]) -> None:
@@ -263,9 +293,17 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
             return
         hs = [eng.chunk(circ, b["chunk"]) for b in sel]
         f = capi.dcs_compress_step(st.h, [b["id"] for b in sel], hs, n_sweeps, stream)
+        up = []
         for b, fv in zip(sel, f):
             b["F"] *= float(fv)
             b["chunk"] = []
+            b["chis"].append(chi_ladder[b["rung"]] if chi_ladder else None)
+            if chi_ladder and fv < f_target and b["rung"] + 1 < len(chi_ladder):
+                b["rung"] += 1
+                up.append(b)
+        if up:
+            capi.dcs_branch_set_chi(st.h, [b["id"] for b in up],
+                                    [chi_ladder[b["rung"]] for b in up])
 
     for li, op in enumerate(circ.ops):
         if isinstance(op, Measure):
@@ -289,7 +327,8 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 c = b["c"].copy()
                 c[op.bit] = m
                 nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
-                            "c": c, "F": b["F"], "chunk": []})
+                            "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
+                            "chis": list(b["chis"])})
             br = nxt
             if chi_of is not None:
                 capi.dcs_branch_set_chi(st.h, [b["id"] for b in br],

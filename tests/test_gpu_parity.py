@@ -280,6 +280,57 @@ def test_warm_start_single_path_replay(eng, prec):
     st.close()
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_adaptive_chi_single_path(eng, prec):
+    """Per-run adaptive bond cap (ladder 4, 8, 16; a run whose compression
+    fidelity is below 0.99 takes the next rung): six shots in lockstep against
+    the oracle replaying each shot's outcomes with the same ladder.  The
+    oracle's fidelities keep a margin from the target far above the kernel
+    tolerance, so both sides must climb at the same compressions."""
+    circ, prm = C.workload("cfg4_n24_chi64_x1024", n=12, depth=6, chi=4)
+    n, shots, k, ladder, tgt = 12, 6, 6, [4, 8, 16], 0.99
+    u = np.stack([shot_uniforms(prm["seed"], s, circ.n_measurements()) for s in range(shots)])
+    st = _E().State(eng, prec, n, shots, 16, 4, ladder, prm["init_seed"])
+    res = _E().run_single_path(eng, st, circ, shots, 4, k, 2, uniforms=u, chi_ladder=ladder,
+                               f_target=tgt)
+    sim = OD.Simulator(n, 4, k, 2, prm["init_seed"])
+    climbed = 0
+    for s in range(shots):
+        ref = OD.run_single_path(circ, sim, outcomes=res["outcomes"][s], chi_ladder=ladder,
+                                 f_target=tgt)
+        assert min(abs(np.array(ref["fids"]) - tgt)) > 1e-3
+        assert res["chis"][s] == ref["chis"], s
+        climbed += ref["chis"][-1] > 4
+        np.testing.assert_allclose(res["p0s"][s], ref["p0s"], atol=TOL[prec], rtol=0)
+        assert abs(res["F"][s] - ref["F"]) < 10 * F_TOL[prec]
+        assert _fid_err(st.export(int(res["ids"][s])), ref["mps"]) < FE_TOL[prec]
+    assert climbed == shots
+    st.close()
+
+
+def test_adaptive_chi_multi_path(eng):
+    """Alg. 2 with the per-branch ladder (2, 4, 8; target 0.99): the branch
+    set, each branch's caps along its path and its fidelity equal the
+    oracle's."""
+    circ, prm = C.workload("cfg1_n10_chi16", n=8, depth=4, chi=2)
+    ladder, tgt = [2, 4, 8], 0.99
+    st = _E().State(eng, "c128", 8, 40, 8, 4, ladder, prm["init_seed"])
+    res = _E().run_multi_path(eng, st, circ, 2, 3, 2, chi_ladder=ladder, f_target=tgt)
+    ref = OD.run_multi_path(circ, OD.Simulator(8, 2, 3, 2, prm["init_seed"]), chi_ladder=ladder,
+                            f_target=tgt)
+    got = {b["path"]: b for b in res["branches"]}
+    assert sorted(got) == sorted(b["path"] for b in ref["branches"])
+    for b in ref["branches"]:
+        g = got[b["path"]]
+        assert g["chis"] == b["chis"], b["path"]
+        assert abs(g["F"] - b["F"]) < 1e-10
+        assert abs(g["p"] - b["p"]) < 1e-11
+        assert _fid_err(st.export(int(g["id"])), b["mps"]) < 1e-10
+    assert abs(res["F_mp"] - ref["F_mp"]) < 1e-10
+    assert any(c > 2 for b in ref["branches"] for c in b["chis"])
+    st.close()
+
+
 def test_exact_regime_run_matches_statevector(eng):
     circ, prm = C.workload("cfg1_n10_chi16", n=8, depth=8, chi=16)
     u = shot_uniforms(5, 0, circ.n_measurements())[None, :]

@@ -268,3 +268,54 @@ def test_warm_start_one_sweep_reproduces_the_ket():
     assert abs(f - 1) < 1e-12
     ov = np.vdot(M.to_statevector(new), M.to_statevector(ket))
     assert abs(abs(ov) ** 2 - 1) < 1e-12
+
+
+def test_chi_ladder_reduces_to_fixed_cap():
+    """A ladder that never climbs (target 0) or has one rung is the fixed-cap
+    run: same outcomes, fidelities and state."""
+    circ, p = C.workload("cfg1_n10_chi16", n=6, depth=6, chi=2)
+    u = np.random.default_rng(5).random(64)
+    ref = D.run_single_path(circ, D.Simulator(6, 2, k=3), uniforms=u)
+    for ladder, target in (([2, 4, 8], 0.0), ([2], 2.0)):
+        r = D.run_single_path(circ, D.Simulator(6, 2, k=3), uniforms=u, chi_ladder=ladder,
+                              f_target=target)
+        assert r["outcomes"] == ref["outcomes"]
+        np.testing.assert_allclose(r["fids"], ref["fids"], atol=1e-13)
+        assert r["chis"] == [2] * len(ref["fids"])
+        assert abs(abs(M.overlap(r["mps"], ref["mps"])) ** 2 - 1) < 1e-11
+
+
+def test_chi_ladder_climbs_to_exact_cap():
+    """A target above 1 climbs one rung per compression; on 6 qubits the top
+    rung 8 is the exact bond dimension, so every later step has fidelity 1
+    and the estimate is the product of the truncated steps alone."""
+    circ, p = C.workload("cfg1_n10_chi16", n=6, depth=6, chi=2)
+    u = np.random.default_rng(5).random(64)
+    r = D.run_single_path(circ, D.Simulator(6, 2, k=6), uniforms=u, chi_ladder=[2, 4, 8],
+                          f_target=2.0)
+    fixed = D.run_single_path(circ, D.Simulator(6, 2, k=6), uniforms=u)
+    nc = len(r["fids"])
+    assert nc >= 3
+    assert r["chis"] == [2, 4] + [8] * (nc - 2)
+    assert r["fids"][0] < 1 - 1e-3
+    assert abs(r["fids"][0] - fixed["fids"][0]) < 1e-13
+    np.testing.assert_allclose(r["fids"][2:], 1.0, atol=1e-11)
+    assert abs(r["F"] - np.prod(r["fids"])) < 1e-14
+    mp = D.run_multi_path(circ, D.Simulator(6, 2, k=3), chi_ladder=[2, 8], f_target=2.0)
+    assert abs(sum(b["p"] for b in mp["branches"]) - 1) < 1e-11
+    for b in mp["branches"]:
+        assert b["chis"][0] == 2 and all(c == 8 for c in b["chis"][1:])
+        assert b["chi"] == 8
+
+
+def test_chi_ladder_multi_path_matches_single_path_replay():
+    """Each multi-path branch, replayed as a single path with the same ladder
+    and its outcomes, climbs the same rungs and reaches the same fidelity."""
+    circ, p = C.workload("cfg1_n10_chi16", n=6, depth=4, chi=2)
+    sim = D.Simulator(6, 2, k=3)
+    mp = D.run_multi_path(circ, sim, chi_ladder=[2, 4, 8], f_target=0.999)
+    for b in mp["branches"][:4]:
+        r = D.run_single_path(circ, sim, outcomes=list(b["path"]), chi_ladder=[2, 4, 8],
+                              f_target=0.999)
+        assert r["chis"] == b["chis"]
+        assert abs(r["F"] - b["F"]) < 1e-12
