@@ -52,7 +52,7 @@ extern "C" {
 enum dcs_status {
   DCS_OK = 0,
   DCS_EINVAL = -1,      /* bad argument (range, null pointer, duplicate id) */
-  DCS_ENONLOCAL = -2,   /* two-qubit gate not on adjacent qubits (q, q+1)   */
+  DCS_ENONLOCAL = -2,   /* two-qubit gate whose two qubits coincide         */
   DCS_EZEROPROB = -3,   /* collapse on an outcome with p_m <= eps           */
   DCS_ECAPACITY = -4,   /* branch id outside the state's capacity           */
   DCS_ENOMEM = -5,      /* buffer too small / chunk operator wider than the
@@ -160,19 +160,33 @@ int dcs_branch_dims(const dcs_state *st, int id, int *dims_out);
 
 /* Compile one chunk (Def. "Unitary chunk", Sec. IV-C) of n_ops unitaries in
  * time order into one layered operator per site: q0[i] the first qubit, q1[i]
- * = q0[i] + 1 for a two-qubit gate or -1 for a one-qubit gate; `mats` holds
- * the matrices back to back (complex128 interleaved, row-major, 2x2 or 4x4 in
- * basis |q0 q1> with q0 the more significant bit).  Gates are placed in ASAP
- * layers; a two-qubit gate is split across its qubits by an SVD of its
- * operator-Schmidt matrix (singular values above 1e-14 of the largest kept);
- * per site the layer operators are multiplied in time order.  Errors:
- * DCS_ENONLOCAL for a non-adjacent pair, DCS_EINVAL for a qubit out of range.
- * Host-only; the handle is independent of any state.  `ctx` may be NULL
- * (no caching of gate splits across calls). */
+ * the second qubit of a two-qubit gate (any other qubit) or -1 for a
+ * one-qubit gate; `mats` holds the matrices back to back (complex128
+ * interleaved, row-major, 2x2 or 4x4 in basis |q0 q1> with q0 the more
+ * significant bit).  Gates are placed in ASAP layers; a two-qubit gate is
+ * split across its qubits by an SVD of its operator-Schmidt matrix (singular
+ * values above 1e-14 of the largest kept, r of them); per site the layer
+ * operators are multiplied in time order.  A gate on non-adjacent qubits a <
+ * b is exact: the sites strictly between them get the identity with the
+ * gate's bond of dimension r passed through, so every bond a..b-1 is
+ * multiplied by r (the chunk's bond j is the product of the ranks of the
+ * gates spanning it).  A gate with q0 > q1 is applied as its qubit-swapped
+ * matrix on (q1, q0).  Errors: DCS_ENONLOCAL for q0 == q1, DCS_EINVAL for a
+ * qubit out of range.  Host-only; the handle is independent of any state.
+ * `ctx` may be NULL (no caching of gate splits across calls). */
 int dcs_chunk_compile(dcs_ctx *ctx, dcs_chunk **out, int n_qubits, int n_ops,
                       const int *q0, const int *q1, const double *mats);
+/* Operator-Schmidt rank r (1, 2 or 4) of one two-qubit gate (16 complex128
+ * interleaved, row-major, as in dcs_chunk_compile): the bond dimension the
+ * gate adds to every bond it spans.  Lets a caller close a chunk before its
+ * operator bond would exceed the state's mpo_bond_max.  Host-only, pure. */
+int dcs_gate_rank(const double *mat, int *rank_out);
 /* Operator bond dims w_0..w_n (n_qubits+1 ints; w_0 = w_n = 1). */
 int dcs_chunk_bonds(const dcs_chunk *ch, int *w_out);
+/* Host copy of the compiled operator: the sites W_0..W_{n-1} back to back,
+ * each row-major [w_j][2 (out)][2 (in)][w_{j+1}] complex128 interleaved
+ * (2 * sum w_j*4*w_{j+1} doubles, at most cap_doubles, else DCS_ENOMEM). */
+int dcs_chunk_export(const dcs_chunk *ch, double *out, size_t cap_doubles);
 int dcs_chunk_destroy(dcs_chunk *ch);
 
 /* Compression step (Sec. III-C) of branch ids[i] with chunk chunks[i], all
@@ -240,6 +254,22 @@ int dcs_measure_sample_collapse(dcs_state *st, int n, const int *ids, const int 
  * *discarded_out = sum of the weights not kept.  Host-only, pure. */
 int dcs_topk_by_weight(int n, const double *weights, int k, int *keep_idx_out,
                        int *n_keep_out, double *discarded_out);
+
+/* Adaptive pruning of the branch set, beyond the fixed top-M (the paper's
+ * closing remarks name it as an open direction; this rule is ours).  The
+ * branches are visited in descending weight (stable, as in
+ * dcs_topk_by_weight) and kept while all of: fewer than k_max are kept; the
+ * weight is at least rel_min times the largest weight; and, if mass_tol > 0,
+ * the mass kept so far is below (1 - mass_tol) times the total (total summed
+ * in index order, kept mass in visiting order).  The heaviest branch is
+ * always kept (n > 0).  mass_tol = rel_min = 0 is dcs_topk_by_weight with
+ * k = k_max.  keep_idx_out: capacity >= min(n, k_max), indices in visiting
+ * order; *discarded_out = sum of the weights not kept.  Errors: EINVAL for n
+ * < 0, k_max < 1, mass_tol outside [0, 1), rel_min outside [0, 1], a
+ * negative or NaN weight, or a null pointer.  Host-only, pure. */
+int dcs_prune_adaptive(int n, const double *weights, int k_max, double mass_tol,
+                       double rel_min, int *keep_idx_out, int *n_keep_out,
+                       double *discarded_out);
 
 /* <a|b> = sum over all indices of conj(A) B for branches id_a (bra) and id_b
  * (ket) of one state, by the FP64 left-transfer contraction E_{j+1} =

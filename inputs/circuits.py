@@ -3,9 +3,9 @@
 A dynamic circuit D = (Q, C, O) (Def. III.5) is an ordered list of operations
 over n qubits and m classical bits.  Operation kinds (Sec. III-A, Sec. IV-B):
 
-* ``Gate``     unitary on one qubit or on two adjacent qubits (q, q+1).  The
-               matrix is row-major in the basis |q q+1>, q the most
-               significant bit (Def. III.2).
+* ``Gate``     unitary on one qubit or on two distinct qubits (q0, q1), in
+               any order and at any distance.  The matrix is row-major in the
+               basis |q0 q1>, q0 the most significant bit (Def. III.2).
 * ``Measure``  computational-basis measurement of one qubit whose outcome is
                written to one classical bit (Def. III.3).
 * ``CGate``    a ``Gate`` applied only when its condition holds (Def. III.4).
@@ -42,15 +42,15 @@ CNOT_10 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]],
 
 @dataclass(frozen=True)
 class Gate:
-    qubits: Tuple[int, ...]          # (q,) or (q, q+1)
+    qubits: Tuple[int, ...]          # (q,) or (q0, q1), q0 != q1
     mat: np.ndarray = field(compare=False)
 
     def __post_init__(self):
         k = len(self.qubits)
         if k not in (1, 2):
             raise ValueError("gates act on one or two qubits")
-        if k == 2 and self.qubits[1] != self.qubits[0] + 1:
-            raise ValueError("two-qubit gates act on adjacent qubits (q, q+1)")
+        if k == 2 and self.qubits[1] == self.qubits[0]:
+            raise ValueError("a two-qubit gate acts on two distinct qubits")
         if self.mat.shape != (2 ** k, 2 ** k):
             raise ValueError("gate matrix shape does not match its qubits")
 
@@ -209,6 +209,54 @@ def brickwork(n: int, depth: int, layers_per_round: int, meas_per_round: int,
                     ops.append(CGate(Cond((b,), 1), Gate((q - 1,), Z)))
     return Circuit(n, n_bits, ops, name=name or f"brick{n}x{depth}",
                    meta={"seed": seed, "layers_per_round": layers_per_round})
+
+
+def random_dynamic(n: int, depth: int, seed: int, p_two: float = 0.5, p_round: float = 0.75,
+                   meas_max: Optional[int] = None, cond_max: int = 4,
+                   name: str = "") -> Circuit:
+    """Seeded random dynamic circuit in the style of the random-circuit study
+    (Sec. V-C): gates on arbitrary qubit pairs, measured subsets of varying
+    size and one or more classically controlled gates.
+
+    Each of the `depth` layers walks a random permutation of the qubits; with
+    probability p_two the next two qubits of the walk (in walk order, so at
+    any distance and in either order) get a Haar 4x4 gate, else the next
+    qubit gets a Haar 2x2 gate.  After a layer, with probability p_round a
+    measurement round follows: a random subset of 1..meas_max qubits (default
+    max(1, n // 3)), ascending, each into a fresh bit; then 1..cond_max
+    gates, each X, Z or a Haar 2x2 on a random qubit, conditioned on the
+    parity of a random non-empty subset of the round's bits equalling a
+    random value."""
+    rng = np.random.default_rng([int(seed), 0xD1A])
+    meas_max = max(1, n // 3) if meas_max is None else meas_max
+    ops: List[object] = []
+    n_bits = 0
+    for _ in range(depth):
+        walk = [int(q) for q in rng.permutation(n)]
+        i = 0
+        while i < n:
+            if i + 1 < n and rng.random() < p_two:
+                ops.append(Gate((walk[i], walk[i + 1]), haar_unitary(rng, 4)))
+                i += 2
+            else:
+                ops.append(Gate((walk[i],), haar_unitary(rng, 2)))
+                i += 1
+        if rng.random() < p_round:
+            size = int(rng.integers(1, meas_max + 1))
+            qs = np.sort(rng.choice(n, size=size, replace=False))
+            bits = []
+            for q in qs:
+                ops.append(Measure(int(q), n_bits))
+                bits.append(n_bits)
+                n_bits += 1
+            for _ in range(int(rng.integers(1, cond_max + 1))):
+                nb = int(rng.integers(1, len(bits) + 1))
+                cb = tuple(sorted(int(b) for b in rng.choice(bits, size=nb, replace=False)))
+                kind = int(rng.integers(3))
+                mat = (X, Z)[kind] if kind < 2 else haar_unitary(rng, 2)
+                ops.append(CGate(Cond(cb, int(rng.integers(2))), Gate((int(rng.integers(n)),), mat)))
+    return Circuit(n, n_bits, ops, name=name or f"random{n}x{depth}",
+                   meta={"seed": seed, "depth": depth})
 
 
 # Synthetic workloads with the shapes of the five benchmark configurations.

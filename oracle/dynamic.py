@@ -7,6 +7,10 @@ are appended to the branch's chunk; a classically controlled gate is appended
 when its condition holds on the branch's register and skipped otherwise
 (Sec. IV-B2); a chunk is compressed when it holds k operations, or, when it is
 non-empty, before a measurement; a residual chunk is compressed at the end.
+With an operator-bond cap w_cap (a reading, for gates on distant qubits whose
+operator bonds multiply): a gate that would make some bond of the chunk's
+operator exceed w_cap (M.span_bonds) first closes the current chunk, which is
+compressed, and then starts the next one.
 
 Single path (Alg. 1): a measurement samples outcome m with probability p_m
 (here: m = 0 when the supplied uniform u < p_0), p <- p p_m, the outcome is
@@ -44,10 +48,21 @@ class Simulator:
     sweeps s, the seed of the starting guess."""
 
     def __init__(self, n: int, chi: int, k: int, n_sweeps: int = 2, init_seed: int = 7,
-                 warm_eta: Optional[float] = None):
+                 warm_eta: Optional[float] = None, w_cap: Optional[int] = None):
         self.n, self.chi, self.k, self.s, self.init_seed = n, chi, k, n_sweeps, init_seed
         self.warm_eta = warm_eta   # None: generic guess; else warm start (M.warm_bra)
+        self.w_cap = w_cap         # None: no operator-bond cap on a chunk
         self._bra = {}
+
+    def closes_chunk(self, chunk, gate) -> bool:
+        """True when appending `gate` to the non-empty `chunk` would push an
+        operator bond past w_cap.  A gate over the cap on its own is an
+        error."""
+        if self.w_cap is None or len(gate[0]) == 1:
+            return False
+        if M.span_bonds(self.n, [gate]).max() > self.w_cap:
+            raise ValueError("a single gate exceeds the operator-bond cap")
+        return bool(chunk) and M.span_bonds(self.n, list(chunk) + [gate]).max() > self.w_cap
 
     def bra_init(self, chi: int) -> List[np.ndarray]:
         if chi not in self._bra:
@@ -122,7 +137,10 @@ def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[f
             rec["p0s"].append(p0)
             i_meas += 1
         else:
-            chunk.append(_unitary(op))
+            g = _unitary(op)
+            if sim.closes_chunk(chunk, g):
+                flush()
+            chunk.append(g)
             if len(chunk) == sim.k:
                 flush()
     if chunk:
@@ -139,11 +157,42 @@ def topk_by_weight(weights: Sequence[float], k: int):
     return keep, dropped
 
 
+def prune_adaptive(weights: Sequence[float], k_max: int, mass_tol: float = 0.0,
+                   rel_min: float = 0.0):
+    """Adaptive pruning beyond top-M (a reading of the open direction in the
+    conclusion): walk the weights from the largest down (ties in list order)
+    and keep each while fewer than k_max are kept, it is at least rel_min
+    times the largest weight, and, for mass_tol > 0, the mass kept before it
+    is below (1 - mass_tol) times the total (summed in list order).  The
+    largest is always kept.  Returns the kept indices and the dropped mass."""
+    order = sorted(range(len(weights)), key=lambda i: -weights[i])   # stable
+    total = 0.0
+    for w in weights:
+        total += float(w)
+    keep, kept = [], 0.0
+    for i in order:
+        w = float(weights[i])
+        if len(keep) == k_max:
+            break
+        if keep and (w < rel_min * float(weights[order[0]])
+                     or (mass_tol > 0 and kept >= (1.0 - mass_tol) * total)):
+            break
+        keep.append(i)
+        kept += w
+    dropped = 0.0
+    for i in order[len(keep):]:
+        dropped += float(weights[i])
+    return keep, dropped
+
+
 def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = None,
                    chi_of: Optional[Callable[[tuple], int]] = None,
                    eps: float = EPS_BRANCH, chi_ladder: Optional[Sequence[int]] = None,
-                   f_target: float = 0.0) -> Dict:
+                   f_target: float = 0.0, prune: Optional[Sequence[float]] = None) -> Dict:
     """Alg. 2.  ``chi_of(path)`` gives a child's bond cap (default: sim.chi).
+    ``prune = (mass_tol, rel_min)`` replaces the top-M step by
+    prune_adaptive(p, max_branches or all, mass_tol, rel_min), applied after
+    every measurement.
     With ``chi_ladder`` (ascending from sim.chi; a reading, the paper fixes
     chi per run) a branch whose compression fidelity falls below ``f_target``
     takes the next rung for its later compressions and passes its rung to
@@ -189,12 +238,20 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
                                     "chi": chi_of(path) if chi_of else b["chi"],
                                     "rung": b["rung"], "chis": list(b["chis"])})
             else:
-                b["chunk"].append(_unitary(op))
+                g = _unitary(op)
+                if sim.closes_chunk(b["chunk"], g):
+                    flush(b)
+                b["chunk"].append(g)
                 if len(b["chunk"]) == sim.k:
                     flush(b)
                 nxt.append(b)
         live = nxt
-        if isinstance(op, Measure) and max_branches is not None and len(live) > max_branches:
+        if isinstance(op, Measure) and prune is not None:
+            keep, d = prune_adaptive([b["p"] for b in live], max_branches or len(live),
+                                     prune[0], prune[1])
+            dropped += d
+            live = [live[i] for i in keep]
+        elif isinstance(op, Measure) and max_branches is not None and len(live) > max_branches:
             keep, d = topk_by_weight([b["p"] for b in live], max_branches)
             dropped += d
             live = [live[i] for i in keep]

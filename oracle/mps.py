@@ -141,6 +141,53 @@ def split_two_qubit(mat: np.ndarray, cutoff: float = SPLIT_CUTOFF) -> Tuple[np.n
     return left, right
 
 
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def route_swaps(ops: Sequence[Tuple[Tuple[int, ...], np.ndarray]]) -> List:
+    """Nearest-neighbour form of a gate list by SWAP routing: a gate on
+    (q0, q1) that is not (q, q+1) becomes the SWAPs (j, j+1) that carry the
+    content of qubit q1 (if q1 > q0) or of qubit q0 (if q0 > q1) next to the
+    other qubit, the gate on the adjacent pair in the order of its own
+    qubits, and the same SWAPs undone in reverse order."""
+    out = []
+    for qubits, mat in ops:
+        if len(qubits) == 1 or qubits[1] == qubits[0] + 1:
+            out.append((tuple(qubits), mat))
+            continue
+        a, b = qubits
+        if a < b:          # move q1 from b down to a + 1
+            swaps = [(j, j + 1) for j in range(b - 1, a, -1)]
+            pair = (a, a + 1)
+        else:              # move q0 from a down to b; q1 then sits at b + 1
+            swaps = [(j, j + 1) for j in range(a - 1, b - 1, -1)]
+            pair = (b, b + 1)
+        out.extend((sw, SWAP) for sw in swaps)
+        out.append((pair, mat))
+        out.extend((sw, SWAP) for sw in reversed(swaps))
+    return out
+
+
+def gate_rank(mat: np.ndarray, cutoff: float = SPLIT_CUTOFF) -> int:
+    """Operator-Schmidt rank of a 4x4 gate: the number of singular values of
+    its regrouped matrix (as in split_two_qubit) above cutoff times the
+    largest."""
+    return split_two_qubit(np.asarray(mat, dtype=np.complex128), cutoff)[0].shape[3]
+
+
+def span_bonds(n: int, ops: Sequence[Tuple[Tuple[int, ...], np.ndarray]]) -> np.ndarray:
+    """Operator bond of a chunk with non-adjacent gates carried exactly across
+    the sites they span: entry j + 1, the bond between qubits j and j+1, is
+    the product of the operator-Schmidt ranks of the two-qubit gates whose
+    qubits lie on both sides of it.  Entries 0 and n are 1."""
+    w = np.ones(n + 1, dtype=np.int64)
+    for qubits, mat in ops:
+        if len(qubits) == 2:
+            lo, hi = min(qubits), max(qubits)
+            w[lo + 1:hi + 1] *= gate_rank(mat)
+    return w
+
+
 def asap_layers(ops: Sequence[Tuple[Tuple[int, ...], np.ndarray]]) -> List[List]:
     """Place each gate in the first layer after the last layer that touches
     any of its qubits (time order preserved per qubit)."""
@@ -159,13 +206,15 @@ def asap_layers(ops: Sequence[Tuple[Tuple[int, ...], np.ndarray]]) -> List[List]
 def chunk_mpo(n: int, ops: Sequence[Tuple[Tuple[int, ...], np.ndarray]]) -> List[np.ndarray]:
     """Layered operator of a chunk: W_j[w_l, s(out), t(in), w_r] per site.
 
-    Each layer gives one operator per site (identity where no gate acts); the
+    Gates on non-adjacent or reversed pairs are first SWAP-routed to
+    nearest-neighbour gates (route_swaps).  Each layer gives one operator per
+    site (identity where no gate acts); the
     per-site operators of successive layers are multiplied in time order, the
     combined bond index being (earlier layer, later layer) with the earlier
     layer most significant."""
     ident = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
     total = [ident.copy() for _ in range(n)]
-    for layer in asap_layers(ops):
+    for layer in asap_layers(route_swaps(ops)):
         site_ops = [ident for _ in range(n)]
         for qubits, mat in layer:
             if len(qubits) == 1:

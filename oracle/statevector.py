@@ -24,18 +24,32 @@ def zero_state(n: int) -> np.ndarray:
 
 
 def apply_gate(psi: np.ndarray, n: int, qubits, mat: np.ndarray) -> np.ndarray:
-    """psi <- (I (x) U (x) I) psi for a gate on qubit q or on (q, q+1)."""
-    q = qubits[0]
+    """psi <- U psi with U acting on the listed qubits (one, or two distinct
+    qubits in the order of the matrix's basis) and the identity elsewhere."""
     k = len(qubits)
-    t = psi.reshape(2 ** q, 2 ** k, 2 ** (n - q - k))
-    return np.einsum("ij,ajb->aib", mat, t).reshape(-1)
+    t = np.moveaxis(psi.reshape((2,) * n), list(qubits), list(range(k)))
+    shape = t.shape
+    t = (mat @ t.reshape(2 ** k, -1)).reshape(shape)
+    return np.moveaxis(t, list(range(k)), list(qubits)).reshape(-1)
 
 
 def full_operator(n: int, qubits, mat: np.ndarray) -> np.ndarray:
-    """The gate embedded in the full 2^n space by Kronecker products."""
+    """The gate embedded in the full 2^n space.  For one qubit or an
+    adjacent pair (q, q+1) by Kronecker products with identities; otherwise
+    entry by entry: <i|U|j> = mat[(i_q0 i_q1), (j_q0 j_q1)] when i and j
+    agree on every other qubit, else 0 (small n only)."""
     q = qubits[0]
     k = len(qubits)
-    return np.kron(np.kron(np.eye(2 ** q), mat), np.eye(2 ** (n - q - k)))
+    if k == 1 or qubits[1] == q + 1:
+        return np.kron(np.kron(np.eye(2 ** q), mat), np.eye(2 ** (n - q - k)))
+    a, b = qubits
+    bit = lambda x, j: (x >> (n - 1 - j)) & 1                         # noqa: E731
+    full = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
+    for i in range(2 ** n):
+        for j in range(2 ** n):
+            if all(bit(i, o) == bit(j, o) for o in range(n) if o not in (a, b)):
+                full[i, j] = mat[2 * bit(i, a) + bit(i, b), 2 * bit(j, a) + bit(j, b)]
+    return full
 
 
 def outcome_norms(psi: np.ndarray, n: int, q: int) -> Tuple[float, float]:

@@ -29,8 +29,8 @@ EXPORTED = [
     "dcs_ctx_timing", "dcs_ctx_set_graphs", "dcs_ctx_set_tuning", "dcs_ctx_tuning_save",
     "dcs_ctx_tuning_load", "dcs_state_bytes", "dcs_state_create", "dcs_state_destroy",
     "dcs_state_set_init", "dcs_state_set_warm_start", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
-    "dcs_branch_dims", "dcs_chunk_compile", "dcs_chunk_bonds", "dcs_chunk_destroy",
-    "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight",
+    "dcs_branch_dims", "dcs_chunk_compile", "dcs_gate_rank", "dcs_chunk_bonds", "dcs_chunk_export", "dcs_chunk_destroy",
+    "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight", "dcs_prune_adaptive",
     "dcs_overlap", "dcs_export_mps", "dcs_import_mps",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
@@ -72,6 +72,8 @@ _SIGS = {
     "dcs_branch_dims": (c_int, [_P, c_int, _IP]),
     "dcs_chunk_compile": (c_int, [_P, POINTER(c_void_p), c_int, c_int, _IP, _IP, _DP]),
     "dcs_chunk_bonds": (c_int, [_P, _IP]),
+    "dcs_gate_rank": (c_int, [_DP, _IP]),
+    "dcs_chunk_export": (c_int, [_P, _DP, c_size_t]),
     "dcs_chunk_destroy": (c_int, [_P]),
     "dcs_state_set_warm_start": (c_int, [_P, c_int, c_double]),
     "dcs_compress_step": (c_int, [_P, c_int, _IP, POINTER(c_void_p), c_int, _DP, _P]),
@@ -79,6 +81,7 @@ _SIGS = {
     "dcs_measure_sample_collapse": (c_int, [_P, c_int, _IP, _IP, _P, c_double, _P, _P, _P]),
     "dcs_collapse": (c_int, [_P, c_int, _IP, _IP, _IP, _IP, c_double, _DP, _P]),
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
+    "dcs_prune_adaptive": (c_int, [c_int, _DP, c_int, c_double, c_double, _IP, _IP, _DP]),
     "dcs_overlap": (c_int, [_P, c_int, c_int, _DP, _P]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
@@ -223,6 +226,27 @@ def dcs_chunk_bonds(ch, n_qubits) -> np.ndarray:
     return out
 
 
+def dcs_chunk_export(ch, n_qubits):
+    """The compiled operator as a list of W_j[w_j, 2, 2, w_j+1] arrays."""
+    w = dcs_chunk_bonds(ch, n_qubits)
+    sizes = [int(w[j]) * 4 * int(w[j + 1]) for j in range(n_qubits)]
+    buf = np.zeros(2 * sum(sizes))
+    _check(_lib.dcs_chunk_export(ch, _dp(buf), buf.size))
+    z = buf.view(np.complex128)
+    out, o = [], 0
+    for j, sz in enumerate(sizes):
+        out.append(z[o:o + sz].reshape(int(w[j]), 2, 2, int(w[j + 1])).copy())
+        o += sz
+    return out
+
+
+def dcs_gate_rank(mat) -> int:
+    m = np.ascontiguousarray(np.asarray(mat, dtype=np.complex128).reshape(16)).view(np.float64)
+    r = c_int()
+    _check(_lib.dcs_gate_rank(_dp(m), ctypes.byref(r)))
+    return r.value
+
+
 def dcs_chunk_destroy(ch) -> None:
     _check(_lib.dcs_chunk_destroy(ch))
 
@@ -269,6 +293,16 @@ def dcs_topk_by_weight(weights, k):
     disc = c_double()
     _check(_lib.dcs_topk_by_weight(len(w), _dp(w), k, _ip(keep), ctypes.byref(nk),
                                    ctypes.byref(disc)))
+    return keep[:nk.value].copy(), disc.value
+
+
+def dcs_prune_adaptive(weights, k_max, mass_tol=0.0, rel_min=0.0):
+    w = _dbl(weights)
+    keep = np.zeros(max(1, min(len(w), k_max)), dtype=np.int32)
+    nk = c_int()
+    disc = c_double()
+    _check(_lib.dcs_prune_adaptive(len(w), _dp(w), k_max, mass_tol, rel_min, _ip(keep),
+                                   ctypes.byref(nk), ctypes.byref(disc)))
     return keep[:nk.value].copy(), disc.value
 
 

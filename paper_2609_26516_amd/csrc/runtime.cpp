@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <array>
 #include <cstdio>
@@ -1113,20 +1114,37 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
     if (q0[i] < 0 || q0[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
     if (q1[i] != -1) {
       if (q1[i] < 0 || q1[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
-      if (q1[i] != q0[i] + 1)
+      if (q1[i] == q0[i])
         return fail(DCS_ENONLOCAL, "two-qubit gate on (" + std::to_string(q0[i]) + ", " +
-                                       std::to_string(q1[i]) + ") is not on (q, q+1)");
+                                       std::to_string(q1[i]) + "): the qubits coincide");
     }
   }
   // ASAP layers: each gate goes to the first layer after the last one that
-  // touches any of its qubits.
+  // touches any of its qubits.  A gate on (a, b) with a > b is the gate
+  // SWAP U SWAP on (b, a); a gate whose qubits are not adjacent acts as the
+  // identity on the sites between them, which carry its operator bond.
   std::vector<int> last(n_qubits, -1);
   std::vector<std::vector<int>> layers;
   std::vector<size_t> mat_off(n_ops);
+  std::vector<double> swapped;   // reordered matrices of the (a > b) gates
+  std::vector<size_t> sw_off(n_ops, SIZE_MAX);
   size_t mo = 0;
   for (int i = 0; i < n_ops; ++i) {
     mat_off[i] = mo;
     mo += (q1[i] == -1) ? 8 : 32;
+    if (q1[i] != -1 && q1[i] < q0[i]) {
+      // element (s0 s1, t0 t1) of the swapped gate is element (s1 s0, t1 t0)
+      const double* m = mats + mat_off[i];
+      sw_off[i] = swapped.size();
+      swapped.resize(swapped.size() + 32);
+      double* d = swapped.data() + sw_off[i];
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          const int rs = ((r & 1) << 1) | (r >> 1), cs = ((c & 1) << 1) | (c >> 1);
+          d[2 * (r * 4 + c)] = m[2 * (rs * 4 + cs)];
+          d[2 * (r * 4 + c) + 1] = m[2 * (rs * 4 + cs) + 1];
+        }
+    }
     int lay = last[q0[i]];
     if (q1[i] != -1) lay = std::max(lay, last[q1[i]]);
     lay += 1;
@@ -1141,8 +1159,9 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
   ch->site.assign(n_qubits, std::vector<cd>{1.0, 0.0, 0.0, 1.0});
   for (const auto& layer : layers) {
     for (int i : layer) {
-      const double* m = mats + mat_off[i];
-      const int q = q0[i];
+      const double* m = sw_off[i] != SIZE_MAX ? swapped.data() + sw_off[i] : mats + mat_off[i];
+      const int q = q1[i] == -1 ? q0[i] : std::min(q0[i], q1[i]);
+      const int qr = q1[i] == -1 ? q : std::max(q0[i], q1[i]);
       if (q1[i] == -1) {
         std::vector<cd> u(4);
         for (int k = 0; k < 4; ++k) u[k] = cd(m[2 * k], m[2 * k + 1]);
@@ -1164,8 +1183,19 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
         const Split& sp = *spp;
         ch->site[q] = op_product(ch->site[q], wl[q], wr[q], sp.left, 1, sp.r);
         wr[q] *= sp.r;
-        ch->site[q + 1] = op_product(ch->site[q + 1], wl[q + 1], wr[q + 1], sp.right, sp.r, 1);
-        wl[q + 1] *= sp.r;
+        if (qr > q + 1) {
+          // identity on the physical leg, the bond index passed through
+          std::vector<cd> pass((size_t)sp.r * 4 * sp.r, 0.0);
+          for (int w = 0; w < sp.r; ++w)
+            for (int t = 0; t < 2; ++t) pass[((size_t)(w * 2 + t) * 2 + t) * sp.r + w] = 1.0;
+          for (int j = q + 1; j < qr; ++j) {
+            ch->site[j] = op_product(ch->site[j], wl[j], wr[j], pass, sp.r, sp.r);
+            wl[j] *= sp.r;
+            wr[j] *= sp.r;
+          }
+        }
+        ch->site[qr] = op_product(ch->site[qr], wl[qr], wr[qr], sp.right, sp.r, 1);
+        wl[qr] *= sp.r;
       }
     }
   }
@@ -1181,9 +1211,29 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
   return DCS_OK;
 }
 
+int dcs_gate_rank(const double* mat, int* rank_out) {
+  if (!mat || !rank_out) return fail(DCS_EINVAL, "null argument");
+  *rank_out = split_gate(mat).r;
+  return DCS_OK;
+}
+
 int dcs_chunk_bonds(const dcs_chunk* ch, int* w_out) {
   if (!ch || !w_out) return fail(DCS_EINVAL, "null argument");
   for (int b = 0; b <= ch->n; ++b) w_out[b] = ch->w[b];
+  return DCS_OK;
+}
+
+int dcs_chunk_export(const dcs_chunk* ch, double* out, size_t cap_doubles) {
+  if (!ch || !out) return fail(DCS_EINVAL, "null argument");
+  size_t need = 0;
+  for (const auto& w : ch->site) need += 2 * w.size();
+  if (need > cap_doubles) return fail(DCS_ENOMEM, "output too small for the chunk operator");
+  for (const auto& w : ch->site) {
+    for (const cd& z : w) {
+      *out++ = z.real();
+      *out++ = z.imag();
+    }
+  }
   return DCS_OK;
 }
 
@@ -1918,6 +1968,38 @@ int dcs_topk_by_weight(int n, const double* weights, int k, int* keep_idx_out, i
   for (int i = keep; i < n; ++i) dropped += weights[order[i]];
   for (int i = 0; i < keep; ++i) keep_idx_out[i] = order[i];
   *n_keep_out = keep;
+  if (discarded_out) *discarded_out = dropped;
+  return DCS_OK;
+}
+
+int dcs_prune_adaptive(int n, const double* weights, int k_max, double mass_tol, double rel_min,
+                       int* keep_idx_out, int* n_keep_out, double* discarded_out) {
+  if (n < 0 || k_max < 1) return fail(DCS_EINVAL, "n must be >= 0 and k_max >= 1");
+  if ((n > 0 && !weights) || !n_keep_out) return fail(DCS_EINVAL, "null argument");
+  if (!(mass_tol >= 0.0 && mass_tol < 1.0) || !(rel_min >= 0.0 && rel_min <= 1.0))
+    return fail(DCS_EINVAL, "mass_tol must be in [0, 1) and rel_min in [0, 1]");
+  if (n > 0 && !keep_idx_out) return fail(DCS_EINVAL, "null keep_idx_out");
+  for (int i = 0; i < n; ++i)
+    if (!(weights[i] >= 0.0)) return fail(DCS_EINVAL, "weights must be non-negative");
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return weights[a] > weights[b]; });
+  double total = 0;
+  for (int i = 0; i < n; ++i) total += weights[i];
+  const double floor_w = n > 0 ? rel_min * weights[order[0]] : 0.0;
+  const double goal = (1.0 - mass_tol) * total;
+  double kept = 0;
+  int nk = 0;
+  for (int i = 0; i < n && nk < k_max; ++i) {
+    const double w = weights[order[i]];
+    if (nk > 0 && (w < floor_w || (mass_tol > 0.0 && kept >= goal))) break;
+    keep_idx_out[nk++] = order[i];
+    kept += w;
+  }
+  double dropped = 0;
+  for (int i = nk; i < n; ++i) dropped += weights[order[i]];
+  *n_keep_out = nk;
   if (discarded_out) *discarded_out = dropped;
   return DCS_OK;
 }

@@ -68,9 +68,28 @@ class Engine:
         self._chunks[key] = (circ, h)
         return h
 
+    def span(self, circ: Circuit, li: int):
+        """(lo, hi, r) of operation li: the qubit range a two-qubit gate's
+        operator bond spans and its operator-Schmidt rank (dcs_gate_rank);
+        None for a one-qubit gate."""
+        key = (id(circ), "span")
+        hit = self._chunks.get(key)
+        if hit is None or hit[0] is not circ:
+            hit = (circ, {})
+            self._chunks[key] = hit
+        cache = hit[1]
+        if li not in cache:
+            g = _gate_of(circ.ops[li])
+            if len(g.qubits) == 1:
+                cache[li] = None
+            else:
+                cache[li] = (min(g.qubits), max(g.qubits), capi.dcs_gate_rank(g.mat))
+        return cache[li]
+
     def clear_chunks(self) -> None:
         for _, h in self._chunks.values():
-            capi.dcs_chunk_destroy(h)
+            if not isinstance(h, dict):
+                capi.dcs_chunk_destroy(h)
         self._chunks.clear()
 
     def tuning(self, enabled: bool, reps: int = 3) -> None:
@@ -107,6 +126,7 @@ class State:
                  mpo_bond_max: int = 4, init_chis: Sequence[int] = (), init_seed: int = 7,
                  gaussians=None):
         self.eng, self.n, self.capacity, self.chi_max = eng, n_qubits, capacity, chi_max
+        self.wmax = mpo_bond_max
         self.precision = PRECISIONS[precision]
         chis = sorted(set(init_chis)) or [chi_max]
         nbytes = capi.dcs_state_bytes(self.precision, n_qubits, capacity, chi_max, mpo_bond_max,
@@ -155,6 +175,34 @@ class State:
             self.buf = None
 
 
+class _Bonds:
+    """Operator bond of an open chunk, bond j + 1 between qubits j and j + 1:
+    the product of the ranks of the gates spanning it (as dcs_chunk_compile
+    builds it).  A gate that would push a bond past the state's
+    mpo_bond_max closes the chunk first."""
+
+    def __init__(self, eng: Engine, circ: Circuit, wmax: int):
+        self.eng, self.circ, self.wmax = eng, circ, wmax
+        self.w = np.ones(circ.n_qubits + 1, dtype=np.int64)
+
+    def closes(self, li: int, nonempty: bool) -> bool:
+        sp = self.eng.span(self.circ, li)
+        if sp is None:
+            return False
+        lo, hi, r = sp
+        if r > self.wmax:
+            raise ValueError(f"gate {li} has operator rank {r} > mpo_bond_max {self.wmax}")
+        return nonempty and int(self.w[lo + 1:hi + 1].max()) * r > self.wmax
+
+    def add(self, li: int) -> None:
+        sp = self.eng.span(self.circ, li)
+        if sp is not None:
+            self.w[sp[0] + 1:sp[1] + 1] *= sp[2]
+
+    def reset(self) -> None:
+        self.w[:] = 1
+
+
 def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int, k: int,
                     n_sweeps: int = 2, uniforms: Optional[np.ndarray] = None,
                     outcomes: Optional[np.ndarray] = None, device_sampling: bool = False,
@@ -193,6 +241,7 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
     p = np.ones(shots)
     fid = np.ones(shots)
     chunk: List[List[int]] = [[] for _ in range(shots)]
+    bonds = [_Bonds(eng, circ, st.wmax) for _ in range(shots)]
     rec_out, rec_p0, rec_f = [], [], []
     i_meas = 0
 
@@ -207,6 +256,7 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
         rec_f.append(f_all)
         for s in sel:
             chunk[s] = []
+            bonds[s].reset()
             chis[s].append(chi_ladder[rung[s]] if chi_ladder else chi)
         if chi_ladder is not None:
             up = [s for s, fv in zip(sel, f) if fv < f_target and rung[s] + 1 < len(chi_ladder)]
@@ -245,9 +295,12 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
                 active = np.nonzero(_cond_true(op.cond, regs))[0]
             else:
                 active = range(shots)
+            compress(np.array([s for s in active if bonds[s].closes(li, bool(chunk[s]))],
+                              dtype=np.int64))
             due = []
             for s in active:
                 chunk[s].append(li)
+                bonds[s].add(li)
                 if len(chunk[s]) == k:
                     due.append(s)
             compress(np.array(due, dtype=np.int64))
@@ -264,10 +317,12 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
 def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sweeps: int = 2,
                    max_branches: Optional[int] = None, chi_of=None,
                    eps: float = EPS_BRANCH, chi_ladder: Optional[Sequence[int]] = None,
-                   f_target: float = 0.0) -> Dict:
+                   f_target: float = 0.0, prune: Optional[Sequence[float]] = None) -> Dict:
     """Alg. 2: every measurement splits each live branch into its outcomes with
     p_m > eps (m = 0 kept in place, m = 1 copied to a new slot); after the
-    measurement at most `max_branches` branches with the largest p are kept.
+    measurement at most `max_branches` branches with the largest p are kept,
+    or, with `prune = (mass_tol, rel_min)`, the branches dcs_prune_adaptive
+    keeps (at most `max_branches`, if given).
     `chi_of(path)` gives a new child's bond cap.  Chunks of all branches due
     at the same operation are compressed in one batched call.
 
@@ -285,7 +340,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     first = st.alloc(1)[0]
     capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
-           "F": 1.0, "chunk": [], "rung": 0, "chis": []}]
+           "F": 1.0, "chunk": [], "rung": 0, "chis": [], "w": _Bonds(eng, circ, st.wmax)}]
     dropped = 0.0
 
     def compress(sel: List[dict]) -> None:
@@ -297,6 +352,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
         for b, fv in zip(sel, f):
             b["F"] *= float(fv)
             b["chunk"] = []
+            b["w"].reset()
             b["chis"].append(chi_ladder[b["rung"]] if chi_ladder else None)
             if chi_ladder and fv < f_target and b["rung"] + 1 < len(chi_ladder):
                 b["rung"] += 1
@@ -328,23 +384,30 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 c[op.bit] = m
                 nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
                             "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
-                            "chis": list(b["chis"])})
+                            "chis": list(b["chis"]), "w": _Bonds(eng, circ, st.wmax)})
             br = nxt
             if chi_of is not None:
                 capi.dcs_branch_set_chi(st.h, [b["id"] for b in br],
                                         [chi_of(b["path"]) for b in br])
-            if max_branches is not None and len(br) > max_branches:
-                keep, disc = capi.dcs_topk_by_weight([b["p"] for b in br], max_branches)
+            if prune is not None or (max_branches is not None and len(br) > max_branches):
+                if prune is not None:
+                    keep, disc = capi.dcs_prune_adaptive([b["p"] for b in br],
+                                                         max_branches or len(br),
+                                                         prune[0], prune[1])
+                else:
+                    keep, disc = capi.dcs_topk_by_weight([b["p"] for b in br], max_branches)
                 dropped += disc
                 kept = set(int(i) for i in keep)
                 st.release([b["id"] for i, b in enumerate(br) if i not in kept])
                 br = [br[int(i)] for i in keep]
             continue
+        act = [b for b in br
+               if not (isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0])]
+        compress([b for b in act if b["w"].closes(li, bool(b["chunk"]))])
         due = []
-        for b in br:
-            if isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0]:
-                continue
+        for b in act:
             b["chunk"].append(li)
+            b["w"].add(li)
             if len(b["chunk"]) == k:
                 due.append(b)
         compress(due)

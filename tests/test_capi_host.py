@@ -85,8 +85,13 @@ def test_chunk_compile_bonds_and_errors():
     assert list(capi.dcs_chunk_bonds(h, 3)) == [1, 1, 4, 1]
     capi.dcs_chunk_destroy(h)
     with pytest.raises(capi.DcsError) as e:
-        capi.dcs_chunk_compile(0, 4, [0], [2], C.CNOT_01.reshape(-1))
+        capi.dcs_chunk_compile(0, 4, [2], [2], C.CNOT_01.reshape(-1))
     assert e.value.code == capi.DCS_ENONLOCAL
+    # a distant pair spans its bonds: CNOT (0, 2) and reversed CNOT (3, 1)
+    mats = np.concatenate([C.CNOT_01.reshape(-1), C.CNOT_01.reshape(-1)])
+    h = capi.dcs_chunk_compile(0, 4, [0, 3], [2, 1], mats)
+    assert list(capi.dcs_chunk_bonds(h, 4)) == [1, 2, 4, 2, 1]
+    capi.dcs_chunk_destroy(h)
     with pytest.raises(capi.DcsError) as e:
         capi.dcs_chunk_compile(0, 4, [4], [-1], C.X.reshape(-1))
     assert e.value.code == capi.DCS_EINVAL
@@ -102,3 +107,69 @@ def test_state_bytes_validation():
         with pytest.raises(capi.DcsError) as e:
             capi.dcs_state_bytes(*bad)
         assert e.value.code == capi.DCS_EINVAL
+
+
+def _op_matrix(mpo):
+    t = mpo[0][0].reshape(2, 2, -1)
+    d = 2
+    for w in mpo[1:]:
+        t = np.einsum("ijw,wstv->isjtv", t, w).reshape(d * 2, d * 2, -1)
+        d *= 2
+    return t[:, :, 0]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_long_range_chunk_operator(seed):
+    """The compiled operator of a chunk with distant and reversed pairs is the
+    product of the gates embedded entry by entry (statevector definition)."""
+    from oracle import statevector as SV
+    from paper_2609_26516_amd import capi
+    rng = np.random.default_rng(seed)
+    n = 5
+    pairs = [(0, 4), (3, 1), (2, 3), (4, 2), (1, 0)]
+    ops = [(p, C.haar_unitary(rng, 4)) for p in pairs[seed:seed + 3]]
+    ops.insert(1, ((2,), C.haar_unitary(rng, 2)))
+    full = np.eye(2 ** n, dtype=complex)
+    for q, m in ops:
+        full = SV.full_operator(n, q, m) @ full
+    q0 = [q[0] for q, _ in ops]
+    q1 = [q[1] if len(q) == 2 else -1 for q, _ in ops]
+    h = capi.dcs_chunk_compile(0, n, q0, q1, np.concatenate([m.reshape(-1) for _, m in ops]))
+    np.testing.assert_allclose(_op_matrix(capi.dcs_chunk_export(h, n)), full, atol=1e-12)
+    capi.dcs_chunk_destroy(h)
+
+
+def test_gate_rank():
+    from paper_2609_26516_amd import capi
+    rng = np.random.default_rng(5)
+    assert capi.dcs_gate_rank(C.CNOT_01) == 2
+    assert capi.dcs_gate_rank(C.CNOT_10) == 2
+    assert capi.dcs_gate_rank(np.kron(C.H, C.X)) == 1
+    assert capi.dcs_gate_rank(C.haar_unitary(rng, 4)) == 4
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    assert capi.dcs_gate_rank(swap) == 4
+
+
+def test_prune_adaptive_matches_oracle():
+    """Kept indices and dropped mass bit-exact against the oracle's rule on
+    random weights with ties."""
+    from oracle import dynamic as D
+    from paper_2609_26516_amd import capi
+    rng = np.random.default_rng(9)
+    for trial in range(300):
+        n = int(rng.integers(0, 40))
+        w = rng.choice([0.0, 0.25, 0.5], size=n) if trial % 3 == 0 else rng.random(n) ** 4
+        k = int(rng.integers(1, 50))
+        tol = float(rng.choice([0.0, 0.01, 0.1, 0.5]))
+        rel = float(rng.choice([0.0, 0.001, 0.1, 1.0]))
+        keep, d = capi.dcs_prune_adaptive(w, k, tol, rel)
+        ref_keep, ref_d = D.prune_adaptive(list(w), k, tol, rel)
+        assert list(keep) == ref_keep, (trial, n, k, tol, rel)
+        assert d == ref_d
+    for bad in [(1.0, 0.0), (-0.1, 0.0), (0.0, 1.5)]:
+        with pytest.raises(capi.DcsError):
+            capi.dcs_prune_adaptive([0.5, 0.5], 2, *bad)
+    with pytest.raises(capi.DcsError):
+        capi.dcs_prune_adaptive([0.5, -0.1], 2)
+    with pytest.raises(capi.DcsError):
+        capi.dcs_prune_adaptive([0.5], 0)

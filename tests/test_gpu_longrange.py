@@ -1,0 +1,130 @@
+"""Gates on distant and reversed qubit pairs, the operator-bond chunk rule and
+adaptive pruning, GPU against the oracle.
+
+The library carries a distant gate's operator bond through the sites between
+its qubits; the oracle SWAP-routes the gate to nearest-neighbour gates.  The
+two are different factorisations of one operator, so the compressed states
+and fidelities agree to the precision's tolerance."""
+import numpy as np
+import pytest
+
+from inputs import circuits as C
+from inputs.randomness import bra_init_gaussians, shot_uniforms
+from oracle import dynamic as OD
+from oracle import mps as OM
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-9, "c64": 1e-6, "bf16x3": 1e-4}
+F_TOL = {"c128": 1e-9, "c64": 1e-5, "bf16x3": 1e-4}
+FE_TOL = {"c128": 1e-9, "c64": 1e-6, "bf16x3": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_26516_amd import engine as E
+    e = E.Engine(0)
+    yield e
+    e.close()
+
+
+def _E():
+    from paper_2609_26516_amd import engine as E
+    return E
+
+
+def _capi():
+    from paper_2609_26516_amd import capi
+    return capi
+
+
+def _fid_err(a, b):
+    return abs(1 - abs(OM.overlap(a, b)) ** 2 / (OM.norm_sq(a) * OM.norm_sq(b)))
+
+
+def _far_ops(rng, n, count):
+    """Haar gates on random distinct pairs (any distance, either order) and
+    one-qubit gates, kept within operator bond 16."""
+    ops, w = [], np.ones(n + 1, dtype=np.int64)
+    while len(ops) < count:
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        lo, hi = min(a, b), max(a, b)
+        if w[lo + 1:hi + 1].max() * 4 > 16:
+            ops.append(((a,), C.haar_unitary(rng, 2)))
+            continue
+        w[lo + 1:hi + 1] *= 4
+        ops.append(((a, b), C.haar_unitary(rng, 4)))
+    return ops
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
+@pytest.mark.parametrize("n,chi,count", [(9, 8, 4), (12, 16, 6), (16, 40, 5)])
+def test_long_range_compress_parity(eng, prec, n, chi, count):
+    capi = _capi()
+    rng = np.random.default_rng(31 * n + chi)
+    init = OM.generic_bra(bra_init_gaussians(n, chi, 5))
+    psi, _, _ = OM.compress(OM.zero_state(n, chi), OM.chunk_mpo(n, _far_ops(rng, n, 3)),
+                            init, 2)
+    ops = _far_ops(rng, n, count)
+    ref, f_ref, _ = OM.compress(psi, OM.chunk_mpo(n, ops), init, 2)
+    st = _E().State(eng, prec, n, 2, chi, 16, [chi], 5)
+    capi.dcs_import_mps(st.h, 0, chi, psi, eng.stream())
+    q0 = [o[0][0] for o in ops]
+    q1 = [o[0][1] if len(o[0]) == 2 else -1 for o in ops]
+    h = capi.dcs_chunk_compile(eng.ctx, n, q0, q1,
+                               np.concatenate([o[1].reshape(-1) for o in ops]))
+    assert capi.dcs_chunk_bonds(h, n).max() > 4
+    f = capi.dcs_compress_step(st.h, [0], [h], 2, eng.stream())
+    gpu = st.export(0)
+    capi.dcs_chunk_destroy(h)
+    st.close()
+    print(f"{prec} far n={n} chi={chi}: |df| = {abs(f[0] - f_ref):.2e}, "
+          f"fid err = {_fid_err(gpu, ref):.2e}")
+    assert abs(f[0] - f_ref) < F_TOL[prec]
+    assert _fid_err(gpu, ref) < FE_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_random_dynamic_single_path(eng, prec):
+    """Random dynamic circuit (distant pairs, measured subsets, parity
+    conditions), four shots in lockstep, chunks closed by k = 20 or by the
+    operator-bond cap 16, against the oracle replaying each shot."""
+    n, chi, k, shots, seed = 10, 4, 20, 4, 3
+    circ = C.random_dynamic(n, 4, seed)
+    nm = circ.n_measurements()
+    u = np.stack([shot_uniforms(seed, s, nm) for s in range(shots)])
+    st = _E().State(eng, prec, n, shots, chi, 16, [chi], 9)
+    res = _E().run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
+    sim = OD.Simulator(n, chi, k, 2, 9, w_cap=16)
+    for s in range(shots):
+        ref = OD.run_single_path(circ, sim, outcomes=res["outcomes"][s])
+        assert len(res["chis"][s]) == len(ref["fids"])      # same chunk boundaries
+        np.testing.assert_allclose(res["p0s"][s], ref["p0s"], atol=TOL[prec], rtol=0)
+        assert abs(res["F"][s] - ref["F"]) < 10 * F_TOL[prec]
+        assert _fid_err(st.export(int(res["ids"][s])), ref["mps"]) < FE_TOL[prec]
+    st.close()
+
+
+@pytest.mark.parametrize("prune", [None, (0.05, 0.0), (0.0, 0.2)])
+def test_random_dynamic_multi_path(eng, prune):
+    """Alg. 2 with M = 8 (top-M, or the adaptive rule capped at 8) on a random
+    dynamic circuit: same kept paths, probabilities, dropped mass and
+    fidelities as the oracle."""
+    n, chi, k, seed = 8, 4, 20, 2
+    circ = C.random_dynamic(n, 3, seed)
+    st = _E().State(eng, "c128", n, 2 * 8 + 2, chi, 16, [chi], 9)
+    res = _E().run_multi_path(eng, st, circ, chi, k, 2, max_branches=8, prune=prune)
+    ref = OD.run_multi_path(circ, OD.Simulator(n, chi, k, 2, 9, w_cap=16), max_branches=8,
+                            prune=prune)
+    got = {b["path"]: b for b in res["branches"]}
+    assert [b["path"] for b in res["branches"]] == [b["path"] for b in ref["branches"]]
+    assert abs(res["dropped"] - ref["dropped"]) < 1e-10
+    for b in ref["branches"]:
+        g = got[b["path"]]
+        assert abs(g["p"] - b["p"]) < 1e-10
+        assert abs(g["F"] - b["F"]) < 1e-9
+        assert _fid_err(st.export(int(g["id"])), b["mps"]) < 1e-9
+    st.close()
