@@ -10,12 +10,16 @@
 * the GHZ distance when at most M branches are kept, without and with
   renormalisation of the kept probabilities (the branch-cap panel);
 * wall time and state memory of the multi-path GHZ run against the number of
-  qubits (the scaling figure).
+  qubits (the scaling figure);
+* fidelity, runtime and state memory against depth for seeded random dynamic
+  circuits (distant gate pairs, measured subsets, parity-conditioned gates),
+  single path over several runs and multi path with a branch cap, for each
+  bond cap (Sec. V-C, MPS columns of its figure and table).
 
 Every tensor operation goes through engine.py and libdcs.so on the GPU; this
 module only groups shots, counts paths and forms distances.
 
-    python -m paper_2609_26516_amd.validation [--study teleport|ghz|cap|scaling]
+    python -m paper_2609_26516_amd.validation [--study teleport|ghz|cap|scaling|random]
 
 prints one JSON line per study.
 """
@@ -168,11 +172,71 @@ def ghz_scaling(eng, ns: Sequence[int], chi: int = 4, k: int = 25, n_sweeps: int
     return rows
 
 
+def random_circuit_study(eng, n: int, depths: Sequence[int], chis: Sequence[int],
+                         circuits: int = 3, runs: int = 10, max_branches: int = 8, k: int = 20,
+                         n_sweeps: int = 2, precision: str = "c128", seed: int = 1,
+                         mpo_bond_max: int = 16) -> List[Dict]:
+    """For each depth, bond cap and seeded circuit (inputs.circuits.random_dynamic
+    with seed c = 0..circuits-1): `runs` single-path runs in one batch (their
+    mean fidelity estimate, Alg. 1) and one multi-path run capped at
+    `max_branches` (probability-weighted fidelity, Alg. 2).  Rows give mean
+    and standard deviation over the circuits, the wall time of the batch and
+    of the multi-path run, and the state memory in use (one slot per run; the
+    slots the multi-path run needs)."""
+    import torch
+    from inputs.circuits import random_dynamic
+    from inputs.randomness import shot_uniforms
+    from .engine import State, run_multi_path, run_single_path
+    rows = []
+    for depth in depths:
+        for chi in chis:
+            f_sp, f_mp, t_sp, t_mp, m_sp, m_mp = [], [], [], [], [], []
+            for c in range(circuits):
+                circ = random_dynamic(n, depth, c)
+                nm = circ.n_measurements()
+                u = (np.stack([shot_uniforms(seed, s, nm) for s in range(runs)]) if nm
+                     else None)
+                st = State(eng, precision, n, runs, chi, mpo_bond_max, [chi], 7 + c)
+                try:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = run_single_path(eng, st, circ, runs, chi, k, n_sweeps, uniforms=u)
+                    torch.cuda.synchronize()
+                    t_sp.append(time.perf_counter() - t0)
+                    f_sp.append(float(np.mean(res["F"])))
+                    m_sp.append(st.nbytes / runs)
+                finally:
+                    st.close()
+                cap = 2 * max_branches + 2
+                st = State(eng, precision, n, cap, chi, mpo_bond_max, [chi], 7 + c)
+                try:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = run_multi_path(eng, st, circ, chi, k, n_sweeps,
+                                         max_branches=max_branches)
+                    torch.cuda.synchronize()
+                    t_mp.append(time.perf_counter() - t0)
+                    f_mp.append(float(res["F_mp"]))
+                    m_mp.append(st.nbytes)
+                finally:
+                    st.close()
+            sd = (lambda x: float(np.std(x, ddof=1)) if len(x) > 1 else 0.0)  # noqa: E731
+            rows.append({"depth": int(depth), "chi": int(chi),
+                         "F_sp": float(np.mean(f_sp)), "F_sp_sd": sd(f_sp),
+                         "F_mp": float(np.mean(f_mp)), "F_mp_sd": sd(f_mp),
+                         "seconds_sp": float(np.mean(t_sp)), "seconds_mp": float(np.mean(t_mp)),
+                         "bytes_per_run_sp": float(np.mean(m_sp)),
+                         "bytes_mp": float(np.mean(m_mp)), "F_sp_each": f_sp,
+                         "F_mp_each": f_mp})
+    return rows
+
+
 def main(argv: Optional[Sequence[str]] = None) -> None:
     from inputs.circuits import ghz_dynamic, teleportation
     from .engine import Engine
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--study", choices=["teleport", "ghz", "cap", "scaling", "all"], default="all")
+    ap.add_argument("--study", choices=["teleport", "ghz", "cap", "scaling", "random", "all"],
+                    default="all")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--precision", default="c128")
     args = ap.parse_args(argv)
@@ -198,6 +262,10 @@ def main(argv: Optional[Sequence[str]] = None) -> None:
             print(json.dumps({"study": "ghz_scaling",
                               "rows": ghz_scaling(eng, [5, 7, 9, 11, 13, 15, 17],
                                                   precision=args.precision)}))
+        if args.study in ("random", "all"):
+            print(json.dumps({"study": "random_dynamic_n27",
+                              "rows": random_circuit_study(eng, 27, range(2, 9), [8, 16, 32],
+                                                           precision=args.precision)}))
     finally:
         eng.close()
 

@@ -105,3 +105,29 @@ def test_ghz_scaling_rows(eng):
     assert all(row["seconds"] > 0 for row in rows)
     mem = [row["state_bytes"] for row in rows]
     assert mem[0] < mem[1] < mem[2]
+
+
+def test_random_circuit_study_rows_match_oracle(eng):
+    """Random dynamic circuits: the study's single-path mean fidelity and
+    multi-path fidelity equal the oracle's for the same circuits, uniforms
+    and starting guesses (complex128); the exact bond cap gives F = 1."""
+    from inputs.randomness import shot_uniforms
+    V = _V()
+    n, runs = 8, 3
+    rows = V.random_circuit_study(eng, n, [2, 3], [4, 16], circuits=2, runs=runs,
+                                  max_branches=8)
+    assert [(r["depth"], r["chi"]) for r in rows] == [(2, 4), (2, 16), (3, 4), (3, 16)]
+    for r in rows:
+        if r["chi"] == 16:
+            assert abs(r["F_sp"] - 1) < 1e-10 and abs(r["F_mp"] - 1) < 1e-10
+        assert r["seconds_sp"] > 0 and r["bytes_mp"] > r["bytes_per_run_sp"]
+    r = rows[2]
+    for c in range(2):
+        circ = C.random_dynamic(n, 3, c)
+        sim = OD.Simulator(n, 4, 20, 2, 7 + c, w_cap=16)
+        nm = circ.n_measurements()
+        f = [OD.run_single_path(circ, sim, uniforms=shot_uniforms(1, s, nm))["F"]
+             for s in range(runs)]
+        assert abs(r["F_sp_each"][c] - np.mean(f)) < 1e-9
+        mp = OD.run_multi_path(circ, sim, max_branches=8)
+        assert abs(r["F_mp_each"][c] - mp["F_mp"]) < 1e-9
