@@ -175,32 +175,55 @@ class State:
             self.buf = None
 
 
-class _Bonds:
-    """Operator bond of an open chunk, bond j + 1 between qubits j and j + 1:
-    the product of the ranks of the gates spanning it (as dcs_chunk_compile
-    builds it).  A gate that would push a bond past the state's
-    mpo_bond_max closes the chunk first."""
-
-    def __init__(self, eng: Engine, circ: Circuit, wmax: int):
-        self.eng, self.circ, self.wmax = eng, circ, wmax
-        self.w = np.ones(circ.n_qubits + 1, dtype=np.int64)
-
-    def closes(self, li: int, nonempty: bool) -> bool:
-        sp = self.eng.span(self.circ, li)
+def _bond_rule_active(eng: Engine, circ: Circuit, wmax: int) -> bool:
+    """False when no chunk of the circuit can have an operator bond above
+    wmax: every run of unitaries between measurements, all its controlled
+    gates included, stays within it.  Then the per-gate bond bookkeeping
+    below is skipped.  A gate whose own rank exceeds wmax raises."""
+    w = np.ones(circ.n_qubits + 1, dtype=np.int64)
+    active = False
+    for li, op in enumerate(circ.ops):
+        if isinstance(op, Measure):
+            w[:] = 1
+            continue
+        sp = eng.span(circ, li)
         if sp is None:
-            return False
+            continue
         lo, hi, r = sp
-        if r > self.wmax:
-            raise ValueError(f"gate {li} has operator rank {r} > mpo_bond_max {self.wmax}")
-        return nonempty and int(self.w[lo + 1:hi + 1].max()) * r > self.wmax
+        if r > wmax:
+            raise ValueError(f"gate {li} has operator rank {r} > mpo_bond_max {wmax}")
+        w[lo + 1:hi + 1] *= r
+        active = active or int(w.max()) > wmax
+    return active
 
-    def add(self, li: int) -> None:
+
+class _Bonds:
+    """Operator bonds of the open chunks of a set of runs, entry j + 1 the
+    bond between qubits j and j + 1: the product of the ranks of the gates
+    spanning it (as dcs_chunk_compile builds it).  A gate that would push a
+    bond of a non-empty chunk past the state's mpo_bond_max closes that chunk
+    first."""
+
+    def __init__(self, eng: Engine, circ: Circuit, wmax: int, runs: int):
+        self.eng, self.circ, self.wmax = eng, circ, wmax
+        self.w = np.ones((runs, circ.n_qubits + 1), dtype=np.int64)
+
+    def closes(self, li: int, rows: np.ndarray, nonempty: np.ndarray) -> np.ndarray:
+        """Rows (of `rows`) whose open chunk must be compressed before li."""
+        sp = self.eng.span(self.circ, li)
+        if sp is None or len(rows) == 0:
+            return rows[:0]
+        lo, hi, r = sp
+        over = self.w[rows, lo + 1:hi + 1].max(axis=1) * r > self.wmax
+        return rows[over & nonempty]
+
+    def add(self, li: int, rows: np.ndarray) -> None:
         sp = self.eng.span(self.circ, li)
         if sp is not None:
-            self.w[sp[0] + 1:sp[1] + 1] *= sp[2]
+            self.w[rows, sp[0] + 1:sp[1] + 1] *= sp[2]
 
-    def reset(self) -> None:
-        self.w[:] = 1
+    def reset(self, rows) -> None:
+        self.w[rows] = 1
 
 
 def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int, k: int,
@@ -241,7 +264,7 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
     p = np.ones(shots)
     fid = np.ones(shots)
     chunk: List[List[int]] = [[] for _ in range(shots)]
-    bonds = [_Bonds(eng, circ, st.wmax) for _ in range(shots)]
+    bonds = _Bonds(eng, circ, st.wmax, shots) if _bond_rule_active(eng, circ, st.wmax) else None
     rec_out, rec_p0, rec_f = [], [], []
     i_meas = 0
 
@@ -254,9 +277,10 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
         f_all = np.full(shots, np.nan)
         f_all[sel] = f
         rec_f.append(f_all)
+        if bonds is not None:
+            bonds.reset(sel)
         for s in sel:
             chunk[s] = []
-            bonds[s].reset()
             chis[s].append(chi_ladder[rung[s]] if chi_ladder else chi)
         if chi_ladder is not None:
             up = [s for s, fv in zip(sel, f) if fv < f_target and rung[s] + 1 < len(chi_ladder)]
@@ -294,13 +318,14 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
             if isinstance(op, CGate):
                 active = np.nonzero(_cond_true(op.cond, regs))[0]
             else:
-                active = range(shots)
-            compress(np.array([s for s in active if bonds[s].closes(li, bool(chunk[s]))],
-                              dtype=np.int64))
+                active = np.arange(shots)
+            if bonds is not None:
+                nonempty = np.array([len(chunk[s]) > 0 for s in active], dtype=bool)
+                compress(bonds.closes(li, active, nonempty))
+                bonds.add(li, active)
             due = []
             for s in active:
                 chunk[s].append(li)
-                bonds[s].add(li)
                 if len(chunk[s]) == k:
                     due.append(s)
             compress(np.array(due, dtype=np.int64))
@@ -339,8 +364,11 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     stream = eng.stream()
     first = st.alloc(1)[0]
     capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
+    rule = _bond_rule_active(eng, circ, st.wmax)
+    new_bonds = (lambda: _Bonds(eng, circ, st.wmax, 1)) if rule else (lambda: None)  # noqa: E731
+    one = np.zeros(1, dtype=np.int64)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
-           "F": 1.0, "chunk": [], "rung": 0, "chis": [], "w": _Bonds(eng, circ, st.wmax)}]
+           "F": 1.0, "chunk": [], "rung": 0, "chis": [], "w": new_bonds()}]
     dropped = 0.0
 
     def compress(sel: List[dict]) -> None:
@@ -352,7 +380,8 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
         for b, fv in zip(sel, f):
             b["F"] *= float(fv)
             b["chunk"] = []
-            b["w"].reset()
+            if b["w"] is not None:
+                b["w"].reset(one)
             b["chis"].append(chi_ladder[b["rung"]] if chi_ladder else None)
             if chi_ladder and fv < f_target and b["rung"] + 1 < len(chi_ladder):
                 b["rung"] += 1
@@ -384,7 +413,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 c[op.bit] = m
                 nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
                             "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
-                            "chis": list(b["chis"]), "w": _Bonds(eng, circ, st.wmax)})
+                            "chis": list(b["chis"]), "w": new_bonds()})
             br = nxt
             if chi_of is not None:
                 capi.dcs_branch_set_chi(st.h, [b["id"] for b in br],
@@ -403,11 +432,14 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
             continue
         act = [b for b in br
                if not (isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0])]
-        compress([b for b in act if b["w"].closes(li, bool(b["chunk"]))])
+        if rule:
+            compress([b for b in act
+                      if len(b["w"].closes(li, one, np.array([bool(b["chunk"])])))])
         due = []
         for b in act:
             b["chunk"].append(li)
-            b["w"].add(li)
+            if rule:
+                b["w"].add(li, one)
             if len(b["chunk"]) == k:
                 due.append(b)
         compress(due)
