@@ -172,14 +172,15 @@ int dcs_branch_dims(const dcs_state *st, int id, int *dims_out);
  * multiplied by r (the chunk's bond j is the product of the ranks of the
  * gates spanning it).  A gate with q0 > q1 is applied as its qubit-swapped
  * matrix on (q1, q0).  Errors: DCS_ENONLOCAL for q0 == q1, DCS_EINVAL for a
- * qubit out of range.  Host-only; the handle is independent of any state.
+ * qubit out of range or a non-finite matrix entry.  Host-only; the handle is independent of any state.
  * `ctx` may be NULL (no caching of gate splits across calls). */
 int dcs_chunk_compile(dcs_ctx *ctx, dcs_chunk **out, int n_qubits, int n_ops,
                       const int *q0, const int *q1, const double *mats);
 /* Operator-Schmidt rank r (1, 2 or 4) of one two-qubit gate (16 complex128
  * interleaved, row-major, as in dcs_chunk_compile): the bond dimension the
  * gate adds to every bond it spans.  Lets a caller close a chunk before its
- * operator bond would exceed the state's mpo_bond_max.  Host-only, pure. */
+ * operator bond would exceed the state's mpo_bond_max.  DCS_EINVAL for a
+ * non-finite entry.  Host-only, pure. */
 int dcs_gate_rank(const double *mat, int *rank_out);
 /* Operator bond dims w_0..w_n (n_qubits+1 ints; w_0 = w_n = 1). */
 int dcs_chunk_bonds(const dcs_chunk *ch, int *w_out);

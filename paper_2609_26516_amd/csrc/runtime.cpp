@@ -1119,6 +1119,12 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
                                        std::to_string(q1[i]) + "): the qubits coincide");
     }
   }
+  {
+    size_t nd = 0;
+    for (int i = 0; i < n_ops; ++i) nd += (q1[i] == -1) ? 8 : 32;
+    for (size_t e = 0; e < nd; ++e)
+      if (!std::isfinite(mats[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
+  }
   // ASAP layers: each gate goes to the first layer after the last one that
   // touches any of its qubits.  A gate on (a, b) with a > b is the gate
   // SWAP U SWAP on (b, a); a gate whose qubits are not adjacent acts as the
@@ -1213,6 +1219,8 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
 
 int dcs_gate_rank(const double* mat, int* rank_out) {
   if (!mat || !rank_out) return fail(DCS_EINVAL, "null argument");
+  for (int e = 0; e < 32; ++e)
+    if (!std::isfinite(mat[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
   *rank_out = split_gate(mat).r;
   return DCS_OK;
 }

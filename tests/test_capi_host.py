@@ -148,6 +148,13 @@ def test_gate_rank():
     assert capi.dcs_gate_rank(C.haar_unitary(rng, 4)) == 4
     swap = np.eye(4)[[0, 2, 1, 3]]
     assert capi.dcs_gate_rank(swap) == 4
+    bad = C.CNOT_01.copy()
+    bad[1, 1] = np.nan
+    with pytest.raises(capi.DcsError):
+        capi.dcs_gate_rank(bad)
+    with pytest.raises(capi.DcsError) as e:
+        capi.dcs_chunk_compile(0, 3, [0], [2], bad.reshape(-1))
+    assert e.value.code == capi.DCS_EINVAL
 
 
 def test_prune_adaptive_matches_oracle():
