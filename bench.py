@@ -56,9 +56,9 @@ TUNE = {"enabled": True, "save": None}
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
                    "paper_2609_26516_amd/csrc/kernel_util.h"],
-           "sha256": "b8b19ab939a4e4e481d9cbbaa63800ea6f53c5e5c1fdd8d033e906bca5166ab7",
-           "fetch_kib": 2847584.7, "write_kib": 965448.4,
-           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.2},
+           "sha256": "f2aef39e9e1efab081820450880fa24e161728c6c552f9d6f9954230e74daf96",
+           "fetch_kib": 2894544.1, "write_kib": 1046062.9,
+           "fetch_factor": 1048576 / 524300.5, "write_factor": 1048576 / 1048576.1},
 }
 
 

@@ -887,15 +887,20 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
   const __amdgpu_buffer_rsrc_t rQ = qrl_rsrc(Q, mn * (long long)sizeof(TO));
   const __amdgpu_buffer_rsrc_t rV = qrl_rsrc(Vw, mn * 16);
   const int oobF = (int)(mn * sizeof(TI)), oobQ = (int)(mn * sizeof(TO)), oobV = (int)(mn * 16);
-  const int loffV = (lk * n + li) * 16;
-  // per-lane parts of the byte offsets of row r0 + lk, column c0 + li (r0, c0 uniform)
-  const int loffF = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TI);
-  const int loffQ = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TO);
   double nsq = 0;   // |F|^2, each entry is read once
   double2 a[MAXB][4], v[MAXB][4];
 #pragma unroll 1
   for (int k = 0; k < npan; ++k) {
     const int p = k * QB, nbk = min(QB, n - p), mp = m - p;
+    // lane-dependent offsets are formed anew for each panel (the empty asm
+    // keeps them from being hoisted and held across the loop)
+    int tl = threadIdx.x;
+    asm volatile("" : "+v"(tl));
+    const int li = tl & 15, lk = (tl & 63) >> 4;
+    const int loffV = (lk * n + li) * 16;
+    // per-lane parts of the byte offsets of row r0 + lk, column c0 + li (r0, c0 uniform)
+    const int loffF = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TI);
+    const int loffQ = (mode == 0 ? lk * n + li : li * m + lk) * (int)sizeof(TO);
     // columns p .. p+15 of A (= F, or F^H in mode 1), and V_0
     // (for k > 0 in the whole QR, v holds V_0 here, loaded by the last step
     // of the previous Q block)

@@ -261,8 +261,7 @@ template <int NB>
 __device__ __forceinline__ void panel_reflector2(int kk, int nbk, double sc, double qn,
                                                  const double* fin, const double2* row,
                                                  double2* cc_out, double2* scal_out,
-                                                 double2* dv, double2* sT) {
-  const int lane = threadIdx.x & 63;
+                                                 double2* dv, double2* sT, int lane) {
   const double2 alpha = row[kk];
   double2 tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   const double amax = fmax(fabs(alpha.x), fabs(alpha.y));
@@ -381,8 +380,7 @@ __device__ __forceinline__ void halve_shfl(double (&x)[32], int lane) {
 }
 
 // Wave sums of 32 values; value s ends in lanes 2s and 2s + 1 (returned).
-__device__ __forceinline__ double wave_scatter_sum32(double (&x)[32]) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ double wave_scatter_sum32(double (&x)[32], int lane) {
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     half_swap<32>(x[s], x[s + 16]);
@@ -404,7 +402,12 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
                                               PanelSmem2<NT / 64, NB>& sm, double2* sT) {
   static_assert(NB <= 16, "at most 32 reduced values");
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // The thread index passes through an empty asm so that the lane-dependent
+  // LDS addresses below are formed here, once per panel, instead of being
+  // hoisted into the caller and kept (spilled) across its loops.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   if (tid < NB * NB) sT[tid] = make_double2(0.0, 0.0);
   __syncthreads();   // the caller's reads of this LDS are done
 
@@ -436,7 +439,7 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
 #pragma unroll
       for (int c = 0; c < NB; ++c) sm.row[c] = a[0][c];
     }
-    const double xs = wave_scatter_sum32(x);
+    const double xs = wave_scatter_sum32(x, lane);
     mx = wave_max_dpp(mx);
     if ((lane & 1) == 0) sm.part[wave][lane >> 1] = xs;
     if (lane == 0) sm.mx[wave] = mx;
@@ -474,7 +477,7 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
         sc = 1.0;
         qn = readlane_d(f, 2 * NB - 2);
       }
-      panel_reflector2<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sm.dv, sT);
+      panel_reflector2<NB>(kk, nbk, sc, qn, sm.fin, sm.row, sm.cc, &sm.scal, sm.dv, sT, lane);
     }
     __syncthreads();
     const double2 scal = sm.scal;
