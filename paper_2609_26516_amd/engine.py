@@ -258,13 +258,14 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
                              device=dev)
         m_dev = torch.empty(u_dev.shape, dtype=torch.int32, device=dev)
         pm_dev = torch.empty(u_dev.shape, dtype=torch.float64, device=dev)
+    rule = _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
     ids = np.array(st.alloc(shots), dtype=np.int32)
     capi.dcs_branch_init_zero(st.h, ids, np.full(shots, chi), stream)
     regs = np.zeros((shots, max(circ.n_bits, 1)), dtype=np.int8)
     p = np.ones(shots)
     fid = np.ones(shots)
     chunk: List[List[int]] = [[] for _ in range(shots)]
-    bonds = _Bonds(eng, circ, st.wmax, shots) if _bond_rule_active(eng, circ, st.wmax) else None
+    bonds = _Bonds(eng, circ, st.wmax, shots) if rule else None
     rec_out, rec_p0, rec_f = [], [], []
     i_meas = 0
 
@@ -362,9 +363,9 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
         if chi_ladder[0] != chi or any(a >= b for a, b in zip(chi_ladder, chi_ladder[1:])):
             raise ValueError("chi_ladder must ascend from chi")
     stream = eng.stream()
+    rule = _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
     first = st.alloc(1)[0]
     capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
-    rule = _bond_rule_active(eng, circ, st.wmax)
     new_bonds = (lambda: _Bonds(eng, circ, st.wmax, 1)) if rule else (lambda: None)  # noqa: E731
     one = np.zeros(1, dtype=np.int64)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),

@@ -128,3 +128,37 @@ def test_random_dynamic_multi_path(eng, prune):
         assert abs(g["F"] - b["F"]) < 1e-9
         assert _fid_err(st.export(int(g["id"])), b["mps"]) < 1e-9
     st.close()
+
+
+def test_gate_wider_than_state_operator_cap(eng):
+    """A two-qubit gate of operator rank 4 cannot fit a state built for
+    operator bonds of 2: both drivers refuse before taking a slot."""
+    circ = C.random_dynamic(6, 2, 0)
+    st = _E().State(eng, "c128", 6, 4, 4, 2, [4], 9)
+    free = len(st.free)
+    with pytest.raises(ValueError):
+        _E().run_single_path(eng, st, circ, 2, 4, 20, 2,
+                             uniforms=np.zeros((2, circ.n_measurements())))
+    with pytest.raises(ValueError):
+        _E().run_multi_path(eng, st, circ, 4, 20, 2)
+    assert len(st.free) == free
+    st.close()
+
+
+def test_adaptive_chi_with_pruning_and_distant_gates(eng):
+    """Ladder, adaptive pruning and distant gates together in one multi-path
+    run, against the oracle."""
+    n, seed, ladder = 8, 4, [2, 4, 8]
+    circ = C.random_dynamic(n, 3, seed)
+    st = _E().State(eng, "c128", n, 2 * 6 + 2, 8, 16, ladder, 9)
+    res = _E().run_multi_path(eng, st, circ, 2, 20, 2, max_branches=6, prune=(0.02, 0.01),
+                              chi_ladder=ladder, f_target=0.995)
+    ref = OD.run_multi_path(circ, OD.Simulator(n, 2, 20, 2, 9, w_cap=16), max_branches=6,
+                            prune=(0.02, 0.01), chi_ladder=ladder, f_target=0.995)
+    assert [b["path"] for b in res["branches"]] == [b["path"] for b in ref["branches"]]
+    for g, b in zip(res["branches"], ref["branches"]):
+        assert g["chis"] == b["chis"]
+        assert abs(g["F"] - b["F"]) < 1e-9 and abs(g["p"] - b["p"]) < 1e-10
+        assert _fid_err(st.export(int(g["id"])), b["mps"]) < 1e-9
+    assert abs(res["dropped"] - ref["dropped"]) < 1e-10
+    st.close()
