@@ -78,8 +78,20 @@ __device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids
   return static_cast<const char*>(o.base) + idx * o.stride;
 }
 
+// Workgroups per CU that the tile's LDS stages allow (160 KB per CU), which
+// with one wave per SIMD each is the waves per SIMD; given to the compiler as
+// its occupancy target (at most 4), so that the register budget does not
+// become the tighter limit (an FP64 64x64 tile otherwise takes more than 256
+// registers and runs one wave per SIMD).
+template <typename R, int BM, int BN>
+constexpr int gemm_min_blocks() {
+  const int n = (int)((160 * 1024) / (2 * 2 * 16 * ((BM + PAD) + (BN + PAD)) * sizeof(R)));
+  return n < 4 ? n : 4;
+}
+
 template <int TA, int TB, int TC, typename R, int OPA, int OPB, int BM, int BN>
-__global__ __launch_bounds__(NT) void gemm_kernel(const GemmArgs args) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(gemm_min_blocks<R, BM, BN>(), 8)))
+void gemm_kernel(const GemmArgs args) {
   using CA = typename Store<TA>::T;
   using CB = typename Store<TB>::T;
   using CC = typename Store<TC>::T;
