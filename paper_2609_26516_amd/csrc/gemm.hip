@@ -11,7 +11,8 @@
 // Tiling: one 256-thread workgroup (4 wave64 in a 2x2 grid) per BM x BN
 // output tile; each wave owns a (BM/2) x (BN/2) quadrant made of 16x16 MFMA
 // blocks with real and imaginary accumulators.  K advances in steps of 16
-// complex columns through LDS held as split real / imaginary planes in
+// complex columns (8 for FP64 tiles) through LDS held as split real /
+// imaginary planes in
 // [k][m] order, so the 16 lanes of an MFMA operand row read consecutive
 // words.  The next K tile is fetched into registers while the current one is
 // multiplied and then stored into the second of two LDS stages, one barrier
@@ -65,7 +66,12 @@ struct Store<CT_F64> {
   using T = double2;
 };
 
-constexpr int BK = 16, NT = 256, PAD = 4;
+constexpr int NT = 256, PAD = 4;
+// K step: 16 complex columns for FP32 tiles, 8 for FP64 tiles (the same LDS
+// bytes); the MFMAs take k in ascending groups of 4 either way, so results
+// do not depend on it
+template <typename R>
+constexpr int gemm_bk() { return sizeof(R) == 8 ? 8 : 16; }
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int q = total >> 3, r = total & 7;
@@ -78,15 +84,20 @@ __device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids
   return static_cast<const char*>(o.base) + idx * o.stride;
 }
 
-// Workgroups per CU that the tile's LDS stages allow (160 KB per CU), which
-// with one wave per SIMD each is the waves per SIMD; given to the compiler as
-// its occupancy target (at most 4), so that the register budget does not
-// become the tighter limit (an FP64 64x64 tile otherwise takes more than 256
-// registers and runs one wave per SIMD).
+// Occupancy target given to the compiler, in waves per SIMD: the workgroups
+// per CU that the tile's LDS stages allow (160 KB per CU; one wave per SIMD
+// each), capped by what the tile's accumulators leave room for in 512
+// registers (FP64 64x64: 96 accumulator registers, 3 waves; FP64 128x64:
+// 192, one wave).  Without it the register budget becomes the tighter limit
+// (an FP64 64x64 tile would take more than 256 registers and run one wave
+// per SIMD).
 template <typename R, int BM, int BN>
 constexpr int gemm_min_blocks() {
-  const int n = (int)((160 * 1024) / (2 * 2 * 16 * ((BM + PAD) + (BN + PAD)) * sizeof(R)));
-  return n < 4 ? n : 4;
+  const int lds = (int)((160 * 1024) / (2 * 2 * gemm_bk<R>() * ((BM + PAD) + (BN + PAD)) * sizeof(R)));
+  const int regs = sizeof(R) == 8 ? (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 3 : 1)
+                                   : (BM * BN <= 64 * 64 ? 4 : 3);
+  const int n = lds < regs ? lds : regs;
+  return n < 1 ? 1 : n;
 }
 
 template <int TA, int TB, int TC, typename R, int OPA, int OPB, int BM, int BN>
@@ -96,9 +107,12 @@ void gemm_kernel(const GemmArgs args) {
   using CB = typename Store<TB>::T;
   using CC = typename Store<TC>::T;
   using V = typename Mfma<R>::V;
+  constexpr int BK = gemm_bk<R>();
+  constexpr int TPK = NT / BK;       // threads per k row when a row is staged along m / n
   constexpr int EA = BM * BK / NT;   // A elements staged per thread
   constexpr int EB = BN * BK / NT;   // B elements staged per thread
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  static_assert(EA >= 1 && EB >= 1 && BK % EA == 0 && BK % EB == 0, "staging map");
 
   // two LDS stages: the next K tile is stored while the current one is read
   __shared__ R sA_r[2][BK][BM + PAD];
@@ -144,7 +158,7 @@ void gemm_kernel(const GemmArgs args) {
         ai[u] = (OPA == OP_J) ? -im : im;
       }
     } else {  // OP_C: stored K x M, conjugated; EA consecutive m
-      const int kr = tid / 16, mq = (tid % 16) * EA;
+      const int kr = tid / TPK, mq = (tid % TPK) * EA;
       const int k = k0 + kr;
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
@@ -170,7 +184,7 @@ void gemm_kernel(const GemmArgs args) {
         sA_i[stage][kq + u][row] = ai[u];
       }
     } else {
-      const int kr = tid / 16, mq = (tid % 16) * EA;
+      const int kr = tid / TPK, mq = (tid % TPK) * EA;
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
         sA_r[stage][kr][mq + u] = ar[u];
@@ -180,7 +194,7 @@ void gemm_kernel(const GemmArgs args) {
   };
   auto load_b = [&](int k0) {
     if constexpr (OPB == OP_N) {  // stored K x N: EB consecutive n
-      const int kr = tid / 16, nq = (tid % 16) * EB;
+      const int kr = tid / TPK, nq = (tid % TPK) * EB;
       const int k = k0 + kr;
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
@@ -214,7 +228,7 @@ void gemm_kernel(const GemmArgs args) {
   };
   auto store_b = [&]() {
     if constexpr (OPB == OP_N) {
-      const int kr = tid / 16, nq = (tid % 16) * EB;
+      const int kr = tid / TPK, nq = (tid % TPK) * EB;
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         sB_r[stage][kr][nq + u] = br[u];
