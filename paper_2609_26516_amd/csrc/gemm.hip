@@ -10,9 +10,8 @@
 //
 // Tiling: one 256-thread workgroup (4 wave64 in a 2x2 grid) per BM x BN
 // output tile; each wave owns a (BM/2) x (BN/2) quadrant made of 16x16 MFMA
-// blocks with real and imaginary accumulators.  K advances in steps of 16
-// complex columns (8 for FP64 tiles) through LDS held as split real /
-// imaginary planes in
+// blocks with real and imaginary accumulators.  K advances in steps of 8
+// complex columns through LDS held as split real / imaginary planes in
 // [k][m] order, so the 16 lanes of an MFMA operand row read consecutive
 // words.  The next K tile is fetched into registers while the current one is
 // multiplied and then stored into the second of two LDS stages, one barrier
@@ -66,12 +65,13 @@ struct Store<CT_F64> {
   using T = double2;
 };
 
+// K step of 8 complex columns: two LDS stages of a 64x64 tile stay small
+// enough (17 KB in FP32, 35 KB in FP64) that registers, not LDS, bound the
+// workgroups per CU; the MFMAs take k in ascending groups of 4, so results do
+// not depend on the step
 constexpr int NT = 256, PAD = 4;
-// K step: 16 complex columns for FP32 tiles, 8 for FP64 tiles (the same LDS
-// bytes); the MFMAs take k in ascending groups of 4 either way, so results
-// do not depend on it
 template <typename R>
-constexpr int gemm_bk() { return sizeof(R) == 8 ? 8 : 16; }
+constexpr int gemm_bk() { return 8; }
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int q = total >> 3, r = total & 7;
@@ -86,16 +86,15 @@ __device__ __forceinline__ const char* item_ptr(const Operand& o, const int* ids
 
 // Occupancy target given to the compiler, in waves per SIMD: the workgroups
 // per CU that the tile's LDS stages allow (160 KB per CU; one wave per SIMD
-// each), capped by what the tile's accumulators leave room for in 512
-// registers (FP64 64x64: 96 accumulator registers, 3 waves; FP64 128x64:
-// 192, one wave).  Without it the register budget becomes the tighter limit
-// (an FP64 64x64 tile would take more than 256 registers and run one wave
-// per SIMD).
+// each), capped by what the tile's registers fit into 512 without spilling
+// (FP32 64x64: 5; FP64 64x64, 96 accumulator registers: 3; FP64 128x64, 192:
+// one).  Without it the compiler spends registers freely (an FP64 64x64 tile
+// took more than 256 and ran one wave per SIMD).
 template <typename R, int BM, int BN>
 constexpr int gemm_min_blocks() {
   const int lds = (int)((160 * 1024) / (2 * 2 * gemm_bk<R>() * ((BM + PAD) + (BN + PAD)) * sizeof(R)));
   const int regs = sizeof(R) == 8 ? (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 3 : 1)
-                                   : (BM * BN <= 64 * 64 ? 4 : 3);
+                                   : (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 5 : 3);
   const int n = lds < regs ? lds : regs;
   return n < 1 ? 1 : n;
 }
