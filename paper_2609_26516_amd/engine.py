@@ -354,8 +354,9 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
 
     Adaptive bond cap: with `chi_ladder` (ascending from chi), a branch whose
     compression returns a partial fidelity below `f_target` moves one rung up
-    for its later compressions, and its children start on its rung; each
-    branch's "chis" lists the caps of the compressions on its path."""
+    for its later compressions, and its children start on its rung.  Each
+    branch's "chi" is its current cap and "chis" the caps of the compressions
+    on its path."""
     if chi_ladder is not None:
         chi_ladder = [int(c) for c in chi_ladder]
         if chi_of is not None:
@@ -369,7 +370,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     new_bonds = (lambda: _Bonds(eng, circ, st.wmax, 1)) if rule else (lambda: None)  # noqa: E731
     one = np.zeros(1, dtype=np.int64)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
-           "F": 1.0, "chunk": [], "rung": 0, "chis": [], "w": new_bonds()}]
+           "F": 1.0, "chunk": [], "rung": 0, "chi": chi, "chis": [], "w": new_bonds()}]
     dropped = 0.0
 
     def compress(sel: List[dict]) -> None:
@@ -383,13 +384,13 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
             b["chunk"] = []
             if b["w"] is not None:
                 b["w"].reset(one)
-            b["chis"].append(chi_ladder[b["rung"]] if chi_ladder else None)
+            b["chis"].append(b["chi"])
             if chi_ladder and fv < f_target and b["rung"] + 1 < len(chi_ladder):
                 b["rung"] += 1
+                b["chi"] = chi_ladder[b["rung"]]
                 up.append(b)
         if up:
-            capi.dcs_branch_set_chi(st.h, [b["id"] for b in up],
-                                    [chi_ladder[b["rung"]] for b in up])
+            capi.dcs_branch_set_chi(st.h, [b["id"] for b in up], [b["chi"] for b in up])
 
     for li, op in enumerate(circ.ops):
         if isinstance(op, Measure):
@@ -414,11 +415,11 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 c[op.bit] = m
                 nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
                             "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
+                            "chi": chi_of(b["path"] + (m,)) if chi_of else b["chi"],
                             "chis": list(b["chis"]), "w": new_bonds()})
             br = nxt
             if chi_of is not None:
-                capi.dcs_branch_set_chi(st.h, [b["id"] for b in br],
-                                        [chi_of(b["path"]) for b in br])
+                capi.dcs_branch_set_chi(st.h, [b["id"] for b in br], [b["chi"] for b in br])
             if prune is not None or (max_branches is not None and len(br) > max_branches):
                 if prune is not None:
                     keep, disc = capi.dcs_prune_adaptive([b["p"] for b in br],

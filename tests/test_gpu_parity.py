@@ -451,6 +451,7 @@ def test_multi_path_uneven_chi_parity(eng, prec):
     for pth, b in want.items():
         assert abs(got[pth]["p"] - b["p"]) < 10 * TOL[prec]
         assert abs(got[pth]["F"] - b["F"]) < 10 * F_TOL[prec]
+        assert got[pth]["chi"] == b["chi"] and got[pth]["chis"] == b["chis"]
         assert _fid_err(st.export(got[pth]["id"]), b["mps"]) < FE_TOL[prec]
     assert abs(res["dropped"] - ref["dropped"]) < 10 * TOL[prec]
     st.close()
