@@ -11,6 +11,7 @@
 #include <array>
 #include <cstdio>
 #include <map>
+#include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -28,6 +29,19 @@ thread_local std::string g_err;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+// Entry points return a status and never let a C++ exception (a failed host
+// allocation inside a std container, say) cross the C ABI.
+template <typename F>
+int guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(DCS_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(DCS_EINVAL, "internal error");
+  }
 }
 
 #define DCS_HIP(expr)                                                                  \
@@ -791,114 +805,130 @@ const char* dcs_last_error(void) { return g_err.c_str(); }
 int dcs_version(void) { return 100; }
 
 int dcs_ctx_create(dcs_ctx** out, int device) {
-  if (!out) return fail(DCS_EINVAL, "null output handle");
-  int count = 0;
-  DCS_HIP(hipGetDeviceCount(&count));
-  if (device < 0 || device >= count) return fail(DCS_EINVAL, "device ordinal out of range");
-  DCS_HIP(hipSetDevice(device));
-  dcs_ctx* c = new dcs_ctx();
-  c->device = device;
-  *out = c;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!out) return fail(DCS_EINVAL, "null output handle");
+    int count = 0;
+    DCS_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(DCS_EINVAL, "device ordinal out of range");
+    DCS_HIP(hipSetDevice(device));
+    dcs_ctx* c = new dcs_ctx();
+    c->device = device;
+    *out = c;
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_destroy(dcs_ctx* ctx) {
-  if (!ctx) return DCS_OK;
-  resolve_timing(ctx);
-  tune_resolve(ctx);
-  for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
-  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  delete ctx;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx) return DCS_OK;
+    resolve_timing(ctx);
+    tune_resolve(ctx);
+    for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_set_tuning(dcs_ctx* ctx, int enabled, int reps) {
-  if (!ctx) return fail(DCS_EINVAL, "null context");
-  if (reps < 1 || reps > 100) return fail(DCS_EINVAL, "reps must be in [1, 100]");
-  ctx->tuning = enabled != 0;
-  ctx->tune_reps = reps;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx) return fail(DCS_EINVAL, "null context");
+    if (reps < 1 || reps > 100) return fail(DCS_EINVAL, "reps must be in [1, 100]");
+    ctx->tuning = enabled != 0;
+    ctx->tune_reps = reps;
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_tuning_save(dcs_ctx* ctx, const char* path) {
-  if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
-  tune_resolve(ctx);
-  FILE* f = std::fopen(path, "w");
-  if (!f) return fail(DCS_EINVAL, std::string("cannot write ") + path);
-  std::fprintf(f, "{\"format\": \"dcs-gemm-tiles-1\", \"entries\": [");
-  bool first = true;
-  for (auto& kv : ctx->tune) {
-    if (kv.second.best < 0) continue;
-    std::fprintf(f, "%s\n  {\"key\": [", first ? "" : ",");
-    for (int i = 0; i < 10; ++i) std::fprintf(f, "%s%d", i ? ", " : "", kv.first[i]);
-    std::fprintf(f, "], \"best\": %d, \"ms\": [", kv.second.best);
-    for (int i = 0; i < GEMM_VARIANTS; ++i)
-      std::fprintf(f, "%s%.6g", i ? ", " : "", kv.second.cnt[i] ? kv.second.ms[i] : -1.0);
-    std::fprintf(f, "]}");
-    first = false;
-  }
-  std::fprintf(f, "\n]}\n");
-  std::fclose(f);
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
+    tune_resolve(ctx);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(DCS_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"format\": \"dcs-gemm-tiles-1\", \"entries\": [");
+    bool first = true;
+    for (auto& kv : ctx->tune) {
+      if (kv.second.best < 0) continue;
+      std::fprintf(f, "%s\n  {\"key\": [", first ? "" : ",");
+      for (int i = 0; i < 10; ++i) std::fprintf(f, "%s%d", i ? ", " : "", kv.first[i]);
+      std::fprintf(f, "], \"best\": %d, \"ms\": [", kv.second.best);
+      for (int i = 0; i < GEMM_VARIANTS; ++i)
+        std::fprintf(f, "%s%.6g", i ? ", " : "", kv.second.cnt[i] ? kv.second.ms[i] : -1.0);
+      std::fprintf(f, "]}");
+      first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    std::fclose(f);
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_tuning_load(dcs_ctx* ctx, const char* path) {
-  if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
-  FILE* f = std::fopen(path, "r");
-  if (!f) return fail(DCS_EINVAL, std::string("cannot read ") + path);
-  std::string txt;
-  char buf[4096];
-  size_t got;
-  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
-  std::fclose(f);
-  if (txt.find("dcs-gemm-tiles-1") == std::string::npos)
-    return fail(DCS_EINVAL, "not a tile-shape table");
-  size_t pos = 0;
-  int loaded = 0;
-  while ((pos = txt.find("\"key\": [", pos)) != std::string::npos) {
-    pos += 8;
-    TuneKey k{};
-    int best = -1;
-    const char* c = txt.c_str() + pos;
-    int used = 0;
-    if (std::sscanf(c, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], \"best\": %d%n", &k[0], &k[1],
-                    &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9], &best, &used) != 11)
-      return fail(DCS_EINVAL, "malformed tile-shape entry");
-    if (best < 0 || best >= GEMM_VARIANTS) return fail(DCS_EINVAL, "bad tile shape id");
-    ctx->tune[k].best = best;
-    ++loaded;
-    pos += used;
-  }
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx || !path) return fail(DCS_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(DCS_EINVAL, std::string("cannot read ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    if (txt.find("dcs-gemm-tiles-1") == std::string::npos)
+      return fail(DCS_EINVAL, "not a tile-shape table");
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = txt.find("\"key\": [", pos)) != std::string::npos) {
+      pos += 8;
+      TuneKey k{};
+      int best = -1;
+      const char* c = txt.c_str() + pos;
+      int used = 0;
+      if (std::sscanf(c, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], \"best\": %d%n", &k[0], &k[1],
+                      &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9], &best, &used) != 11)
+        return fail(DCS_EINVAL, "malformed tile-shape entry");
+      if (best < 0 || best >= GEMM_VARIANTS) return fail(DCS_EINVAL, "bad tile shape id");
+      ctx->tune[k].best = best;
+      ++loaded;
+      pos += used;
+    }
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_set_graphs(dcs_ctx* ctx, int enabled) {
-  if (!ctx) return fail(DCS_EINVAL, "null context");
-  ctx->graphs = enabled != 0;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx) return fail(DCS_EINVAL, "null context");
+    ctx->graphs = enabled != 0;
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_set_timing(dcs_ctx* ctx, int enabled) {
-  if (!ctx) return fail(DCS_EINVAL, "null context");
-  ctx->timing = enabled != 0;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ctx) return fail(DCS_EINVAL, "null context");
+    ctx->timing = enabled != 0;
+    return DCS_OK;
+  });
 }
 
 int dcs_ctx_timing(dcs_ctx* ctx, long long* launches, double* ms, double* flops, double* bytes,
                    int reset) {
-  if (!ctx) return fail(DCS_EINVAL, "null context");
-  resolve_timing(ctx);
-  for (int i = 0; i < DCS_TIMING_CLASSES; ++i) {
-    if (launches) launches[i] = ctx->launches[i];
-    if (ms) ms[i] = ctx->ms[i];
-    if (flops) flops[i] = ctx->flops[i];
-    if (bytes) bytes[i] = ctx->bytes[i];
-    if (reset) {
-      ctx->launches[i] = 0;
-      ctx->ms[i] = ctx->flops[i] = ctx->bytes[i] = 0;
+  return guarded([&]() -> int {
+    if (!ctx) return fail(DCS_EINVAL, "null context");
+    resolve_timing(ctx);
+    for (int i = 0; i < DCS_TIMING_CLASSES; ++i) {
+      if (launches) launches[i] = ctx->launches[i];
+      if (ms) ms[i] = ctx->ms[i];
+      if (flops) flops[i] = ctx->flops[i];
+      if (bytes) bytes[i] = ctx->bytes[i];
+      if (reset) {
+        ctx->launches[i] = 0;
+        ctx->ms[i] = ctx->flops[i] = ctx->bytes[i] = 0;
+      }
     }
-  }
-  return DCS_OK;
+    return DCS_OK;
+  });
 }
 
 static int check_state_args(int precision, int n, int cap, int chi_max, int wmax, int n_init) {
@@ -914,192 +944,208 @@ static int check_state_args(int precision, int n, int cap, int chi_max, int wmax
 
 int dcs_state_bytes(int precision, int n_qubits, int capacity, int chi_max, int mpo_bond_max,
                     int n_init_slots, size_t* bytes_out) {
-  DCS_TRY(check_state_args(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots));
-  if (!bytes_out) return fail(DCS_EINVAL, "null output");
-  *bytes_out = make_layout(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots).total;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    DCS_TRY(check_state_args(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots));
+    if (!bytes_out) return fail(DCS_EINVAL, "null output");
+    *bytes_out = make_layout(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots).total;
+    return DCS_OK;
+  });
 }
 
 int dcs_state_create(dcs_ctx* ctx, dcs_state** out, int precision, int n_qubits, int capacity,
                      int chi_max, int mpo_bond_max, int n_init_slots, void* d_buffer, size_t bytes,
                      void* stream) {
-  if (!ctx || !out) return fail(DCS_EINVAL, "null handle");
-  DCS_TRY(check_state_args(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots));
-  Layout L = make_layout(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots);
-  if (!d_buffer) return fail(DCS_EINVAL, "null device buffer");
-  if (reinterpret_cast<uintptr_t>(d_buffer) % ALIGN != 0)
-    return fail(DCS_EINVAL, "device buffer must be 256-byte aligned");
-  if (bytes < L.total)
-    return fail(DCS_ENOMEM, "device buffer too small: need " + std::to_string(L.total) + " bytes");
-  DCS_HIP(hipSetDevice(ctx->device));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  dcs_state* st = new dcs_state();
-  st->ctx = ctx;
-  st->precision = precision;
-  st->L = L;
-  st->base = static_cast<char*>(d_buffer);
-  st->bytes = bytes;
-  st->slots.assign(capacity, Slot());
-  // boundary environments L_0 = R_n = [[1]] of every slot (never overwritten)
-  std::vector<void*> ptrs;
-  for (int id = 0; id < capacity; ++id) {
-    char* sb = st->slot_base(id);
-    ptrs.push_back(sb + L.o_env + L.env_off[0]);
-    ptrs.push_back(sb + L.o_env + L.env_off[n_qubits]);
-  }
-  size_t done = 0;
-  const size_t chunk_ptrs = (size_t)capacity * (n_qubits + 2);
-  while (done < ptrs.size()) {
-    const size_t cnt = std::min(chunk_ptrs, ptrs.size() - done);
-    void** dptr = reinterpret_cast<void**>(st->base + L.o_items);
-    hipError_t e = hipMemcpyAsync(dptr, ptrs.data() + done, cnt * sizeof(void*),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_fill_unit(L.ct, dptr, (int)cnt, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      delete st;
-      return fail(DCS_EHIP, std::string("state set-up failed: ") + hipGetErrorString(e));
+  return guarded([&]() -> int {
+    if (!ctx || !out) return fail(DCS_EINVAL, "null handle");
+    DCS_TRY(check_state_args(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots));
+    Layout L = make_layout(precision, n_qubits, capacity, chi_max, mpo_bond_max, n_init_slots);
+    if (!d_buffer) return fail(DCS_EINVAL, "null device buffer");
+    if (reinterpret_cast<uintptr_t>(d_buffer) % ALIGN != 0)
+      return fail(DCS_EINVAL, "device buffer must be 256-byte aligned");
+    if (bytes < L.total)
+      return fail(DCS_ENOMEM, "device buffer too small: need " + std::to_string(L.total) + " bytes");
+    DCS_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    dcs_state* st = new dcs_state();
+    st->ctx = ctx;
+    st->precision = precision;
+    st->L = L;
+    st->base = static_cast<char*>(d_buffer);
+    st->bytes = bytes;
+    st->slots.assign(capacity, Slot());
+    // boundary environments L_0 = R_n = [[1]] of every slot (never overwritten)
+    std::vector<void*> ptrs;
+    for (int id = 0; id < capacity; ++id) {
+      char* sb = st->slot_base(id);
+      ptrs.push_back(sb + L.o_env + L.env_off[0]);
+      ptrs.push_back(sb + L.o_env + L.env_off[n_qubits]);
     }
-    done += cnt;
-  }
-  *out = st;
-  return DCS_OK;
+    size_t done = 0;
+    const size_t chunk_ptrs = (size_t)capacity * (n_qubits + 2);
+    while (done < ptrs.size()) {
+      const size_t cnt = std::min(chunk_ptrs, ptrs.size() - done);
+      void** dptr = reinterpret_cast<void**>(st->base + L.o_items);
+      hipError_t e = hipMemcpyAsync(dptr, ptrs.data() + done, cnt * sizeof(void*),
+                                    hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = launch_fill_unit(L.ct, dptr, (int)cnt, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        delete st;
+        return fail(DCS_EHIP, std::string("state set-up failed: ") + hipGetErrorString(e));
+      }
+      done += cnt;
+    }
+    *out = st;
+    return DCS_OK;
+  });
 }
 
 int dcs_state_destroy(dcs_state* st) {
-  delete st;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    delete st;
+    return DCS_OK;
+  });
 }
 
 int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* stream) {
-  if (!st || !gauss) return fail(DCS_EINVAL, "null argument");
-  const Layout& L = st->L;
-  if (chi_cap < 1 || chi_cap > L.chi_max) return fail(DCS_EINVAL, "chi_cap outside [1, chi_max]");
-  int idx = st->init_index(chi_cap);
-  if (idx < 0) {
-    if ((int)st->inits.size() >= L.n_init)
-      return fail(DCS_ENOMEM, "all starting-guess slots are in use");
-    st->inits.push_back(InitSlot{chi_cap});
-    idx = (int)st->inits.size() - 1;
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int n = L.n;
-  const std::vector<int> d = bond_dims(n, chi_cap);
-  size_t total = 0, emax = 0;
-  std::vector<size_t> goff(n);
-  for (int j = 0; j < n; ++j) {
-    goff[j] = total;
-    const size_t e = (size_t)d[j] * 2 * d[j + 1];
-    total += e;
-    emax = std::max(emax, e);
-  }
-  const int per_launch = QR_MAX_GROUPS;
-  void* dg = nullptr;
-  void* dws = nullptr;
-  void* dnrm = nullptr;
-  DCS_HIP(hipMalloc(&dg, total * 16));
-  const size_t ws_item = align_up(qr_ws_elems(emax, (size_t)chi_cap) * 16);
-  hipError_t e = hipMalloc(&dws, ws_item * per_launch);
-  if (e == hipSuccess) e = hipMalloc(&dnrm, 64 * sizeof(double));
-  if (e == hipSuccess) e = hipMemcpyAsync(dg, gauss, total * 16, hipMemcpyHostToDevice, s);
-  int rc = DCS_OK;
-  if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init upload: ") + hipGetErrorString(e));
-  char* ibase = st->base + L.o_init + L.mps_bytes * (size_t)idx;
-  for (int j0 = 0; rc == DCS_OK && j0 < n; j0 += per_launch) {
-    std::vector<QrJob> jobs;
-    for (int j = j0; j < std::min(n, j0 + per_launch); ++j) {
-      QrJob q;
-      q.f = local_op(static_cast<char*>(dg) + goff[j] * 16, 0);
-      q.q = local_op(ibase + L.site_off[j], 0);
-      q.ws = local_op(static_cast<char*>(dws) + (size_t)(j - j0) * ws_item, 0);
-      q.nrm2 = local_op(static_cast<double*>(dnrm) + (j - j0), 0);
-      q.ids = nullptr;
-      q.batch = 1;
-      if (j == 0) {
-        q.m = d[0] * 2 * d[1];
-        q.n = 1;
-        q.mode = 2;
-      } else {
-        q.m = 2 * d[j + 1];
-        q.n = d[j];
-        q.mode = 1;
-      }
-      jobs.push_back(q);
+  return guarded([&]() -> int {
+    if (!st || !gauss) return fail(DCS_EINVAL, "null argument");
+    const Layout& L = st->L;
+    if (chi_cap < 1 || chi_cap > L.chi_max) return fail(DCS_EINVAL, "chi_cap outside [1, chi_max]");
+    int idx = st->init_index(chi_cap);
+    if (idx < 0) {
+      if ((int)st->inits.size() >= L.n_init)
+        return fail(DCS_ENOMEM, "all starting-guess slots are in use");
+      st->inits.push_back(InitSlot{chi_cap});
+      idx = (int)st->inits.size() - 1;
     }
-    rc = run_qr(st->ctx, CT_F64, L.ct, jobs, s);
-  }
-  if (rc == DCS_OK) {
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init LQ: ") + hipGetErrorString(e));
-  }
-  (void)hipFree(dg);
-  if (dws) (void)hipFree(dws);
-  if (dnrm) (void)hipFree(dnrm);
-  return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = L.n;
+    const std::vector<int> d = bond_dims(n, chi_cap);
+    size_t total = 0, emax = 0;
+    std::vector<size_t> goff(n);
+    for (int j = 0; j < n; ++j) {
+      goff[j] = total;
+      const size_t e = (size_t)d[j] * 2 * d[j + 1];
+      total += e;
+      emax = std::max(emax, e);
+    }
+    const int per_launch = QR_MAX_GROUPS;
+    void* dg = nullptr;
+    void* dws = nullptr;
+    void* dnrm = nullptr;
+    DCS_HIP(hipMalloc(&dg, total * 16));
+    const size_t ws_item = align_up(qr_ws_elems(emax, (size_t)chi_cap) * 16);
+    hipError_t e = hipMalloc(&dws, ws_item * per_launch);
+    if (e == hipSuccess) e = hipMalloc(&dnrm, 64 * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(dg, gauss, total * 16, hipMemcpyHostToDevice, s);
+    int rc = DCS_OK;
+    if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init upload: ") + hipGetErrorString(e));
+    char* ibase = st->base + L.o_init + L.mps_bytes * (size_t)idx;
+    for (int j0 = 0; rc == DCS_OK && j0 < n; j0 += per_launch) {
+      std::vector<QrJob> jobs;
+      for (int j = j0; j < std::min(n, j0 + per_launch); ++j) {
+        QrJob q;
+        q.f = local_op(static_cast<char*>(dg) + goff[j] * 16, 0);
+        q.q = local_op(ibase + L.site_off[j], 0);
+        q.ws = local_op(static_cast<char*>(dws) + (size_t)(j - j0) * ws_item, 0);
+        q.nrm2 = local_op(static_cast<double*>(dnrm) + (j - j0), 0);
+        q.ids = nullptr;
+        q.batch = 1;
+        if (j == 0) {
+          q.m = d[0] * 2 * d[1];
+          q.n = 1;
+          q.mode = 2;
+        } else {
+          q.m = 2 * d[j + 1];
+          q.n = d[j];
+          q.mode = 1;
+        }
+        jobs.push_back(q);
+      }
+      rc = run_qr(st->ctx, CT_F64, L.ct, jobs, s);
+    }
+    if (rc == DCS_OK) {
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init LQ: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(dg);
+    if (dws) (void)hipFree(dws);
+    if (dnrm) (void)hipFree(dnrm);
+    return rc;
+  });
 }
 
 int dcs_branch_init_zero(dcs_state* st, int n, const int* ids, const int* chi_caps, void* stream) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  DCS_TRY(check_ids(st, n, ids, false));
-  if (n > 0 && !chi_caps) return fail(DCS_EINVAL, "null chi_caps");
-  const Layout& L = st->L;
-  for (int i = 0; i < n; ++i)
-    if (chi_caps[i] < 1 || chi_caps[i] > L.chi_max)
-      return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // |0...0> with unit bonds: every site tensor is the 1 x 2 x 1 vector (1, 0)
-  std::vector<void*> ptrs;
-  for (int i = 0; i < n; ++i) {
-    char* mps = st->slot_base(ids[i]) + L.o_mps[0];
-    for (int j = 0; j < L.n; ++j) ptrs.push_back(mps + L.site_off[j]);
-  }
-  size_t done = 0;
-  const size_t room = (size_t)L.cap * (L.n + 2);
-  while (done < ptrs.size()) {
-    const size_t cnt = std::min(room, ptrs.size() - done);
-    void** dptr = reinterpret_cast<void**>(st->base + L.o_items);
-    DCS_HIP(hipMemcpyAsync(dptr, ptrs.data() + done, cnt * sizeof(void*), hipMemcpyHostToDevice, s));
-    DCS_HIP(launch_fill_unit(L.ct, dptr, (int)cnt, s));
-    DCS_HIP(hipStreamSynchronize(s));
-    done += cnt;
-  }
-  for (int i = 0; i < n; ++i) {
-    Slot& sl = st->slots[ids[i]];
-    sl = Slot();
-    sl.live = true;
-    sl.chi_cap = chi_caps[i];
-    sl.dims.assign(L.n + 1, 1);
-    sl.cur = 0;
-    sl.lc_end = L.n;
-    sl.rc_start = 0;
-  }
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    DCS_TRY(check_ids(st, n, ids, false));
+    if (n > 0 && !chi_caps) return fail(DCS_EINVAL, "null chi_caps");
+    const Layout& L = st->L;
+    for (int i = 0; i < n; ++i)
+      if (chi_caps[i] < 1 || chi_caps[i] > L.chi_max)
+        return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // |0...0> with unit bonds: every site tensor is the 1 x 2 x 1 vector (1, 0)
+    std::vector<void*> ptrs;
+    for (int i = 0; i < n; ++i) {
+      char* mps = st->slot_base(ids[i]) + L.o_mps[0];
+      for (int j = 0; j < L.n; ++j) ptrs.push_back(mps + L.site_off[j]);
+    }
+    size_t done = 0;
+    const size_t room = (size_t)L.cap * (L.n + 2);
+    while (done < ptrs.size()) {
+      const size_t cnt = std::min(room, ptrs.size() - done);
+      void** dptr = reinterpret_cast<void**>(st->base + L.o_items);
+      DCS_HIP(hipMemcpyAsync(dptr, ptrs.data() + done, cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+      DCS_HIP(launch_fill_unit(L.ct, dptr, (int)cnt, s));
+      DCS_HIP(hipStreamSynchronize(s));
+      done += cnt;
+    }
+    for (int i = 0; i < n; ++i) {
+      Slot& sl = st->slots[ids[i]];
+      sl = Slot();
+      sl.live = true;
+      sl.chi_cap = chi_caps[i];
+      sl.dims.assign(L.n + 1, 1);
+      sl.cur = 0;
+      sl.lc_end = L.n;
+      sl.rc_start = 0;
+    }
+    return DCS_OK;
+  });
 }
 
 int dcs_branch_set_chi(dcs_state* st, int n, const int* ids, const int* chi_caps) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  DCS_TRY(check_ids(st, n, ids, true));
-  for (int i = 0; i < n; ++i)
-    if (!chi_caps || chi_caps[i] < 1 || chi_caps[i] > st->L.chi_max)
-      return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
-  for (int i = 0; i < n; ++i) st->slots[ids[i]].chi_cap = chi_caps[i];
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    DCS_TRY(check_ids(st, n, ids, true));
+    for (int i = 0; i < n; ++i)
+      if (!chi_caps || chi_caps[i] < 1 || chi_caps[i] > st->L.chi_max)
+        return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
+    for (int i = 0; i < n; ++i) st->slots[ids[i]].chi_cap = chi_caps[i];
+    return DCS_OK;
+  });
 }
 
 int dcs_branch_release(dcs_state* st, int n, const int* ids) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  DCS_TRY(check_ids(st, n, ids, false));
-  for (int i = 0; i < n; ++i) st->slots[ids[i]] = Slot();
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    DCS_TRY(check_ids(st, n, ids, false));
+    for (int i = 0; i < n; ++i) st->slots[ids[i]] = Slot();
+    return DCS_OK;
+  });
 }
 
 int dcs_branch_dims(const dcs_state* st, int id, int* dims_out) {
-  if (!st || !dims_out) return fail(DCS_EINVAL, "null argument");
-  if (id < 0 || id >= st->L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
-  const Slot& sl = st->slots[id];
-  if (!sl.live) return fail(DCS_ESTATE, "branch is not live");
-  for (int b = 0; b <= st->L.n; ++b) dims_out[b] = sl.dims[b];
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!st || !dims_out) return fail(DCS_EINVAL, "null argument");
+    if (id < 0 || id >= st->L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
+    const Slot& sl = st->slots[id];
+    if (!sl.live) return fail(DCS_ESTATE, "branch is not live");
+    for (int b = 0; b <= st->L.n; ++b) dims_out[b] = sl.dims[b];
+    return DCS_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,147 +1153,157 @@ int dcs_branch_dims(const dcs_state* st, int id, int* dims_out) {
 
 int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, const int* q0,
                       const int* q1, const double* mats) {
-  if (!out) return fail(DCS_EINVAL, "null handle");
-  if (n_qubits < 1) return fail(DCS_EINVAL, "n_qubits must be positive");
-  if (n_ops < 0 || (n_ops > 0 && (!q0 || !q1 || !mats))) return fail(DCS_EINVAL, "null op arrays");
-  for (int i = 0; i < n_ops; ++i) {
-    if (q0[i] < 0 || q0[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
-    if (q1[i] != -1) {
-      if (q1[i] < 0 || q1[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
-      if (q1[i] == q0[i])
-        return fail(DCS_ENONLOCAL, "two-qubit gate on (" + std::to_string(q0[i]) + ", " +
-                                       std::to_string(q1[i]) + "): the qubits coincide");
-    }
-  }
-  {
-    size_t nd = 0;
-    for (int i = 0; i < n_ops; ++i) nd += (q1[i] == -1) ? 8 : 32;
-    for (size_t e = 0; e < nd; ++e)
-      if (!std::isfinite(mats[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
-  }
-  // ASAP layers: each gate goes to the first layer after the last one that
-  // touches any of its qubits.  A gate on (a, b) with a > b is the gate
-  // SWAP U SWAP on (b, a); a gate whose qubits are not adjacent acts as the
-  // identity on the sites between them, which carry its operator bond.
-  std::vector<int> last(n_qubits, -1);
-  std::vector<std::vector<int>> layers;
-  std::vector<size_t> mat_off(n_ops);
-  std::vector<double> swapped;   // reordered matrices of the (a > b) gates
-  std::vector<size_t> sw_off(n_ops, SIZE_MAX);
-  size_t mo = 0;
-  for (int i = 0; i < n_ops; ++i) {
-    mat_off[i] = mo;
-    mo += (q1[i] == -1) ? 8 : 32;
-    if (q1[i] != -1 && q1[i] < q0[i]) {
-      // element (s0 s1, t0 t1) of the swapped gate is element (s1 s0, t1 t0)
-      const double* m = mats + mat_off[i];
-      sw_off[i] = swapped.size();
-      swapped.resize(swapped.size() + 32);
-      double* d = swapped.data() + sw_off[i];
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) {
-          const int rs = ((r & 1) << 1) | (r >> 1), cs = ((c & 1) << 1) | (c >> 1);
-          d[2 * (r * 4 + c)] = m[2 * (rs * 4 + cs)];
-          d[2 * (r * 4 + c) + 1] = m[2 * (rs * 4 + cs) + 1];
-        }
-    }
-    int lay = last[q0[i]];
-    if (q1[i] != -1) lay = std::max(lay, last[q1[i]]);
-    lay += 1;
-    if ((int)layers.size() <= lay) layers.resize(lay + 1);
-    layers[lay].push_back(i);
-    last[q0[i]] = lay;
-    if (q1[i] != -1) last[q1[i]] = lay;
-  }
-  dcs_chunk* ch = new dcs_chunk();
-  ch->n = n_qubits;
-  std::vector<int> wl(n_qubits, 1), wr(n_qubits, 1);
-  ch->site.assign(n_qubits, std::vector<cd>{1.0, 0.0, 0.0, 1.0});
-  for (const auto& layer : layers) {
-    for (int i : layer) {
-      const double* m = sw_off[i] != SIZE_MAX ? swapped.data() + sw_off[i] : mats + mat_off[i];
-      const int q = q1[i] == -1 ? q0[i] : std::min(q0[i], q1[i]);
-      const int qr = q1[i] == -1 ? q : std::max(q0[i], q1[i]);
-      if (q1[i] == -1) {
-        std::vector<cd> u(4);
-        for (int k = 0; k < 4; ++k) u[k] = cd(m[2 * k], m[2 * k + 1]);
-        ch->site[q] = op_product(ch->site[q], wl[q], wr[q], u, 1, 1);
-      } else {
-        Split local;
-        const Split* spp = &local;
-        if (ctx) {
-          const std::string key(reinterpret_cast<const char*>(m), 32 * sizeof(double));
-          auto it = ctx->split_cache.find(key);
-          if (it == ctx->split_cache.end()) {
-            if (ctx->split_cache.size() > 65536) ctx->split_cache.clear();
-            it = ctx->split_cache.emplace(key, split_gate(m)).first;
-          }
-          spp = &it->second;
-        } else {
-          local = split_gate(m);
-        }
-        const Split& sp = *spp;
-        ch->site[q] = op_product(ch->site[q], wl[q], wr[q], sp.left, 1, sp.r);
-        wr[q] *= sp.r;
-        if (qr > q + 1) {
-          // identity on the physical leg, the bond index passed through
-          std::vector<cd> pass((size_t)sp.r * 4 * sp.r, 0.0);
-          for (int w = 0; w < sp.r; ++w)
-            for (int t = 0; t < 2; ++t) pass[((size_t)(w * 2 + t) * 2 + t) * sp.r + w] = 1.0;
-          for (int j = q + 1; j < qr; ++j) {
-            ch->site[j] = op_product(ch->site[j], wl[j], wr[j], pass, sp.r, sp.r);
-            wl[j] *= sp.r;
-            wr[j] *= sp.r;
-          }
-        }
-        ch->site[qr] = op_product(ch->site[qr], wl[qr], wr[qr], sp.right, sp.r, 1);
-        wl[qr] *= sp.r;
+  return guarded([&]() -> int {
+    if (!out) return fail(DCS_EINVAL, "null handle");
+    if (n_qubits < 1) return fail(DCS_EINVAL, "n_qubits must be positive");
+    if (n_ops < 0 || (n_ops > 0 && (!q0 || !q1 || !mats))) return fail(DCS_EINVAL, "null op arrays");
+    for (int i = 0; i < n_ops; ++i) {
+      if (q0[i] < 0 || q0[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
+      if (q1[i] != -1) {
+        if (q1[i] < 0 || q1[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
+        if (q1[i] == q0[i])
+          return fail(DCS_ENONLOCAL, "two-qubit gate on (" + std::to_string(q0[i]) + ", " +
+                                         std::to_string(q1[i]) + "): the qubits coincide");
       }
     }
-  }
-  ch->w.assign(n_qubits + 1, 1);
-  for (int j = 0; j + 1 < n_qubits; ++j) {
-    if (wr[j] != wl[j + 1]) {
-      delete ch;
-      return fail(DCS_EINVAL, "internal: operator bond mismatch");
+    {
+      size_t nd = 0;
+      for (int i = 0; i < n_ops; ++i) nd += (q1[i] == -1) ? 8 : 32;
+      for (size_t e = 0; e < nd; ++e)
+        if (!std::isfinite(mats[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
     }
-    ch->w[j + 1] = wr[j];
-  }
-  *out = ch;
-  return DCS_OK;
+    // ASAP layers: each gate goes to the first layer after the last one that
+    // touches any of its qubits.  A gate on (a, b) with a > b is the gate
+    // SWAP U SWAP on (b, a); a gate whose qubits are not adjacent acts as the
+    // identity on the sites between them, which carry its operator bond.
+    std::vector<int> last(n_qubits, -1);
+    std::vector<std::vector<int>> layers;
+    std::vector<size_t> mat_off(n_ops);
+    std::vector<double> swapped;   // reordered matrices of the (a > b) gates
+    std::vector<size_t> sw_off(n_ops, SIZE_MAX);
+    size_t mo = 0;
+    for (int i = 0; i < n_ops; ++i) {
+      mat_off[i] = mo;
+      mo += (q1[i] == -1) ? 8 : 32;
+      if (q1[i] != -1 && q1[i] < q0[i]) {
+        // element (s0 s1, t0 t1) of the swapped gate is element (s1 s0, t1 t0)
+        const double* m = mats + mat_off[i];
+        sw_off[i] = swapped.size();
+        swapped.resize(swapped.size() + 32);
+        double* d = swapped.data() + sw_off[i];
+        for (int r = 0; r < 4; ++r)
+          for (int c = 0; c < 4; ++c) {
+            const int rs = ((r & 1) << 1) | (r >> 1), cs = ((c & 1) << 1) | (c >> 1);
+            d[2 * (r * 4 + c)] = m[2 * (rs * 4 + cs)];
+            d[2 * (r * 4 + c) + 1] = m[2 * (rs * 4 + cs) + 1];
+          }
+      }
+      int lay = last[q0[i]];
+      if (q1[i] != -1) lay = std::max(lay, last[q1[i]]);
+      lay += 1;
+      if ((int)layers.size() <= lay) layers.resize(lay + 1);
+      layers[lay].push_back(i);
+      last[q0[i]] = lay;
+      if (q1[i] != -1) last[q1[i]] = lay;
+    }
+    dcs_chunk* ch = new dcs_chunk();
+    ch->n = n_qubits;
+    std::vector<int> wl(n_qubits, 1), wr(n_qubits, 1);
+    ch->site.assign(n_qubits, std::vector<cd>{1.0, 0.0, 0.0, 1.0});
+    for (const auto& layer : layers) {
+      for (int i : layer) {
+        const double* m = sw_off[i] != SIZE_MAX ? swapped.data() + sw_off[i] : mats + mat_off[i];
+        const int q = q1[i] == -1 ? q0[i] : std::min(q0[i], q1[i]);
+        const int qr = q1[i] == -1 ? q : std::max(q0[i], q1[i]);
+        if (q1[i] == -1) {
+          std::vector<cd> u(4);
+          for (int k = 0; k < 4; ++k) u[k] = cd(m[2 * k], m[2 * k + 1]);
+          ch->site[q] = op_product(ch->site[q], wl[q], wr[q], u, 1, 1);
+        } else {
+          Split local;
+          const Split* spp = &local;
+          if (ctx) {
+            const std::string key(reinterpret_cast<const char*>(m), 32 * sizeof(double));
+            auto it = ctx->split_cache.find(key);
+            if (it == ctx->split_cache.end()) {
+              if (ctx->split_cache.size() > 65536) ctx->split_cache.clear();
+              it = ctx->split_cache.emplace(key, split_gate(m)).first;
+            }
+            spp = &it->second;
+          } else {
+            local = split_gate(m);
+          }
+          const Split& sp = *spp;
+          ch->site[q] = op_product(ch->site[q], wl[q], wr[q], sp.left, 1, sp.r);
+          wr[q] *= sp.r;
+          if (qr > q + 1) {
+            // identity on the physical leg, the bond index passed through
+            std::vector<cd> pass((size_t)sp.r * 4 * sp.r, 0.0);
+            for (int w = 0; w < sp.r; ++w)
+              for (int t = 0; t < 2; ++t) pass[((size_t)(w * 2 + t) * 2 + t) * sp.r + w] = 1.0;
+            for (int j = q + 1; j < qr; ++j) {
+              ch->site[j] = op_product(ch->site[j], wl[j], wr[j], pass, sp.r, sp.r);
+              wl[j] *= sp.r;
+              wr[j] *= sp.r;
+            }
+          }
+          ch->site[qr] = op_product(ch->site[qr], wl[qr], wr[qr], sp.right, sp.r, 1);
+          wl[qr] *= sp.r;
+        }
+      }
+    }
+    ch->w.assign(n_qubits + 1, 1);
+    for (int j = 0; j + 1 < n_qubits; ++j) {
+      if (wr[j] != wl[j + 1]) {
+        delete ch;
+        return fail(DCS_EINVAL, "internal: operator bond mismatch");
+      }
+      ch->w[j + 1] = wr[j];
+    }
+    *out = ch;
+    return DCS_OK;
+  });
 }
 
 int dcs_gate_rank(const double* mat, int* rank_out) {
-  if (!mat || !rank_out) return fail(DCS_EINVAL, "null argument");
-  for (int e = 0; e < 32; ++e)
-    if (!std::isfinite(mat[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
-  *rank_out = split_gate(mat).r;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!mat || !rank_out) return fail(DCS_EINVAL, "null argument");
+    for (int e = 0; e < 32; ++e)
+      if (!std::isfinite(mat[e])) return fail(DCS_EINVAL, "non-finite gate matrix entry");
+    *rank_out = split_gate(mat).r;
+    return DCS_OK;
+  });
 }
 
 int dcs_chunk_bonds(const dcs_chunk* ch, int* w_out) {
-  if (!ch || !w_out) return fail(DCS_EINVAL, "null argument");
-  for (int b = 0; b <= ch->n; ++b) w_out[b] = ch->w[b];
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!ch || !w_out) return fail(DCS_EINVAL, "null argument");
+    for (int b = 0; b <= ch->n; ++b) w_out[b] = ch->w[b];
+    return DCS_OK;
+  });
 }
 
 int dcs_chunk_export(const dcs_chunk* ch, double* out, size_t cap_doubles) {
-  if (!ch || !out) return fail(DCS_EINVAL, "null argument");
-  size_t need = 0;
-  for (const auto& w : ch->site) need += 2 * w.size();
-  if (need > cap_doubles) return fail(DCS_ENOMEM, "output too small for the chunk operator");
-  for (const auto& w : ch->site) {
-    for (const cd& z : w) {
-      *out++ = z.real();
-      *out++ = z.imag();
+  return guarded([&]() -> int {
+    if (!ch || !out) return fail(DCS_EINVAL, "null argument");
+    size_t need = 0;
+    for (const auto& w : ch->site) need += 2 * w.size();
+    if (need > cap_doubles) return fail(DCS_ENOMEM, "output too small for the chunk operator");
+    for (const auto& w : ch->site) {
+      for (const cd& z : w) {
+        *out++ = z.real();
+        *out++ = z.imag();
+      }
     }
-  }
-  return DCS_OK;
+    return DCS_OK;
+  });
 }
 
 int dcs_chunk_destroy(dcs_chunk* ch) {
-  delete ch;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    delete ch;
+    return DCS_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,171 +1323,250 @@ struct Group {
 }  // namespace
 
 int dcs_state_set_warm_start(dcs_state* st, int enabled, double eta) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  if (enabled && !(eta >= 0.0 && eta <= 1e6)) return fail(DCS_EINVAL, "eta must be in [0, 1e6]");
-  st->warm_eta = enabled ? eta : -1.0;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    if (enabled && !(eta >= 0.0 && eta <= 1e6)) return fail(DCS_EINVAL, "eta must be in [0, 1e6]");
+    st->warm_eta = enabled ? eta : -1.0;
+    return DCS_OK;
+  });
 }
 
 int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* const* chunks,
                       int n_sweeps, double* fid_out, void* stream) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  DCS_TRY(check_ids(st, n, ids, true));
-  if (n == 0) return DCS_OK;
-  if (!chunks || !fid_out) return fail(DCS_EINVAL, "null chunks or fid_out");
-  if (n_sweeps < 1) return fail(DCS_EINVAL, "n_sweeps must be >= 1");
-  const Layout& L = st->L;
-  const int nq = L.n;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < n; ++i) {
-    const dcs_chunk* ch = chunks[i];
-    if (!ch) return fail(DCS_EINVAL, "null chunk");
-    if (ch->n != nq) return fail(DCS_EINVAL, "chunk qubit count differs from the state's");
-    for (int b = 1; b < nq; ++b)
-      if (ch->w[b] > L.wmax)
-        return fail(DCS_ENOMEM, "chunk operator bond " + std::to_string(ch->w[b]) +
-                                    " exceeds the state's mpo_bond_max");
-    if (st->init_index(st->slots[ids[i]].chi_cap) < 0)
-      return fail(DCS_ESTATE, "no starting guess registered for bond cap " +
-                                  std::to_string(st->slots[ids[i]].chi_cap));
-  }
-  // group branches of identical shapes
-  std::map<std::vector<int>, int> key2g;
-  std::vector<Group> groups;
-  for (int i = 0; i < n; ++i) {
-    const Slot& sl = st->slots[ids[i]];
-    std::vector<int> key;
-    key.push_back(sl.chi_cap);
-    key.push_back(sl.cur);
-    key.insert(key.end(), sl.dims.begin(), sl.dims.end());
-    key.insert(key.end(), chunks[i]->w.begin(), chunks[i]->w.end());
-    auto it = key2g.find(key);
-    if (it == key2g.end()) {
-      Group g;
-      g.chi_cap = sl.chi_cap;
-      g.cur = sl.cur;
-      g.Db = bond_dims(nq, sl.chi_cap);
-      g.Kb = sl.dims;
-      g.w = chunks[i]->w;
-      g.warm = st->warm_eta >= 0.0;
-      for (int b = 0; b <= nq; ++b)
-        if (g.Kb[b] > g.Db[b]) g.warm = false;
-      groups.push_back(g);
-      it = key2g.emplace(key, (int)groups.size() - 1).first;
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    DCS_TRY(check_ids(st, n, ids, true));
+    if (n == 0) return DCS_OK;
+    if (!chunks || !fid_out) return fail(DCS_EINVAL, "null chunks or fid_out");
+    if (n_sweeps < 1) return fail(DCS_EINVAL, "n_sweeps must be >= 1");
+    const Layout& L = st->L;
+    const int nq = L.n;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+      const dcs_chunk* ch = chunks[i];
+      if (!ch) return fail(DCS_EINVAL, "null chunk");
+      if (ch->n != nq) return fail(DCS_EINVAL, "chunk qubit count differs from the state's");
+      for (int b = 1; b < nq; ++b)
+        if (ch->w[b] > L.wmax)
+          return fail(DCS_ENOMEM, "chunk operator bond " + std::to_string(ch->w[b]) +
+                                      " exceeds the state's mpo_bond_max");
+      if (st->init_index(st->slots[ids[i]].chi_cap) < 0)
+        return fail(DCS_ESTATE, "no starting guess registered for bond cap " +
+                                    std::to_string(st->slots[ids[i]].chi_cap));
     }
-    groups[it->second].members.push_back(i);
-  }
-  // ids (group order) and gate operators (call-local, group order)
-  std::vector<int> ids_host;
-  const size_t mpo_host_bytes = L.mpo_stride * (size_t)n;
-  st->host_stage.resize(std::max(st->host_stage.size(), mpo_host_bytes));
-  char* mh = st->host_stage.data();
-  for (auto& g : groups) {
-    g.goff = (int)ids_host.size();
-    for (int i : g.members) {
-      const int ci = (int)ids_host.size();
-      ids_host.push_back(ids[i]);
-      for (int j = 0; j < nq; ++j)
-        to_path_ct(L.ct, chunks[i]->site[j].data(), chunks[i]->site[j].size(),
-                   mh + L.mpo_stride * ci + L.mpo_site_off[j]);
+    // group branches of identical shapes
+    std::map<std::vector<int>, int> key2g;
+    std::vector<Group> groups;
+    for (int i = 0; i < n; ++i) {
+      const Slot& sl = st->slots[ids[i]];
+      std::vector<int> key;
+      key.push_back(sl.chi_cap);
+      key.push_back(sl.cur);
+      key.insert(key.end(), sl.dims.begin(), sl.dims.end());
+      key.insert(key.end(), chunks[i]->w.begin(), chunks[i]->w.end());
+      auto it = key2g.find(key);
+      if (it == key2g.end()) {
+        Group g;
+        g.chi_cap = sl.chi_cap;
+        g.cur = sl.cur;
+        g.Db = bond_dims(nq, sl.chi_cap);
+        g.Kb = sl.dims;
+        g.w = chunks[i]->w;
+        g.warm = st->warm_eta >= 0.0;
+        for (int b = 0; b <= nq; ++b)
+          if (g.Kb[b] > g.Db[b]) g.warm = false;
+        groups.push_back(g);
+        it = key2g.emplace(key, (int)groups.size() - 1).first;
+      }
+      groups[it->second].members.push_back(i);
     }
-  }
-  int* ids_dev = reinterpret_cast<int*>(st->base + L.o_ids);
-  DCS_HIP(hipMemcpyAsync(ids_dev, ids_host.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-  DCS_HIP(hipMemcpyAsync(st->base + L.o_mpo, mh, mpo_host_bytes, hipMemcpyHostToDevice, s));
-  for (auto& g : groups) g.ids_dev = ids_dev + g.goff;
-
-  const int ct = L.ct;
-  // contractions of the compression step: path precision, or split-BF16
-  // products over the complex64 tensors
-  const int acc = st->precision == DCS_BF16X3 ? ACC_BF16X3 : ct;
-  const size_t cs = L.cs;
-  double* nrm_dev = reinterpret_cast<double*>(st->base + L.o_out);
-  auto ket_site = [&](const Group& g, int j) { return slot_op(st, L.o_mps[g.cur], L.site_off[j]); };
-  auto new_site = [&](const Group& g, int j) {
-    return slot_op(st, L.o_mps[1 - g.cur], L.site_off[j]);
-  };
-  auto env = [&](int b) { return slot_op(st, L.o_env, L.env_off[b]); };
-  auto x1 = [&]() { return slot_op(st, L.o_x1, 0); };
-  auto x2 = [&]() { return slot_op(st, L.o_x2, 0); };
-  auto fbuf = [&]() { return slot_op(st, L.o_f, 0); };
-  auto mpo = [&](const Group& g, int j) {
-    return local_op(st->base + L.o_mpo + L.mpo_stride * (size_t)g.goff + L.mpo_site_off[j],
-                    (long long)L.mpo_stride);
-  };
-  auto init_site = [&](const Group& g, int j) {
-    const int ii = st->init_index(g.chi_cap);
-    return local_op(st->base + L.o_init + L.mps_bytes * (size_t)ii + L.site_off[j], 0);
-  };
-  (void)cs;
-
-  // moving left at site j: Y1 = K_j R_{j+1}^T, Y2 = W Y1, then (a) R_j from
-  // bra_j (starting guess or LQ factor) or (b) F = L_j Y2
-  auto left_prologue = [&](int j) -> int {
-    std::vector<GemmJob> gj;
-    std::vector<MpoJob> mj;
+    // ids (group order) and gate operators (call-local, group order)
+    std::vector<int> ids_host;
+    const size_t mpo_host_bytes = L.mpo_stride * (size_t)n;
+    st->host_stage.resize(std::max(st->host_stage.size(), mpo_host_bytes));
+    char* mh = st->host_stage.data();
     for (auto& g : groups) {
-      const int bsz = (int)g.members.size();
-      const int kl = g.Kb[j], kr = g.Kb[j + 1], dr = g.Db[j + 1], wl = g.w[j], wr = g.w[j + 1];
-      gj.push_back({ket_site(g, j), env(j + 1), x1(), g.ids_dev, 2 * kl, dr * wr, kr, kr, kr,
-                    dr * wr, bsz});
-      mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, kl, dr, wl, wr, bsz});
+      g.goff = (int)ids_host.size();
+      for (int i : g.members) {
+        const int ci = (int)ids_host.size();
+        ids_host.push_back(ids[i]);
+        for (int j = 0; j < nq; ++j)
+          to_path_ct(L.ct, chunks[i]->site[j].data(), chunks[i]->site[j].size(),
+                     mh + L.mpo_stride * ci + L.mpo_site_off[j]);
+      }
     }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, gj, s, CLS_GEMM));
-    return run_mpo(st->ctx, ct, 1, mj, s);
-  };
-  auto right_env_from = [&](int j, bool from_init) -> int {
-    std::vector<GemmJob> gj;
-    for (auto& g : groups) {
-      const int bsz = (int)g.members.size();
-      const int kl = g.Kb[j], dl = g.Db[j], dr = g.Db[j + 1], wl = g.w[j];
-      gj.push_back({from_init && !g.warm ? init_site(g, j) : new_site(g, j), x2(), env(j),
-                    g.ids_dev, dl, wl * kl, 2 * dr, 2 * dr, 2 * dr, wl * kl, bsz});
-    }
-    return run_gemm(st->ctx, ct, ct, ct, acc, OP_J, OP_T, gj, s, CLS_GEMM);
-  };
-  // warm start: the ket embedded in the bra's bond dims plus eta times the
-  // generic guess (seeded completion of the directions the ket lacks),
-  // brought to right-canonical form from the right: M_j = L_j Q_j by LQ,
-  // B_j = Q_j, M_{j-1} <- M_{j-1} L_j (L_j^T = conj(Q_j) M_j^T).  B_0 is never
-  // read (the first visit forms site 0 from the environments).
-  auto warm_bra = [&]() -> int {
-    bool any = false;
-    for (auto& g : groups) any = any || g.warm;
-    if (!any) return DCS_OK;
-    auto embed = [&](const Group& g, Operand dst, Operand src, Operand ini, int dl, int dr,
-                     int kl, int kr, double eta) -> int {
-      EmbedArgs a;
-      a.dst = dst;
-      a.src = src;
-      a.init = ini;
-      a.ids = g.ids_dev;
-      a.dl = dl;
-      a.dr = dr;
-      a.kl = kl;
-      a.kr = kr;
-      a.batch = (int)g.members.size();
-      a.eta = eta;
-      DCS_HIP(launch_embed(ct, a, s));
-      return DCS_OK;
+    int* ids_dev = reinterpret_cast<int*>(st->base + L.o_ids);
+    DCS_HIP(hipMemcpyAsync(ids_dev, ids_host.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    DCS_HIP(hipMemcpyAsync(st->base + L.o_mpo, mh, mpo_host_bytes, hipMemcpyHostToDevice, s));
+    for (auto& g : groups) g.ids_dev = ids_dev + g.goff;
+
+    const int ct = L.ct;
+    // contractions of the compression step: path precision, or split-BF16
+    // products over the complex64 tensors
+    const int acc = st->precision == DCS_BF16X3 ? ACC_BF16X3 : ct;
+    const size_t cs = L.cs;
+    double* nrm_dev = reinterpret_cast<double*>(st->base + L.o_out);
+    auto ket_site = [&](const Group& g, int j) { return slot_op(st, L.o_mps[g.cur], L.site_off[j]); };
+    auto new_site = [&](const Group& g, int j) {
+      return slot_op(st, L.o_mps[1 - g.cur], L.site_off[j]);
     };
-    const Operand none = local_op(nullptr, 0);
-    for (auto& g : groups) {
-      if (!g.warm) continue;
-      for (int j = 0; j < nq; ++j)
-        DCS_TRY(embed(g, new_site(g, j), ket_site(g, j), init_site(g, j), g.Db[j], g.Db[j + 1],
-                      g.Kb[j], g.Kb[j + 1], st->warm_eta));
-    }
-    for (int j = nq - 1; j >= 1; --j) {
-      std::vector<QrJob> qj;
-      std::vector<GemmJob> gl, gm;
+    auto env = [&](int b) { return slot_op(st, L.o_env, L.env_off[b]); };
+    auto x1 = [&]() { return slot_op(st, L.o_x1, 0); };
+    auto x2 = [&]() { return slot_op(st, L.o_x2, 0); };
+    auto fbuf = [&]() { return slot_op(st, L.o_f, 0); };
+    auto mpo = [&](const Group& g, int j) {
+      return local_op(st->base + L.o_mpo + L.mpo_stride * (size_t)g.goff + L.mpo_site_off[j],
+                      (long long)L.mpo_stride);
+    };
+    auto init_site = [&](const Group& g, int j) {
+      const int ii = st->init_index(g.chi_cap);
+      return local_op(st->base + L.o_init + L.mps_bytes * (size_t)ii + L.site_off[j], 0);
+    };
+    (void)cs;
+
+    // moving left at site j: Y1 = K_j R_{j+1}^T, Y2 = W Y1, then (a) R_j from
+    // bra_j (starting guess or LQ factor) or (b) F = L_j Y2
+    auto left_prologue = [&](int j) -> int {
+      std::vector<GemmJob> gj;
+      std::vector<MpoJob> mj;
+      for (auto& g : groups) {
+        const int bsz = (int)g.members.size();
+        const int kl = g.Kb[j], kr = g.Kb[j + 1], dr = g.Db[j + 1], wl = g.w[j], wr = g.w[j + 1];
+        gj.push_back({ket_site(g, j), env(j + 1), x1(), g.ids_dev, 2 * kl, dr * wr, kr, kr, kr,
+                      dr * wr, bsz});
+        mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, kl, dr, wl, wr, bsz});
+      }
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, gj, s, CLS_GEMM));
+      return run_mpo(st->ctx, ct, 1, mj, s);
+    };
+    auto right_env_from = [&](int j, bool from_init) -> int {
+      std::vector<GemmJob> gj;
+      for (auto& g : groups) {
+        const int bsz = (int)g.members.size();
+        const int kl = g.Kb[j], dl = g.Db[j], dr = g.Db[j + 1], wl = g.w[j];
+        gj.push_back({from_init && !g.warm ? init_site(g, j) : new_site(g, j), x2(), env(j),
+                      g.ids_dev, dl, wl * kl, 2 * dr, 2 * dr, 2 * dr, wl * kl, bsz});
+      }
+      return run_gemm(st->ctx, ct, ct, ct, acc, OP_J, OP_T, gj, s, CLS_GEMM);
+    };
+    // warm start: the ket embedded in the bra's bond dims plus eta times the
+    // generic guess (seeded completion of the directions the ket lacks),
+    // brought to right-canonical form from the right: M_j = L_j Q_j by LQ,
+    // B_j = Q_j, M_{j-1} <- M_{j-1} L_j (L_j^T = conj(Q_j) M_j^T).  B_0 is never
+    // read (the first visit forms site 0 from the environments).
+    auto warm_bra = [&]() -> int {
+      bool any = false;
+      for (auto& g : groups) any = any || g.warm;
+      if (!any) return DCS_OK;
+      auto embed = [&](const Group& g, Operand dst, Operand src, Operand ini, int dl, int dr,
+                       int kl, int kr, double eta) -> int {
+        EmbedArgs a;
+        a.dst = dst;
+        a.src = src;
+        a.init = ini;
+        a.ids = g.ids_dev;
+        a.dl = dl;
+        a.dr = dr;
+        a.kl = kl;
+        a.kr = kr;
+        a.batch = (int)g.members.size();
+        a.eta = eta;
+        DCS_HIP(launch_embed(ct, a, s));
+        return DCS_OK;
+      };
+      const Operand none = local_op(nullptr, 0);
       for (auto& g : groups) {
         if (!g.warm) continue;
+        for (int j = 0; j < nq; ++j)
+          DCS_TRY(embed(g, new_site(g, j), ket_site(g, j), init_site(g, j), g.Db[j], g.Db[j + 1],
+                        g.Kb[j], g.Kb[j + 1], st->warm_eta));
+      }
+      for (int j = nq - 1; j >= 1; --j) {
+        std::vector<QrJob> qj;
+        std::vector<GemmJob> gl, gm;
+        for (auto& g : groups) {
+          if (!g.warm) continue;
+          const int bsz = (int)g.members.size();
+          const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
+          QrJob q;
+          q.f = new_site(g, j);
+          q.q = fbuf();
+          q.ws = slot_op(st, L.o_ws, 0);
+          q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
+          q.ids = g.ids_dev;
+          q.m = 2 * dr;
+          q.n = dl;
+          q.mode = 1;
+          q.batch = bsz;
+          qj.push_back(q);
+          gl.push_back({fbuf(), new_site(g, j), x2(), g.ids_dev, dl, dl, 2 * dr, 2 * dr, 2 * dr, dl,
+                        bsz});
+          gm.push_back({new_site(g, j - 1), x2(), x1(), g.ids_dev, 2 * dp, dl, dl, dl, dl, dl, bsz});
+        }
+        DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
+        DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_J, OP_T, gl, s, CLS_GEMM));
+        DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_T, gm, s, CLS_GEMM));
+        for (auto& g : groups) {
+          if (!g.warm) continue;
+          const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
+          DCS_TRY(embed(g, new_site(g, j), fbuf(), none, dl, dr, dl, dr, 0.0));
+          DCS_TRY(embed(g, new_site(g, j - 1), x1(), none, dp, dl, dp, dl, 0.0));
+        }
+      }
+      return DCS_OK;
+    };
+    // moving right at site j: X1 = L_j K_j, X2 = W X1, F = X2 R_{j+1}^T
+    auto right_site = [&](int j, int qr_mode) -> int {
+      std::vector<GemmJob> g1, g2;
+      std::vector<MpoJob> mj;
+      std::vector<QrJob> qj;
+      for (auto& g : groups) {
         const int bsz = (int)g.members.size();
-        const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
+        const int kl = g.Kb[j], kr = g.Kb[j + 1], dl = g.Db[j], dr = g.Db[j + 1];
+        const int wl = g.w[j], wr = g.w[j + 1];
+        g1.push_back({env(j), ket_site(g, j), x1(), g.ids_dev, dl * wl, 2 * kr, kl, kl, 2 * kr,
+                      2 * kr, bsz});
+        mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, dl, kr, wl, wr, bsz});
+        g2.push_back({x2(), env(j + 1), fbuf(), g.ids_dev, 2 * dl, dr, wr * kr, wr * kr, wr * kr,
+                      dr, bsz});
         QrJob q;
-        q.f = new_site(g, j);
-        q.q = fbuf();
+        q.f = fbuf();
+        q.q = new_site(g, j);
+        q.ws = slot_op(st, L.o_ws, 0);
+        q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
+        q.ids = g.ids_dev;
+        q.m = (qr_mode == 2) ? 2 * dl * dr : 2 * dl;
+        q.n = (qr_mode == 2) ? 1 : dr;
+        q.mode = qr_mode;
+        q.batch = bsz;
+        qj.push_back(q);
+      }
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, g1, s, CLS_GEMM));
+      DCS_TRY(run_mpo(st->ctx, ct, 0, mj, s));
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, g2, s, CLS_GEMM));
+      DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
+      if (qr_mode == 2) return DCS_OK;
+      std::vector<GemmJob> g3;
+      for (auto& g : groups) {
+        const int bsz = (int)g.members.size();
+        const int kr = g.Kb[j + 1], dl = g.Db[j], dr = g.Db[j + 1], wr = g.w[j + 1];
+        g3.push_back({new_site(g, j), x2(), env(j + 1), g.ids_dev, dr, wr * kr, 2 * dl, dr,
+                      wr * kr, wr * kr, bsz});
+      }
+      return run_gemm(st->ctx, ct, ct, ct, acc, OP_C, OP_N, g3, s, CLS_GEMM);
+    };
+    auto left_site = [&](int j) -> int {
+      DCS_TRY(left_prologue(j));
+      std::vector<GemmJob> gj;
+      std::vector<QrJob> qj;
+      for (auto& g : groups) {
+        const int bsz = (int)g.members.size();
+        const int kl = g.Kb[j], dl = g.Db[j], dr = g.Db[j + 1], wl = g.w[j];
+        gj.push_back({env(j), x2(), fbuf(), g.ids_dev, dl, 2 * dr, wl * kl, wl * kl, 2 * dr, 2 * dr,
+                      bsz});
+        QrJob q;
+        q.f = fbuf();
+        q.q = new_site(g, j);
         q.ws = slot_op(st, L.o_ws, 0);
         q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
         q.ids = g.ids_dev;
@@ -1440,191 +1575,116 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
         q.mode = 1;
         q.batch = bsz;
         qj.push_back(q);
-        gl.push_back({fbuf(), new_site(g, j), x2(), g.ids_dev, dl, dl, 2 * dr, 2 * dr, 2 * dr, dl,
-                      bsz});
-        gm.push_back({new_site(g, j - 1), x2(), x1(), g.ids_dev, 2 * dp, dl, dl, dl, dl, dl, bsz});
       }
+      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, gj, s, CLS_GEMM));
       DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
-      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_J, OP_T, gl, s, CLS_GEMM));
-      DCS_TRY(run_gemm(st->ctx, ct, ct, ct, ct, OP_N, OP_T, gm, s, CLS_GEMM));
-      for (auto& g : groups) {
-        if (!g.warm) continue;
-        const int dl = g.Db[j], dr = g.Db[j + 1], dp = g.Db[j - 1];
-        DCS_TRY(embed(g, new_site(g, j), fbuf(), none, dl, dr, dl, dr, 0.0));
-        DCS_TRY(embed(g, new_site(g, j - 1), x1(), none, dp, dl, dp, dl, 0.0));
-      }
-    }
-    return DCS_OK;
-  };
-  // moving right at site j: X1 = L_j K_j, X2 = W X1, F = X2 R_{j+1}^T
-  auto right_site = [&](int j, int qr_mode) -> int {
-    std::vector<GemmJob> g1, g2;
-    std::vector<MpoJob> mj;
-    std::vector<QrJob> qj;
-    for (auto& g : groups) {
-      const int bsz = (int)g.members.size();
-      const int kl = g.Kb[j], kr = g.Kb[j + 1], dl = g.Db[j], dr = g.Db[j + 1];
-      const int wl = g.w[j], wr = g.w[j + 1];
-      g1.push_back({env(j), ket_site(g, j), x1(), g.ids_dev, dl * wl, 2 * kr, kl, kl, 2 * kr,
-                    2 * kr, bsz});
-      mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, dl, kr, wl, wr, bsz});
-      g2.push_back({x2(), env(j + 1), fbuf(), g.ids_dev, 2 * dl, dr, wr * kr, wr * kr, wr * kr,
-                    dr, bsz});
-      QrJob q;
-      q.f = fbuf();
-      q.q = new_site(g, j);
-      q.ws = slot_op(st, L.o_ws, 0);
-      q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
-      q.ids = g.ids_dev;
-      q.m = (qr_mode == 2) ? 2 * dl * dr : 2 * dl;
-      q.n = (qr_mode == 2) ? 1 : dr;
-      q.mode = qr_mode;
-      q.batch = bsz;
-      qj.push_back(q);
-    }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, g1, s, CLS_GEMM));
-    DCS_TRY(run_mpo(st->ctx, ct, 0, mj, s));
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_T, g2, s, CLS_GEMM));
-    DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
-    if (qr_mode == 2) return DCS_OK;
-    std::vector<GemmJob> g3;
-    for (auto& g : groups) {
-      const int bsz = (int)g.members.size();
-      const int kr = g.Kb[j + 1], dl = g.Db[j], dr = g.Db[j + 1], wr = g.w[j + 1];
-      g3.push_back({new_site(g, j), x2(), env(j + 1), g.ids_dev, dr, wr * kr, 2 * dl, dr,
-                    wr * kr, wr * kr, bsz});
-    }
-    return run_gemm(st->ctx, ct, ct, ct, acc, OP_C, OP_N, g3, s, CLS_GEMM);
-  };
-  auto left_site = [&](int j) -> int {
-    DCS_TRY(left_prologue(j));
-    std::vector<GemmJob> gj;
-    std::vector<QrJob> qj;
-    for (auto& g : groups) {
-      const int bsz = (int)g.members.size();
-      const int kl = g.Kb[j], dl = g.Db[j], dr = g.Db[j + 1], wl = g.w[j];
-      gj.push_back({env(j), x2(), fbuf(), g.ids_dev, dl, 2 * dr, wl * kl, wl * kl, 2 * dr, 2 * dr,
-                    bsz});
-      QrJob q;
-      q.f = fbuf();
-      q.q = new_site(g, j);
-      q.ws = slot_op(st, L.o_ws, 0);
-      q.nrm2 = local_op(nrm_dev + g.goff, sizeof(double));
-      q.ids = g.ids_dev;
-      q.m = 2 * dr;
-      q.n = dl;
-      q.mode = 1;
-      q.batch = bsz;
-      qj.push_back(q);
-    }
-    DCS_TRY(run_gemm(st->ctx, ct, ct, ct, acc, OP_N, OP_N, gj, s, CLS_GEMM));
-    DCS_TRY(run_qr(st->ctx, ct, ct, qj, s));
-    return right_env_from(j, false);
-  };
+      return right_env_from(j, false);
+    };
 
-  std::vector<int> visits;
-  for (int t = 1; t <= n_sweeps; ++t) {
-    if (t % 2 == 1)
-      for (int j = (t == 1 ? 0 : 1); j < nq; ++j) visits.push_back(j);
-    else
-      for (int j = nq - 2; j >= 0; --j) visits.push_back(j);
-  }
-  auto enqueue = [&]() -> int {
-    DCS_TRY(warm_bra());
-    // right environments of the starting guess
-    for (int j = nq - 1; j >= 1; --j) {
-      DCS_TRY(left_prologue(j));
-      DCS_TRY(right_env_from(j, true));
+    std::vector<int> visits;
+    for (int t = 1; t <= n_sweeps; ++t) {
+      if (t % 2 == 1)
+        for (int j = (t == 1 ? 0 : 1); j < nq; ++j) visits.push_back(j);
+      else
+        for (int j = nq - 2; j >= 0; --j) visits.push_back(j);
     }
-    for (size_t v = 0; v < visits.size(); ++v) {
-      const int j = visits[v];
-      if (v + 1 == visits.size()) {
-        DCS_TRY(right_site(j, 2));
-      } else if (visits[v + 1] == j + 1) {
-        DCS_TRY(right_site(j, 0));
+    auto enqueue = [&]() -> int {
+      DCS_TRY(warm_bra());
+      // right environments of the starting guess
+      for (int j = nq - 1; j >= 1; --j) {
+        DCS_TRY(left_prologue(j));
+        DCS_TRY(right_env_from(j, true));
+      }
+      for (size_t v = 0; v < visits.size(); ++v) {
+        const int j = visits[v];
+        if (v + 1 == visits.size()) {
+          DCS_TRY(right_site(j, 2));
+        } else if (visits[v + 1] == j + 1) {
+          DCS_TRY(right_site(j, 0));
+        } else {
+          DCS_TRY(left_site(j));
+        }
+      }
+      return DCS_OK;
+    };
+    if (st->ctx->graphs && !st->ctx->timing) {
+      std::string sig;
+      auto put = [&](int v) { sig.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
+      put(n_sweeps);
+      for (auto& g : groups) {
+        put(-1);
+        put(g.warm ? 1 : 0);
+        if (g.warm) sig.append(reinterpret_cast<const char*>(&st->warm_eta), sizeof(double));
+        put(g.chi_cap);
+        put(g.cur);
+        put(g.goff);
+        for (int v : g.Kb) put(v);
+        for (int v : g.w) put(v);
+        for (int i : g.members) put(ids[i]);
+      }
+      auto it = st->graphs.find(sig);
+      if (it == st->graphs.end() && st->graph_seen[sig]++ >= 1) {
+        if (st->graphs.size() >= 64) {
+          for (auto& kv : st->graphs) (void)hipGraphExecDestroy(kv.second);
+          st->graphs.clear();
+        }
+        // capture on the state's own stream (the caller's may be the legacy
+        // default stream, which cannot capture); the kernels only read data the
+        // caller's stream has produced, so the replay goes on the caller's stream
+        if (!st->capture_stream)
+          DCS_HIP(hipStreamCreateWithFlags(&st->capture_stream, hipStreamNonBlocking));
+        const hipStream_t caller = s;
+        s = st->capture_stream;
+        DCS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        st->ctx->capturing = true;
+        const int rc = enqueue();
+        st->ctx->capturing = false;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        s = caller;
+        if (rc != DCS_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return rc;
+        }
+        DCS_HIP(ec);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        DCS_HIP(ei);
+        it = st->graphs.emplace(sig, exec).first;
+      }
+      if (it != st->graphs.end()) {
+        DCS_HIP(hipGraphLaunch(it->second, s));
       } else {
-        DCS_TRY(left_site(j));
+        DCS_TRY(enqueue());
       }
-    }
-    return DCS_OK;
-  };
-  if (st->ctx->graphs && !st->ctx->timing) {
-    std::string sig;
-    auto put = [&](int v) { sig.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
-    put(n_sweeps);
-    for (auto& g : groups) {
-      put(-1);
-      put(g.warm ? 1 : 0);
-      if (g.warm) sig.append(reinterpret_cast<const char*>(&st->warm_eta), sizeof(double));
-      put(g.chi_cap);
-      put(g.cur);
-      put(g.goff);
-      for (int v : g.Kb) put(v);
-      for (int v : g.w) put(v);
-      for (int i : g.members) put(ids[i]);
-    }
-    auto it = st->graphs.find(sig);
-    if (it == st->graphs.end() && st->graph_seen[sig]++ >= 1) {
-      if (st->graphs.size() >= 64) {
-        for (auto& kv : st->graphs) (void)hipGraphExecDestroy(kv.second);
-        st->graphs.clear();
-      }
-      // capture on the state's own stream (the caller's may be the legacy
-      // default stream, which cannot capture); the kernels only read data the
-      // caller's stream has produced, so the replay goes on the caller's stream
-      if (!st->capture_stream)
-        DCS_HIP(hipStreamCreateWithFlags(&st->capture_stream, hipStreamNonBlocking));
-      const hipStream_t caller = s;
-      s = st->capture_stream;
-      DCS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      st->ctx->capturing = true;
-      const int rc = enqueue();
-      st->ctx->capturing = false;
-      hipGraph_t graph = nullptr;
-      const hipError_t ec = hipStreamEndCapture(s, &graph);
-      s = caller;
-      if (rc != DCS_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      DCS_HIP(ec);
-      hipGraphExec_t exec = nullptr;
-      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      DCS_HIP(ei);
-      it = st->graphs.emplace(sig, exec).first;
-    }
-    if (it != st->graphs.end()) {
-      DCS_HIP(hipGraphLaunch(it->second, s));
     } else {
       DCS_TRY(enqueue());
     }
-  } else {
-    DCS_TRY(enqueue());
-  }
-  std::vector<double> nrm(n);
-  DCS_HIP(hipMemcpyAsync(nrm.data(), nrm_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-  DCS_HIP(hipStreamSynchronize(s));
-  tune_resolve(st->ctx);
-  const int centre = visits.back();
-  int k = 0;
-  for (auto& g : groups) {
-    for (int i : g.members) {
-      fid_out[i] = nrm[k++];
-      Slot& sl = st->slots[ids[i]];
-      sl.dims = g.Db;
-      sl.cur = 1 - sl.cur;
-      sl.lc_end = centre;
-      sl.rc_start = centre + 1;
-      sl.ecache_bond = -1;
-      sl.measured_q = -1;
+    std::vector<double> nrm(n);
+    DCS_HIP(hipMemcpyAsync(nrm.data(), nrm_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    DCS_HIP(hipStreamSynchronize(s));
+    tune_resolve(st->ctx);
+    const int centre = visits.back();
+    int k = 0;
+    for (auto& g : groups) {
+      for (int i : g.members) {
+        fid_out[i] = nrm[k++];
+        Slot& sl = st->slots[ids[i]];
+        sl.dims = g.Db;
+        sl.cur = 1 - sl.cur;
+        sl.lc_end = centre;
+        sl.rc_start = centre + 1;
+        sl.ecache_bond = -1;
+        sl.measured_q = -1;
+      }
     }
-  }
-  for (int i = 0; i < n; ++i)
-    if (!(fid_out[i] > 0.0) || !std::isfinite(fid_out[i]))
-      return fail(DCS_ENUMERIC, "vanishing or non-finite environment tensor in branch " +
-                                    std::to_string(ids[i]));
-  return DCS_OK;
+    for (int i = 0; i < n; ++i)
+      if (!(fid_out[i] > 0.0) || !std::isfinite(fid_out[i]))
+        return fail(DCS_ENUMERIC, "vanishing or non-finite environment tensor in branch " +
+                                      std::to_string(ids[i]));
+    return DCS_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1805,73 +1865,77 @@ int check_measure_args(dcs_state* st, int n, const int* ids, const int* qubits) 
 
 int dcs_measure_prob(dcs_state* st, int n, const int* ids, const int* qubits, double* p0_out,
                      void* stream) {
-  DCS_TRY(check_measure_args(st, n, ids, qubits));
-  if (n == 0) return DCS_OK;
-  if (!p0_out) return fail(DCS_EINVAL, "null p0_out");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<int> pos;
-  DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
-  const double* out_dev = reinterpret_cast<const double*>(st->base + st->L.o_out);
-  std::vector<double> nm(2 * n);
-  DCS_HIP(hipMemcpyAsync(nm.data(), out_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
-  DCS_HIP(hipStreamSynchronize(s));
-  tune_resolve(st->ctx);
-  for (int i = 0; i < n; ++i) {
-    Slot& sl = st->slots[ids[i]];
-    sl.n0 = nm[2 * pos[i]];
-    sl.n1 = nm[2 * pos[i] + 1];
-    sl.measured_q = qubits[i];
-    const double tot = sl.n0 + sl.n1;
-    if (!(tot > 0.0) || !std::isfinite(tot)) {
-      sl.measured_q = -1;
-      return fail(DCS_ENUMERIC, "state norm vanished or is not finite");
+  return guarded([&]() -> int {
+    DCS_TRY(check_measure_args(st, n, ids, qubits));
+    if (n == 0) return DCS_OK;
+    if (!p0_out) return fail(DCS_EINVAL, "null p0_out");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int> pos;
+    DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
+    const double* out_dev = reinterpret_cast<const double*>(st->base + st->L.o_out);
+    std::vector<double> nm(2 * n);
+    DCS_HIP(hipMemcpyAsync(nm.data(), out_dev, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
+    DCS_HIP(hipStreamSynchronize(s));
+    tune_resolve(st->ctx);
+    for (int i = 0; i < n; ++i) {
+      Slot& sl = st->slots[ids[i]];
+      sl.n0 = nm[2 * pos[i]];
+      sl.n1 = nm[2 * pos[i] + 1];
+      sl.measured_q = qubits[i];
+      const double tot = sl.n0 + sl.n1;
+      if (!(tot > 0.0) || !std::isfinite(tot)) {
+        sl.measured_q = -1;
+        return fail(DCS_ENUMERIC, "state norm vanished or is not finite");
+      }
+      p0_out[i] = sl.n0 / tot;
     }
-    p0_out[i] = sl.n0 / tot;
-  }
-  return DCS_OK;
+    return DCS_OK;
+  });
 }
 
 int dcs_measure_sample_collapse(dcs_state* st, int n, const int* ids, const int* qubits,
                                 const double* u_dev, double eps, int* outcome_dev,
                                 double* pm_dev, void* stream) {
-  DCS_TRY(check_measure_args(st, n, ids, qubits));
-  if (n == 0) return DCS_OK;
-  if (!u_dev || !outcome_dev || !pm_dev) return fail(DCS_EINVAL, "null device array");
-  if (!(eps >= 0.0 && eps < 0.5)) return fail(DCS_EINVAL, "eps must be in [0, 0.5)");
-  const Layout& L = st->L;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<int> pos;
-  DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
-  std::vector<SampleItem> items(n);
-  int max_elems = 0;
-  for (int i = 0; i < n; ++i) {
-    const Slot& sl = st->slots[ids[i]];
-    const int q = qubits[i];
-    items[i].a = st->slot_base(ids[i]) + L.o_mps[sl.cur] + L.site_off[q];
-    items[i].dl = sl.dims[q];
-    items[i].dr = sl.dims[q + 1];
-    items[i].k = pos[i];
-    items[i].idx = i;
-    max_elems = std::max(max_elems, sl.dims[q] * sl.dims[q + 1]);
-  }
-  SampleItem* items_dev = reinterpret_cast<SampleItem*>(st->base + L.o_items);
-  DCS_TRY(stage_h2d(st, s, items_dev, items.data(), sizeof(SampleItem) * n));
-  {
-    Timed t(st->ctx, s, CLS_MEAS, 0, 0);
-    DCS_HIP(launch_sample_collapse(L.ct, items_dev, n, max_elems,
-                                   reinterpret_cast<const double*>(st->base + L.o_out), u_dev, eps,
-                                   outcome_dev, pm_dev, s));
-  }
-  // the collapsed site breaks the canonical forms around it, whatever the outcome
-  for (int i = 0; i < n; ++i) {
-    Slot& sl = st->slots[ids[i]];
-    const int q = qubits[i];
-    sl.lc_end = std::min(sl.lc_end, q);
-    sl.rc_start = std::max(sl.rc_start, q + 1);
-    if (sl.ecache_bond > q) sl.ecache_bond = -1;
-    sl.measured_q = -1;
-  }
-  return DCS_OK;
+  return guarded([&]() -> int {
+    DCS_TRY(check_measure_args(st, n, ids, qubits));
+    if (n == 0) return DCS_OK;
+    if (!u_dev || !outcome_dev || !pm_dev) return fail(DCS_EINVAL, "null device array");
+    if (!(eps >= 0.0 && eps < 0.5)) return fail(DCS_EINVAL, "eps must be in [0, 0.5)");
+    const Layout& L = st->L;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int> pos;
+    DCS_TRY(enqueue_norms(st, n, ids, qubits, s, pos));
+    std::vector<SampleItem> items(n);
+    int max_elems = 0;
+    for (int i = 0; i < n; ++i) {
+      const Slot& sl = st->slots[ids[i]];
+      const int q = qubits[i];
+      items[i].a = st->slot_base(ids[i]) + L.o_mps[sl.cur] + L.site_off[q];
+      items[i].dl = sl.dims[q];
+      items[i].dr = sl.dims[q + 1];
+      items[i].k = pos[i];
+      items[i].idx = i;
+      max_elems = std::max(max_elems, sl.dims[q] * sl.dims[q + 1]);
+    }
+    SampleItem* items_dev = reinterpret_cast<SampleItem*>(st->base + L.o_items);
+    DCS_TRY(stage_h2d(st, s, items_dev, items.data(), sizeof(SampleItem) * n));
+    {
+      Timed t(st->ctx, s, CLS_MEAS, 0, 0);
+      DCS_HIP(launch_sample_collapse(L.ct, items_dev, n, max_elems,
+                                     reinterpret_cast<const double*>(st->base + L.o_out), u_dev, eps,
+                                     outcome_dev, pm_dev, s));
+    }
+    // the collapsed site breaks the canonical forms around it, whatever the outcome
+    for (int i = 0; i < n; ++i) {
+      Slot& sl = st->slots[ids[i]];
+      const int q = qubits[i];
+      sl.lc_end = std::min(sl.lc_end, q);
+      sl.rc_start = std::max(sl.rc_start, q + 1);
+      if (sl.ecache_bond > q) sl.ecache_bond = -1;
+      sl.measured_q = -1;
+    }
+    return DCS_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1879,249 +1943,261 @@ int dcs_measure_sample_collapse(dcs_state* st, int n, const int* ids, const int*
 
 int dcs_collapse(dcs_state* st, int n, const int* src_ids, const int* qubits, const int* outcomes,
                  const int* dst_ids, double eps, double* pm_out, void* stream) {
-  if (!st) return fail(DCS_EINVAL, "null state");
-  if (n == 0) return DCS_OK;
-  if (!src_ids || !qubits || !outcomes || !dst_ids) return fail(DCS_EINVAL, "null arrays");
-  const Layout& L = st->L;
-  DCS_TRY(check_ids(st, n, dst_ids, false));
-  std::vector<char> is_src(L.cap, 0);
-  for (int i = 0; i < n; ++i) {
-    const int sid = src_ids[i];
-    if (sid < 0 || sid >= L.cap) return fail(DCS_ECAPACITY, "source id outside capacity");
-    is_src[sid] = 1;
-  }
-  std::vector<double> pm(n);
-  for (int i = 0; i < n; ++i) {
-    const int sid = src_ids[i], did = dst_ids[i];
-    const Slot& sl = st->slots[sid];
-    if (!sl.live) return fail(DCS_ESTATE, "source branch is not live");
-    if (sl.measured_q != qubits[i])
-      return fail(DCS_ESTATE, "collapse of branch " + std::to_string(sid) + " on qubit " +
-                                  std::to_string(qubits[i]) + " without a matching measurement");
-    if (outcomes[i] != 0 && outcomes[i] != 1) return fail(DCS_EINVAL, "outcome must be 0 or 1");
-    if (did != sid && (st->slots[did].live || is_src[did]))
-      return fail(DCS_EINVAL, "destination slot " + std::to_string(did) + " is in use");
-    const double nm = outcomes[i] ? sl.n1 : sl.n0;
-    pm[i] = nm / (sl.n0 + sl.n1);
-    if (!(pm[i] > eps))
-      return fail(DCS_EZEROPROB, "outcome " + std::to_string(outcomes[i]) + " of branch " +
-                                     std::to_string(sid) + " has probability " +
-                                     std::to_string(pm[i]));
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // copies first, so a source may also be collapsed in place
-  std::vector<Slot> src_meta(n);
-  for (int i = 0; i < n; ++i) src_meta[i] = st->slots[src_ids[i]];
-  for (int i = 0; i < n; ++i) {
-    const int sid = src_ids[i], did = dst_ids[i];
-    if (did == sid) continue;
-    const Slot& sl = src_meta[i];
-    char* sb = st->slot_base(sid);
-    char* db = st->slot_base(did);
-    DCS_HIP(hipMemcpyAsync(db + L.o_mps[sl.cur], sb + L.o_mps[sl.cur], L.mps_bytes,
-                           hipMemcpyDeviceToDevice, s));
-    if (sl.ecache_bond >= 0) {
-      const size_t eb = (size_t)sl.dims[sl.ecache_bond] * sl.dims[sl.ecache_bond] * 16;
-      DCS_HIP(hipMemcpyAsync(db + L.o_e, sb + L.o_e, eb, hipMemcpyDeviceToDevice, s));
+  return guarded([&]() -> int {
+    if (!st) return fail(DCS_EINVAL, "null state");
+    if (n == 0) return DCS_OK;
+    if (!src_ids || !qubits || !outcomes || !dst_ids) return fail(DCS_EINVAL, "null arrays");
+    const Layout& L = st->L;
+    DCS_TRY(check_ids(st, n, dst_ids, false));
+    std::vector<char> is_src(L.cap, 0);
+    for (int i = 0; i < n; ++i) {
+      const int sid = src_ids[i];
+      if (sid < 0 || sid >= L.cap) return fail(DCS_ECAPACITY, "source id outside capacity");
+      is_src[sid] = 1;
     }
-  }
-  std::vector<CollapseItem> items(n);
-  int max_elems = 0;
-  for (int i = 0; i < n; ++i) {
-    const Slot& sl = src_meta[i];
-    const int q = qubits[i];
-    const double nm = outcomes[i] ? sl.n1 : sl.n0;
-    items[i].a = st->slot_base(dst_ids[i]) + L.o_mps[sl.cur] + L.site_off[q];
-    items[i].scale = 1.0 / std::sqrt(nm);
-    items[i].dl = sl.dims[q];
-    items[i].dr = sl.dims[q + 1];
-    items[i].m = outcomes[i];
-    items[i].pad_ = 0;
-    max_elems = std::max(max_elems, sl.dims[q] * sl.dims[q + 1]);
-  }
-  CollapseItem* items_dev = reinterpret_cast<CollapseItem*>(st->base + L.o_items);
-  DCS_HIP(hipMemcpyAsync(items_dev, items.data(), sizeof(CollapseItem) * n, hipMemcpyHostToDevice, s));
-  {
-    Timed t(st->ctx, s, CLS_OTHER, 0, 0);
-    DCS_HIP(launch_collapse(L.ct, items_dev, n, max_elems, s));
-  }
-  DCS_HIP(hipStreamSynchronize(s));
-  for (int i = 0; i < n; ++i) {
-    Slot nsl = src_meta[i];
-    const int q = qubits[i];
-    nsl.live = true;
-    nsl.lc_end = std::min(nsl.lc_end, q);
-    nsl.rc_start = std::max(nsl.rc_start, q + 1);
-    if (nsl.ecache_bond > q) nsl.ecache_bond = -1;
-    nsl.measured_q = -1;
-    st->slots[dst_ids[i]] = nsl;
-    if (pm_out) pm_out[i] = pm[i];
-  }
-  return DCS_OK;
+    std::vector<double> pm(n);
+    for (int i = 0; i < n; ++i) {
+      const int sid = src_ids[i], did = dst_ids[i];
+      const Slot& sl = st->slots[sid];
+      if (!sl.live) return fail(DCS_ESTATE, "source branch is not live");
+      if (sl.measured_q != qubits[i])
+        return fail(DCS_ESTATE, "collapse of branch " + std::to_string(sid) + " on qubit " +
+                                    std::to_string(qubits[i]) + " without a matching measurement");
+      if (outcomes[i] != 0 && outcomes[i] != 1) return fail(DCS_EINVAL, "outcome must be 0 or 1");
+      if (did != sid && (st->slots[did].live || is_src[did]))
+        return fail(DCS_EINVAL, "destination slot " + std::to_string(did) + " is in use");
+      const double nm = outcomes[i] ? sl.n1 : sl.n0;
+      pm[i] = nm / (sl.n0 + sl.n1);
+      if (!(pm[i] > eps))
+        return fail(DCS_EZEROPROB, "outcome " + std::to_string(outcomes[i]) + " of branch " +
+                                       std::to_string(sid) + " has probability " +
+                                       std::to_string(pm[i]));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // copies first, so a source may also be collapsed in place
+    std::vector<Slot> src_meta(n);
+    for (int i = 0; i < n; ++i) src_meta[i] = st->slots[src_ids[i]];
+    for (int i = 0; i < n; ++i) {
+      const int sid = src_ids[i], did = dst_ids[i];
+      if (did == sid) continue;
+      const Slot& sl = src_meta[i];
+      char* sb = st->slot_base(sid);
+      char* db = st->slot_base(did);
+      DCS_HIP(hipMemcpyAsync(db + L.o_mps[sl.cur], sb + L.o_mps[sl.cur], L.mps_bytes,
+                             hipMemcpyDeviceToDevice, s));
+      if (sl.ecache_bond >= 0) {
+        const size_t eb = (size_t)sl.dims[sl.ecache_bond] * sl.dims[sl.ecache_bond] * 16;
+        DCS_HIP(hipMemcpyAsync(db + L.o_e, sb + L.o_e, eb, hipMemcpyDeviceToDevice, s));
+      }
+    }
+    std::vector<CollapseItem> items(n);
+    int max_elems = 0;
+    for (int i = 0; i < n; ++i) {
+      const Slot& sl = src_meta[i];
+      const int q = qubits[i];
+      const double nm = outcomes[i] ? sl.n1 : sl.n0;
+      items[i].a = st->slot_base(dst_ids[i]) + L.o_mps[sl.cur] + L.site_off[q];
+      items[i].scale = 1.0 / std::sqrt(nm);
+      items[i].dl = sl.dims[q];
+      items[i].dr = sl.dims[q + 1];
+      items[i].m = outcomes[i];
+      items[i].pad_ = 0;
+      max_elems = std::max(max_elems, sl.dims[q] * sl.dims[q + 1]);
+    }
+    CollapseItem* items_dev = reinterpret_cast<CollapseItem*>(st->base + L.o_items);
+    DCS_HIP(hipMemcpyAsync(items_dev, items.data(), sizeof(CollapseItem) * n, hipMemcpyHostToDevice, s));
+    {
+      Timed t(st->ctx, s, CLS_OTHER, 0, 0);
+      DCS_HIP(launch_collapse(L.ct, items_dev, n, max_elems, s));
+    }
+    DCS_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+      Slot nsl = src_meta[i];
+      const int q = qubits[i];
+      nsl.live = true;
+      nsl.lc_end = std::min(nsl.lc_end, q);
+      nsl.rc_start = std::max(nsl.rc_start, q + 1);
+      if (nsl.ecache_bond > q) nsl.ecache_bond = -1;
+      nsl.measured_q = -1;
+      st->slots[dst_ids[i]] = nsl;
+      if (pm_out) pm_out[i] = pm[i];
+    }
+    return DCS_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------
 
 int dcs_topk_by_weight(int n, const double* weights, int k, int* keep_idx_out, int* n_keep_out,
                        double* discarded_out) {
-  if (n < 0 || k < 0) return fail(DCS_EINVAL, "negative size");
-  if ((n > 0 && !weights) || !n_keep_out) return fail(DCS_EINVAL, "null argument");
-  const int keep = std::min(n, k);
-  if (keep > 0 && !keep_idx_out) return fail(DCS_EINVAL, "null keep_idx_out");
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return weights[a] > weights[b]; });
-  double dropped = 0;
-  for (int i = keep; i < n; ++i) dropped += weights[order[i]];
-  for (int i = 0; i < keep; ++i) keep_idx_out[i] = order[i];
-  *n_keep_out = keep;
-  if (discarded_out) *discarded_out = dropped;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (n < 0 || k < 0) return fail(DCS_EINVAL, "negative size");
+    if ((n > 0 && !weights) || !n_keep_out) return fail(DCS_EINVAL, "null argument");
+    const int keep = std::min(n, k);
+    if (keep > 0 && !keep_idx_out) return fail(DCS_EINVAL, "null keep_idx_out");
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return weights[a] > weights[b]; });
+    double dropped = 0;
+    for (int i = keep; i < n; ++i) dropped += weights[order[i]];
+    for (int i = 0; i < keep; ++i) keep_idx_out[i] = order[i];
+    *n_keep_out = keep;
+    if (discarded_out) *discarded_out = dropped;
+    return DCS_OK;
+  });
 }
 
 int dcs_prune_adaptive(int n, const double* weights, int k_max, double mass_tol, double rel_min,
                        int* keep_idx_out, int* n_keep_out, double* discarded_out) {
-  if (n < 0 || k_max < 1) return fail(DCS_EINVAL, "n must be >= 0 and k_max >= 1");
-  if ((n > 0 && !weights) || !n_keep_out) return fail(DCS_EINVAL, "null argument");
-  if (!(mass_tol >= 0.0 && mass_tol < 1.0) || !(rel_min >= 0.0 && rel_min <= 1.0))
-    return fail(DCS_EINVAL, "mass_tol must be in [0, 1) and rel_min in [0, 1]");
-  if (n > 0 && !keep_idx_out) return fail(DCS_EINVAL, "null keep_idx_out");
-  for (int i = 0; i < n; ++i)
-    if (!(weights[i] >= 0.0)) return fail(DCS_EINVAL, "weights must be non-negative");
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return weights[a] > weights[b]; });
-  double total = 0;
-  for (int i = 0; i < n; ++i) total += weights[i];
-  const double floor_w = n > 0 ? rel_min * weights[order[0]] : 0.0;
-  const double goal = (1.0 - mass_tol) * total;
-  double kept = 0;
-  int nk = 0;
-  for (int i = 0; i < n && nk < k_max; ++i) {
-    const double w = weights[order[i]];
-    if (nk > 0 && (w < floor_w || (mass_tol > 0.0 && kept >= goal))) break;
-    keep_idx_out[nk++] = order[i];
-    kept += w;
-  }
-  double dropped = 0;
-  for (int i = nk; i < n; ++i) dropped += weights[order[i]];
-  *n_keep_out = nk;
-  if (discarded_out) *discarded_out = dropped;
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (n < 0 || k_max < 1) return fail(DCS_EINVAL, "n must be >= 0 and k_max >= 1");
+    if ((n > 0 && !weights) || !n_keep_out) return fail(DCS_EINVAL, "null argument");
+    if (!(mass_tol >= 0.0 && mass_tol < 1.0) || !(rel_min >= 0.0 && rel_min <= 1.0))
+      return fail(DCS_EINVAL, "mass_tol must be in [0, 1) and rel_min in [0, 1]");
+    if (n > 0 && !keep_idx_out) return fail(DCS_EINVAL, "null keep_idx_out");
+    for (int i = 0; i < n; ++i)
+      if (!(weights[i] >= 0.0)) return fail(DCS_EINVAL, "weights must be non-negative");
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return weights[a] > weights[b]; });
+    double total = 0;
+    for (int i = 0; i < n; ++i) total += weights[i];
+    const double floor_w = n > 0 ? rel_min * weights[order[0]] : 0.0;
+    const double goal = (1.0 - mass_tol) * total;
+    double kept = 0;
+    int nk = 0;
+    for (int i = 0; i < n && nk < k_max; ++i) {
+      const double w = weights[order[i]];
+      if (nk > 0 && (w < floor_w || (mass_tol > 0.0 && kept >= goal))) break;
+      keep_idx_out[nk++] = order[i];
+      kept += w;
+    }
+    double dropped = 0;
+    for (int i = nk; i < n; ++i) dropped += weights[order[i]];
+    *n_keep_out = nk;
+    if (discarded_out) *discarded_out = dropped;
+    return DCS_OK;
+  });
 }
 
 int dcs_overlap(dcs_state* st, int id_a, int id_b, double* out, void* stream) {
-  if (!st || !out) return fail(DCS_EINVAL, "null argument");
-  const int pair[2] = {id_a, id_b};
-  DCS_TRY(check_ids(st, id_a == id_b ? 1 : 2, pair, true));
-  const Layout& L = st->L;
-  const int ct = L.ct;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const Slot& A = st->slots[id_a];
-  const Slot& B = st->slots[id_b];
-  auto site = [&](int id, const Slot& sl, int j) {
-    return local_op(st->slot_base(id) + L.o_mps[sl.cur] + L.site_off[j], 0);
-  };
-  // left transfer E_j[a][b] over bonds j (bra a, ket b), FP64, in slot a's
-  // measurement scratch (its cached left transfer becomes invalid)
-  const Operand E = local_op(st->slot_base(id_a) + L.o_e, 0);
-  const Operand TX = local_op(st->slot_base(id_a) + L.o_tx, 0);
-  for (int j = 0; j < L.n; ++j) {
-    const int dla = A.dims[j], dra = A.dims[j + 1], dlb = B.dims[j], drb = B.dims[j + 1];
-    if (j == 0) {   // E_1 = A_0^H B_0 (left bond of dimension 1)
-      std::vector<GemmJob> g{{site(id_a, A, 0), site(id_b, B, 0), E, nullptr, dra, drb, 2 * dla,
-                              dra, drb, drb, 1}};
-      DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, g, s, CLS_OTHER));
-    } else {        // TX = E_j B_j, E_{j+1} = A_j^H TX over (a, s)
-      std::vector<GemmJob> g1{{E, site(id_b, B, j), TX, nullptr, dla, 2 * drb, dlb, dlb, 2 * drb,
-                               2 * drb, 1}};
-      DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, g1, s, CLS_OTHER));
-      std::vector<GemmJob> g2{{site(id_a, A, j), TX, E, nullptr, dra, drb, 2 * dla, dra, drb, drb,
-                               1}};
-      DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, g2, s, CLS_OTHER));
+  return guarded([&]() -> int {
+    if (!st || !out) return fail(DCS_EINVAL, "null argument");
+    const int pair[2] = {id_a, id_b};
+    DCS_TRY(check_ids(st, id_a == id_b ? 1 : 2, pair, true));
+    const Layout& L = st->L;
+    const int ct = L.ct;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Slot& A = st->slots[id_a];
+    const Slot& B = st->slots[id_b];
+    auto site = [&](int id, const Slot& sl, int j) {
+      return local_op(st->slot_base(id) + L.o_mps[sl.cur] + L.site_off[j], 0);
+    };
+    // left transfer E_j[a][b] over bonds j (bra a, ket b), FP64, in slot a's
+    // measurement scratch (its cached left transfer becomes invalid)
+    const Operand E = local_op(st->slot_base(id_a) + L.o_e, 0);
+    const Operand TX = local_op(st->slot_base(id_a) + L.o_tx, 0);
+    for (int j = 0; j < L.n; ++j) {
+      const int dla = A.dims[j], dra = A.dims[j + 1], dlb = B.dims[j], drb = B.dims[j + 1];
+      if (j == 0) {   // E_1 = A_0^H B_0 (left bond of dimension 1)
+        std::vector<GemmJob> g{{site(id_a, A, 0), site(id_b, B, 0), E, nullptr, dra, drb, 2 * dla,
+                                dra, drb, drb, 1}};
+        DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, g, s, CLS_OTHER));
+      } else {        // TX = E_j B_j, E_{j+1} = A_j^H TX over (a, s)
+        std::vector<GemmJob> g1{{E, site(id_b, B, j), TX, nullptr, dla, 2 * drb, dlb, dlb, 2 * drb,
+                                 2 * drb, 1}};
+        DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, g1, s, CLS_OTHER));
+        std::vector<GemmJob> g2{{site(id_a, A, j), TX, E, nullptr, dra, drb, 2 * dla, dra, drb, drb,
+                                 1}};
+        DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, g2, s, CLS_OTHER));
+      }
     }
-  }
-  double v[2];
-  DCS_HIP(hipMemcpyAsync(v, st->slot_base(id_a) + L.o_e, sizeof(v), hipMemcpyDeviceToHost, s));
-  DCS_HIP(hipStreamSynchronize(s));
-  tune_resolve(st->ctx);
-  st->slots[id_a].ecache_bond = -1;
-  out[0] = v[0];
-  out[1] = v[1];
-  return DCS_OK;
+    double v[2];
+    DCS_HIP(hipMemcpyAsync(v, st->slot_base(id_a) + L.o_e, sizeof(v), hipMemcpyDeviceToHost, s));
+    DCS_HIP(hipStreamSynchronize(s));
+    tune_resolve(st->ctx);
+    st->slots[id_a].ecache_bond = -1;
+    out[0] = v[0];
+    out[1] = v[1];
+    return DCS_OK;
+  });
 }
 
 int dcs_export_mps(dcs_state* st, int id, double* host_out, size_t cap_doubles, int* dims_out,
                    void* stream) {
-  if (!st || !host_out || !dims_out) return fail(DCS_EINVAL, "null argument");
-  if (id < 0 || id >= st->L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
-  const Slot& sl = st->slots[id];
-  if (!sl.live) return fail(DCS_ESTATE, "branch is not live");
-  const Layout& L = st->L;
-  size_t need = 0;
-  for (int j = 0; j < L.n; ++j) need += 2 * (size_t)sl.dims[j] * 2 * sl.dims[j + 1];
-  if (cap_doubles < need) return fail(DCS_ENOMEM, "host buffer too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<char> tmp(L.mps_bytes);
-  DCS_HIP(hipMemcpyAsync(tmp.data(), st->slot_base(id) + L.o_mps[sl.cur], L.mps_bytes,
-                         hipMemcpyDeviceToHost, s));
-  DCS_HIP(hipStreamSynchronize(s));
-  size_t o = 0;
-  for (int j = 0; j < L.n; ++j) {
-    const size_t e = (size_t)sl.dims[j] * 2 * sl.dims[j + 1];
-    const char* src = tmp.data() + L.site_off[j];
-    for (size_t k = 0; k < e; ++k) {
-      if (L.ct == CT_F32) {
-        const float2 v = reinterpret_cast<const float2*>(src)[k];
-        host_out[o++] = v.x;
-        host_out[o++] = v.y;
-      } else {
-        const double2 v = reinterpret_cast<const double2*>(src)[k];
-        host_out[o++] = v.x;
-        host_out[o++] = v.y;
+  return guarded([&]() -> int {
+    if (!st || !host_out || !dims_out) return fail(DCS_EINVAL, "null argument");
+    if (id < 0 || id >= st->L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
+    const Slot& sl = st->slots[id];
+    if (!sl.live) return fail(DCS_ESTATE, "branch is not live");
+    const Layout& L = st->L;
+    size_t need = 0;
+    for (int j = 0; j < L.n; ++j) need += 2 * (size_t)sl.dims[j] * 2 * sl.dims[j + 1];
+    if (cap_doubles < need) return fail(DCS_ENOMEM, "host buffer too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<char> tmp(L.mps_bytes);
+    DCS_HIP(hipMemcpyAsync(tmp.data(), st->slot_base(id) + L.o_mps[sl.cur], L.mps_bytes,
+                           hipMemcpyDeviceToHost, s));
+    DCS_HIP(hipStreamSynchronize(s));
+    size_t o = 0;
+    for (int j = 0; j < L.n; ++j) {
+      const size_t e = (size_t)sl.dims[j] * 2 * sl.dims[j + 1];
+      const char* src = tmp.data() + L.site_off[j];
+      for (size_t k = 0; k < e; ++k) {
+        if (L.ct == CT_F32) {
+          const float2 v = reinterpret_cast<const float2*>(src)[k];
+          host_out[o++] = v.x;
+          host_out[o++] = v.y;
+        } else {
+          const double2 v = reinterpret_cast<const double2*>(src)[k];
+          host_out[o++] = v.x;
+          host_out[o++] = v.y;
+        }
       }
     }
-  }
-  for (int b = 0; b <= L.n; ++b) dims_out[b] = sl.dims[b];
-  return DCS_OK;
+    for (int b = 0; b <= L.n; ++b) dims_out[b] = sl.dims[b];
+    return DCS_OK;
+  });
 }
 
 int dcs_import_mps(dcs_state* st, int id, int chi_cap, const double* host_in, const int* dims_in,
                    void* stream) {
-  if (!st || !host_in || !dims_in) return fail(DCS_EINVAL, "null argument");
-  const Layout& L = st->L;
-  if (id < 0 || id >= L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
-  if (chi_cap < 1 || chi_cap > L.chi_max) return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
-  if (dims_in[0] != 1 || dims_in[L.n] != 1) return fail(DCS_EINVAL, "boundary dims must be 1");
-  for (int b = 0; b <= L.n; ++b)
-    if (dims_in[b] < 1 || dims_in[b] > L.D[b]) return fail(DCS_EINVAL, "bond dim out of range");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<char> tmp(L.mps_bytes, 0);
-  size_t o = 0;
-  for (int j = 0; j < L.n; ++j) {
-    const size_t e = (size_t)dims_in[j] * 2 * dims_in[j + 1];
-    char* dst = tmp.data() + L.site_off[j];
-    for (size_t k = 0; k < e; ++k, o += 2) {
-      if (L.ct == CT_F32)
-        reinterpret_cast<float2*>(dst)[k] = make_float2((float)host_in[o], (float)host_in[o + 1]);
-      else
-        reinterpret_cast<double2*>(dst)[k] = make_double2(host_in[o], host_in[o + 1]);
+  return guarded([&]() -> int {
+    if (!st || !host_in || !dims_in) return fail(DCS_EINVAL, "null argument");
+    const Layout& L = st->L;
+    if (id < 0 || id >= L.cap) return fail(DCS_ECAPACITY, "branch id outside capacity");
+    if (chi_cap < 1 || chi_cap > L.chi_max) return fail(DCS_EINVAL, "chi cap outside [1, chi_max]");
+    if (dims_in[0] != 1 || dims_in[L.n] != 1) return fail(DCS_EINVAL, "boundary dims must be 1");
+    for (int b = 0; b <= L.n; ++b)
+      if (dims_in[b] < 1 || dims_in[b] > L.D[b]) return fail(DCS_EINVAL, "bond dim out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<char> tmp(L.mps_bytes, 0);
+    size_t o = 0;
+    for (int j = 0; j < L.n; ++j) {
+      const size_t e = (size_t)dims_in[j] * 2 * dims_in[j + 1];
+      char* dst = tmp.data() + L.site_off[j];
+      for (size_t k = 0; k < e; ++k, o += 2) {
+        if (L.ct == CT_F32)
+          reinterpret_cast<float2*>(dst)[k] = make_float2((float)host_in[o], (float)host_in[o + 1]);
+        else
+          reinterpret_cast<double2*>(dst)[k] = make_double2(host_in[o], host_in[o + 1]);
+      }
     }
-  }
-  DCS_HIP(hipMemcpyAsync(st->slot_base(id) + L.o_mps[0], tmp.data(), L.mps_bytes,
-                         hipMemcpyHostToDevice, s));
-  DCS_HIP(hipStreamSynchronize(s));
-  Slot& sl = st->slots[id];
-  sl = Slot();
-  sl.live = true;
-  sl.chi_cap = chi_cap;
-  sl.dims.assign(dims_in, dims_in + L.n + 1);
-  sl.cur = 0;
-  sl.lc_end = 0;
-  sl.rc_start = L.n;
-  return DCS_OK;
+    DCS_HIP(hipMemcpyAsync(st->slot_base(id) + L.o_mps[0], tmp.data(), L.mps_bytes,
+                           hipMemcpyHostToDevice, s));
+    DCS_HIP(hipStreamSynchronize(s));
+    Slot& sl = st->slots[id];
+    sl = Slot();
+    sl.live = true;
+    sl.chi_cap = chi_cap;
+    sl.dims.assign(dims_in, dims_in + L.n + 1);
+    sl.cur = 0;
+    sl.lc_end = 0;
+    sl.rc_start = L.n;
+    return DCS_OK;
+  });
 }
 
 }  // extern "C"

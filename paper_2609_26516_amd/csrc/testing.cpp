@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,19 @@ int testing_fail(int code, const std::string& msg);
 }
 
 namespace {
+
+// Entry points return a status and never let a C++ exception (a failed host
+// allocation inside a std container, say) cross the C ABI.
+template <typename F>
+int guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return testing_fail(DCS_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return testing_fail(DCS_EINVAL, "internal error");
+  }
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -91,155 +105,163 @@ __global__ void __launch_bounds__(256) copy16_kernel(const int4* __restrict__ sr
 extern "C" {
 
 int dcs_test_copy(const void* src, void* dst, size_t bytes, int reps, void* stream) {
-  if (!src || !dst || bytes % 16 != 0 || reps < 1 || reps > 1000)
-    return testing_fail(DCS_EINVAL, "bad copy test arguments");
-  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
-    return testing_fail(DCS_EINVAL, "copy buffers must be 16-byte aligned");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t n16 = bytes / 16;
-  const int blocks = (int)std::min<size_t>(8192, (n16 + 255) / 256 + (n16 == 0));
-  for (int r = 0; r < reps; ++r) {
-    hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s,
-                       static_cast<const int4*>(src), static_cast<int4*>(dst), n16);
-    T_HIP(hipGetLastError());
-  }
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (!src || !dst || bytes % 16 != 0 || reps < 1 || reps > 1000)
+      return testing_fail(DCS_EINVAL, "bad copy test arguments");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+      return testing_fail(DCS_EINVAL, "copy buffers must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n16 = bytes / 16;
+    const int blocks = (int)std::min<size_t>(8192, (n16 + 255) / 256 + (n16 == 0));
+    for (int r = 0; r < reps; ++r) {
+      hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s,
+                         static_cast<const int4*>(src), static_cast<int4*>(dst), n16);
+      T_HIP(hipGetLastError());
+    }
+    return DCS_OK;
+  });
 }
 
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
                   int batch, int variant, const double* A, const double* B, double* C,
                   void* stream) {
-  if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C)
-    return testing_fail(DCS_EINVAL, "bad gemm test arguments");
-  if ((opa != OP_N && opa != OP_C && opa != OP_J) || (opb != OP_N && opb != OP_T))
-    return testing_fail(DCS_EINVAL, "bad op");
-  if (variant < 0 || variant >= GEMM_VARIANTS) return testing_fail(DCS_EINVAL, "bad tile shape");
-  int bm = 64, bn = 64;
-  gemm_tile_shape(variant, &bm, &bn);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  DevBuf da, db, dc;
-  const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
-  int rc = upload(ta, A, na, da, s);
-  if (rc) return rc;
-  rc = upload(tb, B, nb, db, s);
-  if (rc) return rc;
-  T_HIP(hipMalloc(&dc.p, nc * csz(tc)));
-  GemmArgs args;
-  std::memset(&args, 0, sizeof(args));
-  GemmGroup& g = args.g[0];
-  g.a = op_of(da.p, (long long)M * K * csz(ta));
-  g.b = op_of(db.p, (long long)K * N * csz(tb));
-  g.c = op_of(dc.p, (long long)M * N * csz(tc));
-  g.ids = nullptr;
-  g.M = M;
-  g.N = N;
-  g.K = K;
-  g.lda = (opa == OP_C) ? M : K;
-  g.ldb = (opb == OP_T) ? K : N;
-  g.ldc = N;
-  g.batch = batch;
-  g.tiles_n = (N + bn - 1) / bn;
-  g.tiles_per_item = ((M + bm - 1) / bm) * g.tiles_n;
-  g.tile_begin = 0;
-  args.ngroups = 1;
-  args.total_tiles = g.tiles_per_item * batch;
-  hipError_t e = launch_gemm(ta, tb, tc, tacc, opa, opb, variant, args, s);
-  if (e == hipErrorInvalidValue) return testing_fail(DCS_EINVAL, "type/op combination not built");
-  T_HIP(e);
-  std::vector<char> h(nc * csz(tc));
-  T_HIP(hipMemcpyAsync(h.data(), dc.p, h.size(), hipMemcpyDeviceToHost, s));
-  T_HIP(hipStreamSynchronize(s));
-  unpack(tc, h, C, nc);
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C)
+      return testing_fail(DCS_EINVAL, "bad gemm test arguments");
+    if ((opa != OP_N && opa != OP_C && opa != OP_J) || (opb != OP_N && opb != OP_T))
+      return testing_fail(DCS_EINVAL, "bad op");
+    if (variant < 0 || variant >= GEMM_VARIANTS) return testing_fail(DCS_EINVAL, "bad tile shape");
+    int bm = 64, bn = 64;
+    gemm_tile_shape(variant, &bm, &bn);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf da, db, dc;
+    const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
+    int rc = upload(ta, A, na, da, s);
+    if (rc) return rc;
+    rc = upload(tb, B, nb, db, s);
+    if (rc) return rc;
+    T_HIP(hipMalloc(&dc.p, nc * csz(tc)));
+    GemmArgs args;
+    std::memset(&args, 0, sizeof(args));
+    GemmGroup& g = args.g[0];
+    g.a = op_of(da.p, (long long)M * K * csz(ta));
+    g.b = op_of(db.p, (long long)K * N * csz(tb));
+    g.c = op_of(dc.p, (long long)M * N * csz(tc));
+    g.ids = nullptr;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = (opa == OP_C) ? M : K;
+    g.ldb = (opb == OP_T) ? K : N;
+    g.ldc = N;
+    g.batch = batch;
+    g.tiles_n = (N + bn - 1) / bn;
+    g.tiles_per_item = ((M + bm - 1) / bm) * g.tiles_n;
+    g.tile_begin = 0;
+    args.ngroups = 1;
+    args.total_tiles = g.tiles_per_item * batch;
+    hipError_t e = launch_gemm(ta, tb, tc, tacc, opa, opb, variant, args, s);
+    if (e == hipErrorInvalidValue) return testing_fail(DCS_EINVAL, "type/op combination not built");
+    T_HIP(e);
+    std::vector<char> h(nc * csz(tc));
+    T_HIP(hipMemcpyAsync(h.data(), dc.p, h.size(), hipMemcpyDeviceToHost, s));
+    T_HIP(hipStreamSynchronize(s));
+    unpack(tc, h, C, nc);
+    return DCS_OK;
+  });
 }
 
 int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double* in,
                  const double* w, double* out, void* stream) {
-  if (d0 < 1 || d1 < 1 || wl < 1 || wr < 1 || wl > 16 || wr > 16 || !in || !w || !out)
-    return testing_fail(DCS_EINVAL, "bad mpo test arguments");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  DevBuf di, dw, dout;
-  const size_t nin = (size_t)d0 * d1 * 2 * (dir == 0 ? wl : wr);
-  const size_t nout = (size_t)d0 * d1 * 2 * (dir == 0 ? wr : wl);
-  int rc = upload(ct, in, nin, di, s);
-  if (rc) return rc;
-  rc = upload(ct, w, (size_t)wl * 4 * wr, dw, s);
-  if (rc) return rc;
-  T_HIP(hipMalloc(&dout.p, nout * csz(ct)));
-  MpoArgs args;
-  std::memset(&args, 0, sizeof(args));
-  MpoGroup& g = args.g[0];
-  g.in = op_of(di.p, 0);
-  g.out = op_of(dout.p, 0);
-  g.w = op_of(dw.p, 0);
-  g.ids = nullptr;
-  g.d0 = d0;
-  g.d1 = d1;
-  g.wl = wl;
-  g.wr = wr;
-  g.batch = 1;
-  g.blk_per_item = (int)(((long long)d0 * d1 + 255) / 256);
-  g.blk_begin = 0;
-  args.ngroups = 1;
-  args.total_blocks = g.blk_per_item;
-  T_HIP(launch_mpo(ct, dir, args, s));
-  std::vector<char> h(nout * csz(ct));
-  T_HIP(hipMemcpyAsync(h.data(), dout.p, h.size(), hipMemcpyDeviceToHost, s));
-  T_HIP(hipStreamSynchronize(s));
-  unpack(ct, h, out, nout);
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (d0 < 1 || d1 < 1 || wl < 1 || wr < 1 || wl > 16 || wr > 16 || !in || !w || !out)
+      return testing_fail(DCS_EINVAL, "bad mpo test arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf di, dw, dout;
+    const size_t nin = (size_t)d0 * d1 * 2 * (dir == 0 ? wl : wr);
+    const size_t nout = (size_t)d0 * d1 * 2 * (dir == 0 ? wr : wl);
+    int rc = upload(ct, in, nin, di, s);
+    if (rc) return rc;
+    rc = upload(ct, w, (size_t)wl * 4 * wr, dw, s);
+    if (rc) return rc;
+    T_HIP(hipMalloc(&dout.p, nout * csz(ct)));
+    MpoArgs args;
+    std::memset(&args, 0, sizeof(args));
+    MpoGroup& g = args.g[0];
+    g.in = op_of(di.p, 0);
+    g.out = op_of(dout.p, 0);
+    g.w = op_of(dw.p, 0);
+    g.ids = nullptr;
+    g.d0 = d0;
+    g.d1 = d1;
+    g.wl = wl;
+    g.wr = wr;
+    g.batch = 1;
+    g.blk_per_item = (int)(((long long)d0 * d1 + 255) / 256);
+    g.blk_begin = 0;
+    args.ngroups = 1;
+    args.total_blocks = g.blk_per_item;
+    T_HIP(launch_mpo(ct, dir, args, s));
+    std::vector<char> h(nout * csz(ct));
+    T_HIP(hipMemcpyAsync(h.data(), dout.p, h.size(), hipMemcpyDeviceToHost, s));
+    T_HIP(hipStreamSynchronize(s));
+    unpack(ct, h, out, nout);
+    return DCS_OK;
+  });
 }
 
 int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, const double* F,
                 double* Q, double* nrm2_out, void* stream) {
-  if (m < 1 || n < 1 || n > 1024 || (mode != 2 && m < n) || mode < 0 || mode > 2 || !F || !Q ||
-      !nrm2_out)
-    return testing_fail(DCS_EINVAL, "bad qr test arguments");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  DevBuf df, dq, dws, dn;
-  const size_t mn = (size_t)m * n;
-  int rc = upload(ct_in, F, mn, df, s);
-  if (rc) return rc;
-  T_HIP(hipMalloc(&dq.p, mn * csz(ct_out)));
-  T_HIP(hipMalloc(&dws.p, std::max(mn + ((size_t)n / 16 + 2) * 256, qr_large_ws_elems(m, n)) * 16));
-  T_HIP(hipMalloc(&dn.p, 256));
-  QrArgs args;
-  std::memset(&args, 0, sizeof(args));
-  QrGroup& g = args.g[0];
-  g.f = op_of(df.p, 0);
-  g.q = op_of(dq.p, 0);
-  g.ws = op_of(dws.p, 0);
-  g.nrm2 = op_of(dn.p, 0);
-  g.ids = nullptr;
-  g.m = m;
-  g.n = n;
-  g.mode = mode;
-  g.batch = 1;
-  g.blk_begin = 0;
-  args.ngroups = 1;
-  args.total_blocks = 1;
-  const size_t lds = mn * 16;
-  if (use_lds == 3) {   // large-matrix variant
-    if (mode == 2 || m > qr_large_max_rows())
-      return testing_fail(DCS_EINVAL, "the large-matrix QR takes modes 0/1 and m <= 2048");
-    T_HIP(launch_qr_large(ct_in, ct_out, args, s));
-  } else if (use_lds == 2 || use_lds == 4 || use_lds == 5) {   // blocked: right-, left-looking, split
-    if (m > qr_blocked_max_rows()) return testing_fail(DCS_EINVAL, "too many rows for the blocked QR");
-    args.use_lds = 1;
-    if (use_lds == 2)
-      T_HIP(launch_qr_blocked(ct_in, ct_out, args, m, s));
-    else
-      T_HIP(launch_qr_left(ct_in, ct_out, args, m, use_lds == 5, s));
-  } else {
-    args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
-    T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
-  }
-  std::vector<char> h(mn * csz(ct_out));
-  T_HIP(hipMemcpyAsync(h.data(), dq.p, h.size(), hipMemcpyDeviceToHost, s));
-  T_HIP(hipMemcpyAsync(nrm2_out, dn.p, sizeof(double), hipMemcpyDeviceToHost, s));
-  T_HIP(hipStreamSynchronize(s));
-  unpack(ct_out, h, Q, mn);
-  return DCS_OK;
+  return guarded([&]() -> int {
+    if (m < 1 || n < 1 || n > 1024 || (mode != 2 && m < n) || mode < 0 || mode > 2 || !F || !Q ||
+        !nrm2_out)
+      return testing_fail(DCS_EINVAL, "bad qr test arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf df, dq, dws, dn;
+    const size_t mn = (size_t)m * n;
+    int rc = upload(ct_in, F, mn, df, s);
+    if (rc) return rc;
+    T_HIP(hipMalloc(&dq.p, mn * csz(ct_out)));
+    T_HIP(hipMalloc(&dws.p, std::max(mn + ((size_t)n / 16 + 2) * 256, qr_large_ws_elems(m, n)) * 16));
+    T_HIP(hipMalloc(&dn.p, 256));
+    QrArgs args;
+    std::memset(&args, 0, sizeof(args));
+    QrGroup& g = args.g[0];
+    g.f = op_of(df.p, 0);
+    g.q = op_of(dq.p, 0);
+    g.ws = op_of(dws.p, 0);
+    g.nrm2 = op_of(dn.p, 0);
+    g.ids = nullptr;
+    g.m = m;
+    g.n = n;
+    g.mode = mode;
+    g.batch = 1;
+    g.blk_begin = 0;
+    args.ngroups = 1;
+    args.total_blocks = 1;
+    const size_t lds = mn * 16;
+    if (use_lds == 3) {   // large-matrix variant
+      if (mode == 2 || m > qr_large_max_rows())
+        return testing_fail(DCS_EINVAL, "the large-matrix QR takes modes 0/1 and m <= 2048");
+      T_HIP(launch_qr_large(ct_in, ct_out, args, s));
+    } else if (use_lds == 2 || use_lds == 4 || use_lds == 5) {   // blocked: right-, left-looking, split
+      if (m > qr_blocked_max_rows()) return testing_fail(DCS_EINVAL, "too many rows for the blocked QR");
+      args.use_lds = 1;
+      if (use_lds == 2)
+        T_HIP(launch_qr_blocked(ct_in, ct_out, args, m, s));
+      else
+        T_HIP(launch_qr_left(ct_in, ct_out, args, m, use_lds == 5, s));
+    } else {
+      args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
+      T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
+    }
+    std::vector<char> h(mn * csz(ct_out));
+    T_HIP(hipMemcpyAsync(h.data(), dq.p, h.size(), hipMemcpyDeviceToHost, s));
+    T_HIP(hipMemcpyAsync(nrm2_out, dn.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    T_HIP(hipStreamSynchronize(s));
+    unpack(ct_out, h, Q, mn);
+    return DCS_OK;
+  });
 }
 
 }  // extern "C"
