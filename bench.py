@@ -56,9 +56,9 @@ TUNE = {"enabled": True, "save": None}
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
                    "paper_2609_26516_amd/csrc/kernel_util.h"],
-           "sha256": "f2aef39e9e1efab081820450880fa24e161728c6c552f9d6f9954230e74daf96",
-           "fetch_kib": 2894544.1, "write_kib": 1046062.9,
-           "fetch_factor": 1048576 / 524300.5, "write_factor": 1048576 / 1048576.1},
+           "sha256": "2dcba96d018bdaee29967a083b5b4a09190906f50508ef3efd99c3243923794f",
+           "fetch_kib": 2896256.8, "write_kib": 1032483.1,
+           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
 }
 
 

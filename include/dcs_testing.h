@@ -43,7 +43,9 @@ int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double *
  * multi-kernel path (modes 0 and 1, m <= 2048), 4 left-looking form of the
  * blocked variant (the one compression steps use; m <= 512), 5 the same in
  * two launches (factorisation, then one workgroup per 16-column block of Q),
- * as used for batches that do not fill the chip. */
+ * as used for batches that do not fill the chip, 6 variant 4 with two-wave
+ * workgroups for m <= 128 (as used for batches of more than 512 such
+ * matrices; larger m as variant 4). */
 int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int variant, const double *F,
                 double *Q, double *nrm2_out, void *stream);
 

@@ -105,9 +105,11 @@ int qr_blocked_max_rows();
 // workspace): each panel is updated from the stored V of the earlier panels
 // just before it is factored, and Q is formed 16 columns at a time.  split:
 // two launches, the factorisations, then one workgroup per 16-column block of
-// each Q (for batches too small to fill the chip).
+// each Q (for batches too small to fill the chip).  Matrices of at most 128
+// rows run with 256 threads each, or 128 when there are more than 512 of
+// them; threads = 128 or 256 forces that width (tests), 0 chooses.
 hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
-                          hipStream_t s);
+                          hipStream_t s, int threads = 0);
 // Largest number of matrices for which the runtime splits the left-looking QR.
 int qr_split_max_items();
 // Multi-kernel variant for qr_blocked_max_rows() < m <= qr_large_max_rows()

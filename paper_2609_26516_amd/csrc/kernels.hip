@@ -742,18 +742,35 @@ __device__ __forceinline__ void qrl_step(double2 (&a)[QrShape<NTQ>::QLB][4],
     }
   }
   __syncthreads();
-  if (lane < EPW) {
-    const int e = wave * EPW + lane;
-    double2 x[NW];
+  if constexpr (EPW <= 64) {
+    if (lane < EPW) {
+      const int e = wave * EPW + lane;
+      double2 x[NW];
 #pragma unroll
-    for (int u = 0; u < NW; ++u) x[u] = Wp[u * 256 + e];
-    double2 sum = x[0];
+      for (int u = 0; u < NW; ++u) x[u] = Wp[u * 256 + e];
+      double2 sum = x[0];
 #pragma unroll
-    for (int u = 1; u < NW; ++u) {
-      sum.x += x[u].x;
-      sum.y += x[u].y;
+      for (int u = 1; u < NW; ++u) {
+        sum.x += x[u].x;
+        sum.y += x[u].y;
+      }
+      Wp[wave * 256 + e] = sum;
     }
-    Wp[wave * 256 + e] = sum;
+  } else {   // fewer than 4 waves: each wave sums EPW / 64 entries per lane
+#pragma unroll
+    for (int e0 = 0; e0 < EPW; e0 += 64) {
+      const int e = wave * EPW + e0 + lane;
+      double2 x[NW];
+#pragma unroll
+      for (int u = 0; u < NW; ++u) x[u] = Wp[u * 256 + e];
+      double2 sum = x[0];
+#pragma unroll
+      for (int u = 1; u < NW; ++u) {
+        sum.x += x[u].x;
+        sum.y += x[u].y;
+      }
+      Wp[wave * 256 + e] = sum;
+    }
   }
   __syncthreads();
   double wr[4], wi[4];
@@ -794,7 +811,7 @@ __device__ __forceinline__ void qrl_step(double2 (&a)[QrShape<NTQ>::QLB][4],
 }
 
 template <int CTI, int CTO, int NTQ>
-__global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const QrArgs args, int part) {
+__global__ __launch_bounds__(NTQ, NTQ == 512 ? 1 : 2) void qr_left_kernel(const QrArgs args, int part) {
   using Shape = QrShape<NTQ>;
   constexpr int NW = Shape::NW, MAXB = Shape::QLB;
   using TI = typename St<CTI>::T;
@@ -953,7 +970,11 @@ __global__ __launch_bounds__(NTQ, NTQ == 256 ? 2 : 1) void qr_left_kernel(const 
         P[pidx(tid, c)] = u;
       }
     }
-    if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sT[tid];
+    if constexpr (NTQ >= QB * QB) {
+      if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sT[tid];
+    } else {
+      for (int e = tid; e < QB * QB; e += NTQ) Tg[(long long)k * QB * QB + e] = sT[e];
+    }
     __threadfence_block();
     __syncthreads();
     if (part == 1) continue;
@@ -1175,11 +1196,19 @@ hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_ma
 }
 
 hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
-                          hipStream_t s) {
+                          hipStream_t s, int threads) {
   if (args.total_blocks <= 0) return hipSuccess;
-  const size_t lds = qr_blocked_lds(m_max);
-  const bool small = m_max <= 128;
-  const dim3 blk(small ? 256 : 512);
+  // up to 128 rows: four waves per matrix (two matrices per CU), or, when
+  // there are more matrices than that fits on the chip at once, two waves
+  // per matrix so that four matrices (40 KB of LDS each) share a CU; the
+  // per-column latency of the factorisation, not the arithmetic, bounds
+  // these small QRs
+  const int ntq = m_max > 128 ? 512
+                  : (threads == 128 || threads == 256) ? threads
+                  : (args.total_blocks > 2 * 256 ? 128 : 256);
+  const size_t lds = ntq == 512 ? QrShape<512>::LDS_BYTES
+                                : ntq == 256 ? QrShape<256>::LDS_BYTES : QrShape<128>::LDS_BYTES;
+  const dim3 blk(ntq);
   // split: the factorisations first (one workgroup per matrix), then every
   // 16-column block of every Q in its own workgroup
   QrArgs qa;
@@ -1194,10 +1223,10 @@ hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, 
     }
   }
 #define DCS_QRL(I, O, T)                                                                    \
-  if (ct_in == I && ct_out == O && (T == 256) == small) {                                  \
+  if (ct_in == I && ct_out == O && T == ntq) {                                             \
     static hipError_t attr = hipFuncSetAttribute(                                          \
         reinterpret_cast<const void*>(&qr_left_kernel<I, O, T>),                            \
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)qr_blocked_lds(512));              \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)QrShape<T>::LDS_BYTES);            \
     if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
     hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(args.total_blocks), blk, lds, s, args, \
                        split ? 1 : 0);                                                      \
@@ -1211,6 +1240,9 @@ hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, 
   DCS_QRL(CT_F32, CT_F32, 256)
   DCS_QRL(CT_F64, CT_F64, 256)
   DCS_QRL(CT_F64, CT_F32, 256)
+  DCS_QRL(CT_F32, CT_F32, 128)
+  DCS_QRL(CT_F64, CT_F64, 128)
+  DCS_QRL(CT_F64, CT_F32, 128)
 #undef DCS_QRL
   return hipErrorInvalidValue;
 }

@@ -408,7 +408,11 @@ __device__ __forceinline__ void factor_panel2(double2 (&a)[RP][NB], int mp, int 
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  if (tid < NB * NB) sT[tid] = make_double2(0.0, 0.0);
+  if constexpr (NT >= NB * NB) {
+    if (tid < NB * NB) sT[tid] = make_double2(0.0, 0.0);
+  } else {
+    for (int e = tid; e < NB * NB; e += NT) sT[e] = make_double2(0.0, 0.0);
+  }
   __syncthreads();   // the caller's reads of this LDS are done
 
   static_for<NB>([&](auto kc) {

@@ -244,13 +244,15 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
       if (mode == 2 || m > qr_large_max_rows())
         return testing_fail(DCS_EINVAL, "the large-matrix QR takes modes 0/1 and m <= 2048");
       T_HIP(launch_qr_large(ct_in, ct_out, args, s));
-    } else if (use_lds == 2 || use_lds == 4 || use_lds == 5) {   // blocked: right-, left-looking, split
+    } else if (use_lds == 2 || use_lds == 4 || use_lds == 5 || use_lds == 6) {
+      // blocked: right-looking, left-looking, left-looking split, left-looking
+      // with two-wave workgroups for up to 128 rows
       if (m > qr_blocked_max_rows()) return testing_fail(DCS_EINVAL, "too many rows for the blocked QR");
       args.use_lds = 1;
       if (use_lds == 2)
         T_HIP(launch_qr_blocked(ct_in, ct_out, args, m, s));
       else
-        T_HIP(launch_qr_left(ct_in, ct_out, args, m, use_lds == 5, s));
+        T_HIP(launch_qr_left(ct_in, ct_out, args, m, use_lds == 5, s, use_lds == 6 ? 128 : 0));
     } else {
       args.use_lds = (use_lds && mode != 2 && lds <= qr_lds_limit()) ? 1 : 0;
       T_HIP(launch_qr(ct_in, ct_out, args, args.use_lds ? lds : 0, s));
