@@ -205,7 +205,7 @@ def roofline(stats, prec, counters=False, names=None):
     return rl
 
 
-def run_large_chi(workload: str, steps: int, warmup: int, timing: bool):
+def run_large_chi(workload: str, steps: int, warmup: int, timing: bool, graphs: bool = False):
     """Single-path shots of the large-chi workload in the split-BF16 form,
     then the FP64 path replaying the first shot's outcomes; the two final
     states are compared by the FP64 overlap in one complex128 state."""
@@ -222,6 +222,7 @@ def run_large_chi(workload: str, steps: int, warmup: int, timing: bool):
     nm = circ.n_measurements()
     u = lambda shot: shot_uniforms(prm["seed"], shot, nm)[None, :]  # noqa: E731
     eng = E.Engine(0)
+    eng.graphs(graphs)
     st = E.State(eng, "bf16x3", n, 1, chi, w, [chi], prm["init_seed"])
     for i in range(warmup):
         st.release(E.run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u(10_000 + i))["ids"])
@@ -349,19 +350,21 @@ def main():
         return
     if args.workload in LARGE_CHI:
         wl = LARGE_CHI[args.workload]
-        dt, dt64, stats, cmp = run_large_chi(wl, args.steps, args.warmup, True)
+        dt, dt64, stats, cmp = run_large_chi(wl, args.steps, args.warmup, not args.graphs,
+                                             graphs=args.graphs)
         out = {"metric": "shots/s (split-BF16 form, chi=1024), FP64 path beside it",
                "value": round(args.steps / dt, 5), "unit": "shots/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": round(1e3 * dt / args.steps, 1), "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
                "data": "synthetic: seeded Haar brickwork dynamic circuit",
-               "config": {"workload": wl, "shots_per_step": 1},
+               "config": {"workload": wl, "shots_per_step": 1, "graphs": args.graphs},
                "roofline": roofline(stats, "bf16x3", names={
                    "qr": "qrl_panel_kernel + qrl_wpart_kernel + qrl_update_kernel (m > 512), "
                          "qr_left_kernel (m <= 512)",
                    "gemm_nn": "gemm_bf16x3_kernel<0, 0>", "gemm_nt": "gemm_bf16x3_kernel<0, 1>",
-                   "gemm_cn": "gemm_bf16x3_kernel<2, 0>", "gemm_jt": "gemm_bf16x3_kernel<3, 1>"}),
+                   "gemm_cn": "gemm_bf16x3_kernel<2, 0>", "gemm_jt": "gemm_bf16x3_kernel<3, 1>"})
+               if stats else None,
                "fp64_path": {"value": round(1 / dt64, 5), "unit": "shots/s", "dtype": "c128"},
                "precision_vs_fp64": cmp}
         print(json.dumps(out))
