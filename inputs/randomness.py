@@ -37,6 +37,19 @@ def bra_init_gaussians(n: int, chi: int, seed: int) -> List[np.ndarray]:
     return out
 
 
+def gaussians_for_shapes(shapes: Sequence[Sequence[int]], seed: int, tag: int) -> List[np.ndarray]:
+    """Independent standard complex Gaussian tensors (real and imaginary parts
+    N(0, 1/2)) of the given shapes, drawn in order from
+    default_rng([seed, tag, 0x77E])."""
+    rng = np.random.default_rng([int(seed), int(tag), 0x77E])
+    out = []
+    for shp in shapes:
+        shp = tuple(int(x) for x in shp)
+        g = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) / np.sqrt(2.0)
+        out.append(np.ascontiguousarray(g, dtype=np.complex128))
+    return out
+
+
 def shot_uniforms(seed: int, shot: int, count: int) -> np.ndarray:
     """``count`` uniforms in [0, 1) (53-bit doubles) for one single-path shot."""
     rng = np.random.default_rng([int(seed), int(shot), 0x5A7])

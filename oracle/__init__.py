@@ -9,8 +9,13 @@ Modules
                the exact reference for small circuits
   mps          MPS, layered gate operators, the compression step (Sec. III-C),
                measurement probability and collapse (Sec. IV-B1)
-  dynamic      single-path (Alg. 1) and multi-path (Alg. 2) drivers, chunk
-               construction (Sec. IV-C), top-M retention, TVD (Sec. V-A)
+  ttn          tree tensor network (Sec. II-B): structure, canonical starting
+               guess, the compression step as single-node sweeps over the
+               tree, measurement and collapse (small n: environments by brute
+               force on the statevector)
+  dynamic      single-path (Alg. 1) and multi-path (Alg. 2) drivers over an
+               MPS or a tree, chunk construction (Sec. IV-C), top-M retention
+               and adaptive pruning, TVD (Sec. V-A)
 
 Everything is complex128 / float64, written for checkability, not speed.
 Pins: see tests/test_oracle_*.py.  Parity is unpinned by the paper only for

@@ -34,6 +34,7 @@ from inputs.circuits import CGate, Circuit, Gate, Measure
 from inputs.randomness import bra_init_gaussians
 
 from . import mps as M
+from . import ttn as T
 
 EPS_BRANCH = 1e-10
 
@@ -48,11 +49,25 @@ class Simulator:
     sweeps s, the seed of the starting guess."""
 
     def __init__(self, n: int, chi: int, k: int, n_sweeps: int = 2, init_seed: int = 7,
-                 warm_eta: Optional[float] = None, w_cap: Optional[int] = None):
+                 warm_eta: Optional[float] = None, w_cap: Optional[int] = None,
+                 tree: Optional[Sequence[int]] = None):
         self.n, self.chi, self.k, self.s, self.init_seed = n, chi, k, n_sweeps, init_seed
         self.warm_eta = warm_eta   # None: generic guess; else warm start (M.warm_bra)
         self.w_cap = w_cap         # None: no operator-bond cap on a chunk
+        # None: MPS; else the levels (n_0 = 1, ..., n_L = n) of a tree network (oracle.ttn)
+        self.tree = T.Tree(tree) if tree is not None else None
+        if self.tree is not None and (self.tree.n != n or warm_eta is not None):
+            raise ValueError("the tree must hold n qubits; warm start is an MPS option")
         self._bra = {}
+
+    def zero(self, chi: int):
+        return T.zero_state(self.tree, chi) if self.tree else M.zero_state(self.n, chi)
+
+    def norms(self, state, q: int):
+        return T.outcome_norms(self.tree, state, q) if self.tree else M.outcome_norms(state, q)
+
+    def collapse(self, state, q: int, m: int, nm: float):
+        return T.collapse(self.tree, state, q, m, nm) if self.tree else M.collapse(state, q, m, nm)
 
     def closes_chunk(self, chunk, gate) -> bool:
         """True when appending `gate` to the non-empty `chunk` would push an
@@ -66,10 +81,14 @@ class Simulator:
 
     def bra_init(self, chi: int) -> List[np.ndarray]:
         if chi not in self._bra:
-            self._bra[chi] = M.generic_bra(bra_init_gaussians(self.n, chi, self.init_seed))
+            self._bra[chi] = (T.generic_bra(self.tree, chi, self.init_seed) if self.tree else
+                              M.generic_bra(bra_init_gaussians(self.n, chi, self.init_seed)))
         return self._bra[chi]
 
     def compress(self, state, chunk, chi: int):
+        if self.tree is not None:
+            new, f, _ = T.compress(self.tree, state, chunk, self.bra_init(chi), self.s)
+            return new, f
         mpo = M.chunk_mpo(self.n, chunk)
         bra = self.bra_init(chi)
         if self.warm_eta is not None and all(
@@ -94,7 +113,7 @@ def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[f
     ``chi_ladder`` (ascending from sim.chi), a compression whose partial
     fidelity is below ``f_target`` moves the run one rung up for the next
     compressions; "chis" records the cap of every compression."""
-    state = M.zero_state(circ.n_qubits, sim.chi)
+    state = sim.zero(sim.chi)
     c = [0] * circ.n_bits
     p, fid = 1.0, 1.0
     chunk: List = []
@@ -119,7 +138,7 @@ def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[f
         if isinstance(op, Measure):
             if chunk:
                 flush()
-            n0, n1 = M.outcome_norms(state, op.qubit)
+            n0, n1 = sim.norms(state, op.qubit)
             p0 = n0 / (n0 + n1)
             if outcomes is not None:
                 m = int(outcomes[i_meas])
@@ -129,7 +148,7 @@ def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[f
             pm = nm / (n0 + n1)
             if pm <= EPS_BRANCH:
                 raise ValueError("sampled an outcome of vanishing probability")
-            state = M.collapse(state, op.qubit, m, nm)
+            state = sim.collapse(state, op.qubit, m, nm)
             p *= pm
             c[op.bit] = m
             rec["outcomes"].append(m)
@@ -201,7 +220,7 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
     the probability-weighted fidelity."""
     ladder = list(chi_ladder) if chi_ladder is not None else [sim.chi]
     live = [{"path": (), "p": 1.0, "c": [0] * circ.n_bits, "F": 1.0, "chunk": [],
-             "mps": M.zero_state(circ.n_qubits, sim.chi), "chi": sim.chi, "rung": 0,
+             "mps": sim.zero(sim.chi), "chi": sim.chi, "rung": 0,
              "chis": []}]
     dropped = 0.0
     n_compress = 0
@@ -226,7 +245,7 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
             if isinstance(op, Measure):
                 if b["chunk"]:
                     flush(b)
-                n0, n1 = M.outcome_norms(b["mps"], op.qubit)
+                n0, n1 = sim.norms(b["mps"], op.qubit)
                 for m, nm in ((0, n0), (1, n1)):
                     pm = nm / (n0 + n1)
                     if pm > eps:
@@ -234,7 +253,7 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
                         c[op.bit] = m
                         path = b["path"] + (m,)
                         nxt.append({"path": path, "p": b["p"] * pm, "c": c, "F": b["F"],
-                                    "chunk": [], "mps": M.collapse(b["mps"], op.qubit, m, nm),
+                                    "chunk": [], "mps": sim.collapse(b["mps"], op.qubit, m, nm),
                                     "chi": chi_of(path) if chi_of else b["chi"],
                                     "rung": b["rung"], "chis": list(b["chis"])})
             else:
