@@ -52,3 +52,35 @@ def test_graph_replay_matches_eager(E, prec, name, over, shots):
         for a, b in zip(mps, eager[1]):
             for x, y in zip(a, b):
                 np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_graph_replay_distant_gates_and_warm_start(E, prec):
+    """Chunks of gates on distant pairs (operator bonds up to 16, chunks closed
+    at the cap) with the warm-start guess: graph replays equal the eager run
+    bit for bit."""
+    circ = C.random_dynamic(10, 4, 3)
+    n, chi, shots = 10, 8, 3
+    u = np.stack([shot_uniforms(5, s, circ.n_measurements()) for s in range(shots)])
+
+    def run(graphs, repeats):
+        eng = E.Engine(0)
+        eng.graphs(graphs)
+        st = E.State(eng, prec, n, shots, chi, 16, [chi], 9)
+        st.warm_start(0.05)
+        out = []
+        for _ in range(repeats):
+            r = E.run_single_path(eng, st, circ, shots, chi, 20, 2, uniforms=u)
+            out.append((r, [st.export(int(i)) for i in r["ids"]]))
+            st.release(r["ids"])
+        st.close()
+        eng.close()
+        return out
+
+    eager = run(False, 1)[0]
+    for r, mps in run(True, 3):
+        np.testing.assert_array_equal(r["outcomes"], eager[0]["outcomes"])
+        np.testing.assert_array_equal(r["F"], eager[0]["F"])
+        for a, b in zip(mps, eager[1]):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
