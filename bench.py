@@ -340,8 +340,8 @@ def main():
     TUNE["enabled"] = not args.no_tune
     TUNE["save"] = args.save_tiles
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(shots shard across GPUs without communication; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(independent shots would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
 

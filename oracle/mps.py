@@ -14,7 +14,7 @@ F (everything but the optimised tensor contracted) gives the optimum
 T = F / sqrt(<F|F>); a fixed number s of sweeps; the partial fidelity of the
 chunk is |<psi~'| U |psi~>|^2.
 
-Readings taken where the paper is silent (all recorded in the design notes):
+Readings taken where the paper is silent:
   * single-site updates with the bond dimensions held at chi_b (zero padded);
   * the starting guess is a generic right-canonical MPS built from seeded
     Gaussians, the same for every chunk;
