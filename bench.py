@@ -42,7 +42,7 @@ CLASSES = ["gemm_nn", "gemm_nt", "gemm_cn", "gemm_jt", "gate_operator", "qr", "m
 KERNEL_NAMES = {
     "gemm_nn": "gemm_kernel<0, 0, 0, float, 0, 0>", "gemm_nt": "gemm_kernel<0, 0, 0, float, 0, 1>",
     "gemm_cn": "gemm_kernel<0, 0, 0, float, 2, 0>", "gemm_jt": "gemm_kernel<0, 0, 0, float, 3, 1>",
-    "gate_operator": "mpo_right_kernel / mpo_left_kernel", "qr": "qr_left_kernel<0, 0>",
+    "gate_operator": "mpo_right_kernel / mpo_left_kernel", "qr": "qr_left_kernel<0, 0, 512 | 256>",
 }
 
 

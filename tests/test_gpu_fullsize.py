@@ -1,6 +1,8 @@
 """Full-size check of the benchmark workload (40 qubits, depth-20 brickwork, 4
-measurements every 2 layers, bond cap 256): GPU shots in complex64 and
-complex128 against the FP64 oracle replaying the same outcomes.
+measurements every 2 layers, bond cap 256) in the launch configuration of the
+benchmark step: 256 complex64 shots in one batch with the tile autotuner on.
+Sampled shots (the first and the last of the batch) are replayed by the
+FP64 oracle on the same outcomes, and by the complex128 GPU path.
 
 Sampled outputs: every measurement probability p_0 of the shot, the final
 state (fidelity error 1 - |<gpu|oracle>|^2) and the fidelity estimate.
@@ -19,6 +21,8 @@ from oracle import mps as OM
 pytestmark = pytest.mark.gpu
 
 WORKLOAD = "cfg2_n40_chi256"
+SHOTS = 256
+SAMPLED = (0, SHOTS - 1)
 
 
 @pytest.fixture(scope="module")
@@ -30,28 +34,32 @@ def runs():
     circ, prm = C.workload(WORKLOAD)
     n, chi = prm["n"], prm["chi"]
     k = C.segment_max(circ) + 1
-    shots = 2
-    u = np.stack([shot_uniforms(prm["seed"], s, circ.n_measurements()) for s in range(shots)])
+    nm = circ.n_measurements()
+    u = np.stack([shot_uniforms(prm["seed"], s, nm) for s in range(SHOTS)])
     eng = E.Engine(0)
+    eng.tuning(True)
     out = {}
-    st = E.State(eng, "c64", n, shots, chi, 4, [chi], prm["init_seed"])
+    st = E.State(eng, "c64", n, SHOTS, chi, 4, [chi], prm["init_seed"])
     t = time.time()
-    r64 = E.run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
-    print(f"c64 {shots} shots: {time.time() - t:.1f} s", flush=True)
-    out["c64"] = (r64, [st.export(int(i)) for i in r64["ids"]])
+    r64 = E.run_single_path(eng, st, circ, SHOTS, chi, k, 2, uniforms=u)
+    print(f"c64 {SHOTS} shots: {time.time() - t:.1f} s", flush=True)
+    out["c64"] = (r64, {s: st.export(int(r64["ids"][s])) for s in SAMPLED})
     st.close()
-    st = E.State(eng, "c128", n, shots, chi, 4, [chi], prm["init_seed"])
+    st = E.State(eng, "c128", n, len(SAMPLED), chi, 4, [chi], prm["init_seed"])
     t = time.time()
-    r128 = E.run_single_path(eng, st, circ, shots, chi, k, 2, outcomes=r64["outcomes"])
-    print(f"c128 replay: {time.time() - t:.1f} s", flush=True)
+    r128 = E.run_single_path(eng, st, circ, len(SAMPLED), chi, k, 2,
+                             outcomes=r64["outcomes"][list(SAMPLED)])
+    print(f"c128 replay of shots {SAMPLED}: {time.time() - t:.1f} s", flush=True)
     out["c128"] = (r128, [st.export(int(i)) for i in r128["ids"]])
     st.close()
     eng.close()
-    t = time.time()
-    ref = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"]),
-                             outcomes=r64["outcomes"][0])
-    print(f"oracle shot 0: {time.time() - t:.1f} s", flush=True)
-    out["oracle"] = ref
+    out["oracle"] = {}
+    for s in SAMPLED:
+        t = time.time()
+        out["oracle"][s] = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"]),
+                                              outcomes=r64["outcomes"][s])
+        print(f"oracle shot {s}: {time.time() - t:.1f} s", flush=True)
+    out["u"] = u
     return out
 
 
@@ -60,36 +68,50 @@ def _fid_err(a, b):
 
 
 def test_truncated_regime_reached(runs):
-    ref = runs["oracle"]
-    assert len(ref["p0s"]) == 40
-    assert min(ref["fids"]) < 0.999          # bond cap 256 really truncates
-    assert 0.0 < ref["F"] < 1.0
+    for ref in runs["oracle"].values():
+        assert len(ref["p0s"]) == 40
+        assert min(ref["fids"]) < 0.999          # bond cap 256 really truncates
+        assert 0.0 < ref["F"] < 1.0
+
+
+def test_outcomes_follow_the_uniforms(runs):
+    """Each sampled shot's outcome is 1 exactly when its uniform is at least
+    the oracle's p_0 (no uniform falls within the tolerance of p_0 here)."""
+    r, _ = runs["c64"]
+    for s, ref in runs["oracle"].items():
+        p0 = np.array(ref["p0s"])
+        assert np.min(np.abs(runs["u"][s] - p0)) > 1e-6
+        np.testing.assert_array_equal(r["outcomes"][s], (runs["u"][s] >= p0).astype(np.int8))
 
 
 def test_complex128_matches_oracle(runs):
     r, mps = runs["c128"]
-    ref = runs["oracle"]
-    np.testing.assert_allclose(r["p0s"][0], ref["p0s"], atol=1e-9, rtol=0)
-    assert abs(r["F"][0] - ref["F"]) < 1e-8
-    assert _fid_err(mps[0], ref["mps"]) < 1e-9
+    for i, s in enumerate(SAMPLED):
+        ref = runs["oracle"][s]
+        np.testing.assert_allclose(r["p0s"][i], ref["p0s"], atol=1e-9, rtol=0)
+        assert abs(r["F"][i] - ref["F"]) < 1e-8
+        assert _fid_err(mps[i], ref["mps"]) < 1e-9
 
 
 def test_complex64_meets_precision_targets(runs):
     r, mps = runs["c64"]
-    ref = runs["oracle"]
-    dp = np.max(np.abs(r["p0s"][0] - np.array(ref["p0s"])))
-    fe = _fid_err(mps[0], ref["mps"])
-    print(f"complex64 vs FP64 oracle: max |dp| = {dp:.3e}, state fidelity error = {fe:.3e}, "
-          f"F = {r['F'][0]:.6f} vs {ref['F']:.6f}")
-    assert dp <= 1e-6
-    assert fe <= 1e-6
-    assert abs(r["F"][0] - ref["F"]) < 1e-4
+    for s in SAMPLED:
+        ref = runs["oracle"][s]
+        dp = np.max(np.abs(r["p0s"][s] - np.array(ref["p0s"])))
+        fe = _fid_err(mps[s], ref["mps"])
+        print(f"shot {s}: complex64 vs FP64 oracle: max |dp| = {dp:.3e}, state fidelity error "
+              f"= {fe:.3e}, F = {r['F'][s]:.6f} vs {ref['F']:.6f}")
+        assert dp <= 1e-6
+        assert fe <= 1e-6
+        assert abs(r["F"][s] - ref["F"]) < 1e-4
 
 
-def test_complex64_vs_complex128_second_shot(runs):
-    r64, m64 = runs["c64"]
-    r128, m128 = runs["c128"]
-    dp = np.max(np.abs(r64["p0s"][1] - r128["p0s"][1]))
-    fe = _fid_err(m64[1], m128[1])
-    assert dp <= 1e-6
-    assert fe <= 1e-6
+def test_complex64_batch_properties(runs):
+    """Every shot of the batch: probabilities in [0, 1] and fidelity estimates
+    (products of partial fidelities, each at most 1) in (0, 1]."""
+    r, _ = runs["c64"]
+    p = np.asarray(r["p0s"])
+    assert p.shape == (SHOTS, 40)
+    assert np.all(p >= -1e-12) and np.all(p <= 1 + 1e-12)
+    F = np.asarray(r["F"])
+    assert np.all(F > 0.0) and np.all(F <= 1.0 + 1e-12)
