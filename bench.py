@@ -56,8 +56,8 @@ TUNE = {"enabled": True, "save": None}
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
                    "paper_2609_26516_amd/csrc/kernel_util.h"],
-           "sha256": "2dcba96d018bdaee29967a083b5b4a09190906f50508ef3efd99c3243923794f",
-           "fetch_kib": 2896256.8, "write_kib": 1032483.1,
+           "sha256": "94fc19eb5db57a803e48b6935360cbd34a825997e7d7a116ef27df893a7ade43",
+           "fetch_kib": 2884120.6, "write_kib": 1226957.9,
            "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
 }
 

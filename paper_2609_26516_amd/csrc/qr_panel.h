@@ -366,16 +366,23 @@ __device__ __forceinline__ void half_swap(double& a, double& b) {
   b = __longlong_as_double((long long)(((unsigned long long)r1hi << 32) | r1lo));
 }
 
-// Halving step at lane distance M over K value pairs (s, s + K): lanes with
-// the M bit set keep s + K, the others s.
+// Halving step on the M bit of the lane over K value pairs (s, s + K): lanes
+// with the M bit set keep s + K, the others s.  The partner lane comes from a
+// DPP pattern inside a row of 16 that flips the M bit and keeps every higher
+// bit: the row mirror (i <-> 15 - i) for M = 8, the half-row mirror
+// (i <-> 7 - i) for M = 4, and the quad swap [2, 3, 0, 1] for M = 2.  Across
+// the steps the partners pair disjoint lane sets, so the last step leaves the
+// sum over all 16 lanes of the row.
 template <int M, int K>
 __device__ __forceinline__ void halve_shfl(double (&x)[32], int lane) {
+  static_assert(M == 8 || M == 4 || M == 2, "row-local halving steps only");
+  constexpr int CTRL = M == 8 ? 0x140 : (M == 4 ? 0x141 : 0x4E);
   const bool up = (lane & M) != 0;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     const double send = up ? x[s] : x[s + K];
     const double keep = up ? x[s + K] : x[s];
-    x[s] = keep + __shfl_xor(send, M, 64);
+    x[s] = keep + dpp_d<CTRL>(send);
   }
 }
 
