@@ -245,9 +245,9 @@ __device__ __forceinline__ void factor_panel(double2 (&a)[RP][NB], int mp, int n
 // Variant with two workgroup barriers per column instead of four.  Each wave
 // reduces its 32 partial values (the slots of factor_panel, padded to 32) with
 // a halving exchange: at lane distances 32 and 16 the permlane swaps hand each
-// half of the wave the other half's partials of the values it keeps, at 8, 4
-// and 2 lane shuffles do the same, and a DPP step at distance 1 completes the
-// wave sum of value s in lanes 2s and 2s + 1.  The waves' sums go to LDS, one
+// half of the wave the other half's partials of the values it keeps, inside
+// each row of 16 lanes DPP mirrors and a quad swap do the same, and a DPP
+// step at distance 1 completes the wave sum of value s in lanes 2s and 2s + 1.  The waves' sums go to LDS, one
 // barrier, wave 0 adds them up and forms the reflector, a second barrier, and
 // every thread applies it.  The next column's LDS writes cannot disturb the
 // readers of this one: those all read before the second barrier.
