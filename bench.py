@@ -83,7 +83,11 @@ def mpo_bond_max(prm) -> int:
 
 
 def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload=WORKLOAD,
-            graphs: bool = False):
+            graphs: bool = False, sampled=()):
+    """W warm-up steps, then K timed steps with no per-launch instrumentation.
+    With `timing`, one more step after the timed ones records per-class launch
+    durations with HIP events (the roofline figures); the shots listed in
+    `sampled` are exported from that step (or from the last timed one)."""
     import torch
     from inputs import circuits as C
     from inputs.randomness import shot_uniforms
@@ -97,32 +101,80 @@ def run_gpu(prec: str, shots: int, steps: int, warmup: int, timing: bool, worklo
     eng.tuning(TUNE["enabled"])
     st = E.State(eng, prec, n, shots, chi, mpo_bond_max(prm), [chi], prm["init_seed"])
     nm = circ.n_measurements()
+    samples = {}
 
-    def one_step(step):
+    def one_step(step, export=False):
         u = np.stack([shot_uniforms(prm["seed"], step * shots + s, nm) for s in range(shots)])
         res = E.run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
+        if export:
+            for s in sampled:
+                samples[s] = {"outcomes": res["outcomes"][s].copy(), "p0s": res["p0s"][s].copy(),
+                              "F": float(res["F"][s]), "mps": st.export(int(res["ids"][s]))}
         st.release(res["ids"])
         return res
 
     for w in range(warmup):
         one_step(10_000 + w)
     torch.cuda.synchronize()
-    eng.timing(timing)
-    eng.timing_stats(reset=True)
+    eng.timing(False)
     t0 = time.perf_counter()
     fids = []
     for s in range(steps):
-        r = one_step(s)
+        r = one_step(s, export=(s == steps - 1 and not timing))
         fids.append(float(np.mean(r["F"])))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = eng.timing_stats(reset=True) if timing else None
-    eng.timing(False)
+    stats = None
+    if timing:
+        eng.timing(True)
+        eng.timing_stats(reset=True)
+        one_step(steps, export=True)
+        torch.cuda.synchronize()
+        stats = eng.timing_stats(reset=True)
+        eng.timing(False)
     if TUNE["save"] and prec == "c64":
         eng.save_tuning(TUNE["save"])
     st.close()
     eng.close()
-    return dt, stats, fids
+    return dt, stats, fids, samples
+
+
+def precision_vs_fp64(workload: str, samples: dict):
+    """Sampled shots of a reduced-precision run against the complex128 GPU path
+    replaying their outcomes (the complex128 path is itself held to the FP64
+    oracle): every measurement probability, and the state-fidelity error
+    1 - |<a|b>|^2 / (<a|a><b|b>) from the FP64 overlap of the two final states
+    (the reduced-precision state imported into a complex128 state)."""
+    from inputs import circuits as C
+    from paper_2609_26516_amd import capi
+    from paper_2609_26516_amd import engine as E
+
+    circ, prm = C.workload(workload)
+    n, chi = prm["n"], prm["chi"]
+    k = C.segment_max(circ) + 1
+    shots = sorted(samples)
+    eng = E.Engine(0)
+    st = E.State(eng, "c128", n, 2 * len(shots), chi, mpo_bond_max(prm), [chi],
+                 prm["init_seed"])
+    outs = np.stack([samples[s]["outcomes"] for s in shots])
+    r = E.run_single_path(eng, st, circ, len(shots), chi, k, 2, outcomes=outs)
+    dp, fe, df = [], [], []
+    for i, s in enumerate(shots):
+        ref_id = int(r["ids"][i])
+        other = st.alloc(1)[0]
+        capi.dcs_import_mps(st.h, other, chi, samples[s]["mps"], eng.stream())
+        ov = capi.dcs_overlap(st.h, ref_id, other, eng.stream())
+        na = capi.dcs_overlap(st.h, ref_id, ref_id, eng.stream()).real
+        nb = capi.dcs_overlap(st.h, other, other, eng.stream()).real
+        fe.append(float(abs(1 - abs(ov) ** 2 / (na * nb))))
+        dp.append(float(np.max(np.abs(samples[s]["p0s"] - r["p0s"][i]))))
+        df.append(float(abs(samples[s]["F"] - r["F"][i])))
+    st.close()
+    eng.close()
+    return {"reference": "GPU FP64 path (complex128, FP64 MFMA) replaying the outcomes",
+            "shots": shots, "max_abs_probability_error": max(dp),
+            "state_fidelity_error": max(fe), "fidelity_estimate_abs_error": max(df),
+            "targets": {"max_abs_probability_error": 1e-6, "state_fidelity_error": 1e-6}}
 
 
 def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload: str):
@@ -154,15 +206,20 @@ def run_gpu_multipath(prec: str, steps: int, warmup: int, timing: bool, workload
     for _ in range(warmup):
         one_run()
     torch.cuda.synchronize()
-    eng.timing(timing)
-    eng.timing_stats(reset=True)
+    eng.timing(False)
     t0 = time.perf_counter()
     for _ in range(steps):
         one_run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = eng.timing_stats(reset=True) if timing else None
-    eng.timing(False)
+    stats = None
+    if timing:   # one instrumented run after the timed ones
+        eng.timing(True)
+        eng.timing_stats(reset=True)
+        one_run()
+        torch.cuda.synchronize()
+        stats = eng.timing_stats(reset=True)
+        eng.timing(False)
     st.close()
     eng.close()
     return dt, stats, info
@@ -227,8 +284,7 @@ def run_large_chi(workload: str, steps: int, warmup: int, timing: bool, graphs: 
     for i in range(warmup):
         st.release(E.run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u(10_000 + i))["ids"])
     torch.cuda.synchronize()
-    eng.timing(timing)
-    eng.timing_stats(reset=True)
+    eng.timing(False)
     t0 = time.perf_counter()
     first = None
     for i in range(steps):
@@ -238,8 +294,14 @@ def run_large_chi(workload: str, steps: int, warmup: int, timing: bool, graphs: 
         st.release(r["ids"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = eng.timing_stats(reset=True) if timing else None
-    eng.timing(False)
+    stats = None
+    if timing:   # one instrumented shot after the timed ones
+        eng.timing(True)
+        eng.timing_stats(reset=True)
+        st.release(E.run_single_path(eng, st, circ, 1, chi, k, 2, uniforms=u(steps))["ids"])
+        torch.cuda.synchronize()
+        stats = eng.timing_stats(reset=True)
+        eng.timing(False)
     st.close()
     r_bf, mps_bf = first
     st64 = E.State(eng, "c128", n, 2, chi, w, [chi], prm["init_seed"])
@@ -262,18 +324,19 @@ def run_large_chi(workload: str, steps: int, warmup: int, timing: bool, graphs: 
     return dt, dt64, stats, cmp
 
 
-def cpu_baseline(rounds: int):
-    """The FP64 oracle on the first `rounds` measurement rounds of one shot of
-    the same workload, scaled to shots/s by the fraction of rounds done."""
-    from threadpoolctl import threadpool_info
+def _oracle_shot_sample(rounds: int):
+    """Wall time of the FP64 oracle (numpy, complex128) on a bounded sample of
+    one shot of the headline workload: its first `rounds` measurement rounds
+    (each one compression step and 4 measurements), then the compression of
+    the last round's feed-forward gates, the one compression step a shot has
+    beyond its rounds.  Returns (seconds of the rounds, seconds of the final
+    compression)."""
     from inputs import circuits as C
     from inputs.randomness import shot_uniforms
     from oracle import dynamic as OD
 
     circ, prm = C.workload(WORKLOAD)
     n, chi = prm["n"], prm["chi"]
-    per_round = prm["layers_per_round"] * (n // 2) + 2 * prm["meas_per_round"]
-    total_rounds = prm["depth"] // prm["layers_per_round"]
     ops, seen = [], 0
     for op in circ.ops:
         ops.append(op)
@@ -286,14 +349,47 @@ def cpu_baseline(rounds: int):
     sim.bra_init(chi)   # starting guess built before the clock starts
     u = shot_uniforms(prm["seed"], 0, circ.n_measurements())
     t0 = time.perf_counter()
-    OD.run_single_path(sub, sim, uniforms=u)
-    dt = time.perf_counter() - t0
+    r = OD.run_single_path(sub, sim, uniforms=u)
+    t_rounds = time.perf_counter() - t0
+    # the last round's feed-forward gates, all of them (an upper bound of what fires)
+    last = max(i for i, op in enumerate(circ.ops) if isinstance(op, C.Measure))
+    tail = [(tuple(op.gate.qubits), op.gate.mat) for op in circ.ops[last + 1:]
+            if isinstance(op, C.CGate)]
+    t0 = time.perf_counter()
+    sim.compress(r["mps"], tail, chi)
+    t_final = time.perf_counter() - t0
+    return t_rounds, t_final
+
+
+def cpu_baseline(rounds: int, rounds_multi: int):
+    """The oracle timed in this process on a bounded sample of one shot (first
+    rounds plus the final compression), scaled to a whole shot: 10 rounds and
+    the final compression (all rounds cost the same: the oracle's bond dims
+    are fixed).  The value is single-threaded (BLAS limited to one thread);
+    the same sample on every BLAS thread the process has is given beside it."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from inputs import circuits as C
+
+    _, prm = C.workload(WORKLOAD)
+    total_rounds = prm["depth"] // prm["layers_per_round"]
+
+    def rate(t_rounds, t_final, r):
+        return 1.0 / (t_rounds / r * total_rounds + t_final)
+
+    with threadpool_limits(limits=1, user_api="blas"):
+        t1, f1 = _oracle_shot_sample(rounds)
     threads = sum(i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas")
-    del per_round
-    return {"value": round((rounds / total_rounds) / dt, 6), "unit": "shots/s",
-            "cores": int(threads or 1), "kind": "oracle",
+    tm, fm = _oracle_shot_sample(rounds_multi)
+    return {"value": round(rate(t1, f1, rounds), 6), "unit": "shots/s", "cores": 1,
+            "kind": "oracle",
             "sample": f"first {rounds} of {total_rounds} rounds (compression + 4 measurements "
-                      f"each) of one shot, {dt:.1f} s, scaled by {rounds}/{total_rounds}"}
+                      f"each, {t1:.1f} s) and the final compression ({f1:.1f} s) of one shot, "
+                      f"one BLAS thread; shot time = {total_rounds}/{rounds} x rounds + final",
+            "all_threads": {"value": round(rate(tm, fm, rounds_multi), 6), "unit": "shots/s",
+                            "cores": int(threads or 1),
+                            "sample": f"first {rounds_multi} rounds ({tm:.1f} s) and the final "
+                                      f"compression ({fm:.1f} s), one process, "
+                                      f"{int(threads or 1)} BLAS threads"}}
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
@@ -323,8 +419,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--shots", type=int, default=256)
-    ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-rounds", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-rounds", type=int, default=1,
+                    help="measurement rounds of the single-threaded oracle sample")
+    ap.add_argument("--cpu-rounds-multi", type=int, default=2,
+                    help="measurement rounds of the all-threads oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="sp40",
@@ -365,7 +464,9 @@ def main():
                    "gemm_nn": "gemm_bf16x3_kernel<0, 0>", "gemm_nt": "gemm_bf16x3_kernel<0, 1>",
                    "gemm_cn": "gemm_bf16x3_kernel<2, 0>", "gemm_jt": "gemm_bf16x3_kernel<3, 1>"})
                if stats else None,
-               "fp64_path": {"value": round(1 / dt64, 5), "unit": "shots/s", "dtype": "c128"},
+               "fp64_path": {"value": round(1 / dt64, 5), "unit": "shots/s", "dtype": "c128",
+                             "steps": 1, "warmup": 0,
+                             "note": "one replay shot on a fresh engine (tile tuning included)"},
                "precision_vs_fp64": cmp}
         print(json.dumps(out))
         return
@@ -380,14 +481,16 @@ def main():
                "data": "synthetic: seeded Haar brickwork dynamic circuit",
                "config": {"workload": wl, **info}, "roofline": roofline(stats, "c64")}
         if not args.no_fp64:
-            dt64, _, _ = run_gpu_multipath("c128", 1, 0, False, wl)
-            out["fp64_path"] = {"value": round(1 / dt64, 5), "unit": "runs/s", "dtype": "c128"}
+            dt64, _, _ = run_gpu_multipath("c128", args.fp64_steps, args.warmup, False, wl)
+            out["fp64_path"] = {"value": round(args.fp64_steps / dt64, 5), "unit": "runs/s",
+                                "steps": args.fp64_steps, "warmup": args.warmup,
+                                "dtype": "c128"}
         print(json.dumps(out))
         return
     if args.workload != "sp40":
         wl = SINGLE_PATH[args.workload]
-        dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, not args.graphs, wl,
-                                  graphs=args.graphs)
+        dt, stats, fids, _ = run_gpu("c64", args.shots, args.steps, args.warmup,
+                                     not args.graphs, wl, graphs=args.graphs)
         out = {"metric": "shots/s (batched FP32-MFMA form)", "value": round(args.shots * args.steps / dt, 4),
                "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": round(1e3 * dt / args.steps, 2), "higher_is_better": True,
@@ -397,12 +500,15 @@ def main():
                "roofline": roofline(stats, "c64") if stats else None,
                "mean_fidelity_estimate": round(float(np.mean(fids)), 6)}
         if not args.no_fp64:
-            dt64, _, _ = run_gpu("c128", args.shots, args.fp64_steps, 0, False, wl)
+            dt64, _, _, _ = run_gpu("c128", args.shots, args.fp64_steps, args.warmup, False, wl)
             out["fp64_path"] = {"value": round(args.shots * args.fp64_steps / dt64, 4),
-                                "unit": "shots/s", "dtype": "c128"}
+                                "unit": "shots/s", "steps": args.fp64_steps,
+                                "warmup": args.warmup, "dtype": "c128"}
         print(json.dumps(out))
         return
-    dt, stats, fids = run_gpu("c64", args.shots, args.steps, args.warmup, timing=True)
+    sampled = (0, args.shots - 1)
+    dt, stats, fids, samples = run_gpu("c64", args.shots, args.steps, args.warmup, timing=True,
+                                       sampled=sampled)
     value = args.shots * args.steps / dt
     out = {
         "metric": "shots/s (batched FP32-MFMA form, chi=256), FP64 path beside it",
@@ -416,12 +522,16 @@ def main():
         "roofline": roofline(stats, "c64", counters=args.shots == 256),
         "mean_fidelity_estimate": round(float(np.mean(fids)), 6),
     }
+    out["roofline"]["measured_on"] = ("one instrumented step after the timed ones "
+                                      "(HIP events around every launch)")
+    out["precision_vs_fp64"] = precision_vs_fp64(WORKLOAD, samples)
     if not args.no_fp64:
-        dt64, _, _ = run_gpu("c128", args.shots, args.fp64_steps, 0, timing=False)
+        dt64, _, _, _ = run_gpu("c128", args.shots, args.fp64_steps, args.warmup, timing=False)
         out["fp64_path"] = {"value": round(args.shots * args.fp64_steps / dt64, 4),
-                            "unit": "shots/s", "steps": args.fp64_steps, "dtype": "c128"}
+                            "unit": "shots/s", "steps": args.fp64_steps, "warmup": args.warmup,
+                            "dtype": "c128"}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_rounds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rounds, args.cpu_rounds_multi)
     print(json.dumps(out))
 
 

@@ -24,14 +24,19 @@
  *   - Complex numbers on the host are interleaved (re, im) doubles.
  *   - Device memory of a state is owned by the caller (one buffer of
  *     dcs_state_bytes() bytes, at least 256-byte aligned) and must outlive the
- *     state; the library never frees it.  Host arrays are only read during a
+ *     state; the library never frees it and makes no device allocation of its
+ *     own: every device scratch area a call uses lies inside that buffer.
+ *     (Pinned host staging buffers are allocated on first use and held by the
+ *     state until dcs_state_destroy.)  Host arrays are only read during a
  *     call.  Opaque handles are owned by the caller and released with the
  *     matching *_destroy.
  *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
  *     of a call is enqueued on it; calls that return host values synchronise
  *     that stream before returning.
- *   - Qubit q of the chain is the paper's Q_{q+1}; two-qubit gates act on
- *     adjacent qubits (q, q+1).
+ *   - Qubit q of the chain is the paper's Q_{q+1}.  A two-qubit gate may act
+ *     on any two distinct qubits, in either order (dcs_chunk_compile carries
+ *     the operator bond of a gate on non-adjacent qubits across the sites
+ *     between them).
  *   - Bond dimensions are fixed and zero padded: for bond cap chi the bond b
  *     (between sites b-1 and b) has chi_b = min(chi, 2^b, 2^(n-b)).
  *   - A state holds `capacity` branch slots; a branch is named by its slot
@@ -52,7 +57,9 @@ extern "C" {
 enum dcs_status {
   DCS_OK = 0,
   DCS_EINVAL = -1,      /* bad argument (range, null pointer, duplicate id) */
-  DCS_ENONLOCAL = -2,   /* two-qubit gate whose two qubits coincide         */
+  DCS_EQUBITS = -2,     /* two-qubit gate whose two qubits coincide         */
+  DCS_ENONLOCAL = DCS_EQUBITS,   /* former name of DCS_EQUBITS (from when gates
+                                    had to act on adjacent qubits)          */
   DCS_EZEROPROB = -3,   /* collapse on an outcome with p_m <= eps           */
   DCS_ECAPACITY = -4,   /* branch id outside the state's capacity           */
   DCS_ENOMEM = -5,      /* buffer too small / chunk operator wider than the
@@ -143,7 +150,11 @@ int dcs_state_destroy(dcs_state *st);
  * interleaved, sites j = 0..n-1 concatenated, each row-major
  * [chi_j][2][chi_{j+1}] for the padded dims of chi_cap).  Site j >= 1 becomes
  * the orthonormal-row factor of LQ(G_j as chi_j x 2chi_{j+1}) (FP64 on the
- * GPU); site 0 becomes G_0 / |G_0|. */
+ * GPU); site 0 becomes G_0 / |G_0|.  The Gaussians are staged through the
+ * per-call scratch of the state's slots (live branches keep their contents);
+ * the bond cap is registered only once its guess is complete, so after a
+ * failure no compression step can use a partial guess.  Re-registering a cap
+ * replaces its guess.  Synchronises `stream`. */
 int dcs_state_set_init(dcs_state *st, int chi_cap, const double *gauss, void *stream);
 
 /* Make the listed slots live branches in |0...0> (A_j[0][0][0] = 1) with bond
@@ -171,7 +182,7 @@ int dcs_branch_dims(const dcs_state *st, int id, int *dims_out);
  * gate's bond of dimension r passed through, so every bond a..b-1 is
  * multiplied by r (the chunk's bond j is the product of the ranks of the
  * gates spanning it).  A gate with q0 > q1 is applied as its qubit-swapped
- * matrix on (q1, q0).  Errors: DCS_ENONLOCAL for q0 == q1, DCS_EINVAL for a
+ * matrix on (q1, q0).  Errors: DCS_EQUBITS for q0 == q1, DCS_EINVAL for a
  * qubit out of range or a non-finite matrix entry.  Host-only; the handle is independent of any state.
  * `ctx` may be NULL (no caching of gate splits across calls). */
 int dcs_chunk_compile(dcs_ctx *ctx, dcs_chunk **out, int n_qubits, int n_ops,

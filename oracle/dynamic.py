@@ -105,14 +105,22 @@ def _unitary(op):
 
 def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[float]] = None,
                     outcomes: Optional[Sequence[int]] = None,
-                    chi_ladder: Optional[Sequence[int]] = None, f_target: float = 0.0) -> Dict:
+                    chi_ladder: Optional[Sequence[int]] = None, f_target: float = 0.0,
+                    chis: Optional[Sequence[int]] = None) -> Dict:
     """Alg. 1.  Outcomes come from ``outcomes`` when given (replay), else from
     ``uniforms`` (m = 0 iff u < p_0).  Returns the fidelity estimate, path
     probability, register, final MPS and the per-measurement records.
     Adaptive bond cap (a reading; the paper fixes chi per run): with
     ``chi_ladder`` (ascending from sim.chi), a compression whose partial
     fidelity is below ``f_target`` moves the run one rung up for the next
-    compressions; "chis" records the cap of every compression."""
+    compressions; "chis" records the cap of every compression.
+    Bond-cap schedule: ``chis`` (exclusive with ``chi_ladder``) gives the cap
+    of each compression in order, e.g. the caps a multi-path branch used along
+    its path (each child compresses into its own cap, the ket keeping its
+    parent's bonds); a run needing more compressions than listed is an
+    error."""
+    if chis is not None and chi_ladder is not None:
+        raise ValueError("chis and chi_ladder are exclusive")
     state = sim.zero(sim.chi)
     c = [0] * circ.n_bits
     p, fid = 1.0, 1.0
@@ -124,10 +132,16 @@ def run_single_path(circ: Circuit, sim: Simulator, uniforms: Optional[Sequence[f
 
     def flush():
         nonlocal state, fid, chunk, rung
-        state, f = sim.compress(state, chunk, ladder[rung])
+        if chis is not None:
+            if len(rec["chis"]) >= len(chis):
+                raise ValueError("the bond-cap schedule is shorter than the run")
+            cap = int(chis[len(rec["chis"])])
+        else:
+            cap = ladder[rung]
+        state, f = sim.compress(state, chunk, cap)
         fid *= f
         rec["fids"].append(f)
-        rec["chis"].append(ladder[rung])
+        rec["chis"].append(cap)
         chunk = []
         if f < f_target and rung + 1 < len(ladder):
             rung += 1
@@ -216,12 +230,13 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
     chi per run) a branch whose compression fidelity falls below ``f_target``
     takes the next rung for its later compressions and passes its rung to
     its children; "chis" records each branch's caps along its path.
-    Returns the live branches (path, p, c, F, mps, chi), the dropped mass and
-    the probability-weighted fidelity."""
+    Returns the live branches (path, p, c, F, mps, chi, and p0s: the p_0 of
+    every measurement along the branch's path, taken on its ancestor), the
+    dropped mass and the probability-weighted fidelity."""
     ladder = list(chi_ladder) if chi_ladder is not None else [sim.chi]
     live = [{"path": (), "p": 1.0, "c": [0] * circ.n_bits, "F": 1.0, "chunk": [],
              "mps": sim.zero(sim.chi), "chi": sim.chi, "rung": 0,
-             "chis": []}]
+             "chis": [], "p0s": []}]
     dropped = 0.0
     n_compress = 0
 
@@ -255,7 +270,8 @@ def run_multi_path(circ: Circuit, sim: Simulator, max_branches: Optional[int] = 
                         nxt.append({"path": path, "p": b["p"] * pm, "c": c, "F": b["F"],
                                     "chunk": [], "mps": sim.collapse(b["mps"], op.qubit, m, nm),
                                     "chi": chi_of(path) if chi_of else b["chi"],
-                                    "rung": b["rung"], "chis": list(b["chis"])})
+                                    "rung": b["rung"], "chis": list(b["chis"]),
+                                    "p0s": b["p0s"] + [n0 / (n0 + n1)]})
             else:
                 g = _unitary(op)
                 if sim.closes_chunk(b["chunk"], g):

@@ -18,10 +18,11 @@ import torch  # noqa: F401
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdcs.so")
 
-DCS_OK, DCS_EINVAL, DCS_ENONLOCAL, DCS_EZEROPROB = 0, -1, -2, -3
+DCS_OK, DCS_EINVAL, DCS_EQUBITS, DCS_EZEROPROB = 0, -1, -2, -3
+DCS_ENONLOCAL = DCS_EQUBITS   # former name
 DCS_ECAPACITY, DCS_ENOMEM, DCS_EHIP, DCS_ESTATE, DCS_ENUMERIC = -4, -5, -6, -7, -8
 DCS_C128, DCS_C64, DCS_BF16X3 = 0, 1, 2
-STATUS_NAMES = {0: "DCS_OK", -1: "DCS_EINVAL", -2: "DCS_ENONLOCAL", -3: "DCS_EZEROPROB",
+STATUS_NAMES = {0: "DCS_OK", -1: "DCS_EINVAL", -2: "DCS_EQUBITS", -3: "DCS_EZEROPROB",
                 -4: "DCS_ECAPACITY", -5: "DCS_ENOMEM", -6: "DCS_EHIP", -7: "DCS_ESTATE",
                 -8: "DCS_ENUMERIC"}
 EXPORTED = [

@@ -1013,43 +1013,44 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
     const Layout& L = st->L;
     if (chi_cap < 1 || chi_cap > L.chi_max) return fail(DCS_EINVAL, "chi_cap outside [1, chi_max]");
     int idx = st->init_index(chi_cap);
-    if (idx < 0) {
+    const bool fresh = idx < 0;
+    if (fresh) {
       if ((int)st->inits.size() >= L.n_init)
         return fail(DCS_ENOMEM, "all starting-guess slots are in use");
-      st->inits.push_back(InitSlot{chi_cap});
-      idx = (int)st->inits.size() - 1;
+      idx = (int)st->inits.size();
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = L.n;
     const std::vector<int> d = bond_dims(n, chi_cap);
-    size_t total = 0, emax = 0;
     std::vector<size_t> goff(n);
+    size_t total = 0, emax = 0;
     for (int j = 0; j < n; ++j) {
       goff[j] = total;
       const size_t e = (size_t)d[j] * 2 * d[j + 1];
       total += e;
       emax = std::max(emax, e);
     }
-    const int per_launch = QR_MAX_GROUPS;
-    void* dg = nullptr;
-    void* dws = nullptr;
-    void* dnrm = nullptr;
-    DCS_HIP(hipMalloc(&dg, total * 16));
-    const size_t ws_item = align_up(qr_ws_elems(emax, (size_t)chi_cap) * 16);
-    hipError_t e = hipMalloc(&dws, ws_item * per_launch);
-    if (e == hipSuccess) e = hipMalloc(&dnrm, 64 * sizeof(double));
-    if (e == hipSuccess) e = hipMemcpyAsync(dg, gauss, total * 16, hipMemcpyHostToDevice, s);
-    int rc = DCS_OK;
-    if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init upload: ") + hipGetErrorString(e));
+    // Scratch from the state's own buffer: site j of a launch group uses the
+    // per-call contraction area (x1 and x2, contiguous) of slot i = j - j0
+    // for its FP64 Gaussian and that slot's QR workspace; |G|^2 goes to the
+    // call output area.  None of these hold anything between calls, so live
+    // branches are unaffected.  Their sizes come from chi_max >= chi_cap.
+    if (emax * 16 > L.o_f - L.o_x1 || qr_ws_elems(emax, (size_t)chi_cap) * 16 > L.o_e - L.o_ws)
+      return fail(DCS_ENOMEM, "internal: slot scratch too small for the starting guess");
+    const int per_launch = std::min(L.cap, QR_MAX_GROUPS);
+    double* nrm_dev = reinterpret_cast<double*>(st->base + L.o_out);
     char* ibase = st->base + L.o_init + L.mps_bytes * (size_t)idx;
-    for (int j0 = 0; rc == DCS_OK && j0 < n; j0 += per_launch) {
+    for (int j0 = 0; j0 < n; j0 += per_launch) {
       std::vector<QrJob> jobs;
       for (int j = j0; j < std::min(n, j0 + per_launch); ++j) {
+        char* sb = st->slot_base(j - j0);
+        const size_t e = (size_t)d[j] * 2 * d[j + 1];
+        DCS_HIP(hipMemcpyAsync(sb + L.o_x1, gauss + 2 * goff[j], e * 16, hipMemcpyHostToDevice, s));
         QrJob q;
-        q.f = local_op(static_cast<char*>(dg) + goff[j] * 16, 0);
+        q.f = local_op(sb + L.o_x1, 0);
         q.q = local_op(ibase + L.site_off[j], 0);
-        q.ws = local_op(static_cast<char*>(dws) + (size_t)(j - j0) * ws_item, 0);
-        q.nrm2 = local_op(static_cast<double*>(dnrm) + (j - j0), 0);
+        q.ws = local_op(sb + L.o_ws, 0);
+        q.nrm2 = local_op(nrm_dev + (j - j0), 0);
         q.ids = nullptr;
         q.batch = 1;
         if (j == 0) {
@@ -1063,16 +1064,12 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
         }
         jobs.push_back(q);
       }
-      rc = run_qr(st->ctx, CT_F64, L.ct, jobs, s);
+      DCS_TRY(run_qr(st->ctx, CT_F64, L.ct, jobs, s));
     }
-    if (rc == DCS_OK) {
-      e = hipStreamSynchronize(s);
-      if (e != hipSuccess) rc = fail(DCS_EHIP, std::string("init LQ: ") + hipGetErrorString(e));
-    }
-    (void)hipFree(dg);
-    if (dws) (void)hipFree(dws);
-    if (dnrm) (void)hipFree(dnrm);
-    return rc;
+    DCS_HIP(hipStreamSynchronize(s));
+    // the bond cap is usable only once its guess is complete
+    if (fresh) st->inits.push_back(InitSlot{chi_cap});
+    return DCS_OK;
   });
 }
 
@@ -1162,7 +1159,7 @@ int dcs_chunk_compile(dcs_ctx* ctx, dcs_chunk** out, int n_qubits, int n_ops, co
       if (q1[i] != -1) {
         if (q1[i] < 0 || q1[i] >= n_qubits) return fail(DCS_EINVAL, "qubit out of range");
         if (q1[i] == q0[i])
-          return fail(DCS_ENONLOCAL, "two-qubit gate on (" + std::to_string(q0[i]) + ", " +
+          return fail(DCS_EQUBITS, "two-qubit gate on (" + std::to_string(q0[i]) + ", " +
                                          std::to_string(q1[i]) + "): the qubits coincide");
       }
     }

@@ -355,8 +355,10 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     Adaptive bond cap: with `chi_ladder` (ascending from chi), a branch whose
     compression returns a partial fidelity below `f_target` moves one rung up
     for its later compressions, and its children start on its rung.  Each
-    branch's "chi" is its current cap and "chis" the caps of the compressions
-    on its path."""
+    branch's "chi" is its current cap, "chis" the caps of the compressions
+    on its path and "p0s" the p_0 of every measurement on its path (taken on
+    its ancestor at that measurement).  If anything raises, every slot the run
+    holds is released before the exception propagates."""
     if chi_ladder is not None:
         chi_ladder = [int(c) for c in chi_ladder]
         if chi_of is not None:
@@ -370,7 +372,8 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     new_bonds = (lambda: _Bonds(eng, circ, st.wmax, 1)) if rule else (lambda: None)  # noqa: E731
     one = np.zeros(1, dtype=np.int64)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
-           "F": 1.0, "chunk": [], "rung": 0, "chi": chi, "chis": [], "w": new_bonds()}]
+           "F": 1.0, "chunk": [], "rung": 0, "chi": chi, "chis": [], "p0s": [],
+           "w": new_bonds()}]
     dropped = 0.0
 
     def compress(sel: List[dict]) -> None:
@@ -392,60 +395,80 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
         if up:
             capi.dcs_branch_set_chi(st.h, [b["id"] for b in up], [b["chi"] for b in up])
 
-    for li, op in enumerate(circ.ops):
-        if isinstance(op, Measure):
-            compress([b for b in br if b["chunk"]])
-            ids = [b["id"] for b in br]
-            q = [op.qubit] * len(br)
-            p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
-            src, dst, outc, qq, kids = [], [], [], [], []
-            for b, pz in zip(br, p0):
-                opts = [m for m, pm in ((0, pz), (1, 1.0 - pz)) if pm > eps]
-                for j, m in enumerate(opts):
-                    did = b["id"] if j == 0 else st.alloc(1)[0]
-                    src.append(b["id"])
-                    dst.append(did)
-                    outc.append(m)
-                    qq.append(op.qubit)
-                    kids.append((b, m, did))
-            pm = capi.dcs_collapse(st.h, src, qq, outc, dst, eps, stream)
-            nxt = []
-            for (b, m, did), pmv in zip(kids, pm):
-                c = b["c"].copy()
-                c[op.bit] = m
-                nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
-                            "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
-                            "chi": chi_of(b["path"] + (m,)) if chi_of else b["chi"],
-                            "chis": list(b["chis"]), "w": new_bonds()})
-            br = nxt
-            if chi_of is not None:
-                capi.dcs_branch_set_chi(st.h, [b["id"] for b in br], [b["chi"] for b in br])
-            if prune is not None or (max_branches is not None and len(br) > max_branches):
-                if prune is not None:
-                    keep, disc = capi.dcs_prune_adaptive([b["p"] for b in br],
-                                                         max_branches or len(br),
-                                                         prune[0], prune[1])
-                else:
-                    keep, disc = capi.dcs_topk_by_weight([b["p"] for b in br], max_branches)
-                dropped += disc
-                kept = set(int(i) for i in keep)
-                st.release([b["id"] for i, b in enumerate(br) if i not in kept])
-                br = [br[int(i)] for i in keep]
-            continue
-        act = [b for b in br
-               if not (isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0])]
-        if rule:
-            compress([b for b in act
-                      if len(b["w"].closes(li, one, np.array([bool(b["chunk"])])))])
-        due = []
-        for b in act:
-            b["chunk"].append(li)
+    # slots this run holds: the live branches plus children allocated before
+    # they join them; all are released if anything below raises
+    held = {first}
+
+    def take() -> int:
+        sid = st.alloc(1)[0]
+        held.add(sid)
+        return sid
+
+    def let_go(sids) -> None:
+        sids = [int(x) for x in sids]
+        st.release(sids)
+        held.difference_update(sids)
+
+    try:
+        for li, op in enumerate(circ.ops):
+            if isinstance(op, Measure):
+                compress([b for b in br if b["chunk"]])
+                ids = [b["id"] for b in br]
+                q = [op.qubit] * len(br)
+                p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+                src, dst, outc, qq, kids = [], [], [], [], []
+                for b, pz in zip(br, p0):
+                    opts = [m for m, pm in ((0, pz), (1, 1.0 - pz)) if pm > eps]
+                    for j, m in enumerate(opts):
+                        did = b["id"] if j == 0 else take()
+                        src.append(b["id"])
+                        dst.append(did)
+                        outc.append(m)
+                        qq.append(op.qubit)
+                        kids.append((b, m, did, float(pz)))
+                pm = capi.dcs_collapse(st.h, src, qq, outc, dst, eps, stream)
+                nxt = []
+                for (b, m, did, pz), pmv in zip(kids, pm):
+                    c = b["c"].copy()
+                    c[op.bit] = m
+                    nxt.append({"id": did, "path": b["path"] + (m,), "p": b["p"] * float(pmv),
+                                "c": c, "F": b["F"], "chunk": [], "rung": b["rung"],
+                                "chi": chi_of(b["path"] + (m,)) if chi_of else b["chi"],
+                                "chis": list(b["chis"]), "p0s": b["p0s"] + [pz],
+                                "w": new_bonds()})
+                br = nxt
+                if chi_of is not None:
+                    capi.dcs_branch_set_chi(st.h, [b["id"] for b in br], [b["chi"] for b in br])
+                if prune is not None or (max_branches is not None and len(br) > max_branches):
+                    if prune is not None:
+                        keep, disc = capi.dcs_prune_adaptive([b["p"] for b in br],
+                                                             max_branches or len(br),
+                                                             prune[0], prune[1])
+                    else:
+                        keep, disc = capi.dcs_topk_by_weight([b["p"] for b in br],
+                                                             max_branches)
+                    dropped += disc
+                    kept = set(int(i) for i in keep)
+                    let_go([b["id"] for i, b in enumerate(br) if i not in kept])
+                    br = [br[int(i)] for i in keep]
+                continue
+            act = [b for b in br
+                   if not (isinstance(op, CGate) and not _cond_true(op.cond, b["c"][None, :])[0])]
             if rule:
-                b["w"].add(li, one)
-            if len(b["chunk"]) == k:
-                due.append(b)
-        compress(due)
-    compress([b for b in br if b["chunk"]])
+                compress([b for b in act
+                          if len(b["w"].closes(li, one, np.array([bool(b["chunk"])])))])
+            due = []
+            for b in act:
+                b["chunk"].append(li)
+                if rule:
+                    b["w"].add(li, one)
+                if len(b["chunk"]) == k:
+                    due.append(b)
+            compress(due)
+        compress([b for b in br if b["chunk"]])
+    except BaseException:
+        let_go(sorted(held))
+        raise
     ptot = sum(b["p"] for b in br)
     fmp = sum(b["p"] * b["F"] for b in br) / ptot if ptot > 0 else float("nan")
     return {"branches": br, "dropped": dropped, "F_mp": fmp}

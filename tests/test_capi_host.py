@@ -86,7 +86,7 @@ def test_chunk_compile_bonds_and_errors():
     capi.dcs_chunk_destroy(h)
     with pytest.raises(capi.DcsError) as e:
         capi.dcs_chunk_compile(0, 4, [2], [2], C.CNOT_01.reshape(-1))
-    assert e.value.code == capi.DCS_ENONLOCAL
+    assert e.value.code == capi.DCS_EQUBITS == capi.DCS_ENONLOCAL
     # a distant pair spans its bonds: CNOT (0, 2) and reversed CNOT (3, 1)
     mats = np.concatenate([C.CNOT_01.reshape(-1), C.CNOT_01.reshape(-1)])
     h = capi.dcs_chunk_compile(0, 4, [0, 3], [2, 1], mats)
@@ -180,3 +180,16 @@ def test_prune_adaptive_matches_oracle():
         capi.dcs_prune_adaptive([0.5, -0.1], 2)
     with pytest.raises(capi.DcsError):
         capi.dcs_prune_adaptive([0.5], 0)
+
+
+def test_library_makes_no_device_allocation():
+    """Every device buffer the product library uses lies in the caller's state
+    buffer: no hipMalloc / hipFree outside the kernel-test entry points."""
+    import glob
+    csrc = os.path.join(ROOT, "paper_2609_26516_amd", "csrc")
+    for path in glob.glob(os.path.join(csrc, "*")):
+        if os.path.basename(path) == "testing.cpp":
+            continue
+        txt = re.sub(r"//[^\n]*|/\*.*?\*/", "", open(path).read(), flags=re.S)
+        for call in ("hipMalloc(", "hipFree(", "hipMallocAsync(", "hipExtMallocWithFlags("):
+            assert call not in txt, (path, call)

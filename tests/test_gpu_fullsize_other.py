@@ -5,8 +5,12 @@ configuration its benchmark run uses:
   (autotuner on): the first, a middle and the last shot replayed by the FP64
   oracle on the same outcomes;
 * the 32-qubit multi-path run (Alg. 2, top-M with M = 64, per-branch bond caps
-  drawn from {32, 64, 128, 256}): complex64 against the complex128 path, plus
-  the mass balance of the branch weights;
+  drawn from {32, 48, ..., 256}): complex64 against the complex128 path, plus
+  the mass balance of the branch weights; the heaviest kept branch and the
+  branch at the cut (the lightest kept) of the complex64 run replayed by the
+  FP64 oracle's single-path driver with that branch's outcomes and bond-cap
+  schedule, held to the precision form's targets (every measurement's p_0
+  within 1e-6, state-fidelity error at most 1e-6);
 * 60 qubits, bond cap 1024, three-layer chunks, one split-BF16 shot: against
   the complex128 GPU path replaying its outcomes (the oracle cannot hold this
   size; the complex128 path is held to it at 1e-9 on every smaller case).
@@ -79,6 +83,8 @@ def test_24_qubits_1024_shots_sampled_against_oracle():
 
 
 def _multi_path(E, eng, prec, tuning):
+    """One full-size run; the heaviest kept branch and the lightest kept one
+    (the cut) are exported before the state is freed."""
     circ, prm = C.workload("cfg3_n32_mp64")
     n, chi, M = prm["n"], prm["chi"], prm["max_branches"]
     choices = prm["chi_choices"]
@@ -90,15 +96,53 @@ def _multi_path(E, eng, prec, tuning):
     res = E.run_multi_path(eng, st, circ, chi, k, 2, max_branches=M, chi_of=chi_of)
     print(f"{prec} multi-path run: {time.time() - t:.2f} s, {len(res['branches'])} branches, "
           f"dropped {res['dropped']:.6f}", flush=True)
+    w = [b["p"] for b in res["branches"]]
+    picked = {"heaviest": res["branches"][int(np.argmax(w))],
+              "cut": res["branches"][int(np.argmin(w))]}
+    res["picked"] = {name: (b, st.export(b["id"])) for name, b in picked.items()}
     st.close()
     return res, M
 
 
-def test_32_qubit_multi_path_complex64_against_complex128():
+@pytest.fixture(scope="module")
+def multi_path_runs():
     E, eng = _engine()
     r64, M = _multi_path(E, eng, "c64", True)
     r128, _ = _multi_path(E, eng, "c128", False)
     eng.close()
+    return r64, r128, M
+
+
+@pytest.mark.parametrize("which", ["heaviest", "cut"])
+def test_32_qubit_multi_path_kept_branch_against_oracle(multi_path_runs, which):
+    """A kept branch of the full-size complex64 run against the FP64 oracle
+    replaying its outcomes with its bond-cap schedule (the root's cap for the
+    first compression, then the cap each child drew)."""
+    r64, _, _ = multi_path_runs
+    b, mps = r64["picked"][which]
+    circ, prm = C.workload("cfg3_n32_mp64")
+    n, chi = prm["n"], prm["chi"]
+    k = C.segment_max(circ) + 1
+    nm = circ.n_measurements()
+    assert b["chis"][0] == chi and len(set(b["chis"])) > 1    # uneven caps on the path
+    t = time.time()
+    ref = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"]),
+                             outcomes=list(b["path"]), chis=b["chis"])
+    assert ref["chis"] == b["chis"]
+    dp = np.max(np.abs(np.array(b["p0s"]) - np.array(ref["p0s"])))
+    fe = _fid_err(mps, ref["mps"])
+    print(f"{which} branch (p = {b['p']:.3e}, caps {b['chis']}): oracle {time.time() - t:.1f} s, "
+          f"max |dp| = {dp:.3e}, state fidelity error = {fe:.3e}, "
+          f"F = {b['F']:.6f} vs {ref['F']:.6f}", flush=True)
+    assert len(b["p0s"]) == nm
+    assert dp <= 1e-6
+    assert fe <= 1e-6
+    assert abs(b["p"] - ref["p"]) <= nm * 1e-6 * max(ref["p"], 1e-300) / min(ref["pms"])
+    assert abs(b["F"] - ref["F"]) < 1e-4
+
+
+def test_32_qubit_multi_path_complex64_against_complex128(multi_path_runs):
+    r64, r128, M = multi_path_runs
     for res in (r64, r128):
         w = np.array([b["p"] for b in res["branches"]])
         assert len(w) == M                      # the cap binds at this size

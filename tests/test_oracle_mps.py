@@ -319,3 +319,157 @@ def test_chi_ladder_multi_path_matches_single_path_replay():
                               f_target=0.999)
         assert r["chis"] == b["chis"]
         assert abs(r["F"] - b["F"]) < 1e-12
+
+
+@pytest.mark.parametrize("chi_bra", [4, 8])
+def test_compress_into_narrower_bra(chi_bra):
+    """A ket of bond cap 16 compressed into a bra of cap 4 or 8 (what every
+    multi-path child with a smaller cap than its parent does): the result has
+    the bra's bond dims and unit norm, and f equals |<psi~'|U|psi~>|^2 from
+    contracted state vectors."""
+    n = 10
+    rng = np.random.default_rng(300 + chi_bra)
+    ket = _random_mps(rng, n, 16)
+    assert M.dims_of(ket) == M.bond_dims(n, 16)
+    ops = _random_chunk(rng, n, 2)
+    bra = M.generic_bra(bra_init_gaussians(n, chi_bra, 4))
+    for s in (1, 2, 3):
+        new, f, _ = M.compress(ket, M.chunk_mpo(n, ops), bra, s)
+        assert M.dims_of(new) == M.bond_dims(n, chi_bra)
+        target = M.to_statevector(ket)
+        for qubits, mat in ops:
+            target = SV.apply_gate(target, n, qubits, mat)
+        v = M.to_statevector(new)
+        assert abs(np.linalg.norm(v) - 1) < 1e-12
+        assert abs(abs(np.vdot(v, target)) ** 2 - f) < 1e-12
+        assert 0.0 < f < 1.0 - 1e-3             # the bra really truncates
+
+
+def _mps_from_statevector(psi, n, chi):
+    """Exact MPS of a state vector by successive SVDs, each bond zero-padded
+    to min(chi, 2^b, 2^(n-b)) (chi at least every Schmidt rank)."""
+    dims = M.bond_dims(n, chi)
+    out, rest, left = [], psi.reshape(1, -1), 1
+    for j in range(n - 1):
+        m = rest.reshape(left * 2, -1)
+        u, s, vh = np.linalg.svd(m, full_matrices=False)
+        r = int(np.sum(s > 1e-14 * s[0]))
+        assert r <= dims[j + 1]
+        a = np.zeros((dims[j], 2, dims[j + 1]), dtype=complex)
+        a[:left, :, :r] = u[:, :r].reshape(left, 2, r)
+        out.append(a)
+        rest = (s[:r, None] * vh[:r]).reshape(r, -1)
+        left = r
+    last = np.zeros((dims[n - 1], 2, 1), dtype=complex)
+    last[:left, :, 0] = rest.reshape(left, 2)
+    out.append(last)
+    return out
+
+
+def test_narrower_bra_reaches_eckart_young_bound():
+    """Ket stored at cap 16 whose Schmidt ranks are at most 4 on every bond but
+    the middle one (rank 8: three partially entangled pairs across it), a
+    chunk of one-qubit gates (ranks unchanged), bra of cap 4: only the middle
+    bond truncates, so f never exceeds the sum of the 4 largest squared
+    Schmidt coefficients there and reaches it as the sweeps converge."""
+    n = 8
+    rng = np.random.default_rng(77)
+    psi = np.zeros(2 ** n, dtype=complex)
+    psi[0] = 1.0
+    for (a, b), th in zip(((3, 4), (2, 5), (1, 6)), (0.35, 0.6, 0.9)):
+        # cos th |00> + sin th |11> on (a, b), placed by two exact gates
+        psi = SV.apply_gate(psi, n, (a,), np.array([[np.cos(th), -np.sin(th)],
+                                                     [np.sin(th), np.cos(th)]]))
+        cnot_far = SV.full_operator(n, (a,), np.diag([1.0, 0.0])) + \
+            SV.full_operator(n, (a,), np.diag([0.0, 1.0])) @ SV.full_operator(n, (b,), C.X)
+        psi = cnot_far @ psi
+    for q in range(n):
+        psi = SV.apply_gate(psi, n, (q,), C.haar_unitary(rng, 2))
+    ket = _mps_from_statevector(psi, n, 16)
+    assert M.dims_of(ket) == M.bond_dims(n, 16)
+    ranks = [np.linalg.matrix_rank(psi.reshape(2 ** b, -1), tol=1e-12) for b in range(1, n)]
+    assert ranks == [1, 2, 4, 8, 4, 2, 1]
+    ops = [((q,), C.haar_unitary(rng, 2)) for q in range(n)]
+    target = psi.copy()
+    for qubits, mat in ops:
+        target = SV.apply_gate(target, n, qubits, mat)
+    sv = np.linalg.svd(target.reshape(16, 16), compute_uv=False)
+    bound = float(np.sum(sv[:4] ** 2))
+    assert bound < 1 - 1e-3
+    bra = M.generic_bra(bra_init_gaussians(n, 4, 6))
+    mpo = M.chunk_mpo(n, ops)
+    prev = 0.0
+    for s in (1, 2, 4, 8, 16):
+        _, f, _ = M.compress(ket, mpo, bra, s)
+        assert f <= bound + 1e-12
+        if s >= 4:
+            assert prev - 1e-14 <= f
+        prev = f
+    _, f_conv, _ = M.compress(ket, mpo, bra, 60)
+    assert abs(f_conv - bound) < 1e-10
+
+
+def test_chi_schedule_exact_caps_replay_statevector():
+    """A bond-cap schedule that never cuts below the state's Schmidt ranks
+    (cap 4 after the first two brickwork layers, 16 after four, then 32)
+    leaves the run exact: every p_m and the final state match the state
+    vector, each compression has f = 1 and the final bonds are those of the
+    last cap."""
+    n = 10
+    circ, _ = C.workload("cfg1_n10_chi16", n=n, depth=10, chi=32)
+    sim = D.Simulator(n, 32, k=1000, n_sweeps=2, init_seed=7)
+    u = np.random.default_rng(12).random(64)
+    first = D.run_single_path(circ, sim, uniforms=u)
+    nc = len(first["fids"])
+    sched = [4, 16] + [32] * (nc - 2)
+    r = D.run_single_path(circ, sim, outcomes=first["outcomes"], chis=sched)
+    assert r["chis"] == sched
+    np.testing.assert_allclose(r["fids"], 1.0, atol=1e-11)
+    ref = SV.replay(circ, r["outcomes"])
+    np.testing.assert_allclose(r["pms"], ref["pms"], atol=1e-12)
+    assert M.dims_of(r["mps"]) == M.bond_dims(n, 32)
+    v = M.to_statevector(r["mps"])
+    assert abs(abs(np.vdot(ref["psi"], v)) ** 2 - 1) < 1e-11
+
+
+def test_chi_schedule_truncates_where_the_cap_is_too_small():
+    """The schedule's caps apply in order: a cap of 2 at the second
+    compression (Schmidt ranks up to 16 by then) is the only truncated step;
+    a schedule shorter than the run is an error."""
+    n = 10
+    circ, _ = C.workload("cfg1_n10_chi16", n=n, depth=10, chi=32)
+    sim = D.Simulator(n, 32, k=1000, n_sweeps=2, init_seed=7)
+    u = np.random.default_rng(12).random(64)
+    first = D.run_single_path(circ, sim, uniforms=u)
+    nc = len(first["fids"])
+    sched = [4, 2] + [32] * (nc - 2)
+    r = D.run_single_path(circ, sim, outcomes=first["outcomes"], chis=sched)
+    assert r["chis"] == sched
+    assert abs(r["fids"][0] - 1) < 1e-11
+    assert r["fids"][1] < 1 - 1e-3
+    assert M.bond_dims(n, 2) != M.bond_dims(n, 32)
+    with pytest.raises(ValueError):
+        D.run_single_path(circ, sim, outcomes=first["outcomes"], chis=sched[:-1])
+
+
+def test_multi_path_branches_record_p0_and_replay_with_their_schedule():
+    """Each multi-path branch with per-child caps records p_0 of every
+    measurement on its path; the single-path run replaying its outcomes with
+    its cap schedule reproduces those p_0, its weight, fidelity and state
+    (the replay the full-size GPU checks rely on)."""
+    from inputs.randomness import branch_chi_draw
+    circ, prm = C.workload("cfg3_n32_mp64", n=8, depth=6, chi=16)
+    choices = (4, 8, 12, 16)
+    chi_of = lambda path: branch_chi_draw(prm["seed"], path, choices)  # noqa: E731
+    k = C.segment_max(circ)
+    sim = D.Simulator(8, 16, k, 2, prm["init_seed"])
+    mp = D.run_multi_path(circ, sim, max_branches=5, chi_of=chi_of)
+    nm = circ.n_measurements()
+    for b in mp["branches"]:
+        assert len(b["p0s"]) == nm == len(b["path"])
+        pm = [p0 if m == 0 else 1 - p0 for p0, m in zip(b["p0s"], b["path"])]
+        assert abs(np.prod(pm) - b["p"]) < 1e-12
+        r = D.run_single_path(circ, sim, outcomes=list(b["path"]), chis=b["chis"])
+        np.testing.assert_allclose(r["p0s"], b["p0s"], atol=1e-12)
+        assert abs(r["p"] - b["p"]) < 1e-12 and abs(r["F"] - b["F"]) < 1e-12
+        assert abs(abs(M.overlap(r["mps"], b["mps"])) ** 2 - 1) < 1e-11
