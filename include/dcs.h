@@ -292,6 +292,20 @@ int dcs_prune_adaptive(int n, const double *weights, int k_max, double mass_tol,
  * ECAPACITY, ESTATE (branch not live), EHIP. */
 int dcs_overlap(dcs_state *st, int id_a, int id_b, double *out, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dcs_overlap without any
+ * allocation and without host synchronisation.  The transfer matrices live
+ * in a fixed device array of the library (3 MiB per device, held until the
+ * process ends): branches whose bond dimensions exceed 256 are rejected with
+ * DCS_ENOMEM.  No tile-shape trials and no launch timing run in this call;
+ * slot a's cached measurement transfer is left intact.  out_dev: device
+ * memory, 2 doubles (re, im), written by the last contraction on `stream`.
+ * All calls on one device share that array and nothing in it needs to start
+ * at zero, but calls that overlap in time on one device (other streams, other
+ * host threads) race on it: order them on one stream.  Errors: EINVAL,
+ * ECAPACITY, ESTATE, ENOMEM, EHIP. */
+int dcs_overlap_noalloc(dcs_state *st, int id_a, int id_b, double *out_dev, void *stream);
+
 /* FP64 host copy of branch `id`'s MPS: sites concatenated, each row-major
  * [chi_j][2][chi_{j+1}] complex128 interleaved (2 * sum chi_j*2*chi_{j+1}
  * doubles, at most cap_doubles); dims_out gets chi_0..chi_n. */

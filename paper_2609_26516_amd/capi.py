@@ -32,7 +32,7 @@ EXPORTED = [
     "dcs_state_set_init", "dcs_state_set_warm_start", "dcs_branch_init_zero", "dcs_branch_set_chi", "dcs_branch_release",
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_gate_rank", "dcs_chunk_bonds", "dcs_chunk_export", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight", "dcs_prune_adaptive",
-    "dcs_overlap", "dcs_export_mps", "dcs_import_mps",
+    "dcs_overlap", "dcs_overlap_noalloc", "dcs_export_mps", "dcs_import_mps",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
 
@@ -84,6 +84,7 @@ _SIGS = {
     "dcs_topk_by_weight": (c_int, [c_int, _DP, c_int, _IP, _IP, _DP]),
     "dcs_prune_adaptive": (c_int, [c_int, _DP, c_int, c_double, c_double, _IP, _IP, _DP]),
     "dcs_overlap": (c_int, [_P, c_int, c_int, _DP, _P]),
+    "dcs_overlap_noalloc": (c_int, [_P, c_int, c_int, _P, _P]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
     "dcs_test_gemm": (c_int, [c_int] * 11 + [_DP, _DP, _DP, _P]),
@@ -311,6 +312,12 @@ def dcs_overlap(st: int, id_a: int, id_b: int, stream: int = 0) -> complex:
     out = np.zeros(2)
     _check(_lib.dcs_overlap(st, id_a, id_b, _dp(out), stream))
     return complex(out[0], out[1])
+
+
+def dcs_overlap_noalloc(st: int, id_a: int, id_b: int, out_dev: int, stream: int = 0) -> None:
+    """<a|b> written to device memory out_dev (2 doubles) without allocation
+    or host synchronisation."""
+    _check(_lib.dcs_overlap_noalloc(st, id_a, id_b, out_dev, stream))
 
 
 def dcs_export_mps(st, bid, n_qubits, chi_max, stream):

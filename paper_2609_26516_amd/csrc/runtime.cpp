@@ -11,6 +11,7 @@
 #include <array>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -125,6 +126,10 @@ struct dcs_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   bool timing = false;
+  // > 0 while an entry point that must allocate nothing runs: tile shapes
+  // come from the decided table or the default (no timed trials), and no
+  // launch is timed (both would create events)
+  int no_alloc = 0;
   struct Pending {
     int cls;
     hipEvent_t a, b;
@@ -316,7 +321,7 @@ struct Timed {
   hipEvent_t a = nullptr;
   Timed(dcs_ctx* c_, hipStream_t s_, int cls_, double f, double b)
       : c(c_), s(s_), cls(cls_), flops(f), bytes(b) {
-    if (!c || !c->timing) return;
+    if (!c || !c->timing || c->no_alloc) return;
     a = take();
     (void)hipEventRecord(a, s);
   }
@@ -414,7 +419,7 @@ int tune_choose(dcs_ctx* c, const TuneKey& key, bool* timed) {
   if (it != c->tune.end() && it->second.best >= 0) return it->second.best;
   const bool small = key[6] <= 5 && key[7] <= 5;   // M, N <= 32
   const int fallback = small ? GEMM_32x32 : GEMM_64x64;
-  if (!c->tuning || c->capturing) return fallback;
+  if (!c->tuning || c->capturing || c->no_alloc) return fallback;
   TuneRec& r = c->tune[key];
   int v = 0;
   for (int i = 1; i < GEMM_VARIANTS; ++i)
@@ -795,6 +800,45 @@ std::vector<cd> op_product(const std::vector<cd>& earlier, int el, int er,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of dcs_overlap_noalloc: the FP64 left transfer E_j
+// (at most 256 x 256 complex128) and the product TX = E_j B_j (at most
+// 256 x 512) of the overlap contraction.  One copy per device, for the life
+// of the process; its device address is looked up once per device (the
+// array's name is only a host-side stand-in).
+
+namespace {
+
+constexpr size_t OVL_E_BYTES = (size_t)256 * 256 * 16;
+constexpr size_t OVL_TX_BYTES = (size_t)256 * 512 * 16;
+constexpr size_t OVL_SCRATCH_BYTES = OVL_E_BYTES + OVL_TX_BYTES;
+static __device__ __align__(256) char scratch[OVL_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (made current by the caller).
+int scratch_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(DCS_EINVAL, "device ordinal too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DCS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(DCS_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                              hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return DCS_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 
@@ -811,6 +855,7 @@ int dcs_ctx_create(dcs_ctx** out, int device) {
     DCS_HIP(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(DCS_EINVAL, "device ordinal out of range");
     DCS_HIP(hipSetDevice(device));
+    DCS_TRY(scratch_setup(device));
     dcs_ctx* c = new dcs_ctx();
     c->device = device;
     *out = c;
@@ -2079,38 +2124,57 @@ int dcs_prune_adaptive(int n, const double* weights, int k_max, double mass_tol,
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// <a|b> by the FP64 left transfer E_{j+1} = A_j^H (E_j B_j), E in `E`, the
+// product in `TX`; the last step writes its 1 x 1 result to `last` instead
+// of E when `last` is set.
+int enqueue_overlap(dcs_state* st, int id_a, int id_b, Operand E, Operand TX, void* last,
+                    hipStream_t s) {
+  const Layout& L = st->L;
+  const int ct = L.ct;
+  const Slot& A = st->slots[id_a];
+  const Slot& B = st->slots[id_b];
+  auto site = [&](int id, const Slot& sl, int j) {
+    return local_op(st->slot_base(id) + L.o_mps[sl.cur] + L.site_off[j], 0);
+  };
+  for (int j = 0; j < L.n; ++j) {
+    const int dla = A.dims[j], dra = A.dims[j + 1], dlb = B.dims[j], drb = B.dims[j + 1];
+    const Operand out = (last && j == L.n - 1) ? local_op(last, 0) : E;
+    if (j == 0) {   // E_1 = A_0^H B_0 (left bond of dimension 1)
+      std::vector<GemmJob> g{{site(id_a, A, 0), site(id_b, B, 0), out, nullptr, dra, drb, 2 * dla,
+                              dra, drb, drb, 1}};
+      DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, g, s, CLS_OTHER));
+    } else {        // TX = E_j B_j, E_{j+1} = A_j^H TX over (a, s)
+      std::vector<GemmJob> g1{{E, site(id_b, B, j), TX, nullptr, dla, 2 * drb, dlb, dlb, 2 * drb,
+                               2 * drb, 1}};
+      DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, g1, s, CLS_OTHER));
+      std::vector<GemmJob> g2{{site(id_a, A, j), TX, out, nullptr, dra, drb, 2 * dla, dra, drb, drb,
+                               1}};
+      DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, g2, s, CLS_OTHER));
+    }
+  }
+  return DCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int dcs_overlap(dcs_state* st, int id_a, int id_b, double* out, void* stream) {
   return guarded([&]() -> int {
     if (!st || !out) return fail(DCS_EINVAL, "null argument");
     const int pair[2] = {id_a, id_b};
     DCS_TRY(check_ids(st, id_a == id_b ? 1 : 2, pair, true));
     const Layout& L = st->L;
-    const int ct = L.ct;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Slot& A = st->slots[id_a];
-    const Slot& B = st->slots[id_b];
-    auto site = [&](int id, const Slot& sl, int j) {
-      return local_op(st->slot_base(id) + L.o_mps[sl.cur] + L.site_off[j], 0);
-    };
-    // left transfer E_j[a][b] over bonds j (bra a, ket b), FP64, in slot a's
-    // measurement scratch (its cached left transfer becomes invalid)
+    // left transfer in slot a's measurement scratch (its cached left
+    // transfer becomes invalid)
     const Operand E = local_op(st->slot_base(id_a) + L.o_e, 0);
     const Operand TX = local_op(st->slot_base(id_a) + L.o_tx, 0);
-    for (int j = 0; j < L.n; ++j) {
-      const int dla = A.dims[j], dra = A.dims[j + 1], dlb = B.dims[j], drb = B.dims[j + 1];
-      if (j == 0) {   // E_1 = A_0^H B_0 (left bond of dimension 1)
-        std::vector<GemmJob> g{{site(id_a, A, 0), site(id_b, B, 0), E, nullptr, dra, drb, 2 * dla,
-                                dra, drb, drb, 1}};
-        DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, g, s, CLS_OTHER));
-      } else {        // TX = E_j B_j, E_{j+1} = A_j^H TX over (a, s)
-        std::vector<GemmJob> g1{{E, site(id_b, B, j), TX, nullptr, dla, 2 * drb, dlb, dlb, 2 * drb,
-                                 2 * drb, 1}};
-        DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, g1, s, CLS_OTHER));
-        std::vector<GemmJob> g2{{site(id_a, A, j), TX, E, nullptr, dra, drb, 2 * dla, dra, drb, drb,
-                                 1}};
-        DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, g2, s, CLS_OTHER));
-      }
-    }
+    DCS_TRY(enqueue_overlap(st, id_a, id_b, E, TX, nullptr, s));
     double v[2];
     DCS_HIP(hipMemcpyAsync(v, st->slot_base(id_a) + L.o_e, sizeof(v), hipMemcpyDeviceToHost, s));
     DCS_HIP(hipStreamSynchronize(s));
@@ -2119,6 +2183,33 @@ int dcs_overlap(dcs_state* st, int id_a, int id_b, double* out, void* stream) {
     out[0] = v[0];
     out[1] = v[1];
     return DCS_OK;
+  });
+}
+
+int dcs_overlap_noalloc(dcs_state* st, int id_a, int id_b, double* out_dev, void* stream) {
+  return guarded([&]() -> int {
+    if (!st || !out_dev) return fail(DCS_EINVAL, "null argument");
+    const int pair[2] = {id_a, id_b};
+    DCS_TRY(check_ids(st, id_a == id_b ? 1 : 2, pair, true));
+    const Layout& L = st->L;
+    const Slot& A = st->slots[id_a];
+    const Slot& B = st->slots[id_b];
+    size_t e_need = 0, tx_need = 0;
+    for (int j = 0; j <= L.n; ++j) e_need = std::max(e_need, (size_t)A.dims[j] * B.dims[j] * 16);
+    for (int j = 0; j < L.n; ++j)
+      tx_need = std::max(tx_need, (size_t)A.dims[j] * 2 * B.dims[j + 1] * 16);
+    if (e_need > OVL_E_BYTES || tx_need > OVL_TX_BYTES)
+      return fail(DCS_ENOMEM, "dcs_overlap_noalloc: bond dimensions above 256 need " +
+                                  std::to_string(e_need + tx_need) + " bytes of scratch, the fixed "
+                                  "scratch holds " + std::to_string(OVL_SCRATCH_BYTES));
+    char* base = static_cast<char*>(scratch_ptr(st->ctx->device));
+    if (!base) return fail(DCS_ESTATE, "no scratch address for this device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st->ctx->no_alloc += 1;
+    const int rc = enqueue_overlap(st, id_a, id_b, local_op(base, 0),
+                                   local_op(base + OVL_E_BYTES, 0), out_dev, s);
+    st->ctx->no_alloc -= 1;
+    return rc;
   });
 }
 
