@@ -317,6 +317,96 @@ int dcs_export_mps(dcs_state *st, int id, double *host_out, size_t cap_doubles,
 int dcs_import_mps(dcs_state *st, int id, int chi_cap, const double *host_in,
                    const int *dims_in, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Tree tensor network (Sec. III-B, TTN paragraph: the paper's second ansatz,
+ * whose compression step it takes from the work it builds on).  Readings:
+ *   - structure (n_0 = 1, n_1, ..., n_L = n qubits), each level a proper
+ *     multiple of the previous one; nodes numbered in layer order (root 0);
+ *     the qubits are the leaves in order: leaf node i of layer L-1 holds
+ *     qubits i d .. i d + d - 1, d = n_L / n_{L-1};
+ *   - a node tensor's legs are [edge to the parent (dimension 1 at the root),
+ *     then its children's edges in order, or its qubits' physical legs in
+ *     order], row-major, complex interleaved; the edge above a node whose
+ *     subtree holds s qubits has the fixed, zero-padded dimension
+ *     min(chi, 2^s, 2^(n-s)) for bond cap chi;
+ *   - compression step: the starting guess is canonical towards the root;
+ *     a sweep walks from the root through every subtree and back (each edge
+ *     twice, children in order); every visited node becomes T = F/sqrt(<F|F>)
+ *     and the centre moves to the next node of the walk by a QR of T with the
+ *     edge towards that node as its column index (FP64); the last visit (the
+ *     root) keeps T and gives f = <F|F>;
+ *   - measurement: n_m = <psi|P_m|psi> contracted in FP64 from the leaves up;
+ *     collapse projects the qubit's leg in its leaf node and rescales by
+ *     1/sqrt(n_m).
+ * Two-qubit gates act on any two distinct qubits: a gate inside one leaf is
+ * part of that leaf's operator; a gate across leaves is split by an SVD of
+ * its operator-Schmidt matrix and its bond (rank r) is carried by every edge
+ * on the tree path between the two leaves (the edge's operator bond is the
+ * product of the ranks of the gates crossing it).  Precisions: DCS_C128 and
+ * DCS_C64 (contractions on FP32 MFMA, QR and measurement in FP64).  Memory,
+ * streams, errors and branch slots follow the MPS calls above. */
+typedef struct dcs_tree dcs_tree;
+typedef struct dcs_tchunk dcs_tchunk;
+
+/* Number of nodes of the tree with the given levels. */
+int dcs_tree_n_nodes(const int *levels, int n_levels, int *n_nodes_out);
+
+/* Bytes of device memory of a tree state: capacity branch slots, bond caps up
+ * to chi_max, operator bonds (per edge) up to mpo_bond_max, contraction
+ * intermediates of up to scratch_elems complex128-sized elements (from
+ * dcs_tree_chunk_scratch), n_init_slots registered starting guesses. */
+int dcs_tree_state_bytes(int precision, int n_levels, const int *levels, int capacity,
+                         int chi_max, int mpo_bond_max, size_t scratch_elems,
+                         int n_init_slots, size_t *bytes_out);
+int dcs_tree_create(dcs_ctx *ctx, dcs_tree **out, int precision, int n_levels,
+                    const int *levels, int capacity, int chi_max, int mpo_bond_max,
+                    size_t scratch_elems, int n_init_slots, void *d_buffer, size_t bytes,
+                    void *stream);
+int dcs_tree_destroy(dcs_tree *t);
+
+/* Starting guess for bond cap chi_cap: `gauss` holds a Gaussian tensor per
+ * node (node order, node layout for the padded dims of chi_cap, complex128
+ * interleaved).  From the deepest layer up, node v becomes the isometry of
+ * its QR with the upper edge as the column index and the R factor is
+ * absorbed into the parent's leg of v; the root is normalised.  Built in FP64
+ * in the state's buffer, stored in the path precision.  Synchronises. */
+int dcs_tree_set_init(dcs_tree *t, int chi_cap, const double *gauss, void *stream);
+
+/* Branch slots: |0...0> (every edge of dimension 1), bond caps, release. */
+int dcs_tree_branch_init_zero(dcs_tree *t, int n, const int *ids, const int *chi_caps,
+                              void *stream);
+int dcs_tree_branch_set_chi(dcs_tree *t, int n, const int *ids, const int *chi_caps);
+int dcs_tree_branch_release(dcs_tree *t, int n, const int *ids);
+
+/* Chunk (Sec. IV-C) compiled for the tree with the given levels: gates in time
+ * order as in dcs_chunk_compile.  Host-only. */
+int dcs_tree_chunk_compile(dcs_ctx *ctx, dcs_tchunk **out, int n_levels, const int *levels,
+                           int n_ops, const int *q0, const int *q1, const double *mats);
+int dcs_tchunk_destroy(dcs_tchunk *ch);
+/* Operator bond of the edge above each node (n_nodes ints, 1 at the root). */
+int dcs_tchunk_bonds(const dcs_tchunk *ch, int *w_out, int cap);
+/* Largest contraction intermediate (complex128-sized elements) of a
+ * compression step of this chunk from a ket of bond cap chi_ket into a bra
+ * of cap chi_bra, and of the measurements that follow.  Host-only. */
+int dcs_tree_chunk_scratch(const dcs_tchunk *ch, int chi_bra, int chi_ket, size_t *elems_out);
+
+/* Compression step (as dcs_compress_step) of the listed tree branches;
+ * fid_out[i] = f.  Synchronises. */
+int dcs_tree_compress_step(dcs_tree *t, int n, const int *ids, const dcs_tchunk *const *chunks,
+                           int n_sweeps, double *fid_out, void *stream);
+/* p0_out[i] = n_0 / (n_0 + n_1) of qubit qubits[i]; norms kept for the
+ * collapse.  Synchronises. */
+int dcs_tree_measure_prob(dcs_tree *t, int n, const int *ids, const int *qubits, double *p0_out,
+                          void *stream);
+/* As dcs_collapse. */
+int dcs_tree_collapse(dcs_tree *t, int n, const int *src_ids, const int *qubits,
+                      const int *outcomes, const int *dst_ids, double eps, double *pm_out,
+                      void *stream);
+/* FP64 host copy of a branch: node tensors in node order, node layout for the
+ * current edge dims (dims_out: the edge above each node, n_nodes ints). */
+int dcs_tree_export(dcs_tree *t, int id, double *host_out, size_t cap_doubles, int *dims_out,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,8 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdcs.so")
-SOURCES = ["gemm.hip", "gemm_bf16x3.hip", "kernels.hip", "embed.hip", "qr_large.hip", "runtime.cpp",
-           "testing.cpp"]
+SOURCES = ["gemm.hip", "gemm_bf16x3.hip", "kernels.hip", "embed.hip", "qr_large.hip", "permute.hip",
+           "runtime.cpp", "tree.cpp", "testing.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

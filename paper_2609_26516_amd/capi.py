@@ -33,6 +33,11 @@ EXPORTED = [
     "dcs_branch_dims", "dcs_chunk_compile", "dcs_gate_rank", "dcs_chunk_bonds", "dcs_chunk_export", "dcs_chunk_destroy",
     "dcs_compress_step", "dcs_measure_prob", "dcs_measure_sample_collapse", "dcs_collapse", "dcs_topk_by_weight", "dcs_prune_adaptive",
     "dcs_overlap", "dcs_overlap_noalloc", "dcs_export_mps", "dcs_import_mps",
+    "dcs_tree_n_nodes", "dcs_tree_state_bytes", "dcs_tree_create", "dcs_tree_destroy",
+    "dcs_tree_set_init", "dcs_tree_branch_init_zero", "dcs_tree_branch_set_chi",
+    "dcs_tree_branch_release", "dcs_tree_chunk_compile", "dcs_tchunk_destroy", "dcs_tchunk_bonds",
+    "dcs_tree_chunk_scratch", "dcs_tree_compress_step", "dcs_tree_measure_prob",
+    "dcs_tree_collapse", "dcs_tree_export",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
 
@@ -87,6 +92,24 @@ _SIGS = {
     "dcs_overlap_noalloc": (c_int, [_P, c_int, c_int, _P, _P]),
     "dcs_export_mps": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_import_mps": (c_int, [_P, c_int, c_int, _DP, _IP, _P]),
+    "dcs_tree_n_nodes": (c_int, [_IP, c_int, _IP]),
+    "dcs_tree_state_bytes": (c_int, [c_int, c_int, _IP, c_int, c_int, c_int, c_size_t, c_int,
+                                     POINTER(c_size_t)]),
+    "dcs_tree_create": (c_int, [_P, POINTER(c_void_p), c_int, c_int, _IP, c_int, c_int, c_int,
+                                c_size_t, c_int, _P, c_size_t, _P]),
+    "dcs_tree_destroy": (c_int, [_P]),
+    "dcs_tree_set_init": (c_int, [_P, c_int, _DP, _P]),
+    "dcs_tree_branch_init_zero": (c_int, [_P, c_int, _IP, _IP, _P]),
+    "dcs_tree_branch_set_chi": (c_int, [_P, c_int, _IP, _IP]),
+    "dcs_tree_branch_release": (c_int, [_P, c_int, _IP]),
+    "dcs_tree_chunk_compile": (c_int, [_P, POINTER(c_void_p), c_int, _IP, c_int, _IP, _IP, _DP]),
+    "dcs_tchunk_destroy": (c_int, [_P]),
+    "dcs_tchunk_bonds": (c_int, [_P, _IP, c_int]),
+    "dcs_tree_chunk_scratch": (c_int, [_P, c_int, c_int, POINTER(c_size_t)]),
+    "dcs_tree_compress_step": (c_int, [_P, c_int, _IP, POINTER(c_void_p), c_int, _DP, _P]),
+    "dcs_tree_measure_prob": (c_int, [_P, c_int, _IP, _IP, _DP, _P]),
+    "dcs_tree_collapse": (c_int, [_P, c_int, _IP, _IP, _IP, _IP, c_double, _DP, _P]),
+    "dcs_tree_export": (c_int, [_P, c_int, _DP, c_size_t, _IP, _P]),
     "dcs_test_gemm": (c_int, [c_int] * 11 + [_DP, _DP, _DP, _P]),
     "dcs_test_mpo": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
@@ -340,6 +363,120 @@ def dcs_import_mps(st, bid, chi_cap, sites, stream) -> None:
     flat = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).reshape(-1)
                            for a in sites]).view(np.float64)
     _check(_lib.dcs_import_mps(st, bid, chi_cap, _dp(flat), _ip(dims), stream))
+
+
+# --- tree tensor network -------------------------------------------------------
+
+def dcs_tree_n_nodes(levels) -> int:
+    lv = _ints(levels)
+    out = c_int()
+    _check(_lib.dcs_tree_n_nodes(_ip(lv), len(lv), ctypes.byref(out)))
+    return out.value
+
+
+def dcs_tree_state_bytes(precision, levels, capacity, chi_max, mpo_bond_max, scratch_elems,
+                         n_init_slots) -> int:
+    lv = _ints(levels)
+    out = c_size_t()
+    _check(_lib.dcs_tree_state_bytes(precision, len(lv), _ip(lv), capacity, chi_max, mpo_bond_max,
+                                     scratch_elems, n_init_slots, ctypes.byref(out)))
+    return out.value
+
+
+def dcs_tree_create(ctx, precision, levels, capacity, chi_max, mpo_bond_max, scratch_elems,
+                    n_init_slots, d_buffer: int, nbytes: int, stream: int) -> int:
+    lv = _ints(levels)
+    h = c_void_p()
+    _check(_lib.dcs_tree_create(ctx, ctypes.byref(h), precision, len(lv), _ip(lv), capacity,
+                                chi_max, mpo_bond_max, scratch_elems, n_init_slots, d_buffer,
+                                nbytes, stream))
+    return h.value
+
+
+def dcs_tree_destroy(t: int) -> None:
+    _check(_lib.dcs_tree_destroy(t))
+
+
+def dcs_tree_set_init(t: int, chi_cap: int, gauss: np.ndarray, stream: int) -> None:
+    g = np.ascontiguousarray(gauss, dtype=np.complex128).view(np.float64)
+    _check(_lib.dcs_tree_set_init(t, chi_cap, _dp(g), stream))
+
+
+def dcs_tree_branch_init_zero(t, ids, chi_caps, stream) -> None:
+    a, c = _ints(ids), _ints(chi_caps)
+    _check(_lib.dcs_tree_branch_init_zero(t, len(a), _ip(a), _ip(c), stream))
+
+
+def dcs_tree_branch_set_chi(t, ids, chi_caps) -> None:
+    a, c = _ints(ids), _ints(chi_caps)
+    _check(_lib.dcs_tree_branch_set_chi(t, len(a), _ip(a), _ip(c)))
+
+
+def dcs_tree_branch_release(t, ids) -> None:
+    a = _ints(ids)
+    _check(_lib.dcs_tree_branch_release(t, len(a), _ip(a)))
+
+
+def dcs_tree_chunk_compile(ctx, levels, q0, q1, mats: np.ndarray) -> int:
+    lv, a, b = _ints(levels), _ints(q0), _ints(q1)
+    m = np.ascontiguousarray(mats, dtype=np.complex128).view(np.float64)
+    h = c_void_p()
+    _check(_lib.dcs_tree_chunk_compile(ctx, ctypes.byref(h), len(lv), _ip(lv), len(a), _ip(a),
+                                       _ip(b), _dp(m)))
+    return h.value
+
+
+def dcs_tchunk_destroy(ch) -> None:
+    _check(_lib.dcs_tchunk_destroy(ch))
+
+
+def dcs_tchunk_bonds(ch, n_nodes) -> np.ndarray:
+    w = np.zeros(n_nodes, dtype=np.int32)
+    _check(_lib.dcs_tchunk_bonds(ch, _ip(w), n_nodes))
+    return w
+
+
+def dcs_tree_chunk_scratch(ch, chi_bra, chi_ket) -> int:
+    out = c_size_t()
+    _check(_lib.dcs_tree_chunk_scratch(ch, chi_bra, chi_ket, ctypes.byref(out)))
+    return out.value
+
+
+def dcs_tree_compress_step(t, ids, chunks, n_sweeps, stream) -> np.ndarray:
+    a = _ints(ids)
+    arr = (c_void_p * len(a))(*chunks)
+    f = np.zeros(len(a))
+    _check(_lib.dcs_tree_compress_step(t, len(a), _ip(a), arr, n_sweeps, _dp(f), stream))
+    return f
+
+
+def dcs_tree_measure_prob(t, ids, qubits, stream) -> np.ndarray:
+    a, q = _ints(ids), _ints(qubits)
+    p = np.zeros(len(a))
+    _check(_lib.dcs_tree_measure_prob(t, len(a), _ip(a), _ip(q), _dp(p), stream))
+    return p
+
+
+def dcs_tree_collapse(t, src_ids, qubits, outcomes, dst_ids, eps, stream) -> np.ndarray:
+    a, q, m, d = _ints(src_ids), _ints(qubits), _ints(outcomes), _ints(dst_ids)
+    pm = np.zeros(len(a))
+    _check(_lib.dcs_tree_collapse(t, len(a), _ip(a), _ip(q), _ip(m), _ip(d), eps, _dp(pm), stream))
+    return pm
+
+
+def dcs_tree_export(t, bid, shapes_of, n_nodes, cap_elems, stream):
+    """Node tensors of a branch; shapes_of(dims) gives each node's shape from
+    the edge dims the library reports."""
+    dims = np.zeros(n_nodes, dtype=np.int32)
+    buf = np.zeros(2 * cap_elems, dtype=np.float64)
+    _check(_lib.dcs_tree_export(t, bid, _dp(buf), len(buf), _ip(dims), stream))
+    flat = buf.view(np.complex128)
+    out, o = [], 0
+    for shp in shapes_of([int(x) for x in dims]):
+        e = int(np.prod(shp))
+        out.append(flat[o:o + e].reshape(shp).copy())
+        o += e
+    return out
 
 
 # --- kernel-level test entry points (include/dcs_testing.h) -----------------

@@ -174,6 +174,20 @@ hipError_t launch_sample_collapse(int ct, const SampleItem* items_dev, int n_ite
                                   const double* norms, const double* u, double eps, int* outcome,
                                   double* pm, hipStream_t s);
 
+// Batched transposition: output element o (row-major over dims[0..rank))
+// reads input element sum_k c_k in_stride[k] (c the output coordinates),
+// conjugated when conj, converted between the storage types of the launch.
+constexpr int PERMUTE_MAX_RANK = 12;
+struct PermuteArgs {
+  Operand in, out;
+  const int* ids;
+  int rank, conj, batch, pad_;
+  long long total;
+  int dims[PERMUTE_MAX_RANK];
+  long long in_stride[PERMUTE_MAX_RANK];
+};
+hipError_t launch_permute(int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s);
+
 // Writes (1, 0), (0, 0) as two complex words at each listed address.
 hipError_t launch_fill_unit(int ct, void* const* ptrs_dev, int n, hipStream_t s);
 

@@ -19,6 +19,7 @@
 
 #include "dcs.h"
 #include "dcs_internal.h"
+#include "runtime_shared.h"
 
 using namespace dcs;
 using cd = std::complex<double>;
@@ -389,11 +390,7 @@ Operand local_op(const void* base, long long stride) {
   return o;
 }
 
-struct GemmJob {
-  Operand a, b, c;
-  const int* ids;
-  int M, N, K, lda, ldb, ldc, batch;
-};
+using GemmJob = rt::GemmJob;
 
 int lg2_bucket(long long x) {
   int b = 0;
@@ -571,11 +568,7 @@ int run_mpo(dcs_ctx* ctx, int ct, int dir, const std::vector<MpoJob>& jobs, hipS
   return DCS_OK;
 }
 
-struct QrJob {
-  Operand f, q, ws, nrm2;
-  const int* ids;
-  int m, n, mode, batch;
-};
+using QrJob = rt::QrJob;
 
 // Path of a QR job: 0 blocked single-workgroup kernel, left-looking form
 // (m <= 512 or mode 2),
@@ -2289,3 +2282,65 @@ int dcs_import_mps(dcs_state* st, int id, int chi_cap, const double* host_in, co
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Runtime pieces shared with the tree-tensor-network entry points
+
+namespace dcs {
+namespace rt {
+
+int fail(int code, const std::string& msg) { return ::fail(code, msg); }
+
+int gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
+         const std::vector<GemmJob>& jobs, hipStream_t s, int cls) {
+  return run_gemm(ctx, ta, tb, tc, tacc, opa, opb, jobs, s, cls < 0 ? CLS_GEMM : cls);
+}
+
+int qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& jobs, hipStream_t s) {
+  return run_qr(ctx, ct_in, ct_out, jobs, s);
+}
+
+int permute(dcs_ctx* ctx, int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s) {
+  const double bytes = (double)a.total * a.batch * (csize_of(ct_in) + csize_of(ct_out));
+  Timed t(ctx, s, CLS_OTHER, 0.0, bytes);
+  DCS_HIP(launch_permute(ct_in, ct_out, a, s));
+  return DCS_OK;
+}
+
+void tune_sync(dcs_ctx* ctx) { tune_resolve(ctx); }
+
+int ctx_device(const dcs_ctx* ctx) { return ctx->device; }
+
+size_t qr_job_ws_elems(int m, int n, int mode) {
+  if (mode == 2) return 0;
+  const size_t mn = (size_t)m * n;
+  if (m <= qr_blocked_max_rows()) return mn + ((size_t)n / 16 + 2) * 256;
+  if (m <= qr_large_max_rows()) return std::max(mn + ((size_t)n / 16 + 2) * 256, qr_large_ws_elems(m, n));
+  return mn;
+}
+
+GateSplit split_gate(dcs_ctx* ctx, const double* m) {
+  const Split* spp = nullptr;
+  Split local;
+  if (ctx) {
+    const std::string key(reinterpret_cast<const char*>(m), 32 * sizeof(double));
+    auto it = ctx->split_cache.find(key);
+    if (it == ctx->split_cache.end()) {
+      if (ctx->split_cache.size() > 65536) ctx->split_cache.clear();
+      it = ctx->split_cache.emplace(key, ::split_gate(m)).first;
+    }
+    spp = &it->second;
+  } else {
+    local = ::split_gate(m);
+    spp = &local;
+  }
+  GateSplit g;
+  g.r = spp->r;
+  g.left = spp->left;
+  g.right = spp->right;
+  return g;
+}
+
+}  // namespace rt
+}  // namespace dcs
+

@@ -168,11 +168,185 @@ class State:
     def export(self, bid: int):
         return capi.dcs_export_mps(self.h, bid, self.n, self.chi_max, self.eng.stream())
 
+    # operations the drivers use (TreeState provides the same ones)
+    bond_rule = True            # chunks close before the MPS operator bond passes wmax
+
+    def chunk(self, circ: Circuit, op_ids: Sequence[int]) -> int:
+        return self.eng.chunk(circ, op_ids)
+
+    def init_zero(self, ids, chis) -> None:
+        capi.dcs_branch_init_zero(self.h, ids, chis, self.eng.stream())
+
+    def set_chi(self, ids, chis) -> None:
+        capi.dcs_branch_set_chi(self.h, ids, chis)
+
+    def compress(self, ids, chunks, n_sweeps: int) -> np.ndarray:
+        return capi.dcs_compress_step(self.h, ids, chunks, n_sweeps, self.eng.stream())
+
+    def measure(self, ids, qubits) -> np.ndarray:
+        return capi.dcs_measure_prob(self.h, ids, qubits, self.eng.stream())
+
+    def collapse(self, src, qubits, outcomes, dst, eps: float) -> np.ndarray:
+        return capi.dcs_collapse(self.h, src, qubits, outcomes, dst, eps, self.eng.stream())
+
     def close(self) -> None:
         if self.h:
             capi.dcs_state_destroy(self.h)
             self.h = 0
             self.buf = None
+
+
+class TreeTopology:
+    """Node numbering and shapes of a regular tree (levels n_0 = 1, ..., n_L =
+    n), as the library lays them out (dcs_tree_* in include/dcs.h): nodes in
+    layer order, leaves holding consecutive qubits, node legs [edge above,
+    children's edges or physical legs]."""
+
+    def __init__(self, levels: Sequence[int]):
+        self.levels = [int(x) for x in levels]
+        self.n, self.L = self.levels[-1], len(self.levels) - 1
+        self.kids: List[List[int]] = []
+        self.qn: List[int] = []
+        off = [sum(self.levels[:l]) for l in range(self.L)]
+        for l in range(self.L):
+            for i in range(self.levels[l]):
+                self.qn.append(self.n // self.levels[l])
+                if l + 1 < self.L:
+                    dk = self.levels[l + 1] // self.levels[l]
+                    self.kids.append([off[l + 1] + dk * i + c for c in range(dk)])
+                else:
+                    self.kids.append([])
+        self.N = len(self.kids)
+        self.d = self.levels[-1] // self.levels[-2]
+
+    def edges(self, chi: int) -> List[int]:
+        return [1 if v == 0 else min(chi, 2 ** self.qn[v], 2 ** (self.n - self.qn[v]))
+                for v in range(self.N)]
+
+    def shapes(self, e: Sequence[int]) -> List[tuple]:
+        return [(e[v], *([e[c] for c in self.kids[v]] if self.kids[v] else [2] * self.d))
+                for v in range(self.N)]
+
+
+class TreeState:
+    """Branch slots of a tree tensor network in a caller-owned device buffer
+    (dcs_tree_* calls); the drivers below run on it as on an MPS State.
+    Scratch for the contraction intermediates is sized from the circuit: the
+    largest need of any run of unitaries between measurements (every
+    controlled gate included) compressed into any of the bond caps."""
+
+    bond_rule = False
+
+    def __init__(self, eng: Engine, precision: str, levels: Sequence[int], capacity: int,
+                 chi_max: int, mpo_bond_max: int = 16, init_chis: Sequence[int] = (),
+                 init_seed: int = 7, circ: Optional[Circuit] = None, scratch_elems: int = 0):
+        if precision not in ("c128", "c64"):
+            raise ValueError("trees run in complex128 or complex64")
+        self.eng, self.capacity, self.chi_max = eng, capacity, chi_max
+        self.topo = TreeTopology(levels)
+        self.levels, self.n, self.wmax = self.topo.levels, self.topo.n, mpo_bond_max
+        self.precision = PRECISIONS[precision]
+        self._chunks: Dict[tuple, tuple] = {}
+        chis = sorted(set(init_chis)) or [chi_max]
+        if circ is not None:
+            for seg in _segments(circ):
+                h = self.chunk(circ, seg)
+                for c in chis:
+                    scratch_elems = max(scratch_elems,
+                                        capi.dcs_tree_chunk_scratch(h, c, chi_max))
+        scratch_elems = max(int(scratch_elems), 1)
+        self.scratch_elems = scratch_elems
+        nbytes = capi.dcs_tree_state_bytes(self.precision, self.levels, capacity, chi_max,
+                                           mpo_bond_max, scratch_elems, len(chis))
+        self.nbytes = nbytes
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{eng.device}")
+        self.ptr = (self.buf.data_ptr() + 255) // 256 * 256
+        self.h = capi.dcs_tree_create(eng.ctx, self.precision, self.levels, capacity, chi_max,
+                                      mpo_bond_max, scratch_elems, len(chis), self.ptr, nbytes,
+                                      eng.stream())
+        from inputs.randomness import gaussians_for_shapes
+        for chi in chis:
+            g = gaussians_for_shapes(self.topo.shapes(self.topo.edges(chi)), init_seed, 0x7EE)
+            flat = np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in g])
+            capi.dcs_tree_set_init(self.h, chi, flat, eng.stream())
+        self.free = list(range(capacity - 1, -1, -1))
+
+    def alloc(self, k: int = 1) -> List[int]:
+        if len(self.free) < k:
+            raise capi.DcsError(capi.DCS_ECAPACITY, "no free branch slot")
+        return [self.free.pop() for _ in range(k)]
+
+    def release(self, ids: Sequence[int]) -> None:
+        if len(ids):
+            capi.dcs_tree_branch_release(self.h, ids)
+            self.free.extend(int(i) for i in ids)
+
+    def reset(self) -> None:
+        capi.dcs_tree_branch_release(self.h, list(range(self.capacity)))
+        self.free = list(range(self.capacity - 1, -1, -1))
+
+    def export(self, bid: int):
+        cap = sum(int(np.prod(s)) for s in self.topo.shapes(self.topo.edges(self.chi_max)))
+        return capi.dcs_tree_export(self.h, bid, self.topo.shapes, self.topo.N, cap,
+                                    self.eng.stream())
+
+    def chunk(self, circ: Circuit, op_ids: Sequence[int]) -> int:
+        key = (id(circ), tuple(op_ids))
+        hit = self._chunks.get(key)
+        if hit is not None and hit[0] is circ:
+            return hit[1]
+        q0, q1, mats = [], [], []
+        for i in op_ids:
+            g = _gate_of(circ.ops[i])
+            q0.append(g.qubits[0])
+            q1.append(g.qubits[1] if len(g.qubits) == 2 else -1)
+            mats.append(np.asarray(g.mat, dtype=np.complex128).reshape(-1))
+        h = capi.dcs_tree_chunk_compile(self.eng.ctx, self.levels, q0, q1,
+                                        np.concatenate(mats) if mats else np.zeros(0, complex))
+        if hit is not None:
+            capi.dcs_tchunk_destroy(hit[1])
+        self._chunks[key] = (circ, h)
+        return h
+
+    def init_zero(self, ids, chis) -> None:
+        capi.dcs_tree_branch_init_zero(self.h, ids, chis, self.eng.stream())
+
+    def set_chi(self, ids, chis) -> None:
+        capi.dcs_tree_branch_set_chi(self.h, ids, chis)
+
+    def compress(self, ids, chunks, n_sweeps: int) -> np.ndarray:
+        return capi.dcs_tree_compress_step(self.h, ids, chunks, n_sweeps, self.eng.stream())
+
+    def measure(self, ids, qubits) -> np.ndarray:
+        return capi.dcs_tree_measure_prob(self.h, ids, qubits, self.eng.stream())
+
+    def collapse(self, src, qubits, outcomes, dst, eps: float) -> np.ndarray:
+        return capi.dcs_tree_collapse(self.h, src, qubits, outcomes, dst, eps, self.eng.stream())
+
+    def close(self) -> None:
+        for _, h in self._chunks.values():
+            capi.dcs_tchunk_destroy(h)
+        self._chunks.clear()
+        if self.h:
+            capi.dcs_tree_destroy(self.h)
+            self.h = 0
+            self.buf = None
+
+
+def _segments(circ: Circuit) -> List[List[int]]:
+    """Operation indices of every maximal run of unitaries (gates and
+    controlled gates) between measurements."""
+    out, cur = [], []
+    for li, op in enumerate(circ.ops):
+        if isinstance(op, Measure):
+            if cur:
+                out.append(cur)
+            cur = []
+        else:
+            cur.append(li)
+    if cur:
+        out.append(cur)
+    return out
 
 
 def _bond_rule_active(eng: Engine, circ: Circuit, wmax: int) -> bool:
@@ -258,9 +432,11 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
                              device=dev)
         m_dev = torch.empty(u_dev.shape, dtype=torch.int32, device=dev)
         pm_dev = torch.empty(u_dev.shape, dtype=torch.float64, device=dev)
-    rule = _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
+    if device_sampling and not st.bond_rule:
+        raise ValueError("device sampling is an MPS option")
+    rule = st.bond_rule and _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
     ids = np.array(st.alloc(shots), dtype=np.int32)
-    capi.dcs_branch_init_zero(st.h, ids, np.full(shots, chi), stream)
+    st.init_zero(ids, np.full(shots, chi))
     regs = np.zeros((shots, max(circ.n_bits, 1)), dtype=np.int8)
     p = np.ones(shots)
     fid = np.ones(shots)
@@ -272,8 +448,8 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
     def compress(sel: np.ndarray) -> None:
         if len(sel) == 0:
             return
-        hs = [eng.chunk(circ, chunk[s]) for s in sel]
-        f = capi.dcs_compress_step(st.h, ids[sel], hs, n_sweeps, stream)
+        hs = [st.chunk(circ, chunk[s]) for s in sel]
+        f = st.compress(ids[sel], hs, n_sweeps)
         fid[sel] *= f
         f_all = np.full(shots, np.nan)
         f_all[sel] = f
@@ -287,7 +463,7 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
             up = [s for s, fv in zip(sel, f) if fv < f_target and rung[s] + 1 < len(chi_ladder)]
             if up:
                 rung[up] += 1
-                capi.dcs_branch_set_chi(st.h, ids[up], [chi_ladder[rung[s]] for s in up])
+                st.set_chi(ids[up], [chi_ladder[rung[s]] for s in up])
 
     try:
         for li, op in enumerate(circ.ops):
@@ -304,12 +480,12 @@ def run_single_path(eng: Engine, st: State, circ: Circuit, shots: int, chi: int,
                         raise capi.DcsError(capi.DCS_ENUMERIC, "state norm vanished")
                     p0 = np.full(shots, np.nan)
                 else:
-                    p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+                    p0 = st.measure(ids, q)
                     if outcomes is not None:
                         m = np.asarray(outcomes[:, i_meas], dtype=np.int32)
                     else:
                         m = (uniforms[:, i_meas] >= p0).astype(np.int32)
-                    pm = capi.dcs_collapse(st.h, ids, q, m, ids, EPS_BRANCH, stream)
+                    pm = st.collapse(ids, q, m, ids, EPS_BRANCH)
                 p *= pm
                 regs[:, op.bit] = m
                 rec_out.append(m.copy())
@@ -365,10 +541,9 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
             raise ValueError("chi_ladder and chi_of are exclusive")
         if chi_ladder[0] != chi or any(a >= b for a, b in zip(chi_ladder, chi_ladder[1:])):
             raise ValueError("chi_ladder must ascend from chi")
-    stream = eng.stream()
-    rule = _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
+    rule = st.bond_rule and _bond_rule_active(eng, circ, st.wmax)   # raises before any slot is taken
     first = st.alloc(1)[0]
-    capi.dcs_branch_init_zero(st.h, [first], [chi], stream)
+    st.init_zero([first], [chi])
     new_bonds = (lambda: _Bonds(eng, circ, st.wmax, 1)) if rule else (lambda: None)  # noqa: E731
     one = np.zeros(1, dtype=np.int64)
     br = [{"id": first, "path": (), "p": 1.0, "c": np.zeros(max(circ.n_bits, 1), np.int8),
@@ -379,8 +554,8 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
     def compress(sel: List[dict]) -> None:
         if not sel:
             return
-        hs = [eng.chunk(circ, b["chunk"]) for b in sel]
-        f = capi.dcs_compress_step(st.h, [b["id"] for b in sel], hs, n_sweeps, stream)
+        hs = [st.chunk(circ, b["chunk"]) for b in sel]
+        f = st.compress([b["id"] for b in sel], hs, n_sweeps)
         up = []
         for b, fv in zip(sel, f):
             b["F"] *= float(fv)
@@ -393,7 +568,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 b["chi"] = chi_ladder[b["rung"]]
                 up.append(b)
         if up:
-            capi.dcs_branch_set_chi(st.h, [b["id"] for b in up], [b["chi"] for b in up])
+            st.set_chi([b["id"] for b in up], [b["chi"] for b in up])
 
     # slots this run holds: the live branches plus children allocated before
     # they join them; all are released if anything below raises
@@ -415,7 +590,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                 compress([b for b in br if b["chunk"]])
                 ids = [b["id"] for b in br]
                 q = [op.qubit] * len(br)
-                p0 = capi.dcs_measure_prob(st.h, ids, q, stream)
+                p0 = st.measure(ids, q)
                 src, dst, outc, qq, kids = [], [], [], [], []
                 for b, pz in zip(br, p0):
                     opts = [m for m, pm in ((0, pz), (1, 1.0 - pz)) if pm > eps]
@@ -426,7 +601,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                         outc.append(m)
                         qq.append(op.qubit)
                         kids.append((b, m, did, float(pz)))
-                pm = capi.dcs_collapse(st.h, src, qq, outc, dst, eps, stream)
+                pm = st.collapse(src, qq, outc, dst, eps)
                 nxt = []
                 for (b, m, did, pz), pmv in zip(kids, pm):
                     c = b["c"].copy()
@@ -438,7 +613,7 @@ def run_multi_path(eng: Engine, st: State, circ: Circuit, chi: int, k: int, n_sw
                                 "w": new_bonds()})
                 br = nxt
                 if chi_of is not None:
-                    capi.dcs_branch_set_chi(st.h, [b["id"] for b in br], [b["chi"] for b in br])
+                    st.set_chi([b["id"] for b in br], [b["chi"] for b in br])
                 if prune is not None or (max_branches is not None and len(br) > max_branches):
                     if prune is not None:
                         keep, disc = capi.dcs_prune_adaptive([b["p"] for b in br],

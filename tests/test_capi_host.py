@@ -193,3 +193,47 @@ def test_library_makes_no_device_allocation():
         txt = re.sub(r"//[^\n]*|/\*.*?\*/", "", open(path).read(), flags=re.S)
         for call in ("hipMalloc(", "hipFree(", "hipMallocAsync(", "hipExtMallocWithFlags("):
             assert call not in txt, (path, call)
+
+
+def test_tree_topology_matches_the_oracle_numbering():
+    """The driver's tree layout (node order, shapes for a bond cap) is the one
+    the FP64 tree oracle uses, and the library counts the same nodes."""
+    from oracle import ttn as OT
+    from paper_2609_26516_amd import capi
+    from paper_2609_26516_amd.engine import TreeTopology
+    for levels in ([1, 2, 4], [1, 3, 9], [1, 2, 4, 8], [1, 3, 9, 27], [1, 2, 8]):
+        tr, tp = OT.Tree(levels), TreeTopology(levels)
+        assert tp.N == tr.n_nodes == capi.dcs_tree_n_nodes(levels)
+        for chi in (1, 2, 4, 32, 1024):
+            assert tp.shapes(tp.edges(chi)) == [tr.shape(v, chi) for v in range(tr.n_nodes)]
+
+
+def test_tree_chunk_bonds_and_scratch():
+    """Operator bond of every tree edge: the product of the operator-Schmidt
+    ranks of the gates whose leaves lie on both sides of it; a gate inside one
+    leaf adds none.  The contraction scratch grows with the bond caps."""
+    from oracle import mps as OM
+    from paper_2609_26516_amd import capi
+    rng = np.random.default_rng(3)
+    levels = [1, 3, 9]            # root 0, leaves 1, 2, 3 with qubits 0-2, 3-5, 6-8
+    gates = [((2, 3), C.haar_unitary(rng, 4)),    # leaf 1 - leaf 2
+             ((4, 5), C.haar_unitary(rng, 4)),    # inside leaf 2
+             ((8, 0), C.CNOT_01),                 # leaf 3 - leaf 1, reversed order
+             ((7,), C.H)]
+    mats = np.concatenate([np.asarray(m, complex).reshape(-1) for _, m in gates])
+    q0 = [g[0][0] for g in gates]
+    q1 = [g[0][1] if len(g[0]) == 2 else -1 for g in gates]
+    ch = capi.dcs_tree_chunk_compile(None, levels, q0, q1, mats)
+    w = capi.dcs_tchunk_bonds(ch, 4)
+    r0, r2 = OM.gate_rank(gates[0][1]), OM.gate_rank(gates[2][1])
+    assert (r0, r2) == (4, 2)
+    np.testing.assert_array_equal(w, [1, r0 * r2, r0, r2])
+    s4 = capi.dcs_tree_chunk_scratch(ch, 4, 4)
+    s8 = capi.dcs_tree_chunk_scratch(ch, 8, 8)
+    assert 0 < s4 < s8
+    capi.dcs_tchunk_destroy(ch)
+    with pytest.raises(capi.DcsError) as e:
+        capi.dcs_tree_chunk_compile(None, levels, [1], [1], np.eye(4, dtype=complex).reshape(-1))
+    assert e.value.code == capi.DCS_EQUBITS
+    with pytest.raises(capi.DcsError):
+        capi.dcs_tree_n_nodes([1, 3, 8])

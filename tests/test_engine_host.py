@@ -27,6 +27,31 @@ class _FakeState:
             self.live.discard(int(i))
             self.free.append(int(i))
 
+    # the driver-facing operations, routed to the (replaced) library calls
+    bond_rule = True
+
+    def _capi(self):
+        from paper_2609_26516_amd import capi
+        return capi
+
+    def chunk(self, circ, op_ids):
+        return 1
+
+    def init_zero(self, ids, chis):
+        self._capi().dcs_branch_init_zero(self.h, ids, chis, 0)
+
+    def set_chi(self, ids, chis):
+        self._capi().dcs_branch_set_chi(self.h, ids, chis)
+
+    def compress(self, ids, chunks, n_sweeps):
+        return self._capi().dcs_compress_step(self.h, ids, chunks, n_sweeps, 0)
+
+    def measure(self, ids, qubits):
+        return self._capi().dcs_measure_prob(self.h, ids, qubits, 0)
+
+    def collapse(self, src, qubits, outcomes, dst, eps):
+        return self._capi().dcs_collapse(self.h, src, qubits, outcomes, dst, eps, 0)
+
 
 class _FakeEngine:
     def stream(self):

@@ -1,0 +1,123 @@
+"""Tree tensor network on the GPU (dcs_tree_* through the C ABI) against the
+FP64 tree oracle (oracle/ttn.py, pinned by the statevector, the direct
+overlap and every edge's Schmidt bound): single-path runs of seeded brickwork
+dynamic circuits with the oracle's outcomes replayed, and multi-path runs
+with top-M and per-child bond caps, on the trees [1, 2, 4, 8] and [1, 3, 9]
+in the exact and the truncated regime.
+
+Tolerances as for the MPS path: complex128 1e-9 (rounding of the same
+algorithm); complex64 1e-6 on every probability and on the state-fidelity
+error 1 - |<gpu|oracle>|^2, 1e-5 on one partial fidelity and 1e-4 on a run's
+product of them."""
+import numpy as np
+import pytest
+
+from inputs import circuits as C
+from inputs.randomness import branch_chi_draw, shot_uniforms
+from oracle import dynamic as OD
+from oracle import ttn as OT
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-9, "c64": 1e-6}
+RUN_F_TOL = {"c128": 1e-9, "c64": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_26516_amd import engine as E
+    e = E.Engine(0)
+    yield e
+    e.close()
+
+
+def _E():
+    from paper_2609_26516_amd import engine as E
+    return E
+
+
+def _fid_err(tree, a, b):
+    va, vb = OT.to_statevector(tree, a), OT.to_statevector(tree, b)
+    return abs(1 - abs(np.vdot(va, vb)) ** 2 / (np.vdot(va, va).real * np.vdot(vb, vb).real))
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("levels,chi,depth", [
+    ([1, 2, 4, 8], 16, 6),     # exact regime
+    ([1, 2, 4, 8], 4, 8),      # truncated
+    ([1, 3, 9], 8, 6),         # 3 children per node, truncated at the root's edges
+    ([1, 3, 9], 3, 6),         # truncated everywhere
+])
+def test_tree_single_path_against_oracle(eng, prec, levels, chi, depth):
+    n = levels[-1]
+    circ, prm = C.workload("cfg1_n10_chi16", n=n, depth=depth, chi=chi)
+    k = C.segment_max(circ)
+    u = shot_uniforms(prm["seed"], 0, circ.n_measurements())
+    tree = OT.Tree(levels)
+    ref = OD.run_single_path(circ, OD.Simulator(n, chi, k, 2, prm["init_seed"], tree=levels),
+                             uniforms=u)
+    st = _E().TreeState(eng, prec, levels, 2, chi, 16, [chi], prm["init_seed"], circ=circ)
+    r = _E().run_single_path(eng, st, circ, 1, chi, k, 2,
+                             outcomes=np.array([ref["outcomes"]], dtype=np.int32))
+    got = st.export(int(r["ids"][0]))
+    st.close()
+    dp = np.max(np.abs(np.array(ref["p0s"]) - r["p0s"][0]))
+    fe = _fid_err(tree, got, ref["mps"])
+    print(f"{levels} chi {chi} {prec}: max |dp| {dp:.2e}, fidelity error {fe:.2e}, "
+          f"F {r['F'][0]:.6f} vs {ref['F']:.6f}")
+    assert dp <= TOL[prec]
+    assert fe <= TOL[prec]
+    assert abs(r["F"][0] - ref["F"]) <= RUN_F_TOL[prec]
+    assert [c for c in r["chis"][0]] == ref["chis"]
+    if chi >= 2 ** (n // 2):
+        assert abs(ref["F"] - 1) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_tree_multi_path_uneven_chi_against_oracle(eng, prec):
+    levels = [1, 3, 9]
+    n = 9
+    circ, prm = C.workload("cfg3_n32_mp64", n=n, depth=6, chi=8)
+    choices = (2, 3, 4, 6, 8)
+    chi_of = lambda path: branch_chi_draw(prm["seed"], path, choices)  # noqa: E731
+    k = C.segment_max(circ)
+    ref = OD.run_multi_path(circ, OD.Simulator(n, 8, k, 2, prm["init_seed"], tree=levels),
+                            max_branches=5, chi_of=chi_of)
+    st = _E().TreeState(eng, prec, levels, 12, 8, 16, list(choices) + [8], prm["init_seed"],
+                        circ=circ)
+    res = _E().run_multi_path(eng, st, circ, 8, k, 2, max_branches=5, chi_of=chi_of)
+    got = {b["path"]: b for b in res["branches"]}
+    want = {b["path"]: b for b in ref["branches"]}
+    assert set(got) == set(want)
+    tree = OT.Tree(levels)
+    nm = circ.n_measurements()
+    for pth, b in want.items():
+        g = got[pth]
+        assert np.max(np.abs(np.array(g["p0s"]) - np.array(b["p0s"]))) <= TOL[prec]
+        assert abs(g["p"] - b["p"]) <= nm * TOL[prec]
+        assert abs(g["F"] - b["F"]) <= RUN_F_TOL[prec]
+        assert g["chis"] == b["chis"]
+        assert _fid_err(tree, st.export(g["id"]), b["mps"]) <= TOL[prec]
+    assert abs(res["dropped"] - ref["dropped"]) <= len(want) * nm * TOL[prec]
+    st.close()
+
+
+def test_tree_chunk_over_the_operator_bond_is_refused(eng):
+    """A chunk whose operator bond on some edge exceeds the state's maximum is
+    rejected before any work."""
+    from paper_2609_26516_amd import capi
+    levels = [1, 2, 4]
+    st = _E().TreeState(eng, "c128", levels, 1, 4, 4, [4], 3, scratch_elems=1 << 16)
+    rng = np.random.default_rng(2)
+    gates = [((1, 2), C.haar_unitary(rng, 4)), ((0, 3), C.haar_unitary(rng, 4))]
+    mats = np.concatenate([np.asarray(m).reshape(-1) for _, m in gates])
+    ch = capi.dcs_tree_chunk_compile(eng.ctx, levels, [1, 0], [2, 3], mats)
+    st.init_zero([0], [4])
+    with pytest.raises(capi.DcsError) as e:
+        st.compress([0], [ch], 2)
+    assert e.value.code == capi.DCS_ENOMEM
+    capi.dcs_tchunk_destroy(ch)
+    st.close()
