@@ -33,6 +33,7 @@ SINGLE_PATH = {"sp40": "cfg2_n40_chi256", "sp24": "cfg4_n24_chi64_x1024",
                "sp10": "cfg1_n10_chi16"}
 MULTI_PATH = {"mp32": "cfg3_n32_mp64"}
 LARGE_CHI = {"sp60": "cfg5_n60_chi1024"}
+TREE = {"tt27": "ttn27_chi32"}
 PEAK = {"c64": (157.3, "fp32 dense MFMA"), "c128": (78.6, "fp64 dense MFMA"),
         "bf16x3": (2500.0 / 3.0, "bf16 dense MFMA / 3 products per real product")}
 HBM_PEAK_GBS = 8000.0
@@ -361,6 +362,96 @@ def _oracle_shot_sample(rounds: int):
     return t_rounds, t_final
 
 
+def tree_overlap(topo, a, b) -> complex:
+    """<a|b> of two tree states (node tensors in node order) by contraction
+    from the leaves up: E_v = conj(A_v) B_v over v's lower legs, the children's
+    E's inserted."""
+    E = [None] * topo.N
+    for v in reversed(range(topo.N)):
+        x = b[v]
+        for i, c in enumerate(topo.kids[v]):
+            # replace lower leg i + 1 (ket index) by the bra index through E_c
+            x = np.moveaxis(np.tensordot(E[c], x, axes=([1], [i + 1])), 0, i + 1)
+        lower = tuple(range(1, a[v].ndim))
+        E[v] = np.tensordot(a[v].conj(), x, axes=(lower, lower))
+    return complex(E[0].reshape(-1)[0])
+
+
+def run_gpu_tree(prec: str, shots: int, steps: int, warmup: int, timing: bool, workload: str,
+                 sampled=(), outcomes=None):
+    """Single-path shots on the tree tensor network state: W warm-up steps, K
+    timed steps without instrumentation, one instrumented step with timing;
+    `outcomes` replays given outcome rows instead of sampling (one step)."""
+    import torch
+    from inputs import circuits as C
+    from inputs.randomness import shot_uniforms
+    from paper_2609_26516_amd import engine as E
+
+    circ, prm = C.workload(workload)
+    chi, levels = prm["chi"], prm["tree"]
+    k = C.segment_max(circ) + 1
+    eng = E.Engine(0)
+    eng.tuning(TUNE["enabled"])
+    st = E.TreeState(eng, prec, levels, shots, chi, 16, [chi], prm["init_seed"], circ=circ)
+    nm = circ.n_measurements()
+    samples = {}
+
+    def one_step(step, export=False):
+        if outcomes is not None:
+            res = E.run_single_path(eng, st, circ, shots, chi, k, 2, outcomes=outcomes)
+        else:
+            u = np.stack([shot_uniforms(prm["seed"], step * shots + s, nm) for s in range(shots)])
+            res = E.run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
+        if export:
+            for s in sampled:
+                samples[s] = {"outcomes": res["outcomes"][s].copy(), "p0s": res["p0s"][s].copy(),
+                              "F": float(res["F"][s]), "state": st.export(int(res["ids"][s]))}
+        st.release(res["ids"])
+        return res
+
+    for w in range(warmup):
+        one_step(10_000 + w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        one_step(s, export=(s == steps - 1 and not timing))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = None
+    if timing:
+        eng.timing(True)
+        eng.timing_stats(reset=True)
+        one_step(steps, export=True)
+        torch.cuda.synchronize()
+        stats = eng.timing_stats(reset=True)
+        eng.timing(False)
+    topo = st.topo
+    st.close()
+    eng.close()
+    return dt, stats, samples, topo
+
+
+def tree_precision_vs_fp64(workload: str, samples: dict):
+    """Sampled complex64 tree shots against the complex128 tree path replaying
+    their outcomes: every p_0 and the state-fidelity error from the FP64
+    overlap of the exported states."""
+    shots = sorted(samples)
+    outs = np.stack([samples[s]["outcomes"] for s in shots])
+    _, _, ref, topo = run_gpu_tree("c128", len(shots), 1, 0, False, workload,
+                                   sampled=range(len(shots)), outcomes=outs)
+    dp, fe = [], []
+    for i, s in enumerate(shots):
+        a, b = samples[s]["state"], ref[i]["state"]
+        ov = tree_overlap(topo, a, b)
+        na, nb = tree_overlap(topo, a, a).real, tree_overlap(topo, b, b).real
+        fe.append(float(abs(1 - abs(ov) ** 2 / (na * nb))))
+        dp.append(float(np.max(np.abs(samples[s]["p0s"] - ref[i]["p0s"]))))
+    return {"reference": "GPU FP64 tree path (complex128) replaying the outcomes",
+            "shots": shots, "max_abs_probability_error": max(dp),
+            "state_fidelity_error": max(fe),
+            "targets": {"max_abs_probability_error": 1e-6, "state_fidelity_error": 1e-6}}
+
+
 def cpu_baseline(rounds: int, rounds_multi: int):
     """The oracle timed in this process on a bounded sample of one shot (first
     rounds plus the final compression), scaled to a whole shot: 10 rounds and
@@ -427,7 +518,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="sp40",
-                    choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH) + sorted(LARGE_CHI))
+                    choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH) + sorted(LARGE_CHI)
+                    + sorted(TREE))
     ap.add_argument("--graphs", action="store_true",
                     help="replay recurring compression steps from HIP graphs (no per-kernel timing)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -468,6 +560,34 @@ def main():
                              "steps": 1, "warmup": 0,
                              "note": "one replay shot on a fresh engine (tile tuning included)"},
                "precision_vs_fp64": cmp}
+        print(json.dumps(out))
+        return
+    if args.workload in TREE:
+        wl = TREE[args.workload]
+        shots = args.shots if args.shots != 256 else 64
+        dt, stats, samples, _ = run_gpu_tree("c64", shots, args.steps, args.warmup, True, wl,
+                                             sampled=(0, shots - 1))
+        out = {"metric": "shots/s (tree tensor network [1,3,9,27], chi=32, FP32-MFMA form)",
+               "value": round(shots * args.steps / dt, 4), "unit": "shots/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": round(1e3 * dt / args.steps, 2), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+               "data": "synthetic: seeded Haar brickwork dynamic circuit",
+               "config": {"workload": wl, "shots_per_step": shots, "tree": [1, 3, 9, 27],
+                          "chi": 32},
+               "roofline": roofline(stats, "c64", names={
+                   "gemm_nn": "gemm_kernel (tree contractions, A B)",
+                   "gemm_nt": "gemm_kernel (tree contractions, A B^T)",
+                   "gemm_cn": "gemm_kernel (tree contractions, A^H B)",
+                   "gemm_jt": "gemm_kernel (tree contractions, conj(A) B^T)",
+                   "qr": "qr_left_kernel / qrl_* (node QR)",
+                   "other": "permute_kernel (leg transpositions)"}),
+               "precision_vs_fp64": tree_precision_vs_fp64(wl, samples)}
+        if not args.no_fp64:
+            dt64, _, _, _ = run_gpu_tree("c128", shots, args.fp64_steps, args.warmup, False, wl)
+            out["fp64_path"] = {"value": round(shots * args.fp64_steps / dt64, 4),
+                                "unit": "shots/s", "steps": args.fp64_steps,
+                                "warmup": args.warmup, "dtype": "c128"}
         print(json.dumps(out))
         return
     if args.workload in MULTI_PATH:

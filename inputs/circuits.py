@@ -279,6 +279,13 @@ WORKLOADS = {
     "cfg5_n60_chi1024": dict(n=60, depth=24, layers_per_round=3, meas_per_round=1,
                              feedforward="x_right", meas_range=None, chi=1024, seed=5001,
                              mode="single", shots=1, precision="bf16x3", init_seed=35),
+    # tree tensor network [1, 3, 9, 27] at bond cap 32 (the tree and cap of the
+    # paper's tree runs on 27 qubits), seeded brickwork standing in for its
+    # random dynamic circuits
+    "ttn27_chi32": dict(n=27, depth=8, layers_per_round=2, meas_per_round=2,
+                        feedforward="x_right", meas_range=None, chi=32, seed=6001,
+                        mode="single", shots=64, precision="c64", init_seed=42,
+                        tree=(1, 3, 9, 27)),
 }
 
 

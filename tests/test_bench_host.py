@@ -46,3 +46,13 @@ def test_traffic_guard_matches_sources():
     t = bench.measured_traffic("qr")
     assert t is None or 1e9 < t < 1e11
     assert bench.measured_traffic("no such class") is None
+
+
+def test_tree_overlap_is_the_state_vector_overlap():
+    from oracle import ttn as OT
+    from paper_2609_26516_amd.engine import TreeTopology
+    for lv in ([1, 3, 9], [1, 2, 4, 8]):
+        tr, tp = OT.Tree(lv), TreeTopology(lv)
+        a, b = OT.generic_bra(tr, 4, 1), OT.generic_bra(tr, 4, 2)
+        b = [x * (1 + 0.3j) if i == 0 else x for i, x in enumerate(b)]
+        assert abs(bench.tree_overlap(tp, a, b) - OT.overlap(tr, a, b)) < 1e-14

@@ -121,3 +121,54 @@ def test_tree_chunk_over_the_operator_bond_is_refused(eng):
     assert e.value.code == capi.DCS_ENOMEM
     capi.dcs_tchunk_destroy(ch)
     st.close()
+
+
+def _tree_overlap(topo, a, b):
+    """<a|b> by contraction from the leaves up (no state vector)."""
+    E = [None] * topo.N
+    for v in reversed(range(topo.N)):
+        x = b[v]
+        for i, c in enumerate(topo.kids[v]):
+            x = np.moveaxis(np.tensordot(E[c], x, axes=([1], [i + 1])), 0, i + 1)
+        lower = tuple(range(1, a[v].ndim))
+        E[v] = np.tensordot(a[v].conj(), x, axes=(lower, lower))
+    return complex(E[0].reshape(-1)[0])
+
+
+def test_tree_27_qubits_chi_32_complex64_against_complex128(eng):
+    """The 27-qubit [1, 3, 9, 27] bond-cap-32 workload in its benchmark launch
+    configuration (64 complex64 shots in one batch): the first and the last
+    shot replayed by the complex128 tree path (itself held to the oracle at
+    1e-9 on every smaller tree above); the oracle's brute-force environments
+    cannot reach 27 qubits."""
+    from inputs.randomness import shot_uniforms as su
+    circ, prm = C.workload("ttn27_chi32")
+    levels, chi, shots = list(prm["tree"]), prm["chi"], 64
+    k = C.segment_max(circ) + 1
+    nm = circ.n_measurements()
+    u = np.stack([su(prm["seed"], s, nm) for s in range(shots)])
+    E = _E()
+    st = E.TreeState(eng, "c64", levels, shots, chi, 16, [chi], prm["init_seed"], circ=circ)
+    r = E.run_single_path(eng, st, circ, shots, chi, k, 2, uniforms=u)
+    picked = (0, shots - 1)
+    got = {s: st.export(int(r["ids"][s])) for s in picked}
+    topo = st.topo
+    st.close()
+    assert np.all(r["p0s"] >= 0) and np.all(r["p0s"] <= 1)
+    assert np.all(r["F"] > 0) and np.all(r["F"] <= 1 + 1e-9)
+    st = E.TreeState(eng, "c128", levels, 2, chi, 16, [chi], prm["init_seed"], circ=circ)
+    r2 = E.run_single_path(eng, st, circ, 2, chi, k, 2, outcomes=r["outcomes"][list(picked)])
+    for i, s in enumerate(picked):
+        ref = st.export(int(r2["ids"][i]))
+        ov = _tree_overlap(topo, got[s], ref)
+        na, nb = _tree_overlap(topo, got[s], got[s]).real, _tree_overlap(topo, ref, ref).real
+        fe = abs(1 - abs(ov) ** 2 / (na * nb))
+        dp = np.max(np.abs(r["p0s"][s] - r2["p0s"][i]))
+        print(f"shot {s}: max |dp| {dp:.2e}, fidelity error {fe:.2e}, "
+              f"F {r['F'][s]:.6f} vs {r2['F'][i]:.6f}")
+        assert abs(nb - 1) < 1e-9 and abs(na - 1) < 1e-5
+        assert dp <= 1e-6
+        assert fe <= 1e-6
+        assert abs(r["F"][s] - r2["F"][i]) < 1e-4
+    assert r2["F"][0] < 0.999          # the bond cap truncates
+    st.close()
