@@ -33,13 +33,27 @@ struct GemmGroup {
   int batch;
   int tiles_n, tiles_per_item;
   int tile_begin;
+  // gate operator applied in the epilogue (GEMM_EPI_*): W[wl][s][t][wr]
+  // per batch item, call-locally addressed
+  Operand w;
+  int wl, wr;
 };
 
 constexpr int GEMM_MAX_GROUPS = 16;
+// Epilogues: none (C = op(A) op(B)), or the gate operator of a site applied
+// to the product before it is stored (the product itself is never written):
+//   RIGHT  product X1[a][wl][t][y] (M = dl wl, N = 2 kr, columns (t, y)) ->
+//          C = X2[a][s][wr][y], ldc = kr
+//   LEFT   product Y1[x][t][c][wr] (M = 2 kl, N = dr wr) ->
+//          C = Y2[wl][x][s][c], ldc = dr
+// for operator bonds wl, wr <= GEMM_EPI_WMAX.
+enum { GEMM_EPI_NONE = 0, GEMM_EPI_RIGHT = 1, GEMM_EPI_LEFT = 2 };
+constexpr int GEMM_EPI_WMAX = 4;
 struct GemmArgs {
   GemmGroup g[GEMM_MAX_GROUPS];
   int ngroups;
   int total_tiles;
+  int epi;   // one epilogue for every group of a launch
 };
 
 // Tile shapes of the GEMM kernel (output tile BM x BN per workgroup).

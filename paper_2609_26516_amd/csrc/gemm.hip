@@ -73,6 +73,13 @@ constexpr int NT = 256, PAD = 4;
 template <typename R>
 constexpr int gemm_bk() { return 8; }
 
+// Explicit fused multiply-adds in the operator epilogue: every tile shape
+// then performs exactly the same operations (the compiler may not contract
+// the products differently in different instantiations), so results stay
+// bit-identical across tile shapes.
+__device__ __forceinline__ float efma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double efma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int q = total >> 3, r = total & 7;
   const int x = bid & 7, i = bid >> 3;
@@ -99,9 +106,10 @@ constexpr int gemm_min_blocks() {
   return n < 1 ? 1 : n;
 }
 
-template <int TA, int TB, int TC, typename R, int OPA, int OPB, int BM, int BN>
+template <int TA, int TB, int TC, typename R, int OPA, int OPB, int BM, int BN, int EPI>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(gemm_min_blocks<R, BM, BN>(), 8)))
 void gemm_kernel(const GemmArgs args) {
+  static_assert(EPI != GEMM_EPI_RIGHT || OPB == OP_N, "the right epilogue maps B's columns");
   using CA = typename Store<TA>::T;
   using CB = typename Store<TB>::T;
   using CC = typename Store<TC>::T;
@@ -113,11 +121,23 @@ void gemm_kernel(const GemmArgs args) {
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   static_assert(EA >= 1 && EB >= 1 && BK % EA == 0 && BK % EB == 0, "staging map");
 
-  // two LDS stages: the next K tile is stored while the current one is read
-  __shared__ R sA_r[2][BK][BM + PAD];
-  __shared__ R sA_i[2][BK][BM + PAD];
-  __shared__ R sB_r[2][BK][BN + PAD];
-  __shared__ R sB_i[2][BK][BN + PAD];
+  // two LDS stages: the next K tile is stored while the current one is read;
+  // the epilogue's half tile of the product (rows) reuses the same memory
+  // once the K loop is done
+  constexpr int EH = EPI == GEMM_EPI_NONE ? 1 : BM / 2;
+  constexpr int EW = EPI == GEMM_EPI_NONE ? 1 : BN + 1;
+  constexpr size_t SA = sizeof(R) * 2 * BK * (BM + PAD), SB = sizeof(R) * 2 * BK * (BN + PAD);
+  constexpr size_t SC = sizeof(R) * EH * EW;
+  constexpr size_t SMEM = (2 * SA + 2 * SB) > 2 * SC ? (2 * SA + 2 * SB) : 2 * SC;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  R(*sA_r)[BK][BM + PAD] = reinterpret_cast<R(*)[BK][BM + PAD]>(smem);
+  R(*sA_i)[BK][BM + PAD] = reinterpret_cast<R(*)[BK][BM + PAD]>(smem + SA);
+  R(*sB_r)[BK][BN + PAD] = reinterpret_cast<R(*)[BK][BN + PAD]>(smem + 2 * SA);
+  R(*sB_i)[BK][BN + PAD] = reinterpret_cast<R(*)[BK][BN + PAD]>(smem + 2 * SA + SB);
+  R(*sC_r)[EW] = reinterpret_cast<R(*)[EW]>(smem);
+  R(*sC_i)[EW] = reinterpret_cast<R(*)[EW]>(smem + SC);
+  // the item's gate operator (epilogue)
+  __shared__ CC sW[EPI == GEMM_EPI_NONE ? 1 : GEMM_EPI_WMAX * 4 * GEMM_EPI_WMAX];
   int stage = 0;
 
   const int tile = xcd_remap(blockIdx.x, args.total_tiles);
@@ -128,7 +148,8 @@ void gemm_kernel(const GemmArgs args) {
   const int item = local / G.tiles_per_item;
   const int t = local - item * G.tiles_per_item;
   const int m0 = (t / G.tiles_n) * BM;
-  const int n0 = (t % G.tiles_n) * BN;
+  // right epilogue: tile columns (t, y) for y in [n0, n0 + BN / 2), t = 0, 1
+  const int n0 = (t % G.tiles_n) * (EPI == GEMM_EPI_RIGHT ? BN / 2 : BN);
   const int M = G.M, N = G.N, K = G.K;
   const int lda = G.lda, ldb = G.ldb, ldc = G.ldc;
 
@@ -138,6 +159,11 @@ void gemm_kernel(const GemmArgs args) {
 
   const int tid = threadIdx.x;
   R ar[EA], ai[EA], br[EB], bi[EB];
+  if constexpr (EPI != GEMM_EPI_NONE) {   // visible after the first barrier
+    const CC* __restrict__ W = reinterpret_cast<const CC*>(item_ptr(G.w, nullptr, item));
+    const int nw = G.wl * 4 * G.wr;
+    for (int i = tid; i < nw; i += NT) sW[i] = W[i];
+  }
 
   auto load_a = [&](int k0) {
     if constexpr (OPA == OP_N || OPA == OP_J) {   // stored M x K: EA consecutive k
@@ -197,9 +223,15 @@ void gemm_kernel(const GemmArgs args) {
       const int k = k0 + kr;
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
-        const int n = n0 + nq + u;
+        int n = n0 + nq + u;
+        bool inb = n < N;
+        if constexpr (EPI == GEMM_EPI_RIGHT) {   // column (t, y) of the stored (t, y) pairs
+          const int cl = nq + u, half = N / 2, y = n0 + cl % (BN / 2);
+          n = (cl / (BN / 2)) * half + y;
+          inb = y < half;
+        }
         R re = 0, im = 0;
-        if (n < N && k < K) {
+        if (inb && k < K) {
           const CB v = B[(long long)k * ldb + n];
           re = v.x;
           im = v.y;
@@ -308,40 +340,148 @@ void gemm_kernel(const GemmArgs args) {
     __syncthreads();
   }
 
+  if constexpr (EPI == GEMM_EPI_NONE) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int col = n0 + wn + j * 16 + li;
+      for (int j = 0; j < FN; ++j) {
+        const int col = n0 + wn + j * 16 + li;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + Mfma<R>::row(lk, r);
-        if (row < M && col < N) {
-          CC v;
-          v.x = p1[i][j][r] - p2[i][j][r];
-          v.y = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
-          C[(long long)row * ldc + col] = v;
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + Mfma<R>::row(lk, r);
+          if (row < M && col < N) {
+            CC v;
+            v.x = p1[i][j][r] - p2[i][j][r];
+            v.y = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+            C[(long long)row * ldc + col] = v;
+          }
+        }
+      }
+  } else {
+    // The product tile goes through LDS half by half (rows); every thread then
+    // applies the gate operator to whole (row group, column group) blocks, in
+    // the order of the stand-alone operator kernels.
+    constexpr int W4 = GEMM_EPI_WMAX;
+    const int wl = G.wl, wr = G.wr;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();   // the K loop's (or the previous half's) LDS reads are done
+      if ((wave >> 1) == h) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = i * 16 + Mfma<R>::row(lk, r), col = wn + j * 16 + li;
+              sC_r[row][col] = p1[i][j][r] - p2[i][j][r];
+              sC_i[row][col] = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+            }
+      }
+      __syncthreads();
+      const int mh = m0 + h * (BM / 2);
+      if constexpr (EPI == GEMM_EPI_RIGHT) {
+        // X1[a][wl][t][y] -> X2[a][s][wr][y]
+        constexpr int HB = BN / 2;
+        const int kr = N / 2, dl = M / wl, na = (BM / 2) / wl;
+        for (int p = tid; p < na * HB; p += NT) {
+          const int yl = p % HB, al = p / HB;
+          const int a = mh / wl + al, y = n0 + yl;
+          if (a >= dl || y >= kr) continue;
+          R xr[2 * W4], xi[2 * W4];
+#pragma unroll
+          for (int k = 0; k < 2 * W4; ++k) {   // k = wl_i * 2 + t
+            xr[k] = 0;
+            xi[k] = 0;
+            if (k < 2 * wl) {
+              xr[k] = sC_r[al * wl + (k >> 1)][(k & 1) * HB + yl];
+              xi[k] = sC_i[al * wl + (k >> 1)][(k & 1) * HB + yl];
+            }
+          }
+#pragma unroll
+          for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+            for (int o = 0; o < W4; ++o) {
+              if (o < wr) {
+                R accr = 0, acci = 0;
+#pragma unroll
+                for (int k = 0; k < 2 * W4; ++k) {
+                  if (k < 2 * wl) {
+                    const CC w = sW[(((k >> 1) * 2 + sp) * 2 + (k & 1)) * wr + o];
+                    accr = efma(-w.y, xi[k], efma(w.x, xr[k], accr));
+                    acci = efma(w.y, xr[k], efma(w.x, xi[k], acci));
+                  }
+                }
+                CC v;
+                v.x = accr;
+                v.y = acci;
+                C[(((long long)a * 2 + sp) * wr + o) * ldc + y] = v;
+              }
+            }
+          }
+        }
+      } else {
+        // Y1[x][t][c][wr] -> Y2[wl][x][s][c]
+        const int kl = M / 2, dr = N / wr, nx = BM / 4, nc = BN / wr;
+        for (int p = tid; p < nx * nc; p += NT) {
+          const int cl = p % nc, xl = p / nc;
+          const int x = mh / 2 + xl, c = n0 / wr + cl;
+          if (x >= kl || c >= dr) continue;
+          R yr[2 * W4], yi[2 * W4];
+#pragma unroll
+          for (int k = 0; k < 2 * W4; ++k) {   // k = t * W4 + wr_i
+            const int tt = k / W4, o = k % W4;
+            yr[k] = 0;
+            yi[k] = 0;
+            if (o < wr) {
+              yr[k] = sC_r[xl * 2 + tt][cl * wr + o];
+              yi[k] = sC_i[xl * 2 + tt][cl * wr + o];
+            }
+          }
+#pragma unroll
+          for (int l = 0; l < W4; ++l) {
+            if (l < wl) {
+#pragma unroll
+              for (int sp = 0; sp < 2; ++sp) {
+                R accr = 0, acci = 0;
+#pragma unroll
+                for (int k = 0; k < 2 * W4; ++k) {
+                  const int tt = k / W4, o = k % W4;
+                  if (o < wr) {
+                    const CC w = sW[((l * 2 + sp) * 2 + tt) * wr + o];
+                    accr = efma(-w.y, yi[k], efma(w.x, yr[k], accr));
+                    acci = efma(w.y, yr[k], efma(w.x, yi[k], acci));
+                  }
+                }
+                CC v;
+                v.x = accr;
+                v.y = acci;
+                C[(((long long)l * kl + x) * 2 + sp) * ldc + c] = v;
+              }
+            }
+          }
         }
       }
     }
+  }
 }
 
-template <int TA, int TB, int TC, typename R, int OPA, int OPB>
+template <int TA, int TB, int TC, typename R, int OPA, int OPB, int EPI = GEMM_EPI_NONE>
 hipError_t run(int variant, const GemmArgs& args, hipStream_t s) {
   if (args.total_tiles <= 0) return hipSuccess;
   const dim3 grid(args.total_tiles), blk(NT);
   switch (variant) {
     case GEMM_64x64:
-      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 64>), grid, blk, 0, s, args);
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 64, EPI>), grid, blk, 0, s, args);
       break;
     case GEMM_32x32:
-      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 32, 32>), grid, blk, 0, s, args);
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 32, 32, EPI>), grid, blk, 0, s, args);
       break;
     case GEMM_128x64:
-      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 128, 64>), grid, blk, 0, s, args);
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 128, 64, EPI>), grid, blk, 0, s, args);
       break;
     case GEMM_64x128:
-      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 128>), grid, blk, 0, s, args);
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 128, EPI>), grid, blk, 0, s, args);
       break;
     default:
       return hipErrorInvalidValue;
@@ -374,9 +514,23 @@ void gemm_tile_shape(int variant, int* bm, int* bn) {
 hipError_t launch_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int variant,
                        const GemmArgs& args, hipStream_t s) {
   if (tacc == ACC_BF16X3)
-    return (ta == CT_F32 && tb == CT_F32 && tc == CT_F32)
+    return (ta == CT_F32 && tb == CT_F32 && tc == CT_F32 && args.epi == GEMM_EPI_NONE)
                ? launch_gemm_bf16x3(opa, opb, variant, args, s)
                : hipErrorInvalidValue;
+  if (args.epi != GEMM_EPI_NONE) {   // gate operator in the epilogue
+    for (int g = 0; g < args.ngroups; ++g)
+      if (args.g[g].wl < 1 || args.g[g].wl > GEMM_EPI_WMAX || args.g[g].wr < 1 ||
+          args.g[g].wr > GEMM_EPI_WMAX)
+        return hipErrorInvalidValue;
+    const bool same = ta == tb && tb == tc && tacc == ta;
+    if (same && args.epi == GEMM_EPI_RIGHT && opa == OP_N && opb == OP_N)
+      return ta == CT_F32 ? run<CT_F32, CT_F32, CT_F32, float, OP_N, OP_N, GEMM_EPI_RIGHT>(variant, args, s)
+                          : run<CT_F64, CT_F64, CT_F64, double, OP_N, OP_N, GEMM_EPI_RIGHT>(variant, args, s);
+    if (same && args.epi == GEMM_EPI_LEFT && opa == OP_N && opb == OP_T)
+      return ta == CT_F32 ? run<CT_F32, CT_F32, CT_F32, float, OP_N, OP_T, GEMM_EPI_LEFT>(variant, args, s)
+                          : run<CT_F64, CT_F64, CT_F64, double, OP_N, OP_T, GEMM_EPI_LEFT>(variant, args, s);
+    return hipErrorInvalidValue;
+  }
 #define DCS_GEMM_CASE(TA, TB, TC, R, OA, OB)                                             \
   if (ta == TA && tb == TB && tc == TC && tacc == (sizeof(R) == 8 ? CT_F64 : CT_F32) && \
       opa == OA && opb == OB)                                                            \

@@ -458,15 +458,16 @@ int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
     int ng = 0;
     long long big = -1;
     TuneKey key{};
-    for (; j_end < jobs.size() && ng < GEMM_MAX_GROUPS; ++j_end) {
+    const int epi = jobs[i].epi;   // one epilogue per launch
+    for (; j_end < jobs.size() && ng < GEMM_MAX_GROUPS && jobs[j_end].epi == epi; ++j_end) {
       const GemmJob& j = jobs[j_end];
       if (j.batch <= 0 || j.M <= 0 || j.N <= 0) continue;
       ++ng;
       const long long w = (long long)j.M * j.N * j.batch;
       if (w > big) {
         big = w;
-        key = {ta, tb, tc, tacc, opa, opb, lg2_bucket(j.M), lg2_bucket(j.N), lg2_bucket(j.K),
-               lg2_bucket(j.batch)};
+        key = {ta, tb, tc, tacc, opa + 4 * epi, opb, lg2_bucket(j.M), lg2_bucket(j.N),
+               lg2_bucket(j.K), lg2_bucket(j.batch)};
       }
     }
     if (ng == 0) {
@@ -498,15 +499,24 @@ int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
       g.ldb = j.ldb;
       g.ldc = j.ldc;
       g.batch = j.batch;
-      g.tiles_n = (j.N + bn - 1) / bn;
+      g.w = j.w;
+      g.wl = j.wl;
+      g.wr = j.wr;
+      // the right epilogue's tiles hold columns (0, y) and (1, y) for bn / 2 values of y
+      g.tiles_n = epi == GEMM_EPI_RIGHT ? (j.N / 2 + bn / 2 - 1) / (bn / 2) : (j.N + bn - 1) / bn;
       g.tiles_per_item = ((j.M + bm - 1) / bm) * g.tiles_n;
       g.tile_begin = tiles;
       tiles += g.tiles_per_item * j.batch;
       flops += 8.0 * j.M * j.N * (double)j.K * j.batch;
       bytes += es * ((double)j.M * j.K + (double)j.K * j.N + (double)j.M * j.N) * j.batch;
+      if (epi != GEMM_EPI_NONE)   // operator: 8 (2 wl)(2 wr) flops per (row, column) group
+        flops += 8.0 * (2.0 * j.wl) * (2.0 * j.wr) * j.batch *
+                 (epi == GEMM_EPI_RIGHT ? (double)(j.M / j.wl) * (j.N / 2)
+                                        : (double)(j.M / 2) * (j.N / j.wr));
     }
     args.ngroups = ng;
     args.total_tiles = tiles;
+    args.epi = epi;
     hipEvent_t ta_ev = nullptr, tb_ev = nullptr;
     if (timed) {
       ta_ev = take_event(ctx);
@@ -1461,12 +1471,27 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
 
     // moving left at site j: Y1 = K_j R_{j+1}^T, Y2 = W Y1, then (a) R_j from
     // bra_j (starting guess or LQ factor) or (b) F = L_j Y2
+    // the gate operator goes into the epilogue of the contraction that
+    // produces its input (complex64 / complex128 contractions, bonds <= 4)
+    auto fuse = [&](int wl, int wr) {
+      return acc != ACC_BF16X3 && wl <= GEMM_EPI_WMAX && wr <= GEMM_EPI_WMAX;
+    };
     auto left_prologue = [&](int j) -> int {
       std::vector<GemmJob> gj;
       std::vector<MpoJob> mj;
       for (auto& g : groups) {
         const int bsz = (int)g.members.size();
         const int kl = g.Kb[j], kr = g.Kb[j + 1], dr = g.Db[j + 1], wl = g.w[j], wr = g.w[j + 1];
+        if (fuse(wl, wr)) {
+          GemmJob q{ket_site(g, j), env(j + 1), x2(), g.ids_dev, 2 * kl, dr * wr, kr, kr, kr, dr,
+                    bsz};
+          q.epi = GEMM_EPI_LEFT;
+          q.w = mpo(g, j);
+          q.wl = wl;
+          q.wr = wr;
+          gj.push_back(q);
+          continue;
+        }
         gj.push_back({ket_site(g, j), env(j + 1), x1(), g.ids_dev, 2 * kl, dr * wr, kr, kr, kr,
                       dr * wr, bsz});
         mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, kl, dr, wl, wr, bsz});
@@ -1559,9 +1584,19 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
         const int bsz = (int)g.members.size();
         const int kl = g.Kb[j], kr = g.Kb[j + 1], dl = g.Db[j], dr = g.Db[j + 1];
         const int wl = g.w[j], wr = g.w[j + 1];
-        g1.push_back({env(j), ket_site(g, j), x1(), g.ids_dev, dl * wl, 2 * kr, kl, kl, 2 * kr,
-                      2 * kr, bsz});
-        mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, dl, kr, wl, wr, bsz});
+        if (fuse(wl, wr)) {
+          GemmJob q{env(j), ket_site(g, j), x2(), g.ids_dev, dl * wl, 2 * kr, kl, kl, 2 * kr, kr,
+                    bsz};
+          q.epi = GEMM_EPI_RIGHT;
+          q.w = mpo(g, j);
+          q.wl = wl;
+          q.wr = wr;
+          g1.push_back(q);
+        } else {
+          g1.push_back({env(j), ket_site(g, j), x1(), g.ids_dev, dl * wl, 2 * kr, kl, kl, 2 * kr,
+                        2 * kr, bsz});
+          mj.push_back({x1(), x2(), mpo(g, j), g.ids_dev, dl, kr, wl, wr, bsz});
+        }
         g2.push_back({x2(), env(j + 1), fbuf(), g.ids_dev, 2 * dl, dr, wr * kr, wr * kr, wr * kr,
                       dr, bsz});
         QrJob q;

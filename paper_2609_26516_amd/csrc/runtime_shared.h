@@ -37,6 +37,10 @@ struct GemmJob {
   Operand a, b, c;
   const int* ids;
   int M, N, K, lda, ldb, ldc, batch;
+  // gate operator applied in the epilogue (GEMM_EPI_*, see GemmArgs)
+  int epi = GEMM_EPI_NONE;
+  Operand w = Operand{nullptr, 0, 0, 0};
+  int wl = 0, wr = 0;
 };
 struct QrJob {
   Operand f, q, ws, nrm2;
