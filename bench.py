@@ -517,6 +517,8 @@ def main():
                     help="measurement rounds of the all-threads oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the (untimed) complex128 replay of sampled shots")
     ap.add_argument("--workload", default="sp40",
                     choices=sorted(SINGLE_PATH) + sorted(MULTI_PATH) + sorted(LARGE_CHI)
                     + sorted(TREE))
@@ -582,7 +584,8 @@ def main():
                    "gemm_jt": "gemm_kernel (tree contractions, conj(A) B^T)",
                    "qr": "qr_left_kernel / qrl_* (node QR)",
                    "other": "permute_kernel (leg transpositions)"}),
-               "precision_vs_fp64": tree_precision_vs_fp64(wl, samples)}
+               "precision_vs_fp64": None if args.no_precision
+               else tree_precision_vs_fp64(wl, samples)}
         if not args.no_fp64:
             dt64, _, _, _ = run_gpu_tree("c128", shots, args.fp64_steps, args.warmup, False, wl)
             out["fp64_path"] = {"value": round(shots * args.fp64_steps / dt64, 4),
@@ -644,7 +647,8 @@ def main():
     }
     out["roofline"]["measured_on"] = ("one instrumented step after the timed ones "
                                       "(HIP events around every launch)")
-    out["precision_vs_fp64"] = precision_vs_fp64(WORKLOAD, samples)
+    if not args.no_precision:
+        out["precision_vs_fp64"] = precision_vs_fp64(WORKLOAD, samples)
     if not args.no_fp64:
         dt64, _, _, _ = run_gpu("c128", args.shots, args.fp64_steps, args.warmup, timing=False)
         out["fp64_path"] = {"value": round(args.shots * args.fp64_steps / dt64, 4),
