@@ -6,6 +6,7 @@
 #include <cstring>
 #include "kernel_util.h"
 #include "qr_panel.h"
+#include "qr_cholpanel.h"
 
 namespace dcs {
 namespace {
@@ -336,10 +337,6 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrArgs args) {
 //     trailing matrix per panel.
 // Q is then accumulated backwards panel by panel in place, the same way with
 // X = T, after the panel's own columns [I; 0] - V (T V1^H).
-
-constexpr int QB = 16;
-
-__device__ __forceinline__ int pidx(int i, int c) { return i * QB + (c ^ (i & 15)); }
 
 // Reflector r of the panel at local row i; the panel in LDS is explicit (0
 // above the diagonal, 1 on it, 0 in unused columns and rows).
@@ -944,31 +941,44 @@ __global__ __launch_bounds__(NTQ, NTQ == 512 ? 1 : 2) void qr_left_kernel(const 
     for (int j = 0; j < k; ++j)
       qrl_step<NTQ, true>(a, v, rV, Tg, m, n, j, j + 1 < k ? j + 1 : -1, false, P, Wp);
 
-    // factor the panel: rows p.. to LDS, one row per thread
+    // factor the panel: by Cholesky QR and Householder reconstruction where
+    // the panel allows it, else column by column (rows p.. to LDS, one row
+    // per thread)
     __syncthreads();
+    bool chol = false;
+    if (mp > nbk) {
+      chol = panel_cholqr<NW, MAXB>(a, m, k, mp, nbk, P, Wp);
+    } else {
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b) {
-      const int beta = wave + NW * b;
-      if (beta >= k && 16 * beta < m) {
+      for (int b = 0; b < MAXB; ++b) {
+        const int beta = wave + NW * b;
+        if (beta >= k && 16 * beta < m) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) P[pidx(16 * (beta - k) + 4 * t + lk, li)] = a[b][t];
+          for (int t = 0; t < 4; ++t) P[pidx(16 * (beta - k) + 4 * t + lk, li)] = a[b][t];
+        }
+      }
+      __syncthreads();
+    }
+    if (!chol) {
+      double2 ar[1][QB];
+#pragma unroll
+      for (int c = 0; c < QB; ++c) ar[0][c] = tid < mp ? P[pidx(tid, c)] : zero;
+      factor_panel2<1, QB, NTQ>(ar, mp, nbk, psm, sT);
+      // explicit V_k (rows p.., zero past m) to LDS
+      if (tid < Shape::PROWS) {
+#pragma unroll
+        for (int c = 0; c < QB; ++c) {
+          const bool in = tid < mp && c < nbk;
+          P[pidx(tid, c)] = !in ? zero : (tid > c ? ar[0][c] : make_double2(tid == c ? 1.0 : 0.0, 0.0));
+        }
       }
     }
     __syncthreads();
-    double2 ar[1][QB];
+    // V_k and T_k to the workspace
+    if (tid < mp) {
 #pragma unroll
-    for (int c = 0; c < QB; ++c) ar[0][c] = tid < mp ? P[pidx(tid, c)] : zero;
-    factor_panel2<1, QB, NTQ>(ar, mp, nbk, psm, sT);
-    // explicit V_k to the workspace and (rows p.., zero past m) to LDS, T_k to
-    // the workspace
-    if (tid < Shape::PROWS) {
-#pragma unroll
-      for (int c = 0; c < QB; ++c) {
-        const bool in = tid < mp && c < nbk;
-        const double2 u = !in ? zero : (tid > c ? ar[0][c] : make_double2(tid == c ? 1.0 : 0.0, 0.0));
-        if (in) Vw[(long long)(p + tid) * n + p + c] = u;
-        P[pidx(tid, c)] = u;
-      }
+      for (int c = 0; c < QB; ++c)
+        if (c < nbk) Vw[(long long)(p + tid) * n + p + c] = P[pidx(tid, c)];
     }
     if constexpr (NTQ >= QB * QB) {
       if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sT[tid];
