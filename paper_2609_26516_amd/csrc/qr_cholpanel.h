@@ -148,14 +148,20 @@ __device__ __forceinline__ bool chol_inv16(double2 (&g)[4], double2 (&z)[4], int
     const double dd = ok ? dk : 1.0;
     const double inv = rsqrt_nr(dd);
     const double2 rk = cscale(brow2<kr>(g[ks]), li > k ? inv : 0.0);   // R[k][li], li > k
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double2 ck = cscale(bcol2<k>(g[r]), lk + 4 * r > k ? inv : 0.0);   // conj(R[k][i])
-      g[r] = cfms(g[r], ck, rk);
-      const double2 zk = cscale(bcol2<k>(z[r]), inv);   // Z[i][k]
-      const double2 zn = cfms(z[r], zk, rk);
-      z[r] = csel(li == k, zk, zn);
-    }
+    // slot r holds rows 4r .. 4r + 3: G' changes only below row k, and Z
+    // (upper triangular) only in rows up to k
+    static_for<4>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      if constexpr (4 * r + 3 > k) {
+        const double2 ck = cscale(bcol2<k>(g[r]), lk + 4 * r > k ? inv : 0.0);   // conj(R[k][i])
+        g[r] = cfms(g[r], ck, rk);
+      }
+      if constexpr (4 * r <= k) {
+        const double2 zk = cscale(bcol2<k>(z[r]), inv);   // Z[i][k]
+        const double2 zn = cfms(z[r], zk, rk);
+        z[r] = csel(li == k, zk, zn);
+      }
+    });
   });
   return ok;
 }
@@ -208,17 +214,23 @@ __device__ __forceinline__ void lu_inv16(double2 (&w)[4], double2 (&zu)[4], doub
     const double2 iu = make_double2(ux * den, -uy * den);
     const double2 uk = cscale(brow2<kr>(w[ks]), li > k ? 1.0 : 0.0);   // U[k][li], li > k
     const double2 rowzl = brow2<kr>(zl[ks]);                           // row k of L^{-1}
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    // slot r holds rows 4r .. 4r + 3: W and L^{-1} (lower triangular) change
+    // only from row k down, U^{-1} (upper triangular) only in rows up to k
+    static_for<4>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
       const int i = lk + 4 * r;
-      const double2 lik = cscale(cmul(bcol2<k>(w[r]), iu), i > k ? 1.0 : 0.0);   // L[i][k]
-      const double2 wn = cfms(w[r], lik, uk);
-      w[r] = csel(li != k, wn, csel(i > k, lik, csel(i == k, make_double2(ux, uy), w[r])));
-      const double2 zuk = cmul(bcol2<k>(zu[r]), iu);   // U^{-1}[i][k]
-      const double2 zun = cfms(zu[r], zuk, uk);
-      zu[r] = csel(li == k, zuk, zun);
-      zl[r] = cfms(zl[r], lik, rowzl);
-    }
+      if constexpr (4 * r + 3 >= k) {
+        const double2 lik = cscale(cmul(bcol2<k>(w[r]), iu), i > k ? 1.0 : 0.0);   // L[i][k]
+        const double2 wn = cfms(w[r], lik, uk);
+        w[r] = csel(li != k, wn, csel(i > k, lik, csel(i == k, make_double2(ux, uy), w[r])));
+        zl[r] = cfms(zl[r], lik, rowzl);
+      }
+      if constexpr (4 * r <= k) {
+        const double2 zuk = cmul(bcol2<k>(zu[r]), iu);   // U^{-1}[i][k]
+        const double2 zun = cfms(zu[r], zuk, uk);
+        zu[r] = csel(li == k, zuk, zun);
+      }
+    });
   });
 }
 
