@@ -45,7 +45,9 @@ int dcs_test_mpo(int ct, int dir, int d0, int d1, int wl, int wr, const double *
  * two launches (factorisation, then one workgroup per 16-column block of Q),
  * as used for batches that do not fill the chip, 6 variant 4 with two-wave
  * workgroups for m <= 128 (as used for batches of more than 512 such
- * matrices; larger m as variant 4). */
+ * matrices; larger m as variant 4), 7 the spread path (modes 0 and 1,
+ * n <= m <= 512: one workgroup per 16-column panel, trailing updates and Q
+ * blocks over many workgroups, as used for small batches of large matrices). */
 int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int variant, const double *F,
                 double *Q, double *nrm2_out, void *stream);
 

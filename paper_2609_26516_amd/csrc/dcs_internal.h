@@ -131,6 +131,19 @@ int qr_split_max_items();
 // updates and the backward Q accumulation spread over 16-column strips.  The
 // workspace of each item holds qr_large_ws_elems(m, n) complex128 values.
 hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args, hipStream_t s);
+// Spread variant for small batches of matrices of at most qr_spread_max_rows()
+// rows (modes 0 and 1): one workgroup per matrix factors each 16-column panel
+// (Cholesky QR and Householder reconstruction where the panel allows it),
+// the trailing updates and the Q blocks are spread over many workgroups.  The
+// workspace of each item holds qr_large_ws_elems(m, n) complex128 values.
+hipError_t launch_qr_spread(int ct_in, int ct_out, const QrArgs& args, hipStream_t s);
+int qr_spread_max_rows();
+// Largest number of matrices for which the runtime takes the spread path.
+int qr_spread_max_items();
+// The Q blocks of the left-looking kernel alone (one workgroup per 16-column
+// block of each Q) from the explicit V (m x n) and the T factors after it at
+// each item's workspace.
+hipError_t launch_qr_qblocks(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s);
 int qr_large_max_rows();
 size_t qr_large_ws_elems(int m, int n);
 

@@ -1205,8 +1205,9 @@ hipError_t launch_qr_blocked(int ct_in, int ct_out, const QrArgs& args, int m_ma
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
-                          hipStream_t s, int threads) {
+namespace {
+hipError_t launch_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
+                       bool qblocks_only, hipStream_t s, int threads) {
   if (args.total_blocks <= 0) return hipSuccess;
   // up to 128 rows: four waves per matrix (two matrices per CU), or, when
   // there are more matrices than that fits on the chip at once, two waves
@@ -1238,8 +1239,9 @@ hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, 
         reinterpret_cast<const void*>(&qr_left_kernel<I, O, T>),                            \
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)QrShape<T>::LDS_BYTES);            \
     if (lds > 48 * 1024 && attr != hipSuccess) return attr;                                 \
-    hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(args.total_blocks), blk, lds, s, args, \
-                       split ? 1 : 0);                                                      \
+    if (!qblocks_only)                                                                      \
+      hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(args.total_blocks), blk, lds, s,   \
+                         args, split ? 1 : 0);                                              \
     if (split && qa.total_blocks > 0)                                                       \
       hipLaunchKernelGGL((qr_left_kernel<I, O, T>), dim3(qa.total_blocks), blk, lds, s, qa, 2); \
     return hipGetLastError();                                                               \
@@ -1255,6 +1257,24 @@ hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, 
   DCS_QRL(CT_F64, CT_F32, 128)
 #undef DCS_QRL
   return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_qr_left(int ct_in, int ct_out, const QrArgs& args, int m_max, bool split,
+                          hipStream_t s, int threads) {
+  return launch_left(ct_in, ct_out, args, m_max, split, false, s, threads);
+}
+
+hipError_t launch_qr_qblocks(int ct_in, int ct_out, const QrArgs& args, int m_max, hipStream_t s) {
+  QrArgs a = args;
+  int blocks = 0;
+  for (int g = 0; g < a.ngroups; ++g) {
+    a.g[g].blk_begin = blocks;
+    blocks += a.g[g].batch;
+  }
+  a.total_blocks = blocks;
+  a.use_lds = 1;
+  return launch_left(ct_in, ct_out, a, m_max, true, true, s, 0);
 }
 
 hipError_t launch_qr(int ct_in, int ct_out, const QrArgs& args, size_t lds_bytes, hipStream_t s) {

@@ -21,6 +21,7 @@
 #include "dcs_internal.h"
 #include "kernel_util.h"
 #include "qr_panel.h"
+#include "qr_cholpanel.h"
 
 namespace dcs {
 namespace {
@@ -332,6 +333,101 @@ hipError_t run_large(QrArgs args, int items, int m_max, int n_max, hipStream_t s
   return hipGetLastError();
 }
 
+// Spread path for small batches of matrices of at most 512 rows: the panels
+// are factored by one 512-thread workgroup per matrix (Cholesky QR and
+// Householder reconstruction where the panel allows it, else column by
+// column), the trailing updates run over 16-column strips as above, and Q is
+// formed by the blocked kernel's Q-block launch from the explicit V and T in
+// the workspace.  The workspace is the large path's.
+constexpr int QRS_NW = 8, QRS_MAXB = 4;   // 512 threads, rows in 16-row blocks
+constexpr size_t QRS_LDS = (size_t)512 * QB * sizeof(double2) + (size_t)QRS_NW * 256 * sizeof(double2);
+
+__global__ __launch_bounds__(512, 1) void qrs_panel_kernel(const QrArgs args, int p) {
+  extern __shared__ __attribute__((aligned(16))) double2 qrs_dyn[];
+  double2* P = qrs_dyn;                  // the panel rows, then V
+  double2* Wp = qrs_dyn + 512 * QB;      // per-wave areas; T at the end
+  PanelSmem2<QRS_NW, QB>& psm = *reinterpret_cast<PanelSmem2<QRS_NW, QB>*>(qrs_dyn);
+  const QrlItem it = qrl_item(args, blockIdx.x);
+  const int m = it.g->m, n = it.g->n;
+  if (p >= n) return;
+  double2* A = qrl_ws(it);
+  double2* V = A + (long long)m * n;
+  double2* Tg = V + (long long)m * n;
+  const int mp = m - p, nbk = min(QB, n - p), k = p / QB;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+
+  if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
+    const double* part = qrl_partials(A, m, n);
+    double s = 0.0;
+    for (int c = 0; c < QRL_CHUNKS; ++c) s += part[c];
+    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
+  }
+  double2 a[QRS_MAXB][4];   // rows 16 beta + 4t + lk, column p + li
+#pragma unroll
+  for (int b = 0; b < QRS_MAXB; ++b) {
+    const int beta = wave + QRS_NW * b;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int row = 16 * beta + 4 * t + lk;
+      a[b][t] = (beta >= k && row < m && li < nbk) ? A[(long long)row * n + p + li] : zero;
+    }
+  }
+  bool chol = false;
+  if (mp > nbk) {
+    chol = panel_cholqr<QRS_NW, QRS_MAXB>(a, m, k, mp, nbk, P, Wp);
+  } else {
+#pragma unroll
+    for (int b = 0; b < QRS_MAXB; ++b) {
+      const int beta = wave + QRS_NW * b;
+      if (beta >= k && 16 * beta < m) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[pidx(16 * (beta - k) + 4 * t + lk, li)] = a[b][t];
+      }
+    }
+    __syncthreads();
+  }
+  if (!chol) {
+    double2 ar[1][QB];
+#pragma unroll
+    for (int c = 0; c < QB; ++c) ar[0][c] = tid < mp ? P[pidx(tid, c)] : zero;
+    factor_panel2<1, QB, 512>(ar, mp, nbk, psm, Wp);
+#pragma unroll
+    for (int c = 0; c < QB; ++c) {
+      const bool in = tid < mp && c < nbk;
+      P[pidx(tid, c)] = !in ? zero : (tid > c ? ar[0][c] : make_double2(tid == c ? 1.0 : 0.0, 0.0));
+    }
+  }
+  __syncthreads();
+  if (tid < mp) {
+#pragma unroll
+    for (int c = 0; c < QB; ++c)
+      if (c < nbk) V[(long long)(p + tid) * n + p + c] = P[pidx(tid, c)];
+  }
+  if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = Wp[tid];
+}
+
+template <int CTI>
+hipError_t run_spread(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_panel_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)QRS_LDS);
+  if (attr != hipSuccess) return attr;
+  const dim3 chunks(QRL_CHUNKS, items);
+  hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
+  for (int p = 0; p < n_max; p += QB) {
+    hipLaunchKernelGGL(qrs_panel_kernel, dim3(items), dim3(512), QRS_LDS, s, args, p);
+    const int strips = (n_max - p - QB + 15) / 16;
+    if (strips > 0) {
+      const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
+      hipLaunchKernelGGL((qrl_wpart_kernel<QB>), grid, dim3(256), 0, s, args, p, QB);
+      hipLaunchKernelGGL((qrl_update_kernel<QB>), grid, dim3(256), 0, s, args, p, QB, 1);
+    }
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int qr_large_max_rows() { return 2048; }
@@ -363,6 +459,34 @@ hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStre
   DCS_QRL(CT_F64, CT_F32)
 #undef DCS_QRL
   return hipErrorInvalidValue;
+}
+
+int qr_spread_max_rows() { return 512; }
+int qr_spread_max_items() { return 96; }
+
+hipError_t launch_qr_spread(int ct_in, int ct_out, const QrArgs& args_in, hipStream_t s) {
+  QrArgs args = args_in;
+  int items = 0, m_max = 0, n_max = 0;
+  for (int g = 0; g < args.ngroups; ++g) {
+    if (args.g[g].mode == 2 || args.g[g].m < args.g[g].n) return hipErrorInvalidValue;
+    args.g[g].blk_begin = items;
+    items += args.g[g].batch;
+    m_max = max(m_max, args.g[g].m);
+    n_max = max(n_max, args.g[g].n);
+  }
+  if (items == 0) return hipSuccess;
+  if (m_max > qr_spread_max_rows()) return hipErrorInvalidValue;
+  hipError_t e = ct_in == CT_F32   ? run_spread<CT_F32>(args, items, m_max, n_max, s)
+                 : ct_in == CT_F64 ? run_spread<CT_F64>(args, items, m_max, n_max, s)
+                                   : hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  // Q from V and T: the blocked kernel's Q blocks read V at the workspace
+  // start and T after it, so each group's workspace is taken m n further on
+  QrArgs qa = args;
+  for (int g = 0; g < qa.ngroups; ++g)
+    qa.g[g].ws.base = static_cast<const char*>(qa.g[g].ws.base) +
+                      (size_t)qa.g[g].m * qa.g[g].n * sizeof(double2);
+  return launch_qr_qblocks(ct_in, ct_out, qa, m_max, s);
 }
 
 }  // namespace dcs

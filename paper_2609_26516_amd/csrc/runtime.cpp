@@ -76,10 +76,9 @@ std::vector<int> bond_dims(int n, int chi) {
 // Complex128 workspace elements of one QR item with at most `emax` matrix
 // elements and at most `dmax` columns (rows <= 2 dmax).
 size_t qr_ws_elems(size_t emax, size_t dmax) {
-  size_t w = emax + (dmax / 16 + 2) * 256;
-  if (2 * dmax > (size_t)qr_blocked_max_rows())
-    w = std::max(w, qr_large_ws_elems((int)(2 * dmax), (int)dmax));
-  return w;
+  // the blocked kernel's, or the large and spread paths' (which small
+  // batches take at any size)
+  return std::max(emax + (dmax / 16 + 2) * 256, qr_large_ws_elems((int)(2 * dmax), (int)dmax));
 }
 
 int ctype_of(int precision) { return precision == DCS_C128 ? CT_F64 : CT_F32; }
@@ -581,18 +580,35 @@ int run_mpo(dcs_ctx* ctx, int ct, int dir, const std::vector<MpoJob>& jobs, hipS
 using QrJob = rt::QrJob;
 
 // Path of a QR job: 0 blocked single-workgroup kernel, left-looking form
-// (m <= 512 or mode 2),
-// 1 multi-kernel large-matrix path, 2 unblocked kernel (beyond both).
-int qr_path(const QrJob& j) {
-  if (j.mode == 2 || j.m <= qr_blocked_max_rows()) return 0;
+// (m <= 512 or mode 2), 3 the spread path for the same matrices when `spread`
+// (see run_qr), 1 multi-kernel large-matrix path, 2 unblocked kernel (beyond
+// both).
+int qr_path(const QrJob& j, bool spread) {
+  if (j.mode == 2) return 0;
+  if (j.m <= qr_blocked_max_rows()) return spread && j.m >= j.n ? 3 : 0;
   return j.m <= qr_large_max_rows() ? 1 : 2;
 }
 
 int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, hipStream_t s) {
-  for (int path = 0; path < 3; ++path) {
+  // A call with few matrices of up to 512 rows leaves most of the chip idle
+  // under one workgroup per matrix; when its largest matrix is big enough for
+  // that to matter (more than 256 rows, at least 128 columns) its QRs take the
+  // spread path, whose updates run over many workgroups.  Its strip updates
+  // read and write the trailing matrix once per panel, so it stops paying off
+  // as the batch grows (512 x 256: 1.03 against 1.78 ms for 8 matrices, 2.22
+  // against 2.36 ms for 64, 4.52 against 3.30 ms for 160).
+  int items = 0, m_big = 0, n_big = 0;
+  for (const QrJob& j : all)
+    if (j.batch > 0 && j.mode != 2 && j.m <= qr_blocked_max_rows()) {
+      items += j.batch;
+      m_big = std::max(m_big, j.m);
+      n_big = std::max(n_big, j.n);
+    }
+  const bool spread = items <= qr_spread_max_items() && m_big > 256 && n_big >= 128;
+  for (int path : {0, 3, 1, 2}) {
     std::vector<QrJob> jobs;
     for (const QrJob& j : all)
-      if (j.batch > 0 && qr_path(j) == path) jobs.push_back(j);
+      if (j.batch > 0 && qr_path(j, spread) == path) jobs.push_back(j);
     size_t i = 0;
     while (i < jobs.size()) {
       QrArgs args;
@@ -631,6 +647,8 @@ int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, h
         // in separate launches so the Q blocks spread over the chip
         DCS_HIP(launch_qr_left(ct_in, ct_out, args, std::max(m_max, 1),
                                args.total_blocks <= qr_split_max_items(), s));
+      } else if (path == 3) {
+        DCS_HIP(launch_qr_spread(ct_in, ct_out, args, s));
       } else if (path == 1) {
         DCS_HIP(launch_qr_large(ct_in, ct_out, args, s));
       } else {
@@ -2349,7 +2367,6 @@ int ctx_device(const dcs_ctx* ctx) { return ctx->device; }
 size_t qr_job_ws_elems(int m, int n, int mode) {
   if (mode == 2) return 0;
   const size_t mn = (size_t)m * n;
-  if (m <= qr_blocked_max_rows()) return mn + ((size_t)n / 16 + 2) * 256;
   if (m <= qr_large_max_rows()) return std::max(mn + ((size_t)n / 16 + 2) * 256, qr_large_ws_elems(m, n));
   return mn;
 }

@@ -240,7 +240,11 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
     args.ngroups = 1;
     args.total_blocks = 1;
     const size_t lds = mn * 16;
-    if (use_lds == 3) {   // large-matrix variant
+    if (use_lds == 7) {   // spread variant (small batches)
+      if (mode == 2 || m > qr_spread_max_rows() || m < n)
+        return testing_fail(DCS_EINVAL, "the spread QR takes modes 0/1 and n <= m <= 512");
+      T_HIP(launch_qr_spread(ct_in, ct_out, args, s));
+    } else if (use_lds == 3) {   // large-matrix variant
       if (mode == 2 || m > qr_large_max_rows())
         return testing_fail(DCS_EINVAL, "the large-matrix QR takes modes 0/1 and m <= 2048");
       T_HIP(launch_qr_large(ct_in, ct_out, args, s));

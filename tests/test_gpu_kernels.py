@@ -127,7 +127,7 @@ def test_gate_operator(capi, ct, direction, d0, d1, wl, wr):
     assert np.max(np.abs(out - ref.reshape(-1))) < tol * np.sqrt(wl * wr * 4)
 
 
-@pytest.mark.parametrize("use_lds", [0, 1, 2, 4, 5, 6])
+@pytest.mark.parametrize("use_lds", [0, 1, 2, 4, 5, 6, 7])
 @pytest.mark.parametrize("m,n", [(2, 1), (4, 2), (8, 8), (32, 16), (64, 32), (128, 64),
                                  (128, 128), (130, 65),
                                  (512, 256), (34, 17), (100, 100), (512, 512), (511, 257),
@@ -150,7 +150,7 @@ def test_qr_full_rank(capi, use_lds, m, n):
     assert np.max(np.abs(ql - qn.conj().T)) < 1e-10
 
 
-@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5, 6, 7])
 def test_qr_rank_deficient_and_normalise(capi, variant):
     rng = np.random.default_rng(1)
     m, n = 64, 32
@@ -170,7 +170,7 @@ def test_qr_rank_deficient_and_normalise(capi, variant):
     np.testing.assert_allclose(z.reshape(6, 3), np.eye(6)[:, :3], atol=0)
 
 
-@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("tiny", [1e-120, 1e-170, 1e-250])
 @pytest.mark.parametrize("m,n", [(256, 128), (128, 64)])
