@@ -336,9 +336,10 @@ hipError_t run_large(QrArgs args, int items, int m_max, int n_max, hipStream_t s
 // Spread path for small batches of matrices of at most 512 rows: the panels
 // are factored by one 512-thread workgroup per matrix (Cholesky QR and
 // Householder reconstruction where the panel allows it, else column by
-// column), the trailing updates run over 16-column strips as above, and Q is
-// formed by the blocked kernel's Q-block launch from the explicit V and T in
-// the workspace.  The workspace is the large path's.
+// column), the trailing updates run over 16-column strips with one workgroup
+// per strip and matrix, and Q is formed by the blocked kernel's Q-block
+// launch from the explicit V and T in the workspace.  The workspace is the
+// large path's.
 constexpr int QRS_NW = 8, QRS_MAXB = 4;   // 512 threads, rows in 16-row blocks
 constexpr size_t QRS_LDS = (size_t)512 * QB * sizeof(double2) + (size_t)QRS_NW * 256 * sizeof(double2);
 
@@ -408,6 +409,105 @@ __global__ __launch_bounds__(512, 1) void qrs_panel_kernel(const QrArgs args, in
   if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = Wp[tid];
 }
 
+// Trailing update of the spread path, one 512-thread workgroup per (16-column
+// strip, matrix): A[p:, c0:c0+16] -= V T^H (V^H A[p:, c0:c0+16]).  Wave w
+// takes panel rows 64w .. 64w + 63 (at most 512 rows); the waves' parts of
+// W = V^H A are summed through LDS in a fixed order.
+__global__ __launch_bounds__(512, 1) void qrs_update_kernel(const QrArgs args, int p) {
+  __shared__ double2 sW[QRS_NW][256];
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  const int m = it.g->m, n = it.g->n;
+  const int c0 = p + QB + 16 * blockIdx.x;
+  if (p >= n || c0 >= n) return;   // uniform over the workgroup
+  double2* A = qrl_ws(it);
+  const double2* V = A + (long long)m * n;
+  const double2* T = V + (long long)m * n + (long long)(p / QB) * QB * QB;
+  const int mp = m - p, nbk = min(QB, n - p);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  const bool col_ok = col < n;
+  const int r0 = 64 * wave, r1 = min(mp, r0 + 64);
+  const double2 zero = make_double2(0.0, 0.0);
+  // this wave's rows of the strip (row r0 + 16h + 4t + lk) and its part of W
+  double2 av[4][4];
+  CAcc3 w;
+  w.zero();
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    double2 vw[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = r0 + 16 * h + 4 * t + lk;
+      av[h][t] = (i < r1 && col_ok) ? A[(long long)(p + i) * n + col] : zero;
+      vw[t] = (i < r1 && li < nbk) ? V[(long long)(p + i) * n + p + li] : zero;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) w.add(vw[t].x, -vw[t].y, av[h][t].x, av[h][t].y);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sW[wave][(lk + 4 * r) * 16 + li] = make_double2(w.re(r), w.im(r));
+  __syncthreads();
+  if (tid < 256) {
+    double2 sum = sW[0][tid];
+#pragma unroll
+    for (int u = 1; u < QRS_NW; ++u) {
+      sum.x += sW[u][tid].x;
+      sum.y += sW[u][tid].y;
+    }
+    sW[0][tid] = sum;
+  }
+  __syncthreads();
+  v4d_t wr, wi;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double2 x = sW[0][(lk + 4 * t) * 16 + li];
+    wr[t] = x.x;
+    wi[t] = x.y;
+  }
+  // W2 = T^H W (item t = row lk + 4t = the B operand of k-step t)
+  CAcc3 x2;
+  x2.zero();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int sr = 4 * t + lk;
+    double2 x = zero;
+    if (li < nbk && sr < nbk) {
+      const double2 tt = T[sr * QB + li];
+      x = make_double2(tt.x, -tt.y);
+    }
+    x2.add(x.x, x.y, wr[t], wi[t]);
+  }
+  double x2r[4], x2i[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    x2r[t] = x2.re(t);
+    x2i[t] = x2.im(t);
+  }
+  // A -= V W2, block by block
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int rb = r0 + 16 * h;
+    if (rb >= r1) break;   // uniform over the wave
+    CAcc3 e;
+    e.zero();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = rb + li, sr = 4 * t + lk;
+      const double2 v = (i < r1 && sr < nbk) ? V[(long long)(p + i) * n + p + sr] : zero;
+      e.add(v.x, v.y, x2r[t], x2i[t]);
+    }
+    if (col_ok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = rb + lk + 4 * t;
+        if (i < r1)
+          A[(long long)(p + i) * n + col] = make_double2(av[h][t].x - e.re(t), av[h][t].y - e.im(t));
+      }
+    }
+  }
+}
+
 template <int CTI>
 hipError_t run_spread(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
   static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_panel_kernel),
@@ -419,11 +519,8 @@ hipError_t run_spread(QrArgs args, int items, int m_max, int n_max, hipStream_t 
   for (int p = 0; p < n_max; p += QB) {
     hipLaunchKernelGGL(qrs_panel_kernel, dim3(items), dim3(512), QRS_LDS, s, args, p);
     const int strips = (n_max - p - QB + 15) / 16;
-    if (strips > 0) {
-      const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
-      hipLaunchKernelGGL((qrl_wpart_kernel<QB>), grid, dim3(256), 0, s, args, p, QB);
-      hipLaunchKernelGGL((qrl_update_kernel<QB>), grid, dim3(256), 0, s, args, p, QB, 1);
-    }
+    if (strips > 0)
+      hipLaunchKernelGGL(qrs_update_kernel, dim3(strips, items), dim3(512), 0, s, args, p);
   }
   return hipGetLastError();
 }
