@@ -56,7 +56,7 @@ TUNE = {"enabled": True, "save": None}
 # of known size.  Valid only for the kernel source they were taken on.
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
-                   "paper_2609_26516_amd/csrc/kernel_util.h"],
+                   "paper_2609_26516_amd/csrc/qr_cholpanel.h", "paper_2609_26516_amd/csrc/kernel_util.h"],
            "sha256": "e9514baa141c1bbe0363725e22c0b9962fbf9f1ca37250c4f9138f047803bc63",
            "fetch_kib": 2884120.6, "write_kib": 1226957.9,
            "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
