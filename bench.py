@@ -57,9 +57,9 @@ TUNE = {"enabled": True, "save": None}
 TRAFFIC = {
     "qr": {"src": ["paper_2609_26516_amd/csrc/kernels.hip", "paper_2609_26516_amd/csrc/qr_panel.h",
                    "paper_2609_26516_amd/csrc/qr_cholpanel.h", "paper_2609_26516_amd/csrc/kernel_util.h"],
-           "sha256": "e9514baa141c1bbe0363725e22c0b9962fbf9f1ca37250c4f9138f047803bc63",
-           "fetch_kib": 2884120.6, "write_kib": 1226957.9,
-           "fetch_factor": 1048576 / 524300.6, "write_factor": 1048576 / 1048576.1},
+           "sha256": "c83839423b301ba0c9187665c893ee8c5b6bb761681f887b94c1238a938f87da",
+           "fetch_kib": 2501359.8, "write_kib": 979570.9,
+           "fetch_factor": 1048576 / 524300.5, "write_factor": 1048576 / 1048576.3},
 }
 
 
