@@ -1,17 +1,18 @@
 // FP64 Householder QR with explicit thin Q for local matrices of more than
 // 512 rows (bond caps above 256), where one workgroup per matrix would leave
-// the chip idle and the panel no longer fits in LDS.  Same reflectors as the
-// other QR kernels (LAPACK convention: v_k = 1, beta = -sign(Re alpha) |x|,
+// the chip idle and the panel no longer fits in LDS, and the spread path for
+// small batches of smaller matrices.  Same reflectors as the other QR kernels
+// (LAPACK convention: v_k = 1, beta = -sign(Re alpha) |x|,
 // tau = ((beta - Re alpha) / beta, -Im alpha / beta), tau = 0 for a zero
-// column), blocked in panels of NB columns with the compact WY form
-// H_p ... H_{p+NB-1} = I - V T V^H:
+// column), blocked in panels of 16 columns with the compact WY form
+// H_p ... H_{p+15} = I - V T V^H:
 //   qrl_load   F (mode 0) or F^H (mode 1) -> FP64 working matrix A (m x n,
 //              row-major), |F|^2 partial sums per chunk
-//   qrl_panel  one 512-thread workgroup per matrix factors A[p:, p:p+NB]
-//              with the panel in registers (RP rows per thread), reducing
-//              norms and inner products over the workgroup; writes the
-//              explicit V (unit diagonal) and T (zlarft recurrence, Gram
-//              entries v_j^H v_k reduced together with the panel updates)
+//   qrs_panel_tall (m > 512) / qrs_panel (m <= 512)
+//              one 512-thread workgroup per matrix factors A[p:, p:p+16] by
+//              Cholesky QR and Householder reconstruction (qr_cholpanel.h),
+//              or column by column where the panel does not allow it; writes
+//              the explicit V (unit diagonal) and T
 //   qrl_wpart  W = V^H A[p:, c:] in parts over (16-column strip, 256-row
 //   qrl_update chunk) tiles on FP64 MFMA, then A[p:, c:] -= V X W with
 //              X = T^H, every chunk summing its strip's parts in one order
@@ -28,8 +29,6 @@ namespace {
 
 
 constexpr int QRL_CHUNKS = 64;   // load / store / fill work units per matrix
-constexpr int QRL_NT = 512;      // panel workgroup
-constexpr int QRL_NW = QRL_NT / 64;
 
 struct QrlItem {
   const QrGroup* g;
@@ -76,55 +75,6 @@ __global__ __launch_bounds__(256) void qrl_load_kernel(const QrArgs args) {
   }
   part = block_sum(part, s_red);
   if (threadIdx.x == 0) qrl_partials(A, m, n)[blockIdx.x] = part;
-}
-
-// Panel factorisation: RP rows per thread (rows tid + r QRL_NT), NB columns
-// in registers (factor_panel2).
-template <int RP, int NB>
-__global__ __launch_bounds__(QRL_NT) void qrl_panel_kernel(const QrArgs args, int p) {
-  __shared__ PanelSmem2<QRL_NW, NB> sm;
-  __shared__ double2 s_T[NB * NB];
-  const QrlItem it = qrl_item(args, blockIdx.x);
-  const int m = it.g->m, n = it.g->n;
-  if (p >= n) return;
-  double2* A = qrl_ws(it);
-  double2* V = A + (long long)m * n;
-  double2* Tg = V + (long long)m * n;
-  const int mp = m - p, nbk = min(NB, n - p);
-  const int tid = threadIdx.x;
-
-  if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
-    const double* part = qrl_partials(A, m, n);
-    double s = 0.0;
-    for (int c = 0; c < QRL_CHUNKS; ++c) s += part[c];
-    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
-  }
-
-  double2 a[RP][NB];
-#pragma unroll
-  for (int r = 0; r < RP; ++r) {
-    const int i = tid + r * QRL_NT;
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-      a[r][c] = (i < mp && c < nbk) ? A[(long long)(p + i) * n + p + c] : make_double2(0.0, 0.0);
-  }
-  factor_panel2<RP, NB, QRL_NT>(a, mp, nbk, sm, s_T);
-  // explicit V of the panel (zero above, one on the diagonal) and T
-#pragma unroll
-  for (int r = 0; r < RP; ++r) {
-    const int i = tid + r * QRL_NT;
-    if (i < mp) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (c < nbk) {
-          const double2 v = (i < c) ? make_double2(0.0, 0.0)
-                                    : (i == c ? make_double2(1.0, 0.0) : a[r][c]);
-          V[(long long)(p + i) * n + p + c] = v;
-        }
-      }
-    }
-  }
-  if (tid < NB * NB) Tg[(long long)(p / NB) * NB * NB + tid] = s_T[tid];
 }
 
 // A[p:, c0:c0+16] -= V X (V^H A[p:, c0:c0+16]) with X = T^H (conj_t) or T,
@@ -312,26 +262,6 @@ __global__ __launch_bounds__(256) void qrl_store_kernel(const QrArgs args) {
   }
 }
 
-template <int RP, int NB, int CTI, int CTO>
-hipError_t run_large(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
-  const dim3 chunks(QRL_CHUNKS, items);
-  hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
-  auto apply = [&](int p, int c_off, int conj_t) {
-    const int strips = (n_max - p - c_off + 15) / 16;
-    if (strips <= 0) return;
-    const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
-    hipLaunchKernelGGL((qrl_wpart_kernel<NB>), grid, dim3(256), 0, s, args, p, c_off);
-    hipLaunchKernelGGL((qrl_update_kernel<NB>), grid, dim3(256), 0, s, args, p, c_off, conj_t);
-  };
-  for (int p = 0; p < n_max; p += NB) {
-    hipLaunchKernelGGL((qrl_panel_kernel<RP, NB>), dim3(items), dim3(QRL_NT), 0, s, args, p);
-    apply(p, NB, 1);
-  }
-  hipLaunchKernelGGL(qrl_fill_kernel, chunks, dim3(256), 0, s, args);
-  for (int p = ((n_max - 1) / NB) * NB; p >= 0; p -= NB) apply(p, 0, 0);
-  hipLaunchKernelGGL((qrl_store_kernel<CTO>), chunks, dim3(256), 0, s, args);
-  return hipGetLastError();
-}
 
 // Spread path for small batches of matrices of at most 512 rows: the panels
 // are factored by one 512-thread workgroup per matrix (Cholesky QR and
@@ -508,6 +438,182 @@ __global__ __launch_bounds__(512, 1) void qrs_update_kernel(const QrArgs args, i
   }
 }
 
+// Panel factorisation for 512 < m <= 2048 rows, one 512-thread workgroup per
+// matrix: as qrs_panel_kernel, with the panel streamed from the working
+// matrix in 16-row blocks (block c to wave c mod 8) instead of held in
+// registers: G1 from A, Q1 = A R1^{-1} into the V area (its top block also to
+// LDS) with G2 beside it, then V = Q1 R2^{-1} U^{-1} in place in the V area.
+// The fallback factors the panel rows of A column by column, four rows per
+// thread.
+constexpr int QRT_RP = 4;   // rows per thread of the fallback (2048 rows)
+
+__global__ __launch_bounds__(512, 1) void qrs_panel_tall_kernel(const QrArgs args, int p) {
+  __shared__ __attribute__((aligned(16))) double2 sP[16 * QB];   // top block; fallback scratch
+  __shared__ __attribute__((aligned(16))) double2 sWp[QRS_NW * 256];
+  static_assert(sizeof(PanelSmem2<QRS_NW, QB>) <= sizeof(sP), "fallback scratch fits");
+  PanelSmem2<QRS_NW, QB>& psm = *reinterpret_cast<PanelSmem2<QRS_NW, QB>*>(sP);
+  const QrlItem it = qrl_item(args, blockIdx.x);
+  const int m = it.g->m, n = it.g->n;
+  if (p >= n) return;
+  double2* A = qrl_ws(it);
+  double2* V = A + (long long)m * n;
+  double2* Tg = V + (long long)m * n;
+  const int mp = m - p, nbk = min(QB, n - p), k = p / QB, nblk = (mp + 15) / 16;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));   // lane offsets formed here, not hoisted
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+
+  if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
+    const double* part = qrl_partials(A, m, n);
+    double s = 0.0;
+    for (int c = 0; c < QRL_CHUNKS; ++c) s += part[c];
+    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
+  }
+  bool chol = mp > nbk;   // uniform
+  if (chol) {
+    {   // this wave's part of G1 = A^H A; imaginary part of entry (0, 0): an exact zero seen
+      CAcc3 g;
+      g.zero();
+      bool z = false;
+      for (int c = wave; c < nblk; c += QRS_NW) {
+        double2 a4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = 16 * c + 4 * t + lk;
+          const bool in = i < mp && li < nbk;
+          a4[t] = in ? A[(long long)(p + i) * n + p + li] : zero;
+          z = z || (in && a4[t].x == 0.0 && a4[t].y == 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g.add(a4[t].x, -a4[t].y, a4[t].x, a4[t].y);
+      }
+      const bool anyz = __ballot(z) != 0ull;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        sWp[wave * 256 + (lk + 4 * r) * 16 + li] =
+            make_double2(g.re(r), lane == 0 && r == 0 ? (anyz ? 1.0 : 0.0) : g.im(r));
+    }
+    __syncthreads();
+    if (wave == 0) panel_first_pass<QRS_NW>(sWp, nbk);
+    __syncthreads();
+    chol = sWp[16].x == 0.0;
+    double2 xb[4];   // X1[lk + 4s][li], the B operand of k-step s
+#pragma unroll
+    for (int s = 0; s < 4; ++s) xb[s] = sWp[(lk + 4 * s) * 16 + li];
+    __syncthreads();   // flag and X1 read everywhere before the LDS is rewritten
+    if (chol) {   // Q1 = A X1 into the V area, G2 parts
+      CAcc3 g2;
+      g2.zero();
+      for (int c = wave; c < nblk; c += QRS_NW) {
+        CAcc3 q;
+        q.zero();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int i = 16 * c + li, col = 4 * s + lk;
+          const double2 av = (i < mp && col < nbk) ? A[(long long)(p + i) * n + p + col] : zero;
+          q.add(av.x, av.y, xb[s].x, xb[s].y);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * c + lk + 4 * r;
+          const double2 qv = make_double2(q.re(r), q.im(r));
+          if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = qv;
+          if (c == 0) sP[pidx(lk + 4 * r, li)] = qv;
+          g2.add(qv.x, -qv.y, qv.x, qv.y);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        sWp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(g2.re(r), g2.im(r));
+      __threadfence_block();
+      __syncthreads();
+      if (wave == 0) panel_second_pass<QRS_NW>(sP, sWp, nbk, mp);
+      __syncthreads();
+      chol = sWp[16].x == 0.0;
+      if (chol) {   // V below the top block = Q1 M in place; the top block and T
+        double2 mb[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) mb[s] = sWp[256 + (lk + 4 * s) * 16 + li];
+        for (int c = wave; c < nblk; c += QRS_NW) {
+          if (c == 0) continue;
+          CAcc3 y;
+          y.zero();
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int i = 16 * c + li, col = 4 * s + lk;
+            const double2 av = (i < mp && col < nbk) ? V[(long long)(p + i) * n + p + col] : zero;
+            y.add(av.x, av.y, mb[s].x, mb[s].y);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * c + lk + 4 * r;
+            if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = make_double2(y.re(r), y.im(r));
+          }
+        }
+        if (wave == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = lk + 4 * r;
+            if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = sP[pidx(i, li)];
+          }
+        }
+        if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sWp[tid];
+        return;
+      }
+      __syncthreads();   // every wave has read the flag before the fallback reuses the LDS
+    }
+  }
+  // column by column, the panel rows of A (four rows per thread)
+  double2 a[QRT_RP][QB];
+#pragma unroll
+  for (int r = 0; r < QRT_RP; ++r) {
+    const int i = tid + r * 512;
+#pragma unroll
+    for (int c = 0; c < QB; ++c)
+      a[r][c] = (i < mp && c < nbk) ? A[(long long)(p + i) * n + p + c] : zero;
+  }
+  factor_panel2<QRT_RP, QB, 512>(a, mp, nbk, psm, sWp);
+#pragma unroll
+  for (int r = 0; r < QRT_RP; ++r) {
+    const int i = tid + r * 512;
+    if (i < mp) {
+#pragma unroll
+      for (int c = 0; c < QB; ++c) {
+        if (c < nbk) {
+          const double2 v = (i < c) ? zero : (i == c ? make_double2(1.0, 0.0) : a[r][c]);
+          V[(long long)(p + i) * n + p + c] = v;
+        }
+      }
+    }
+  }
+  if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sWp[tid];
+}
+
+template <int CTI, int CTO>
+hipError_t run_tall(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
+  const dim3 chunks(QRL_CHUNKS, items);
+  hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
+  for (int p = 0; p < n_max; p += QB) {
+    hipLaunchKernelGGL(qrs_panel_tall_kernel, dim3(items), dim3(512), 0, s, args, p);
+    const int strips = (n_max - p - QB + 15) / 16;
+    if (strips > 0) {
+      const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
+      hipLaunchKernelGGL((qrl_wpart_kernel<QB>), grid, dim3(256), 0, s, args, p, QB);
+      hipLaunchKernelGGL((qrl_update_kernel<QB>), grid, dim3(256), 0, s, args, p, QB, 1);
+    }
+  }
+  hipLaunchKernelGGL(qrl_fill_kernel, chunks, dim3(256), 0, s, args);
+  for (int p = ((n_max - 1) / QB) * QB; p >= 0; p -= QB) {
+    const dim3 grid((n_max - p + 15) / 16, (m_max - p + QRL_CH - 1) / QRL_CH, items);
+    hipLaunchKernelGGL((qrl_wpart_kernel<QB>), grid, dim3(256), 0, s, args, p, 0);
+    hipLaunchKernelGGL((qrl_update_kernel<QB>), grid, dim3(256), 0, s, args, p, 0, 0);
+  }
+  hipLaunchKernelGGL((qrl_store_kernel<CTO>), chunks, dim3(256), 0, s, args);
+  return hipGetLastError();
+}
+
 template <int CTI>
 hipError_t run_spread(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
   static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_panel_kernel),
@@ -546,11 +652,9 @@ hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStre
   }
   if (items == 0) return hipSuccess;
   if (m_max > qr_large_max_rows()) return hipErrorInvalidValue;
-  const bool wide = m_max <= 1024;   // 2 rows per thread and 12-column panels, else 4 and 8
-#define DCS_QRL(I, O)                                                     \
-  if (ct_in == I && ct_out == O)                                          \
-    return wide ? run_large<2, 12, I, O>(args, items, m_max, n_max, s)    \
-                : run_large<4, 8, I, O>(args, items, m_max, n_max, s);
+#define DCS_QRL(I, O)            \
+  if (ct_in == I && ct_out == O) \
+    return run_tall<I, O>(args, items, m_max, n_max, s);
   DCS_QRL(CT_F32, CT_F32)
   DCS_QRL(CT_F64, CT_F64)
   DCS_QRL(CT_F64, CT_F32)

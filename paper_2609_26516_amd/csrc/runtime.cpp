@@ -1100,8 +1100,10 @@ int dcs_state_set_init(dcs_state* st, int chi_cap, const double* gauss, void* st
     // per-call contraction area (x1 and x2, contiguous) of slot i = j - j0
     // for its FP64 Gaussian and that slot's QR workspace; |G|^2 goes to the
     // call output area.  None of these hold anything between calls, so live
-    // branches are unaffected.  Their sizes come from chi_max >= chi_cap.
-    if (emax * 16 > L.o_f - L.o_x1 || qr_ws_elems(emax, (size_t)chi_cap) * 16 > L.o_e - L.o_ws)
+    // branches are unaffected.  Their sizes come from chi_max >= chi_cap (the
+    // QR matrices have at most 2 dmx rows and dmx columns).
+    const size_t dmx = (size_t)*std::max_element(d.begin(), d.end());
+    if (emax * 16 > L.o_f - L.o_x1 || qr_ws_elems(emax, dmx) * 16 > L.o_e - L.o_ws)
       return fail(DCS_ENOMEM, "internal: slot scratch too small for the starting guess");
     const int per_launch = std::min(L.cap, QR_MAX_GROUPS);
     double* nrm_dev = reinterpret_cast<double*>(st->base + L.o_out);
