@@ -273,12 +273,11 @@ __global__ __launch_bounds__(256) void qrl_store_kernel(const QrArgs args) {
 constexpr int QRS_NW = 8, QRS_MAXB = 4;   // 512 threads, rows in 16-row blocks
 constexpr size_t QRS_LDS = (size_t)512 * QB * sizeof(double2) + (size_t)QRS_NW * 256 * sizeof(double2);
 
-__global__ __launch_bounds__(512, 1) void qrs_panel_kernel(const QrArgs args, int p) {
-  extern __shared__ __attribute__((aligned(16))) double2 qrs_dyn[];
-  double2* P = qrs_dyn;                  // the panel rows, then V
-  double2* Wp = qrs_dyn + 512 * QB;      // per-wave areas; T at the end
-  PanelSmem2<QRS_NW, QB>& psm = *reinterpret_cast<PanelSmem2<QRS_NW, QB>*>(qrs_dyn);
-  const QrlItem it = qrl_item(args, blockIdx.x);
+// The panel at column p of one matrix, by the whole 512-thread workgroup; P
+// (512 x 16 panel rows) and Wp (8 areas of 256) in LDS.  Uniform early exit
+// when p >= n.
+__device__ __forceinline__ void spread_panel(const QrlItem& it, int p, double2* P, double2* Wp) {
+  PanelSmem2<QRS_NW, QB>& psm = *reinterpret_cast<PanelSmem2<QRS_NW, QB>*>(P);
   const int m = it.g->m, n = it.g->n;
   if (p >= n) return;
   double2* A = qrl_ws(it);
@@ -339,12 +338,21 @@ __global__ __launch_bounds__(512, 1) void qrs_panel_kernel(const QrArgs args, in
   if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = Wp[tid];
 }
 
+__global__ __launch_bounds__(512, 1) void qrs_panel_kernel(const QrArgs args, int p) {
+  extern __shared__ __attribute__((aligned(16))) double2 qrs_dyn[];
+  spread_panel(qrl_item(args, blockIdx.x), p, qrs_dyn, qrs_dyn + 512 * QB);
+}
+
 // Trailing update of the spread path, one 512-thread workgroup per (16-column
 // strip, matrix): A[p:, c0:c0+16] -= V T^H (V^H A[p:, c0:c0+16]).  Wave w
 // takes panel rows 64w .. 64w + 63 (at most 512 rows); the waves' parts of
 // W = V^H A are summed through LDS in a fixed order.
+// The workgroup of strip 0, whose columns are the next panel's, then factors
+// that panel (look-ahead): its latency overlaps the other strips' updates,
+// and the next update launch finds V and T in place.
 __global__ __launch_bounds__(512, 1) void qrs_update_kernel(const QrArgs args, int p) {
-  __shared__ double2 sW[QRS_NW][256];
+  extern __shared__ __attribute__((aligned(16))) double2 qrs_dyn[];
+  double2 (*sW)[256] = reinterpret_cast<double2 (*)[256]>(qrs_dyn + 512 * QB);
   const QrlItem it = qrl_item(args, blockIdx.y);
   const int m = it.g->m, n = it.g->n;
   const int c0 = p + QB + 16 * blockIdx.x;
@@ -435,6 +443,11 @@ __global__ __launch_bounds__(512, 1) void qrs_update_kernel(const QrArgs args, i
           A[(long long)(p + i) * n + col] = make_double2(av[h][t].x - e.re(t), av[h][t].y - e.im(t));
       }
     }
+  }
+  if (blockIdx.x == 0) {   // the next panel (columns c0 .. c0 + 15, just updated)
+    __threadfence_block();
+    __syncthreads();
+    spread_panel(it, c0, qrs_dyn, qrs_dyn + 512 * QB);
   }
 }
 
@@ -616,18 +629,20 @@ hipError_t run_tall(QrArgs args, int items, int m_max, int n_max, hipStream_t s)
 
 template <int CTI>
 hipError_t run_spread(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
-  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_panel_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)QRS_LDS);
-  if (attr != hipSuccess) return attr;
+  static hipError_t attr1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_panel_kernel),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)QRS_LDS);
+  static hipError_t attr2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&qrs_update_kernel),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)QRS_LDS);
+  if (attr1 != hipSuccess) return attr1;
+  if (attr2 != hipSuccess) return attr2;
   const dim3 chunks(QRL_CHUNKS, items);
   hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
-  for (int p = 0; p < n_max; p += QB) {
-    hipLaunchKernelGGL(qrs_panel_kernel, dim3(items), dim3(512), QRS_LDS, s, args, p);
-    const int strips = (n_max - p - QB + 15) / 16;
-    if (strips > 0)
-      hipLaunchKernelGGL(qrs_update_kernel, dim3(strips, items), dim3(512), 0, s, args, p);
-  }
+  hipLaunchKernelGGL(qrs_panel_kernel, dim3(items), dim3(512), QRS_LDS, s, args, 0);
+  for (int p = 0; p + QB < n_max; p += QB)   // update by panel p, factor panel p + 16
+    hipLaunchKernelGGL(qrs_update_kernel, dim3((n_max - p - QB + 15) / 16, items), dim3(512), QRS_LDS,
+                       s, args, p);
   return hipGetLastError();
 }
 
