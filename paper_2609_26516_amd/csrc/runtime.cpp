@@ -592,11 +592,13 @@ int qr_path(const QrJob& j, bool spread) {
 int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, hipStream_t s) {
   // A call with few matrices of up to 512 rows leaves most of the chip idle
   // under one workgroup per matrix; when its largest matrix is big enough for
-  // that to matter (more than 256 rows, at least 128 columns) its QRs take the
+  // that to matter (more than 128 rows, at least 64 columns) its QRs take the
   // spread path, whose updates run over many workgroups.  Its strip updates
   // read and write the trailing matrix once per panel, so it stops paying off
-  // as the batch grows (512 x 256: 1.03 against 1.78 ms for 8 matrices, 2.22
-  // against 2.36 ms for 64, 4.52 against 3.30 ms for 160).
+  // as the batch grows (512 x 256: 0.96 against 1.78 ms for 8 matrices, 2.05
+  // against 2.36 ms for 64; 192 x 96: 0.32 against 0.36 ms for 64; 128 x 64:
+  // 0.155 against 0.136 ms for 16, where the blocked kernel runs four waves per
+  // matrix).
   int items = 0, m_big = 0, n_big = 0;
   for (const QrJob& j : all)
     if (j.batch > 0 && j.mode != 2 && j.m <= qr_blocked_max_rows()) {
@@ -604,7 +606,7 @@ int run_qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& all, h
       m_big = std::max(m_big, j.m);
       n_big = std::max(n_big, j.n);
     }
-  const bool spread = items <= qr_spread_max_items() && m_big > 256 && n_big >= 128;
+  const bool spread = items <= qr_spread_max_items() && m_big > 128 && n_big >= 64;
   for (int path : {0, 3, 1, 2}) {
     std::vector<QrJob> jobs;
     for (const QrJob& j : all)
