@@ -24,7 +24,7 @@ extern "C" {
  * 0 = FP32 MFMA, 2 = split-BF16 products on BF16 MFMA with FP32 accumulation,
  * complex64 storage only); only the combinations the library uses are available
  * (DCS_EINVAL otherwise).  variant: output tile shape 0 64x64, 1 32x32,
- * 2 128x64, 3 64x128. */
+ * 2 128x64, 3 64x128, 4 128x128 (FP32 accumulation only). */
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
                   int batch, int variant, const double *A, const double *B, double *C,
                   void *stream);

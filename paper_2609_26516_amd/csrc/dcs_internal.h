@@ -57,8 +57,11 @@ struct GemmArgs {
 };
 
 // Tile shapes of the GEMM kernel (output tile BM x BN per workgroup).
-enum GemmVariant { GEMM_64x64 = 0, GEMM_32x32 = 1, GEMM_128x64 = 2, GEMM_64x128 = 3 };
-constexpr int GEMM_VARIANTS = 4;
+enum GemmVariant { GEMM_64x64 = 0, GEMM_32x32 = 1, GEMM_128x64 = 2, GEMM_64x128 = 3, GEMM_128x128 = 4 };
+constexpr int GEMM_VARIANTS = 5;
+// Tile shapes available for an accumulation type: 128 x 128 only for FP32
+// accumulation (its FP64 accumulators would not fit the registers).
+inline int gemm_variants(int tacc) { return tacc == CT_F32 ? 5 : 4; }
 void gemm_tile_shape(int variant, int* bm, int* bn);
 // Accumulation mode of a GEMM besides the storage types: split-BF16 products
 // (three BF16 MFMA products per real product, FP32 accumulation) over

@@ -101,7 +101,8 @@ template <typename R, int BM, int BN>
 constexpr int gemm_min_blocks() {
   const int lds = (int)((160 * 1024) / (2 * 2 * gemm_bk<R>() * ((BM + PAD) + (BN + PAD)) * sizeof(R)));
   const int regs = sizeof(R) == 8 ? (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 3 : 1)
-                                   : (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 5 : 3);
+                                   : (BM * BN <= 32 * 32 ? 4 : BM * BN <= 64 * 64 ? 5
+                                                            : BM * BN <= 128 * 64 ? 3 : 2);
   const int n = lds < regs ? lds : regs;
   return n < 1 ? 1 : n;
 }
@@ -483,6 +484,12 @@ hipError_t run(int variant, const GemmArgs& args, hipStream_t s) {
     case GEMM_64x128:
       hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 64, 128, EPI>), grid, blk, 0, s, args);
       break;
+    case GEMM_128x128:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, R, OPA, OPB, 128, 128, EPI>), grid, blk, 0, s, args);
+        break;
+      }
+      return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
@@ -503,6 +510,10 @@ void gemm_tile_shape(int variant, int* bm, int* bn) {
       return;
     case GEMM_64x128:
       *bm = 64;
+      *bn = 128;
+      return;
+    case GEMM_128x128:
+      *bm = 128;
       *bn = 128;
       return;
     default:

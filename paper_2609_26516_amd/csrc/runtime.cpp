@@ -417,8 +417,9 @@ int tune_choose(dcs_ctx* c, const TuneKey& key, bool* timed) {
   const int fallback = small ? GEMM_32x32 : GEMM_64x64;
   if (!c->tuning || c->capturing || c->no_alloc) return fallback;
   TuneRec& r = c->tune[key];
+  const int nv = gemm_variants(key[3]);
   int v = 0;
-  for (int i = 1; i < GEMM_VARIANTS; ++i)
+  for (int i = 1; i < nv; ++i)
     if (r.issued[i] < r.issued[v]) v = i;
   if (r.issued[v] >= c->tune_reps) return fallback;   // all trials in flight
   r.issued[v] += 1;
@@ -434,11 +435,12 @@ void tune_resolve(dcs_ctx* c) {
     TuneRec& r = c->tune[p.key];
     r.ms[p.variant] = r.cnt[p.variant] ? std::min(r.ms[p.variant], (double)ms) : ms;
     r.cnt[p.variant] += 1;
+    const int nv = gemm_variants(p.key[3]);
     bool done = true;
-    for (int i = 0; i < GEMM_VARIANTS; ++i) done = done && r.cnt[i] >= c->tune_reps;
+    for (int i = 0; i < nv; ++i) done = done && r.cnt[i] >= c->tune_reps;
     if (done && r.best < 0) {
       int b = 0;
-      for (int i = 1; i < GEMM_VARIANTS; ++i)
+      for (int i = 1; i < nv; ++i)
         if (r.ms[i] < r.ms[b]) b = i;
       r.best = b;
     }
@@ -955,7 +957,7 @@ int dcs_ctx_tuning_load(dcs_ctx* ctx, const char* path) {
       if (std::sscanf(c, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], \"best\": %d%n", &k[0], &k[1],
                       &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9], &best, &used) != 11)
         return fail(DCS_EINVAL, "malformed tile-shape entry");
-      if (best < 0 || best >= GEMM_VARIANTS) return fail(DCS_EINVAL, "bad tile shape id");
+      if (best < 0 || best >= gemm_variants(k[3])) return fail(DCS_EINVAL, "bad tile shape id");
       ctx->tune[k].best = best;
       ++loaded;
       pos += used;

@@ -33,12 +33,14 @@ COMBOS = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("combo", COMBOS)
 @pytest.mark.parametrize("mnk", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 130, 37),
-                                 (200, 96, 257)])
+                                 (200, 96, 257), (300, 260, 40)])
 def test_gemm(capi, combo, mnk, variant):
     ta, tb, tc, tacc, opa, opb = combo
+    if variant == 4 and tacc != F32:
+        pytest.skip("the 128 x 128 tile exists for FP32 accumulation only")
     m, n, k = mnk
     rng = np.random.default_rng(m * 7 + n * 3 + k)
     batch = 3
