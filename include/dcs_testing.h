@@ -57,6 +57,24 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int variant, cons
  * Reference point that converts the profiler's HBM byte counters. */
 int dcs_test_copy(const void *src, void *dst, size_t bytes, int reps, void *stream);
 
+/* Batched transposition with optional conjugation and storage conversion.
+ * `in` holds `batch` items, each a row-major tensor of `rank` legs with
+ * extents dims[0..rank); item b of `out` is item b of `in` with its legs in
+ * the order perm (output leg k = input leg perm[k]), conjugated when conj.
+ * variant: 0 the kernel the library picks, 1 the element-wise kernel, 2 the
+ * LDS-tiled kernel (DCS_EINVAL where it does not take the transposition).
+ * rank <= 12, batch * prod(dims) <= 2^28. */
+int dcs_test_permute(int ct_in, int ct_out, int rank, const int *dims, const int *perm, int conj,
+                     int batch, int variant, const double *in, double *out, void *stream);
+
+/* The same transposition on device buffers (`in`: batch items of the input
+ * storage type, `out`: batch items of the output type, both device memory),
+ * `reps` times, enqueued on the stream without synchronisation.  For timing
+ * the kernels on the transpositions of a workload. */
+int dcs_test_permute_dev(int ct_in, int ct_out, int rank, const int *dims, const int *perm,
+                         int conj, int batch, int variant, const void *in, void *out, int reps,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

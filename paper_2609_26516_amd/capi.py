@@ -39,7 +39,8 @@ EXPORTED = [
     "dcs_tree_chunk_scratch", "dcs_tree_compress_step", "dcs_tree_measure_prob",
     "dcs_tree_collapse", "dcs_tree_export",
 ]
-EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy"]
+EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy",
+                    "dcs_test_permute", "dcs_test_permute_dev"]
 
 
 class DcsError(RuntimeError):
@@ -114,6 +115,8 @@ _SIGS = {
     "dcs_test_mpo": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_copy": (c_int, [_P, _P, ctypes.c_size_t, c_int, _P]),
+    "dcs_test_permute": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_DP, _DP, _P]),
+    "dcs_test_permute_dev": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_P, _P, c_int, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -518,3 +521,28 @@ def dcs_test_qr(ct_in, ct_out, m, n, mode, variant, f, stream=0):
 
 def dcs_test_copy(src: int, dst: int, nbytes: int, reps: int = 1, stream: int = 0) -> None:
     _check(_lib.dcs_test_copy(src, dst, nbytes, reps, stream))
+
+
+def dcs_test_permute(ct_in, ct_out, x, perm, conj=False, variant=0, stream=0) -> np.ndarray:
+    """x: (batch, *dims) complex; returns (batch, *dims[perm]) complex128."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    batch, dims = x.shape[0], [int(d) for d in x.shape[1:]]
+    perm = [int(p) for p in perm]
+    out = np.zeros((batch, *[dims[p] for p in perm]), dtype=np.complex128)
+    d = (ctypes.c_int * len(dims))(*dims)
+    p = (ctypes.c_int * len(perm))(*perm)
+    _check(_lib.dcs_test_permute(ct_in, ct_out, len(dims), d, p, int(bool(conj)), batch,
+                                 int(variant), _dp(x.view(np.float64).reshape(-1)),
+                                 _dp(out.view(np.float64).reshape(-1)), stream))
+    return out
+
+
+def dcs_test_permute_dev(ct_in, ct_out, dims, perm, src: int, dst: int, conj=False, batch=1,
+                         variant=0, reps=1, stream=0) -> None:
+    """Device-buffer form of dcs_test_permute (no synchronisation)."""
+    dims = [int(d) for d in dims]
+    perm = [int(p) for p in perm]
+    d = (ctypes.c_int * len(dims))(*dims)
+    p = (ctypes.c_int * len(perm))(*perm)
+    _check(_lib.dcs_test_permute_dev(ct_in, ct_out, len(dims), d, p, int(bool(conj)), batch,
+                                     int(variant), src, dst, reps, stream))

@@ -216,7 +216,22 @@ struct PermuteArgs {
   int dims[PERMUTE_MAX_RANK];
   long long in_stride[PERMUTE_MAX_RANK];
 };
-hipError_t launch_permute(int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s);
+// variant: PERMUTE_AUTO picks the kernel, PERMUTE_ELEMENTWISE and
+// PERMUTE_TILED force one (the tiled kernel returns hipErrorInvalidValue for
+// a transposition it cannot tile).
+enum { PERMUTE_AUTO = 0, PERMUTE_ELEMENTWISE = 1, PERMUTE_TILED = 2 };
+hipError_t launch_permute(int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s,
+                          int variant = PERMUTE_AUTO);
+
+// Sum of the split-K partial products of a contraction (complex128):
+// out[item][e] = sum_{s < parts} part[item][s * mn + e] for e < mn, the
+// parts added in order s = 0, 1, ...
+struct KsumArgs {
+  Operand part, out;
+  const int* ids;
+  int parts, mn, batch, pad_;
+};
+hipError_t launch_ksum(const KsumArgs& a, hipStream_t s);
 
 // Writes (1, 0), (0, 0) as two complex words at each listed address.
 hipError_t launch_fill_unit(int ct, void* const* ptrs_dev, int n, hipStream_t s);

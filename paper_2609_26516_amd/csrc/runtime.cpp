@@ -2366,6 +2366,13 @@ int permute(dcs_ctx* ctx, int ct_in, int ct_out, const PermuteArgs& a, hipStream
   return DCS_OK;
 }
 
+int ksum(dcs_ctx* ctx, const KsumArgs& a, hipStream_t s, int cls) {
+  const double bytes = 16.0 * a.mn * (a.parts + 1.0) * a.batch;
+  Timed t(ctx, s, cls, 2.0 * a.mn * a.parts * a.batch, bytes);
+  DCS_HIP(launch_ksum(a, s));
+  return DCS_OK;
+}
+
 void tune_sync(dcs_ctx* ctx) { tune_resolve(ctx); }
 
 int ctx_device(const dcs_ctx* ctx) { return ctx->device; }

@@ -56,6 +56,7 @@ int gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
          const std::vector<GemmJob>& jobs, hipStream_t s, int cls);
 int qr(dcs_ctx* ctx, int ct_in, int ct_out, const std::vector<QrJob>& jobs, hipStream_t s);
 int permute(dcs_ctx* ctx, int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s);
+int ksum(dcs_ctx* ctx, const KsumArgs& a, hipStream_t s, int cls);
 // Resolves pending tile-shape trials (after the stream has been synchronised).
 void tune_sync(dcs_ctx* ctx);
 int ctx_device(const dcs_ctx* ctx);

@@ -100,6 +100,49 @@ __global__ void __launch_bounds__(256) copy16_kernel(const int4* __restrict__ sr
     dst[i] = src[i];
 }
 
+// Arguments of a batched transposition of row-major items `dims` into leg
+// order `perm`, item b at base + b * (item bytes); DCS_OK or the error.
+int permute_args(int ct_in, int ct_out, int rank, const int* dims, const int* perm, int conj,
+                 int batch, int variant, PermuteArgs* a) {
+  if (rank < 1 || rank > PERMUTE_MAX_RANK || batch < 1 || batch > 65535 || !dims || !perm ||
+      variant < 0 || variant > 2 || ct_in < 0 || ct_in > 1 || ct_out < 0 || ct_out > 1)
+    return testing_fail(DCS_EINVAL, "bad permute test arguments");
+  long long total = 1;
+  std::vector<long long> stride(rank, 1);
+  std::vector<int> seen(rank, 0);
+  for (int k = rank - 1; k >= 0; --k) {
+    if (dims[k] < 1) return testing_fail(DCS_EINVAL, "permute test: leg extents must be positive");
+    stride[k] = total;
+    total *= dims[k];
+    if (total > (1LL << 28)) return testing_fail(DCS_EINVAL, "permute test: too large");
+  }
+  for (int k = 0; k < rank; ++k)
+    if (perm[k] < 0 || perm[k] >= rank || seen[perm[k]]++)
+      return testing_fail(DCS_EINVAL, "permute test: perm is not a permutation");
+  if (total * batch > (1LL << 28)) return testing_fail(DCS_EINVAL, "permute test: too large");
+  std::memset(a, 0, sizeof(*a));
+  a->in = op_of(nullptr, total * (long long)csz(ct_in));
+  a->out = op_of(nullptr, total * (long long)csz(ct_out));
+  a->ids = nullptr;
+  a->rank = rank;
+  a->conj = conj ? 1 : 0;
+  a->batch = batch;
+  a->total = total;
+  for (int k = 0; k < rank; ++k) {
+    a->dims[k] = dims[perm[k]];
+    a->in_stride[k] = stride[perm[k]];
+  }
+  return DCS_OK;
+}
+
+int run_permute(int ct_in, int ct_out, const PermuteArgs& a, int variant, hipStream_t s) {
+  const hipError_t e = launch_permute(ct_in, ct_out, a, s, variant);
+  if (e == hipErrorInvalidValue && variant == PERMUTE_TILED)
+    return testing_fail(DCS_EINVAL, "permute test: the tiled kernel does not take this transposition");
+  T_HIP(e);
+  return DCS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -266,6 +309,50 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
     T_HIP(hipMemcpyAsync(nrm2_out, dn.p, sizeof(double), hipMemcpyDeviceToHost, s));
     T_HIP(hipStreamSynchronize(s));
     unpack(ct_out, h, Q, mn);
+    return DCS_OK;
+  });
+}
+
+int dcs_test_permute(int ct_in, int ct_out, int rank, const int* dims, const int* perm, int conj,
+                     int batch, int variant, const double* in, double* out, void* stream) {
+  return guarded([&]() -> int {
+    PermuteArgs a;
+    int rc = permute_args(ct_in, ct_out, rank, dims, perm, conj, batch, variant, &a);
+    if (rc) return rc;
+    if (!in || !out) return testing_fail(DCS_EINVAL, "bad permute test arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf di, dout;
+    const size_t count = (size_t)a.total * batch;
+    rc = upload(ct_in, in, count, di, s);
+    if (rc) return rc;
+    T_HIP(hipMalloc(&dout.p, std::max<size_t>(count * csz(ct_out), 256)));
+    a.in.base = di.p;
+    a.out.base = dout.p;
+    rc = run_permute(ct_in, ct_out, a, variant, s);
+    if (rc) return rc;
+    std::vector<char> h(count * csz(ct_out));
+    T_HIP(hipMemcpyAsync(h.data(), dout.p, h.size(), hipMemcpyDeviceToHost, s));
+    T_HIP(hipStreamSynchronize(s));
+    unpack(ct_out, h, out, count);
+    return DCS_OK;
+  });
+}
+
+int dcs_test_permute_dev(int ct_in, int ct_out, int rank, const int* dims, const int* perm,
+                         int conj, int batch, int variant, const void* in, void* out, int reps,
+                         void* stream) {
+  return guarded([&]() -> int {
+    PermuteArgs a;
+    int rc = permute_args(ct_in, ct_out, rank, dims, perm, conj, batch, variant, &a);
+    if (rc) return rc;
+    if (!in || !out || reps < 1 || reps > 1000)
+      return testing_fail(DCS_EINVAL, "bad permute test arguments");
+    a.in.base = in;
+    a.out.base = out;
+    for (int r = 0; r < reps; ++r) {
+      rc = run_permute(ct_in, ct_out, a, variant, static_cast<hipStream_t>(stream));
+      if (rc) return rc;
+    }
     return DCS_OK;
   });
 }

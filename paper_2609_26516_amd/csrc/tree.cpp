@@ -636,7 +636,58 @@ struct Exec {
     j.ldc = (int)N;
     j.batch = batch;
     const int acc = tc == CT_F64 ? CT_F64 : tacc;
-    if (!dry) TT_TRY(rt::gemm(tr->ctx, A.ct, B.ct, tc, acc, opa, opb, {j}, s, cls));
+    // Split sum: a complex128 contraction with a single output tile per item
+    // and a long sum (the top-level inner products of the measurement) would
+    // run as one workgroup per item; its sum is cut into chunks computed side
+    // by side into an executor buffer, then added chunk by chunk in order.
+    const long long item_tiles = ((M + 31) / 32) * ((N + 31) / 32) * (long long)batch;
+    long long parts = 1;
+    if (tc == CT_F64 && M * N <= 1024 && K >= 4096)
+      parts = std::max(1LL, std::min({K / 1024, 1024 / item_tiles, (long long)GEMM_MAX_GROUPS}));
+    // (without a free executor buffer the contraction runs unsplit)
+    int pbuf = -1;
+    if (parts > 1 && !dry) {
+      for (int i = 0; i < NBUF && pbuf < 0; ++i)
+        if (!used[i]) {
+          used[i] = true;
+          pbuf = i;
+        }
+      if (pbuf < 0) parts = 1;
+    }
+    if (parts > 1) {
+      const long long kc = (K + parts - 1) / parts;
+      parts = (K + kc - 1) / kc;
+      TT_TRY(fits(parts * M * N, CT_F64));
+      const Operand pop = pbuf >= 0 ? buf_op(pbuf) : rt::local(nullptr, 0);
+      std::vector<rt::GemmJob> jobs;
+      for (long long q = 0; q < parts; ++q) {
+        const long long k0 = q * kc;
+        rt::GemmJob jq = j;
+        jq.K = (int)std::min(kc, K - k0);
+        jq.a = offset_op(A.op, (size_t)(k0 * (opa == OP_C ? j.lda : 1)) * csize(A.ct));
+        jq.b = offset_op(B.op, (size_t)(k0 * (opb == OP_N ? j.ldb : 1)) * csize(B.ct));
+        jq.c = offset_op(pop, (size_t)(q * M * N) * csize(CT_F64));
+        jq.ldc = (int)N;
+        jobs.push_back(jq);
+      }
+      if (!dry) {
+        TT_TRY(rt::gemm(tr->ctx, A.ct, B.ct, tc, acc, opa, opb, jobs, s, cls));
+        KsumArgs ka;
+        std::memset(&ka, 0, sizeof(ka));
+        ka.part = pop;
+        ka.out = c.op;
+        ka.ids = ids;
+        ka.parts = (int)parts;
+        ka.mn = (int)(M * N);
+        ka.batch = batch;
+        TT_TRY(rt::ksum(tr->ctx, ka, s, cls));
+      }
+      Ten pt;
+      pt.buf = pbuf;
+      give(pt);
+    } else if (!dry) {
+      TT_TRY(rt::gemm(tr->ctx, A.ct, B.ct, tc, acc, opa, opb, {j}, s, cls));
+    }
     if (pa) give(tmpA);
     if (pb) give(tmpB);
     *out = c;

@@ -241,3 +241,80 @@ def test_copy_kernel(capi):
                        torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+def _perm_ref(x, perm, conj, ct_out):
+    """Definition of the batched transposition: item b's legs reordered."""
+    y = np.transpose(x, [0] + [p + 1 for p in perm])
+    if conj:
+        y = np.conj(y)
+    if ct_out == F32:
+        y = y.astype(np.complex64)
+    return y.astype(np.complex128)
+
+
+# Leg transpositions of the tree contraction executor (the kind that move a
+# bond leg to the end or bring shared legs together), and ragged ones.
+PERM_CASES = [
+    ((8, 32, 32, 4), (1, 2, 0, 3)),          # middle legs outward
+    ((32, 32, 8, 8, 4), (3, 0, 1, 4, 2)),
+    ((1024, 8, 4, 8), (0, 3, 2, 1)),
+    ((64, 128), (1, 0)),                     # plain matrix transpose
+    ((512, 32), (1, 0)),
+    ((8, 1024, 32), (0, 2, 1)),
+    ((33, 31, 5), (2, 0, 1)),                # no power-of-two leg
+    ((7, 3, 100, 2), (3, 2, 1, 0)),
+    ((2, 2, 2, 2, 2, 2, 2, 2), (7, 0, 6, 1, 5, 2, 4, 3)),
+    ((67, 129), (1, 0)),                     # prime-ish extents larger than a run
+    ((5, 1, 7, 1), (3, 2, 1, 0)),            # unit legs
+    ((300,), (0,)),                          # rank 1: a copy
+]
+
+
+@pytest.mark.parametrize("cts", [(F32, F32), (F64, F64), (F32, F64), (F64, F32)])
+@pytest.mark.parametrize("case", PERM_CASES)
+def test_permute(capi, case, cts):
+    """Every kernel of the leg transposition against its definition, bit for
+    bit (a copy with a storage conversion; the tiled kernel only where it
+    takes the transposition)."""
+    dims, perm = case
+    rng = np.random.default_rng(sum(dims) + 7 * len(dims))
+    for batch, conj in ((1, False), (3, True)):
+        x = _rand(rng, batch, *dims)
+        if cts[0] == F32:
+            x = x.astype(np.complex64).astype(np.complex128)
+        ref = _perm_ref(x, perm, conj, cts[1])
+        for variant in (0, 1, 2):
+            try:
+                y = capi.dcs_test_permute(cts[0], cts[1], x, perm, conj, variant)
+            except RuntimeError as e:
+                assert variant == 2 and "tiled kernel does not take" in str(e)
+                continue
+            np.testing.assert_array_equal(y, ref, err_msg=f"variant {variant}")
+
+
+def test_permute_tiled_takes_tree_shapes(capi):
+    """The tiled kernel takes the transpositions of bond legs with extents of
+    powers of two (the tree's), and random ragged ones agree with the
+    definition."""
+    rng = np.random.default_rng(11)
+    for dims, perm in PERM_CASES[:6]:
+        x = _rand(rng, 2, *dims).astype(np.complex64).astype(np.complex128)
+        y = capi.dcs_test_permute(F32, F32, x, perm, False, 2)
+        np.testing.assert_array_equal(y, _perm_ref(x, perm, False, F32))
+    choices = [1, 2, 3, 4, 5, 7, 8, 16, 31, 32, 33, 64]
+    for _ in range(40):
+        rank = int(rng.integers(2, 7))
+        dims = [int(rng.choice(choices)) for _ in range(rank)]
+        while np.prod(dims) > 200000:
+            dims[int(np.argmax(dims))] //= 2
+        perm = [int(p) for p in rng.permutation(rank)]
+        x = _rand(rng, 2, *dims)
+        for variant in (0, 2):
+            try:
+                y = capi.dcs_test_permute(F64, F64, x, perm, True, variant)
+            except RuntimeError as e:
+                assert variant == 2 and "tiled kernel does not take" in str(e)
+                continue
+            np.testing.assert_array_equal(y, _perm_ref(x, perm, True, F64),
+                                          err_msg=f"{dims} {perm} variant {variant}")

@@ -77,6 +77,46 @@ def test_tree_single_path_against_oracle(eng, prec, levels, chi, depth):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("levels,chi", [([1, 4, 16], 16), ([1, 2, 4, 8, 16], 64)])
+def test_tree_long_sums_against_statevector(eng, prec, levels, chi):
+    """Trees whose top-level contractions have one small output and a long
+    sum (16^4 and 64^2 terms at the root, computed in chunks side by side):
+    in the exact regime the compressed state is U|0> (statevector of the
+    circuit's first run of gates) and every p_0 of the measurement
+    contraction is the Born-rule value of the exported state."""
+    from inputs.circuits import CGate
+    from oracle import statevector as SV
+    E = _E()
+    n = levels[-1]
+    circ, prm = C.workload("cfg1_n10_chi16", n=n, depth=4, chi=chi)
+    seg = E._segments(circ)[0]
+    psi = SV.zero_state(n)
+    for i in seg:
+        assert not isinstance(circ.ops[i], CGate)
+        g = circ.ops[i]
+        psi = SV.apply_gate(psi, n, g.qubits, np.asarray(g.mat, dtype=np.complex128))
+    tree = OT.Tree(levels)
+    st = E.TreeState(eng, prec, levels, 2, chi, 16, [chi], prm["init_seed"], circ=circ)
+    try:
+        ids = st.alloc(2)
+        st.init_zero(ids, [chi, chi])
+        h = st.chunk(circ, seg)
+        st.compress(ids, [h, h], 2)
+        p0 = np.array([st.measure(ids, [q, q]) for q in range(n)])
+        for b in range(2):
+            got = OT.to_statevector(tree, st.export(int(ids[b])))
+            nrm = np.vdot(got, got).real
+            fe = abs(1 - abs(np.vdot(got, psi)) ** 2 / nrm)
+            born = np.array([SV.outcome_norms(got, n, q)[0] / nrm for q in range(n)])
+            dp = np.max(np.abs(p0[:, b] - born))
+            print(f"{levels} chi {chi} {prec}: fidelity error {fe:.2e}, max |dp| {dp:.2e}")
+            assert fe <= TOL[prec]
+            assert dp <= TOL[prec]
+    finally:
+        st.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_tree_multi_path_uneven_chi_against_oracle(eng, prec):
     levels = [1, 3, 9]
     n = 9
