@@ -88,6 +88,17 @@ __device__ __forceinline__ double2* qrl_wparts(double2* ws, int m, int n) {
   return reinterpret_cast<double2*>(qrl_partials(ws, m, n) + QRL_CHUNKS);
 }
 
+// Scratch of the split panel factorisation (after the W parts): G1 and G2
+// parts of up to QRT_MAXCH row chunks, a copy of Q1's top block, and the
+// fallback flag (its real part).
+constexpr int QRT_CH = 256;                          // rows per chunk workgroup
+constexpr int QRT_MAXCH = 2048 / QRT_CH;
+constexpr int QRT_SCRATCH = 2 * QRT_MAXCH * 256 + 256 + 16;
+__device__ __forceinline__ double2* qrt_scratch(double2* ws, int m, int n) {
+  const long long parts = (long long)((n + 15) / 16) * ((m + QRL_CH - 1) / QRL_CH) * 256;
+  return qrl_wparts(ws, m, n) + parts;
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void qrl_wpart_kernel(const QrArgs args, int p, int c_off) {
   __shared__ double2 sW[4][256];
@@ -131,10 +142,14 @@ __global__ __launch_bounds__(256) void qrl_wpart_kernel(const QrArgs args, int p
   qrl_wparts(A, m, n)[((long long)blockIdx.x * nchunk + blockIdx.y) * 256 + e] = sum;
 }
 
+// In the forward pass (c_off = NB) the strip-0 workgroups, which update the
+// next panel's columns, also leave that panel's G1 part of their rows (those
+// below the next panel's first row) in the split panel's scratch.
 template <int NB>
 __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int p, int c_off,
                                                          int conj_t) {
   __shared__ double2 sW[256];
+  __shared__ double2 sG[4 * 256];
   const QrlItem it = qrl_item(args, blockIdx.z);
   const int m = it.g->m, n = it.g->n;
   const int c0 = p + c_off + 16 * blockIdx.x;
@@ -209,20 +224,46 @@ __global__ __launch_bounds__(256) void qrl_update_kernel(const QrArgs args, int 
       vv[h][t] = (i < r1 && sref < nbk) ? V[(long long)(p + i) * n + p + sref] : zero;
     }
   }
+  const bool gram = c_off == NB && blockIdx.x == 0;   // uniform
+  CAcc3 g;
+  g.zero();
+  bool z = false;
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     CAcc3 e;   // V W2 for this block
     e.zero();
 #pragma unroll
     for (int t = 0; t < NB / 4; ++t) e.add(vv[h][t].x, vv[h][t].y, xr[t], xi[t]);
-    if (col_ok) {
+    double2 nv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = r0 + 16 * h + lk + 4 * t;
+      nv[t] = make_double2(av[h][t].x - e.re(t), av[h][t].y - e.im(t));
+      if (col_ok && i < r1) A[(long long)(p + i) * n + col] = nv[t];
+    }
+    if (gram) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int i = r0 + 16 * h + lk + 4 * t;
-        if (i < r1)
-          A[(long long)(p + i) * n + col] = make_double2(av[h][t].x - e.re(t), av[h][t].y - e.im(t));
+        const bool in = col_ok && i >= NB && i < r1;
+        const double2 a = in ? nv[t] : zero;
+        z = z || (in && a.x == 0.0 && a.y == 0.0);
+        g.add(a.x, -a.y, a.x, a.y);
       }
     }
+  }
+  if (gram) {
+    const bool anyz = __ballot(z) != 0ull;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      sG[wave * 256 + (lk + 4 * r) * 16 + li] =
+          make_double2(g.re(r), lane == 0 && r == 0 ? (anyz ? 1.0 : 0.0) : g.im(r));
+    __syncthreads();
+    const int e = threadIdx.x;
+    double2 sum = sG[e];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) sum = make_double2(sum.x + sG[w * 256 + e].x, sum.y + sG[w * 256 + e].y);
+    qrt_scratch(A, m, n)[blockIdx.y * 256 + e] = sum;
   }
 }
 
@@ -451,134 +492,18 @@ __global__ __launch_bounds__(512, 1) void qrs_update_kernel(const QrArgs args, i
   }
 }
 
-// Panel factorisation for 512 < m <= 2048 rows, one 512-thread workgroup per
-// matrix: as qrs_panel_kernel, with the panel streamed from the working
-// matrix in 16-row blocks (block c to wave c mod 8) instead of held in
-// registers: G1 from A, Q1 = A R1^{-1} into the V area (its top block also to
-// LDS) with G2 beside it, then V = Q1 R2^{-1} U^{-1} in place in the V area.
-// The fallback factors the panel rows of A column by column, four rows per
-// thread.
-constexpr int QRT_RP = 4;   // rows per thread of the fallback (2048 rows)
+// Column-by-column factorisation of the panel rows of A (512 < m <= 2048
+// rows, four rows per thread of a 512-thread workgroup), for panels the
+// Cholesky QR does not take: writes V (unit diagonal) and T.  sP (16 QB
+// values) and sWp (8 x 256) are its LDS scratch.
+constexpr int QRT_RP = 4;   // rows per thread (2048 rows)
 
-__global__ __launch_bounds__(512, 1) void qrs_panel_tall_kernel(const QrArgs args, int p) {
-  __shared__ __attribute__((aligned(16))) double2 sP[16 * QB];   // top block; fallback scratch
-  __shared__ __attribute__((aligned(16))) double2 sWp[QRS_NW * 256];
-  static_assert(sizeof(PanelSmem2<QRS_NW, QB>) <= sizeof(sP), "fallback scratch fits");
+__device__ __noinline__ void tall_fallback(const double2* A, double2* V, double2* Tg, int p, int n,
+                                           int mp, int nbk, int k, double2* sP, double2* sWp) {
+  static_assert(sizeof(PanelSmem2<QRS_NW, QB>) <= 16 * QB * sizeof(double2), "fallback scratch fits");
   PanelSmem2<QRS_NW, QB>& psm = *reinterpret_cast<PanelSmem2<QRS_NW, QB>*>(sP);
-  const QrlItem it = qrl_item(args, blockIdx.x);
-  const int m = it.g->m, n = it.g->n;
-  if (p >= n) return;
-  double2* A = qrl_ws(it);
-  double2* V = A + (long long)m * n;
-  double2* Tg = V + (long long)m * n;
-  const int mp = m - p, nbk = min(QB, n - p), k = p / QB, nblk = (mp + 15) / 16;
-  int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));   // lane offsets formed here, not hoisted
-  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int li = lane & 15, lk = lane >> 4;
+  const int tid = threadIdx.x;
   const double2 zero = make_double2(0.0, 0.0);
-
-  if (p == 0 && tid == 0) {   // |F|^2 from the chunk partials, in a fixed order
-    const double* part = qrl_partials(A, m, n);
-    double s = 0.0;
-    for (int c = 0; c < QRL_CHUNKS; ++c) s += part[c];
-    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
-  }
-  bool chol = mp > nbk;   // uniform
-  if (chol) {
-    {   // this wave's part of G1 = A^H A; imaginary part of entry (0, 0): an exact zero seen
-      CAcc3 g;
-      g.zero();
-      bool z = false;
-      for (int c = wave; c < nblk; c += QRS_NW) {
-        double2 a4[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = 16 * c + 4 * t + lk;
-          const bool in = i < mp && li < nbk;
-          a4[t] = in ? A[(long long)(p + i) * n + p + li] : zero;
-          z = z || (in && a4[t].x == 0.0 && a4[t].y == 0.0);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) g.add(a4[t].x, -a4[t].y, a4[t].x, a4[t].y);
-      }
-      const bool anyz = __ballot(z) != 0ull;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        sWp[wave * 256 + (lk + 4 * r) * 16 + li] =
-            make_double2(g.re(r), lane == 0 && r == 0 ? (anyz ? 1.0 : 0.0) : g.im(r));
-    }
-    __syncthreads();
-    if (wave == 0) panel_first_pass<QRS_NW>(sWp, nbk);
-    __syncthreads();
-    chol = sWp[16].x == 0.0;
-    double2 xb[4];   // X1[lk + 4s][li], the B operand of k-step s
-#pragma unroll
-    for (int s = 0; s < 4; ++s) xb[s] = sWp[(lk + 4 * s) * 16 + li];
-    __syncthreads();   // flag and X1 read everywhere before the LDS is rewritten
-    if (chol) {   // Q1 = A X1 into the V area, G2 parts
-      CAcc3 g2;
-      g2.zero();
-      for (int c = wave; c < nblk; c += QRS_NW) {
-        CAcc3 q;
-        q.zero();
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int i = 16 * c + li, col = 4 * s + lk;
-          const double2 av = (i < mp && col < nbk) ? A[(long long)(p + i) * n + p + col] : zero;
-          q.add(av.x, av.y, xb[s].x, xb[s].y);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * c + lk + 4 * r;
-          const double2 qv = make_double2(q.re(r), q.im(r));
-          if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = qv;
-          if (c == 0) sP[pidx(lk + 4 * r, li)] = qv;
-          g2.add(qv.x, -qv.y, qv.x, qv.y);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        sWp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(g2.re(r), g2.im(r));
-      __threadfence_block();
-      __syncthreads();
-      if (wave == 0) panel_second_pass<QRS_NW>(sP, sWp, nbk, mp);
-      __syncthreads();
-      chol = sWp[16].x == 0.0;
-      if (chol) {   // V below the top block = Q1 M in place; the top block and T
-        double2 mb[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) mb[s] = sWp[256 + (lk + 4 * s) * 16 + li];
-        for (int c = wave; c < nblk; c += QRS_NW) {
-          if (c == 0) continue;
-          CAcc3 y;
-          y.zero();
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int i = 16 * c + li, col = 4 * s + lk;
-            const double2 av = (i < mp && col < nbk) ? V[(long long)(p + i) * n + p + col] : zero;
-            y.add(av.x, av.y, mb[s].x, mb[s].y);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * c + lk + 4 * r;
-            if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = make_double2(y.re(r), y.im(r));
-          }
-        }
-        if (wave == 0) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = lk + 4 * r;
-            if (i < mp && li < nbk) V[(long long)(p + i) * n + p + li] = sP[pidx(i, li)];
-          }
-        }
-        if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sWp[tid];
-        return;
-      }
-      __syncthreads();   // every wave has read the flag before the fallback reuses the LDS
-    }
-  }
-  // column by column, the panel rows of A (four rows per thread)
   double2 a[QRT_RP][QB];
 #pragma unroll
   for (int r = 0; r < QRT_RP; ++r) {
@@ -604,12 +529,233 @@ __global__ __launch_bounds__(512, 1) void qrs_panel_tall_kernel(const QrArgs arg
   if (tid < QB * QB) Tg[(long long)k * QB * QB + tid] = sWp[tid];
 }
 
+// Panel factorisation for 512 < m <= 2048 rows: Cholesky QR twice and
+// Householder reconstruction (qr_cholpanel.h) with the row work of each
+// 16-column panel spread over one 512-thread workgroup per 256-row chunk
+// (block c of the chunk to wave c mod 8):
+//   G1 parts   one per row chunk (exact-zero flag in Im G[0][0]): for the
+//              first panel from qrt_gram, for the others from the strip-0
+//              workgroups of the previous panel's update, which have just
+//              written those columns
+//   qrt_q1     every workgroup sums the parts in chunk order and forms
+//              R1^{-1} (identical in all of them); Q1 = A R1^{-1} into the V
+//              area, its top block also to the scratch, G2 parts
+//   qrt_v      every workgroup sums the G2 parts and runs the
+//              reconstruction on the top block (identical in all of them);
+//              V = Q1 M in place, V's top block and T from chunk 0
+// A panel the Cholesky QR does not take (an exact zero, a small pivot, a
+// squared norm out of range, no rows below the diagonal block) is factored
+// column by column by the chunk-0 workgroup of qrt_v (tall_fallback); qrt_q1
+// passes its verdict on through the flag in the scratch.
+struct QrtCtx {
+  double2 *A, *V, *Tg, *sc;
+  int m, n, mp, nbk, k, nblk, nch;
+  bool live;   // this workgroup's chunk holds rows of the panel
+};
+
+__device__ __forceinline__ QrtCtx qrt_ctx(const QrArgs& args, int p) {
+  const QrlItem it = qrl_item(args, blockIdx.y);
+  QrtCtx c;
+  c.m = it.g->m;
+  c.n = it.g->n;
+  c.A = qrl_ws(it);
+  c.V = c.A + (long long)c.m * c.n;
+  c.Tg = c.V + (long long)c.m * c.n;
+  c.sc = qrt_scratch(c.A, c.m, c.n);
+  c.mp = c.m - p;
+  c.nbk = min(QB, c.n - p);
+  c.k = p / QB;
+  c.nblk = (c.mp + 15) / 16;
+  c.nch = (c.mp + QRT_CH - 1) / QRT_CH;
+  c.live = p < c.n && (int)blockIdx.x < c.nch;
+  return c;
+}
+
+// Sums the waves' 16 x 16 parts in sWp (8 x 256) into part 0 of sWp, then
+// writes it to dst (256 values).
+__device__ __forceinline__ void qrt_reduce_store(double2* sWp, double2* dst, int tid) {
+  __syncthreads();
+  if (tid < 256) {
+    double2 s = sWp[tid];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) s = make_double2(s.x + sWp[w * 256 + tid].x, s.y + sWp[w * 256 + tid].y);
+    dst[tid] = s;
+  }
+}
+
+// Loads the chunk parts src[0 .. nch) into sWp as eight parts (zeros beyond
+// nch).
+__device__ __forceinline__ void qrt_load_parts(double2* sWp, const double2* src, int nch, int tid) {
+  for (int e = tid; e < 8 * 256; e += 512)
+    sWp[e] = (e >> 8) < nch ? src[e] : make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(512, 1) void qrt_gram_kernel(const QrArgs args, int p) {
+  __shared__ __attribute__((aligned(16))) double2 sWp[8 * 256];
+  const QrtCtx c = qrt_ctx(args, p);
+  if (!c.live) return;
+  if (p == 0 && blockIdx.x == 0 && threadIdx.x == 0) {   // |F|^2 from the load's chunk sums
+    const QrlItem it = qrl_item(args, blockIdx.y);
+    const double* part = qrl_partials(c.A, c.m, c.n);
+    double s = 0.0;
+    for (int q = 0; q < QRL_CHUNKS; ++q) s += part[q];
+    *reinterpret_cast<double*>(const_cast<char*>(item_ptr(it.g->nrm2, it.g->ids, it.item))) = s;
+  }
+  if (c.mp <= c.nbk) return;   // column by column
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+  const int b0 = blockIdx.x * (QRT_CH / 16), b1 = min(c.nblk, b0 + QRT_CH / 16);
+  CAcc3 g;
+  g.zero();
+  bool z = false;
+  for (int b = b0 + wave; b < b1; b += 8) {
+    double2 a4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = 16 * b + 4 * t + lk;
+      const bool in = i < c.mp && li < c.nbk;
+      a4[t] = in ? c.A[(long long)(p + i) * c.n + p + li] : zero;
+      z = z || (in && a4[t].x == 0.0 && a4[t].y == 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g.add(a4[t].x, -a4[t].y, a4[t].x, a4[t].y);
+  }
+  const bool anyz = __ballot(z) != 0ull;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    sWp[wave * 256 + (lk + 4 * r) * 16 + li] =
+        make_double2(g.re(r), lane == 0 && r == 0 ? (anyz ? 1.0 : 0.0) : g.im(r));
+  qrt_reduce_store(sWp, c.sc + blockIdx.x * 256, tid);
+}
+
+__global__ __launch_bounds__(512, 1) void qrt_q1_kernel(const QrArgs args, int p) {
+  __shared__ __attribute__((aligned(16))) double2 sWp[8 * 256];
+  const QrtCtx c = qrt_ctx(args, p);
+  if (!c.live) return;
+  double2* flag = c.sc + QRT_SCRATCH - 16;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+  if (c.mp <= c.nbk) {   // no rows below the diagonal block: column by column
+    if (blockIdx.x == 0 && tid == 0) *flag = make_double2(1.0, 0.0);
+    return;
+  }
+  // G1 parts: one per chunk of qrt_gram (first panel) or of the previous
+  // panel's update (its rows start 16 above)
+  const int nparts = p == 0 ? c.nch : (c.mp + QB + QRL_CH - 1) / QRL_CH;
+  qrt_load_parts(sWp, c.sc, nparts, tid);
+  __syncthreads();
+  if (wave == 0) panel_first_pass<8>(sWp, c.nbk);
+  __syncthreads();
+  const bool ok = sWp[16].x == 0.0;
+  if (blockIdx.x == 0 && tid == 0) *flag = make_double2(ok ? 0.0 : 1.0, 0.0);
+  if (!ok) return;
+  double2 xb[4];   // X1[lk + 4s][li], the B operand of k-step s
+#pragma unroll
+  for (int s = 0; s < 4; ++s) xb[s] = sWp[(lk + 4 * s) * 16 + li];
+  __syncthreads();   // X1 read everywhere before the parts are rewritten
+  const int b0 = blockIdx.x * (QRT_CH / 16), b1 = min(c.nblk, b0 + QRT_CH / 16);
+  double2* qtop = c.sc + 2 * QRT_MAXCH * 256;
+  CAcc3 g2;
+  g2.zero();
+  for (int b = b0 + wave; b < b1; b += 8) {
+    CAcc3 q;
+    q.zero();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = 16 * b + li, col = 4 * s + lk;
+      const double2 av = (i < c.mp && col < c.nbk) ? c.A[(long long)(p + i) * c.n + p + col] : zero;
+      q.add(av.x, av.y, xb[s].x, xb[s].y);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * b + lk + 4 * r;
+      const double2 qv = make_double2(q.re(r), q.im(r));
+      if (i < c.mp && li < c.nbk) c.V[(long long)(p + i) * c.n + p + li] = qv;
+      if (b == 0) qtop[pidx(lk + 4 * r, li)] = qv;
+      g2.add(qv.x, -qv.y, qv.x, qv.y);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    sWp[wave * 256 + (lk + 4 * r) * 16 + li] = make_double2(g2.re(r), g2.im(r));
+  qrt_reduce_store(sWp, c.sc + (QRT_MAXCH + blockIdx.x) * 256, tid);
+}
+
+__global__ __launch_bounds__(512, 1) void qrt_v_kernel(const QrArgs args, int p) {
+  __shared__ __attribute__((aligned(16))) double2 sP[16 * QB];
+  __shared__ __attribute__((aligned(16))) double2 sWp[8 * 256];
+  const QrtCtx c = qrt_ctx(args, p);
+  if (!c.live) return;
+  const double2* flag = c.sc + QRT_SCRATCH - 16;
+  if (flag->x != 0.0) {   // the first pass did not take the panel
+    if (blockIdx.x == 0) tall_fallback(c.A, c.V, c.Tg, p, c.n, c.mp, c.nbk, c.k, sP, sWp);
+    return;
+  }
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
+  qrt_load_parts(sWp, c.sc + QRT_MAXCH * 256, c.nch, tid);
+  const double2* qtop = c.sc + 2 * QRT_MAXCH * 256;
+  if (tid < 256) sP[tid] = qtop[tid];
+  __syncthreads();
+  if (wave == 0) panel_second_pass<8>(sP, sWp, c.nbk, c.mp);
+  __syncthreads();
+  if (sWp[16].x != 0.0) {   // identical in every workgroup
+    if (blockIdx.x == 0) {
+      __syncthreads();   // the flag read everywhere before the LDS is reused
+      tall_fallback(c.A, c.V, c.Tg, p, c.n, c.mp, c.nbk, c.k, sP, sWp);
+    }
+    return;
+  }
+  double2 mb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) mb[s] = sWp[256 + (lk + 4 * s) * 16 + li];
+  const int b0 = blockIdx.x * (QRT_CH / 16), b1 = min(c.nblk, b0 + QRT_CH / 16);
+  for (int b = b0 + wave; b < b1; b += 8) {
+    if (b == 0) continue;
+    CAcc3 y;
+    y.zero();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = 16 * b + li, col = 4 * s + lk;
+      const double2 av = (i < c.mp && col < c.nbk) ? c.V[(long long)(p + i) * c.n + p + col] : zero;
+      y.add(av.x, av.y, mb[s].x, mb[s].y);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * b + lk + 4 * r;
+      if (i < c.mp && li < c.nbk) c.V[(long long)(p + i) * c.n + p + li] = make_double2(y.re(r), y.im(r));
+    }
+  }
+  if (blockIdx.x == 0) {
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = lk + 4 * r;
+        if (i < c.mp && li < c.nbk) c.V[(long long)(p + i) * c.n + p + li] = sP[pidx(i, li)];
+      }
+    }
+    if (tid < QB * QB) c.Tg[(long long)c.k * QB * QB + tid] = sWp[tid];
+  }
+}
+
 template <int CTI, int CTO>
 hipError_t run_tall(QrArgs args, int items, int m_max, int n_max, hipStream_t s) {
   const dim3 chunks(QRL_CHUNKS, items);
   hipLaunchKernelGGL((qrl_load_kernel<CTI>), chunks, dim3(256), 0, s, args);
+  const dim3 pch((m_max + QRT_CH - 1) / QRT_CH, items);
+  hipLaunchKernelGGL(qrt_gram_kernel, pch, dim3(512), 0, s, args, 0);
   for (int p = 0; p < n_max; p += QB) {
-    hipLaunchKernelGGL(qrs_panel_tall_kernel, dim3(items), dim3(512), 0, s, args, p);
+    hipLaunchKernelGGL(qrt_q1_kernel, pch, dim3(512), 0, s, args, p);
+    hipLaunchKernelGGL(qrt_v_kernel, pch, dim3(512), 0, s, args, p);
     const int strips = (n_max - p - QB + 15) / 16;
     if (strips > 0) {
       const dim3 grid(strips, (m_max - p + QRL_CH - 1) / QRL_CH, items);
@@ -652,7 +798,7 @@ int qr_large_max_rows() { return 2048; }
 
 size_t qr_large_ws_elems(int m, int n) {
   const size_t parts = (((size_t)n + 15) / 16) * (((size_t)m + QRL_CH - 1) / QRL_CH) * 256;
-  return 2 * (size_t)m * n + 16 * ((size_t)n + 16) + QRL_CHUNKS / 2 + parts + 1;
+  return 2 * (size_t)m * n + 16 * ((size_t)n + 16) + QRL_CHUNKS / 2 + parts + QRT_SCRATCH + 1;
 }
 
 hipError_t launch_qr_large(int ct_in, int ct_out, const QrArgs& args_in, hipStream_t s) {

@@ -203,9 +203,9 @@ def test_qr_tiny_noise_columns(capi, mode, tiny, variant, m, n):
 @pytest.mark.parametrize("m,n", [(64, 32), (513, 200), (600, 300), (1024, 512), (1030, 515),
                                  (1500, 700), (2048, 37), (2048, 1024)])
 def test_qr_large_matches_lapack(capi, m, n):
-    """Multi-kernel path for more than 512 rows (16-column panels up to 1024
-    rows, 8-column panels above): same reflectors as LAPACK, so Q agrees
-    element-wise, in both the QR and the LQ layout."""
+    """Multi-kernel path for more than 512 rows (16-column panels factored
+    over 256-row chunks, strip updates over 256-row chunks): same reflectors
+    as LAPACK, so Q agrees element-wise, in both the QR and the LQ layout."""
     rng = np.random.default_rng(m * 3 + n)
     f = _rand(rng, m, n)
     qn, _ = np.linalg.qr(f)
@@ -220,6 +220,30 @@ def test_qr_large_matches_lapack(capi, m, n):
     # complex64 storage in and out, FP64 inside
     q32, _ = capi.dcs_test_qr(F32, F32, m, n, 0, 3, f.astype(np.complex64).reshape(-1))
     assert np.max(np.abs(q32.reshape(m, n) - qn)) < 1e-5
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_qr_large_tiny_noise_columns(capi, mode):
+    """Panels the chunked Cholesky QR does not take (a column of noise far
+    below the FP64 square range, an exactly rank-deficient block) on the
+    multi-kernel path with several row chunks: finite and orthonormal."""
+    rng = np.random.default_rng(17 + mode)
+    m, n = 1100, 300
+    f = _rand(rng, m, 2) @ _rand(rng, 2, n) + 1e-170 * _rand(rng, m, n)
+    f[:, 7] *= 1e-170
+    f[:, 40] = 0
+    if mode == 0:
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 0, 3, f.reshape(-1))
+        q = q.reshape(m, n)
+        gram, rec, target = q.conj().T @ q, q @ (q.conj().T @ f), f
+    else:
+        g = f.conj().T.copy()
+        q, _ = capi.dcs_test_qr(F64, F64, m, n, 1, 3, g.reshape(-1))
+        q = q.reshape(n, m)
+        gram, rec, target = q @ q.conj().T, (g @ q.conj().T) @ q, g
+    assert np.all(np.isfinite(q))
+    np.testing.assert_allclose(gram, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(rec, target, atol=1e-12)
 
 
 def test_tile_shapes_bit_identical(capi):
