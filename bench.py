@@ -553,7 +553,7 @@ def main():
                "data": "synthetic: seeded Haar brickwork dynamic circuit",
                "config": {"workload": wl, "shots_per_step": 1, "graphs": args.graphs},
                "roofline": roofline(stats, "bf16x3", names={
-                   "qr": "qrs_panel_tall_kernel + qrl_wpart_kernel + qrl_update_kernel (m > 512), "
+                   "qr": "qrt_q1_kernel + qrt_v_kernel + qrl_wpart_kernel + qrl_update_kernel (m > 512), "
                          "qrs_* / qr_left_kernel (m <= 512)",
                    "gemm_nn": "gemm_bf16x3_kernel<0, 0>", "gemm_nt": "gemm_bf16x3_kernel<0, 1>",
                    "gemm_cn": "gemm_bf16x3_kernel<2, 0>", "gemm_jt": "gemm_bf16x3_kernel<3, 1>"})

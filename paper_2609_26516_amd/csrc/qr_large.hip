@@ -8,11 +8,12 @@
 // H_p ... H_{p+15} = I - V T V^H:
 //   qrl_load   F (mode 0) or F^H (mode 1) -> FP64 working matrix A (m x n,
 //              row-major), |F|^2 partial sums per chunk
-//   qrs_panel_tall (m > 512) / qrs_panel (m <= 512)
-//              one 512-thread workgroup per matrix factors A[p:, p:p+16] by
-//              Cholesky QR and Householder reconstruction (qr_cholpanel.h),
-//              or column by column where the panel does not allow it; writes
-//              the explicit V (unit diagonal) and T
+//   qrt_* (m > 512) / qrs_panel (m <= 512)
+//              A[p:, p:p+16] factored by Cholesky QR and Householder
+//              reconstruction (qr_cholpanel.h), or column by column where
+//              the panel does not allow it, by one 512-thread workgroup per
+//              256-row chunk (m > 512) or per matrix (m <= 512); writes the
+//              explicit V (unit diagonal) and T
 //   qrl_wpart  W = V^H A[p:, c:] in parts over (16-column strip, 256-row
 //   qrl_update chunk) tiles on FP64 MFMA, then A[p:, c:] -= V X W with
 //              X = T^H, every chunk summing its strip's parts in one order
