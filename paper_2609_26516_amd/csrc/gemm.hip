@@ -160,6 +160,12 @@ void gemm_kernel(const GemmArgs args) {
 
   const int tid = threadIdx.x;
   R ar[EA], ai[EA], br[EB], bi[EB];
+  // complex64 operands whose rows start on 16 bytes are staged two elements
+  // (16 bytes) per load where a thread's run lies inside the matrix
+  constexpr bool PA = sizeof(CA) == 8 && EA % 2 == 0, PB = sizeof(CB) == 8 && EB % 2 == 0;
+  const bool vec_a = PA && lda % 2 == 0 && (reinterpret_cast<unsigned long long>(A) & 15) == 0;
+  const bool vec_b = PB && EPI != GEMM_EPI_RIGHT && ldb % 2 == 0 &&
+                     (reinterpret_cast<unsigned long long>(B) & 15) == 0;
   if constexpr (EPI != GEMM_EPI_NONE) {   // visible after the first barrier
     const CC* __restrict__ W = reinterpret_cast<const CC*>(item_ptr(G.w, nullptr, item));
     const int nw = G.wl * 4 * G.wr;
@@ -171,6 +177,20 @@ void gemm_kernel(const GemmArgs args) {
       constexpr int TPR = BK / EA;
       const int row = tid / TPR, kq = (tid % TPR) * EA;
       const int m = m0 + row;
+      if constexpr (PA) {
+        if (vec_a && m < M && k0 + kq + EA <= K) {
+          const float4* q = reinterpret_cast<const float4*>(A + (long long)m * lda + k0 + kq);
+#pragma unroll
+          for (int u = 0; u < EA / 2; ++u) {
+            const float4 v = q[u];
+            ar[2 * u] = v.x;
+            ai[2 * u] = (OPA == OP_J) ? -v.y : v.y;
+            ar[2 * u + 1] = v.z;
+            ai[2 * u + 1] = (OPA == OP_J) ? -v.w : v.w;
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int k = k0 + kq + u;
@@ -186,6 +206,20 @@ void gemm_kernel(const GemmArgs args) {
     } else {  // OP_C: stored K x M, conjugated; EA consecutive m
       const int kr = tid / TPK, mq = (tid % TPK) * EA;
       const int k = k0 + kr;
+      if constexpr (PA) {
+        if (vec_a && k < K && m0 + mq + EA <= M) {
+          const float4* q = reinterpret_cast<const float4*>(A + (long long)k * lda + m0 + mq);
+#pragma unroll
+          for (int u = 0; u < EA / 2; ++u) {
+            const float4 v = q[u];
+            ar[2 * u] = v.x;
+            ai[2 * u] = -v.y;
+            ar[2 * u + 1] = v.z;
+            ai[2 * u + 1] = -v.w;
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int m = m0 + mq + u;
@@ -222,6 +256,20 @@ void gemm_kernel(const GemmArgs args) {
     if constexpr (OPB == OP_N) {  // stored K x N: EB consecutive n
       const int kr = tid / TPK, nq = (tid % TPK) * EB;
       const int k = k0 + kr;
+      if constexpr (PB && EPI != GEMM_EPI_RIGHT) {
+        if (vec_b && k < K && n0 + nq + EB <= N) {
+          const float4* q = reinterpret_cast<const float4*>(B + (long long)k * ldb + n0 + nq);
+#pragma unroll
+          for (int u = 0; u < EB / 2; ++u) {
+            const float4 v = q[u];
+            br[2 * u] = v.x;
+            bi[2 * u] = v.y;
+            br[2 * u + 1] = v.z;
+            bi[2 * u + 1] = v.w;
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         int n = n0 + nq + u;
@@ -244,6 +292,20 @@ void gemm_kernel(const GemmArgs args) {
       constexpr int TPR = BK / EB;
       const int nr = tid / TPR, kq = (tid % TPR) * EB;
       const int n = n0 + nr;
+      if constexpr (PB) {
+        if (vec_b && n < N && k0 + kq + EB <= K) {
+          const float4* q = reinterpret_cast<const float4*>(B + (long long)n * ldb + k0 + kq);
+#pragma unroll
+          for (int u = 0; u < EB / 2; ++u) {
+            const float4 v = q[u];
+            br[2 * u] = v.x;
+            bi[2 * u] = v.y;
+            br[2 * u + 1] = v.z;
+            bi[2 * u + 1] = v.w;
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int k = k0 + kq + u;
