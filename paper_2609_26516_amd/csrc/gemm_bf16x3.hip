@@ -76,11 +76,27 @@ struct Stage {
   static constexpr int E = R * BK / NT;
   float re[E], im[E];
 
+  // vec: rows of X start on 16 bytes; a thread's run inside the matrix is then
+  // read 16 bytes (two elements) at a time
   __device__ __forceinline__ void load(const float2* __restrict__ X, long long ld, int r0,
-                                       int rmax, int k0, int kmax, int tid) {
+                                       int rmax, int k0, int kmax, int tid, bool vec) {
     if constexpr (KMAJOR) {
       constexpr int TPR = BK / E;
       const int row = r0 + tid / TPR, kq = k0 + (tid % TPR) * E;
+      if constexpr (E % 2 == 0) {
+        if (vec && row < rmax && kq + E <= kmax) {
+          const float4* q = reinterpret_cast<const float4*>(X + (long long)row * ld + kq);
+#pragma unroll
+          for (int u = 0; u < E / 2; ++u) {
+            const float4 v = q[u];
+            re[2 * u] = v.x;
+            im[2 * u] = CONJ ? -v.y : v.y;
+            re[2 * u + 1] = v.z;
+            im[2 * u + 1] = CONJ ? -v.w : v.w;
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         float2 v = make_float2(0.f, 0.f);
@@ -91,6 +107,23 @@ struct Stage {
     } else {
       constexpr int H = E / 2, TPK = R / H;   // TPK threads per k pair
       const int kp = tid / TPK, rq = r0 + (tid % TPK) * H;
+      if constexpr (H % 2 == 0) {
+        if (vec && rq + H <= rmax && k0 + 2 * kp + 1 < kmax) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4* q = reinterpret_cast<const float4*>(X + (long long)(k0 + 2 * kp + h) * ld + rq);
+#pragma unroll
+            for (int u = 0; u < H / 2; ++u) {
+              const float4 v = q[u];
+              re[h * H + 2 * u] = v.x;
+              im[h * H + 2 * u] = CONJ ? -v.y : v.y;
+              re[h * H + 2 * u + 1] = v.z;
+              im[h * H + 2 * u + 1] = CONJ ? -v.w : v.w;
+            }
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = k0 + 2 * kp + h;
@@ -161,6 +194,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3_kernel(const GemmArgs args) {
   const float2* __restrict__ A = reinterpret_cast<const float2*>(item_ptr(G.a, G.ids, item));
   const float2* __restrict__ B = reinterpret_cast<const float2*>(item_ptr(G.b, G.ids, item));
   float2* __restrict__ C = reinterpret_cast<float2*>(const_cast<char*>(item_ptr(G.c, G.ids, item)));
+  const bool vec_a = G.lda % 2 == 0 && (reinterpret_cast<unsigned long long>(A) & 15) == 0;
+  const bool vec_b = G.ldb % 2 == 0 && (reinterpret_cast<unsigned long long>(B) & 15) == 0;
 
   const int tid = threadIdx.x;
   Stage<BM, OPA == OP_N || OPA == OP_J, OPA == OP_C || OPA == OP_J> sa;
@@ -183,8 +218,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3_kernel(const GemmArgs args) {
 
   const int nk = (K + BK - 1) / BK;
   if (nk > 0) {
-    sa.load(A, G.lda, m0, M, 0, K, tid);
-    sb.load(B, G.ldb, n0, N, 0, K, tid);
+    sa.load(A, G.lda, m0, M, 0, K, tid, vec_a);
+    sb.load(B, G.ldb, n0, N, 0, K, tid, vec_b);
   }
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
@@ -192,8 +227,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3_kernel(const GemmArgs args) {
     sb.store(sB, tid);
     __syncthreads();
     if (kt + 1 < nk) {
-      sa.load(A, G.lda, m0, M, (kt + 1) * BK, K, tid);
-      sb.load(B, G.ldb, n0, N, (kt + 1) * BK, K, tid);
+      sa.load(A, G.lda, m0, M, (kt + 1) * BK, K, tid, vec_a);
+      sb.load(B, G.ldb, n0, N, (kt + 1) * BK, K, tid, vec_b);
     }
     bf8 y[FN][4];
 #pragma unroll
