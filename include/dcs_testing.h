@@ -24,7 +24,11 @@ extern "C" {
  * 0 = FP32 MFMA, 2 = split-BF16 products on BF16 MFMA with FP32 accumulation,
  * complex64 storage only); only the combinations the library uses are available
  * (DCS_EINVAL otherwise).  variant: output tile shape 0 64x64, 1 32x32,
- * 2 128x64, 3 64x128, 4 128x128 (FP32 accumulation only). */
+ * 2 128x64, 3 64x128, 4 128x128 (FP32 accumulation only); plus 16 for the
+ * Hermitian mode of the measurement transfers (M = N, square tiles, not the
+ * split-BF16 form): only the tiles on and below the diagonal are computed and
+ * those below it also write their conjugate transpose above it, so C is
+ * exactly Hermitian when the product is Hermitian. */
 int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int N, int K,
                   int batch, int variant, const double *A, const double *B, double *C,
                   void *stream);

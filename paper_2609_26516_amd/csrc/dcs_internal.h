@@ -37,6 +37,11 @@ struct GemmGroup {
   // per batch item, call-locally addressed
   Operand w;
   int wl, wr;
+  // Hermitian product (M = N, square tiles, no epilogue): only the tiles on
+  // and below the diagonal are computed, tiles_per_item = T (T + 1) / 2 for
+  // T tile rows; each tile below the diagonal also writes its conjugate
+  // transpose above it
+  int herm, pad_;
 };
 
 constexpr int GEMM_MAX_GROUPS = 16;

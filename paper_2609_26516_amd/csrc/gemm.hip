@@ -148,9 +148,17 @@ void gemm_kernel(const GemmArgs args) {
   const int local = tile - G.tile_begin;
   const int item = local / G.tiles_per_item;
   const int t = local - item * G.tiles_per_item;
-  const int m0 = (t / G.tiles_n) * BM;
+  int tm = t / G.tiles_n, tn = t % G.tiles_n;
+  if (EPI == GEMM_EPI_NONE && G.herm) {   // t = tm (tm + 1) / 2 + tn, tn <= tm
+    tm = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    while (tm * (tm + 1) / 2 > t) --tm;
+    tn = t - tm * (tm + 1) / 2;
+  }
+  const int m0 = tm * BM;
   // right epilogue: tile columns (t, y) for y in [n0, n0 + BN / 2), t = 0, 1
-  const int n0 = (t % G.tiles_n) * (EPI == GEMM_EPI_RIGHT ? BN / 2 : BN);
+  const int n0 = tn * (EPI == GEMM_EPI_RIGHT ? BN / 2 : BN);
+  const bool mirror = EPI == GEMM_EPI_NONE && G.herm && tn != tm;   // uniform
   const int M = G.M, N = G.N, K = G.K;
   const int lda = G.lda, ldb = G.ldb, ldc = G.ldc;
 
@@ -417,6 +425,10 @@ void gemm_kernel(const GemmArgs args) {
             v.x = p1[i][j][r] - p2[i][j][r];
             v.y = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
             C[(long long)row * ldc + col] = v;
+            if (mirror) {
+              v.y = -v.y;
+              C[(long long)col * ldc + row] = v;
+            }
           }
         }
       }

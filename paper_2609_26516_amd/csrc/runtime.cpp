@@ -506,9 +506,15 @@ int run_gemm(dcs_ctx* ctx, int ta, int tb, int tc, int tacc, int opa, int opb,
       // the right epilogue's tiles hold columns (0, y) and (1, y) for bn / 2 values of y
       g.tiles_n = epi == GEMM_EPI_RIGHT ? (j.N / 2 + bn / 2 - 1) / (bn / 2) : (j.N + bn - 1) / bn;
       g.tiles_per_item = ((j.M + bm - 1) / bm) * g.tiles_n;
+      g.herm = j.herm && j.M == j.N && bm == bn && epi == GEMM_EPI_NONE && tacc != ACC_BF16X3;
+      double part = 1.0;   // share of the product's tiles computed
+      if (g.herm) {
+        g.tiles_per_item = g.tiles_n * (g.tiles_n + 1) / 2;
+        part = (double)g.tiles_per_item / ((double)g.tiles_n * g.tiles_n);
+      }
       g.tile_begin = tiles;
       tiles += g.tiles_per_item * j.batch;
-      flops += 8.0 * j.M * j.N * (double)j.K * j.batch;
+      flops += 8.0 * j.M * j.N * (double)j.K * j.batch * part;
       bytes += es * ((double)j.M * j.K + (double)j.K * j.N + (double)j.M * j.N) * j.batch;
       if (epi != GEMM_EPI_NONE)   // operator: 8 (2 wl)(2 wr) flops per (row, column) group
         flops += 8.0 * (2.0 * j.wl) * (2.0 * j.wr) * j.batch *
@@ -1880,6 +1886,7 @@ int enqueue_norms(dcs_state* st, int n, const int* ids, const int* qubits, hipSt
         // E_{j+1} = A_j^H A_j
         std::vector<GemmJob> a{{site(g, j), site(g, j), ebuf(), g.ids_dev, dr, dr, 2 * dl, dr, dr,
                                 dr, bsz}};
+        a[0].herm = 1;
         DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_C, OP_N, a, s, CLS_MEAS));
         e_nontrivial = true;
       } else {
@@ -1888,6 +1895,7 @@ int enqueue_norms(dcs_state* st, int n, const int* ids, const int* qubits, hipSt
         DCS_TRY(run_gemm(st->ctx, CT_F64, ct, CT_F64, CT_F64, OP_N, OP_N, a, s, CLS_MEAS));
         std::vector<GemmJob> b{{site(g, j), tx(), ebuf(), g.ids_dev, dr, dr, 2 * dl, dr, dr, dr,
                                 bsz}};
+        b[0].herm = 1;   // A^H (E A), E Hermitian
         DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_C, OP_N, b, s, CLS_MEAS));
       }
     }
@@ -1898,6 +1906,7 @@ int enqueue_norms(dcs_state* st, int n, const int* ids, const int* qubits, hipSt
         // G_j = conj(A_j) A_j^T over (s, b)
         std::vector<GemmJob> a{{site(g, j), site(g, j), gbuf(), g.ids_dev, dl, dl, 2 * dr, 2 * dr,
                                 2 * dr, dl, bsz}};
+        a[0].herm = 1;
         DCS_TRY(run_gemm(st->ctx, ct, ct, CT_F64, CT_F64, OP_J, OP_T, a, s, CLS_MEAS));
         g_nontrivial = true;
       } else {
@@ -1906,6 +1915,7 @@ int enqueue_norms(dcs_state* st, int n, const int* ids, const int* qubits, hipSt
         DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_N, OP_T, a, s, CLS_MEAS));
         std::vector<GemmJob> b{{site(g, j), ty(), gbuf(), g.ids_dev, dl, dl, 2 * dr, 2 * dr,
                                 2 * dr, dl, bsz}};
+        b[0].herm = 1;   // conj(A) (A G^T)^T, Hermitian as G is
         DCS_TRY(run_gemm(st->ctx, ct, CT_F64, CT_F64, CT_F64, OP_J, OP_T, b, s, CLS_MEAS));
       }
     }

@@ -41,6 +41,9 @@ struct GemmJob {
   int epi = GEMM_EPI_NONE;
   Operand w = Operand{nullptr, 0, 0, 0};
   int wl = 0, wr = 0;
+  // the product is Hermitian (M = N): computed on and below the diagonal
+  // where the tile shape is square, and mirrored
+  int herm = 0;
 };
 struct QrJob {
   Operand f, q, ws, nrm2;

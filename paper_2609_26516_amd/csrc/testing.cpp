@@ -173,9 +173,13 @@ int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int
       return testing_fail(DCS_EINVAL, "bad gemm test arguments");
     if ((opa != OP_N && opa != OP_C && opa != OP_J) || (opb != OP_N && opb != OP_T))
       return testing_fail(DCS_EINVAL, "bad op");
+    const bool herm = (variant & 16) != 0;
+    variant &= ~16;
     if (variant < 0 || variant >= GEMM_VARIANTS) return testing_fail(DCS_EINVAL, "bad tile shape");
     int bm = 64, bn = 64;
     gemm_tile_shape(variant, &bm, &bn);
+    if (herm && (M != N || bm != bn))
+      return testing_fail(DCS_EINVAL, "the Hermitian mode takes M = N and a square tile");
     hipStream_t s = static_cast<hipStream_t>(stream);
     DevBuf da, db, dc;
     const size_t na = (size_t)M * K * batch, nb = (size_t)K * N * batch, nc = (size_t)M * N * batch;
@@ -200,6 +204,11 @@ int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int
     g.batch = batch;
     g.tiles_n = (N + bn - 1) / bn;
     g.tiles_per_item = ((M + bm - 1) / bm) * g.tiles_n;
+    if (herm) {
+      if (tacc == ACC_BF16X3) return testing_fail(DCS_EINVAL, "no Hermitian mode in the split-BF16 form");
+      g.herm = 1;
+      g.tiles_per_item = g.tiles_n * (g.tiles_n + 1) / 2;
+    }
     g.tile_begin = 0;
     args.ngroups = 1;
     args.total_tiles = g.tiles_per_item * batch;

@@ -342,3 +342,33 @@ def test_permute_tiled_takes_tree_shapes(capi):
                 continue
             np.testing.assert_array_equal(y, _perm_ref(x, perm, True, F64),
                                           err_msg=f"{dims} {perm} variant {variant}")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 4])
+@pytest.mark.parametrize("n,k", [(1, 3), (64, 40), (70, 33), (256, 130), (300, 64)])
+def test_gemm_hermitian_mode(capi, variant, n, k):
+    """Measurement transfers A^H (E A) and conj(A) (A G^T)^T: in the Hermitian
+    mode only the tiles on and below the diagonal are computed; they equal the
+    full product's, and every tile above the diagonal is exactly the conjugate
+    transpose of its mirror."""
+    rng = np.random.default_rng(n * 7 + k + variant)
+    tile = {0: 64, 1: 32, 4: 128}[variant]
+    a = _rand(rng, 2, k, n).astype(np.complex64).astype(np.complex128)   # stored K x M
+    e = _rand(rng, 2, k, k)
+    e = e + e.conj().transpose(0, 2, 1)
+    ea = e @ a                                                           # E A, K x N
+    cases = [((F32, F32, F64, F64), OPC, OPN, a, a, a.conj().transpose(0, 2, 1) @ a),
+             ((F32, F64, F64, F64), OPC, OPN, a, ea, a.conj().transpose(0, 2, 1) @ ea)]
+    if variant == 4:   # the 128 x 128 tile exists for FP32 accumulation only
+        cases = [((F32, F32, F32, F32), OPC, OPN, a, a, a.conj().transpose(0, 2, 1) @ a)]
+    i, j = np.indices((n, n))
+    below = (i // tile) > (j // tile)
+    on_or_below = (i // tile) >= (j // tile)
+    for types, opa, opb, x, y, ref in cases:
+        full = capi.dcs_test_gemm(*types, opa, opb, x, y, variant=variant).reshape(2, n, n)
+        herm = capi.dcs_test_gemm(*types, opa, opb, x, y, variant=variant | 16).reshape(2, n, n)
+        tol = 1e-12 if types[3] == F64 else 1e-4
+        assert np.max(np.abs(herm - ref)) <= tol * max(1.0, np.max(np.abs(ref)))
+        for b in range(2):
+            np.testing.assert_array_equal(herm[b][on_or_below], full[b][on_or_below])
+            np.testing.assert_array_equal(herm[b][below.T], herm[b].conj().T[below.T])
