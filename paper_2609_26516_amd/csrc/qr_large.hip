@@ -547,7 +547,7 @@ __device__ __noinline__ void tall_fallback(const double2* A, double2* V, double2
 // A panel the Cholesky QR does not take (an exact zero, a small pivot, a
 // squared norm out of range, no rows below the diagonal block) is factored
 // column by column by the chunk-0 workgroup of qrt_v (tall_fallback); qrt_q1
-// passes its verdict on through the flag in the scratch.
+// passes its decision on through the flag in the scratch.
 struct QrtCtx {
   double2 *A, *V, *Tg, *sc;
   int m, n, mp, nbk, k, nblk, nch;

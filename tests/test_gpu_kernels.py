@@ -372,3 +372,17 @@ def test_gemm_hermitian_mode(capi, variant, n, k):
         for b in range(2):
             np.testing.assert_array_equal(herm[b][on_or_below], full[b][on_or_below])
             np.testing.assert_array_equal(herm[b][below.T], herm[b].conj().T[below.T])
+
+
+def test_permute_tree_full_size(capi):
+    """The largest leg transposition of the 27-qubit tree workload at its real
+    size (4.2 million elements per item: a node tensor with two operator legs),
+    tiled kernel and the kernel the library picks, against the definition."""
+    dims = [8, 8, 4, 4, 32, 4, 32]               # input legs, row-major
+    perm = [0, 2, 4, 6, 1, 5, 3]                 # output leg k = input leg perm[k]
+    rng = np.random.default_rng(27)
+    x = (_rand(rng, 1, *dims)).astype(np.complex64).astype(np.complex128)
+    ref = _perm_ref(x, perm, False, F32)
+    for variant in (0, 2):
+        y = capi.dcs_test_permute(F32, F32, x, perm, False, variant)
+        np.testing.assert_array_equal(y, ref)
