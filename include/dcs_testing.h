@@ -33,6 +33,19 @@ int dcs_test_gemm(int ta, int tb, int tc, int tacc, int opa, int opb, int M, int
                   int batch, int variant, const double *A, const double *B, double *C,
                   void *stream);
 
+/* Contraction with the gate operator applied in its epilogue (the fused
+ * form of the compression step, operator bonds wl, wr in {1, 2, 4}), one
+ * item, storage and accumulation type ct (0 complex64 / FP32, 1 complex128 /
+ * FP64).  dir 0 (moving right): X1 = A B (A M x K, B K x N row-major, M =
+ * d0 wl, N = 2 d1, X1[a][wl][t][y]) -> C = X2[a][s][wr][y] (d0 x 2 x wr x
+ * d1).  dir 1 (moving left): Y1 = A B^T (A M x K, B stored N x K, M = 2 d0,
+ * N = d1 wr, Y1[x][t][c][wr]) -> C = Y2[wl][x][s][c] (wl x d0 x 2 x d1).
+ * W[wl][s][t][wr] as for dcs_test_mpo; variant: tile shape as for
+ * dcs_test_gemm (128 x 128 for complex64 only). */
+int dcs_test_gemm_gate(int ct, int dir, int M, int N, int K, int wl, int wr, int variant,
+                       const double *A, const double *B, const double *W, double *C,
+                       void *stream);
+
 /* Gate-operator application.  dir 0: in X1[d0][wl][2][d1] -> out
  * X2[d0][2][wr][d1]; dir 1: in Y1[d0][2][d1][wr] -> out Y2[wl][d0][2][d1];
  * w = W[wl][2][2][wr]. */

@@ -40,7 +40,7 @@ EXPORTED = [
     "dcs_tree_collapse", "dcs_tree_export",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy",
-                    "dcs_test_permute", "dcs_test_permute_dev"]
+                    "dcs_test_permute", "dcs_test_permute_dev", "dcs_test_gemm_gate"]
 
 
 class DcsError(RuntimeError):
@@ -116,6 +116,7 @@ _SIGS = {
     "dcs_test_qr": (c_int, [c_int] * 6 + [_DP, _DP, _DP, _P]),
     "dcs_test_copy": (c_int, [_P, _P, ctypes.c_size_t, c_int, _P]),
     "dcs_test_permute": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_DP, _DP, _P]),
+    "dcs_test_gemm_gate": (c_int, [c_int] * 8 + [_DP, _DP, _DP, _DP, _P]),
     "dcs_test_permute_dev": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_P, _P, c_int, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -546,3 +547,18 @@ def dcs_test_permute_dev(ct_in, ct_out, dims, perm, src: int, dst: int, conj=Fal
     p = (ctypes.c_int * len(perm))(*perm)
     _check(_lib.dcs_test_permute_dev(ct_in, ct_out, len(dims), d, p, int(bool(conj)), batch,
                                      int(variant), src, dst, reps, stream))
+
+
+def dcs_test_gemm_gate(ct, direction, a, b, w, variant=0, stream=0) -> np.ndarray:
+    """a: (M, K); b: (K, N) for direction 0, (N, K) for 1; w: (wl, 2, 2, wr).
+    Returns the operator-applied product, flat."""
+    a, b, w = _c128(a), _c128(b), _c128(w)
+    m, k = a.shape
+    n = b.shape[1] if direction == 0 else b.shape[0]
+    wl, wr = w.shape[0], w.shape[3]
+    nc = (m // wl) * 2 * wr * (n // 2) if direction == 0 else wl * (m // 2) * 2 * (n // wr)
+    c = np.zeros(nc, dtype=np.complex128)
+    _check(_lib.dcs_test_gemm_gate(ct, direction, m, n, k, wl, wr, int(variant),
+                                   _dp(a.view(np.float64)), _dp(b.view(np.float64)),
+                                   _dp(w.view(np.float64)), _dp(c.view(np.float64)), stream))
+    return c

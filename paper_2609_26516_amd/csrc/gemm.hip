@@ -438,6 +438,36 @@ void gemm_kernel(const GemmArgs args) {
     // the order of the stand-alone operator kernels.
     constexpr int W4 = GEMM_EPI_WMAX;
     const int wl = G.wl, wr = G.wr;
+    // A operand: W_real[li][4 kk + lk], row li = output (j, c'), column
+    // 4 kk + lk = input (k = (4 kk + lk) / 2, c = lk & 1); W is in LDS since
+    // the K loop's first barrier
+    R wa[4];
+    {
+      int j, cp;
+      if constexpr (sizeof(R) == 4) {
+        j = li >> 1;
+        cp = li & 1;
+      } else {
+        j = li & 7;
+        cp = li >> 3;
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 2 * kk + (lk >> 1), c = lk & 1;
+        CC w;
+        w.x = 0;
+        w.y = 0;
+        if constexpr (EPI == GEMM_EPI_RIGHT) {
+          const int wli = k >> 1, t = k & 1, sp = j / W4, o = j % W4;
+          if (wli < wl && o < wr) w = sW[((wli * 2 + sp) * 2 + t) * wr + o];
+        } else {
+          const int t = k / W4, o = k % W4, l = j >> 1, sp = j & 1;
+          if (o < wr && l < wl) w = sW[((l * 2 + sp) * 2 + t) * wr + o];
+        }
+        // y = w x: re(y) = re w re x - im w im x, im(y) = im w re x + re w im x
+        wa[kk] = cp == 0 ? (c == 0 ? w.x : -w.y) : (c == 0 ? w.y : w.x);
+      }
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       __syncthreads();   // the K loop's (or the previous half's) LDS reads are done
@@ -455,84 +485,92 @@ void gemm_kernel(const GemmArgs args) {
       }
       __syncthreads();
       const int mh = m0 + h * (BM / 2);
-      if constexpr (EPI == GEMM_EPI_RIGHT) {
-        // X1[a][wl][t][y] -> X2[a][s][wr][y]
-        constexpr int HB = BN / 2;
-        const int kr = N / 2, dl = M / wl, na = (BM / 2) / wl;
-        for (int p = tid; p < na * HB; p += NT) {
-          const int yl = p % HB, al = p / HB;
+      // The operator as one real 16 x 16 matrix on the matrix cores: item n
+      // (a row group and a column) has 8 complex inputs x_k and 8 complex
+      // outputs y_j = sum_k W_jk x_k; as reals, row jrow(j, c') of the
+      // product is component c' of y_j and row 2k + c of the input component
+      // c of x_k.  16 items per product, 4 MFMA k-steps.
+      //   RIGHT  k = 2 wl_i + t, j = 4 sp + o: W[wl_i][sp][t][o]
+      //          x_k = X1[a][wl_i][t][y], y_j to X2[a][sp][o][y]
+      //   LEFT   k = 4 t + o,   j = 2 l + sp: W[l][sp][t][o]
+      //          x_k = Y1[x][t][c][o], y_j to Y2[l][x][sp][c]
+      // The output rows are ordered so that a lane holds whole complex
+      // outputs: 2 j + c' for the FP32 layout (rows 4 lk + r), 8 c' + j for
+      // the FP64 layout (rows lk + 4 r).
+      const int nitems = EPI == GEMM_EPI_RIGHT ? ((BM / 2) / wl) * (BN / 2) : (BM / 4) * (BN / wr);
+      for (int blk0 = wave * 16; blk0 < nitems; blk0 += 4 * 16) {
+        const int item = blk0 + li;
+        bool valid = item < nitems;
+        int ra = 0, rb = 0, cbase = 0;   // LDS row base / column base of the item, and its output place
+        long long obase = 0;
+        if constexpr (EPI == GEMM_EPI_RIGHT) {
+          constexpr int HB = BN / 2;
+          const int yl = item % HB, al = item / HB;
           const int a = mh / wl + al, y = n0 + yl;
-          if (a >= dl || y >= kr) continue;
-          R xr[2 * W4], xi[2 * W4];
-#pragma unroll
-          for (int k = 0; k < 2 * W4; ++k) {   // k = wl_i * 2 + t
-            xr[k] = 0;
-            xi[k] = 0;
-            if (k < 2 * wl) {
-              xr[k] = sC_r[al * wl + (k >> 1)][(k & 1) * HB + yl];
-              xi[k] = sC_i[al * wl + (k >> 1)][(k & 1) * HB + yl];
-            }
-          }
-#pragma unroll
-          for (int sp = 0; sp < 2; ++sp) {
-#pragma unroll
-            for (int o = 0; o < W4; ++o) {
-              if (o < wr) {
-                R accr = 0, acci = 0;
-#pragma unroll
-                for (int k = 0; k < 2 * W4; ++k) {
-                  if (k < 2 * wl) {
-                    const CC w = sW[(((k >> 1) * 2 + sp) * 2 + (k & 1)) * wr + o];
-                    accr = efma(-w.y, xi[k], efma(w.x, xr[k], accr));
-                    acci = efma(w.y, xr[k], efma(w.x, xi[k], acci));
-                  }
-                }
-                CC v;
-                v.x = accr;
-                v.y = acci;
-                C[(((long long)a * 2 + sp) * wr + o) * ldc + y] = v;
-              }
-            }
-          }
-        }
-      } else {
-        // Y1[x][t][c][wr] -> Y2[wl][x][s][c]
-        const int kl = M / 2, dr = N / wr, nx = BM / 4, nc = BN / wr;
-        for (int p = tid; p < nx * nc; p += NT) {
-          const int cl = p % nc, xl = p / nc;
+          valid = valid && a < M / wl && y < N / 2;
+          ra = al * wl;
+          cbase = yl;
+          obase = (long long)a * 2 * wr * ldc + y;
+          rb = HB;
+        } else {
+          const int nc = BN / wr;
+          const int cl = item % nc, xl = item / nc;
           const int x = mh / 2 + xl, c = n0 / wr + cl;
-          if (x >= kl || c >= dr) continue;
-          R yr[2 * W4], yi[2 * W4];
+          valid = valid && x < M / 2 && c < N / wr;
+          ra = xl * 2;
+          cbase = cl * wr;
+          obase = (long long)x * 2 * ldc + c;
+        }
+        // B operand: input row 4 kk + lk = component (lk & 1) of x_k,
+        // k = 2 kk + (lk >> 1)
+        R acc_v[4];
+        V acc;
 #pragma unroll
-          for (int k = 0; k < 2 * W4; ++k) {   // k = t * W4 + wr_i
-            const int tt = k / W4, o = k % W4;
-            yr[k] = 0;
-            yi[k] = 0;
-            if (o < wr) {
-              yr[k] = sC_r[xl * 2 + tt][cl * wr + o];
-              yi[k] = sC_i[xl * 2 + tt][cl * wr + o];
-            }
+        for (int r = 0; r < 4; ++r) acc[r] = 0;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 2 * kk + (lk >> 1);
+          int row, col;
+          bool in;
+          if constexpr (EPI == GEMM_EPI_RIGHT) {
+            const int wli = k >> 1, t = k & 1;
+            in = valid && wli < wl;
+            row = ra + wli;
+            col = t * rb + cbase;
+          } else {
+            const int t = k / W4, o = k % W4;
+            in = valid && o < wr;
+            row = ra + t;
+            col = cbase + o;
           }
+          const R xv = !in ? R(0) : ((lk & 1) ? sC_i[row][col] : sC_r[row][col]);
+          acc = Mfma<R>::mma(wa[kk], xv, acc);
+        }
 #pragma unroll
-          for (int l = 0; l < W4; ++l) {
-            if (l < wl) {
+        for (int r = 0; r < 4; ++r) acc_v[r] = acc[r];
+        if (valid) {
+          // the two complex outputs of this lane: (j, re at slot r0, im at slot r1)
 #pragma unroll
-              for (int sp = 0; sp < 2; ++sp) {
-                R accr = 0, acci = 0;
-#pragma unroll
-                for (int k = 0; k < 2 * W4; ++k) {
-                  const int tt = k / W4, o = k % W4;
-                  if (o < wr) {
-                    const CC w = sW[((l * 2 + sp) * 2 + tt) * wr + o];
-                    accr = efma(-w.y, yi[k], efma(w.x, yr[k], accr));
-                    acci = efma(w.y, yr[k], efma(w.x, yi[k], acci));
-                  }
-                }
-                CC v;
-                v.x = accr;
-                v.y = acci;
-                C[(((long long)l * kl + x) * 2 + sp) * ldc + c] = v;
-              }
+          for (int q = 0; q < 2; ++q) {
+            int j, r0, r1;
+            if constexpr (sizeof(R) == 4) {   // rows 4 lk + r: 2 j + c'
+              j = 2 * lk + q;
+              r0 = 2 * q;
+              r1 = 2 * q + 1;
+            } else {                          // rows lk + 4 r: 8 c' + j
+              j = lk + 4 * q;
+              r0 = q;
+              r1 = q + 2;
+            }
+            CC v;
+            v.x = acc_v[r0];
+            v.y = acc_v[r1];
+            if constexpr (EPI == GEMM_EPI_RIGHT) {
+              const int sp = j / W4, o = j % W4;
+              if (o < wr) C[obase + (long long)(sp * wr + o) * ldc] = v;
+            } else {
+              const int l = j >> 1, sp = j & 1;
+              if (l < wl) C[obase + ((long long)l * (M / 2) * 2 + sp) * ldc] = v;
             }
           }
         }

@@ -1503,8 +1503,10 @@ int dcs_compress_step(dcs_state* st, int n, const int* ids, const dcs_chunk* con
     // bra_j (starting guess or LQ factor) or (b) F = L_j Y2
     // the gate operator goes into the epilogue of the contraction that
     // produces its input (complex64 / complex128 contractions, bonds <= 4)
+    // (bonds of 1, 2 or 4: a tile then holds whole row and column groups)
     auto fuse = [&](int wl, int wr) {
-      return acc != ACC_BF16X3 && wl <= GEMM_EPI_WMAX && wr <= GEMM_EPI_WMAX;
+      return acc != ACC_BF16X3 && wl <= GEMM_EPI_WMAX && wr <= GEMM_EPI_WMAX &&
+             (wl & (wl - 1)) == 0 && (wr & (wr - 1)) == 0;
     };
     auto left_prologue = [&](int j) -> int {
       std::vector<GemmJob> gj;

@@ -322,6 +322,62 @@ int dcs_test_qr(int ct_in, int ct_out, int m, int n, int mode, int use_lds, cons
   });
 }
 
+int dcs_test_gemm_gate(int ct, int dir, int M, int N, int K, int wl, int wr, int variant,
+                       const double* A, const double* B, const double* W, double* C,
+                       void* stream) {
+  return guarded([&]() -> int {
+    auto pow2 = [](int w) { return w >= 1 && w <= GEMM_EPI_WMAX && (w & (w - 1)) == 0; };
+    if (M < 1 || N < 1 || K < 1 || !A || !B || !W || !C || (ct != CT_F32 && ct != CT_F64) ||
+        (dir != 0 && dir != 1) || !pow2(wl) || !pow2(wr) || variant < 0 || variant >= GEMM_VARIANTS ||
+        (ct == CT_F64 && variant == GEMM_128x128))
+      return testing_fail(DCS_EINVAL, "bad gate-epilogue test arguments");
+    if (dir == 0 ? (M % wl != 0 || N % 2 != 0) : (M % 2 != 0 || N % wr != 0))
+      return testing_fail(DCS_EINVAL, "gate-epilogue test: shape does not hold whole groups");
+    int bm = 64, bn = 64;
+    gemm_tile_shape(variant, &bm, &bn);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf da, db, dw, dc;
+    // output: d0 x 2 x wr x d1 (M = d0 wl, N = 2 d1) or wl x d0 x 2 x d1 (M = 2 d0, N = d1 wr)
+    const size_t na = (size_t)M * K, nb = (size_t)K * N, nw = (size_t)wl * 4 * wr;
+    const size_t nc = dir == 0 ? (size_t)(M / wl) * 2 * wr * (N / 2) : (size_t)wl * (M / 2) * 2 * (N / wr);
+    int rc = upload(ct, A, na, da, s);
+    if (rc) return rc;
+    rc = upload(ct, B, nb, db, s);
+    if (rc) return rc;
+    rc = upload(ct, W, nw, dw, s);
+    if (rc) return rc;
+    T_HIP(hipMalloc(&dc.p, nc * csz(ct)));
+    GemmArgs args;
+    std::memset(&args, 0, sizeof(args));
+    GemmGroup& g = args.g[0];
+    g.a = op_of(da.p, 0);
+    g.b = op_of(db.p, 0);
+    g.c = op_of(dc.p, 0);
+    g.w = op_of(dw.p, 0);
+    g.ids = nullptr;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = K;
+    g.ldb = dir == 0 ? N : K;
+    g.ldc = dir == 0 ? N / 2 : N / wr;
+    g.batch = 1;
+    g.wl = wl;
+    g.wr = wr;
+    g.tiles_n = dir == 0 ? (N / 2 + bn / 2 - 1) / (bn / 2) : (N + bn - 1) / bn;
+    g.tiles_per_item = ((M + bm - 1) / bm) * g.tiles_n;
+    args.ngroups = 1;
+    args.total_tiles = g.tiles_per_item;
+    args.epi = dir == 0 ? GEMM_EPI_RIGHT : GEMM_EPI_LEFT;
+    T_HIP(launch_gemm(ct, ct, ct, ct, OP_N, dir == 0 ? OP_N : OP_T, variant, args, s));
+    std::vector<char> h(nc * csz(ct));
+    T_HIP(hipMemcpyAsync(h.data(), dc.p, h.size(), hipMemcpyDeviceToHost, s));
+    T_HIP(hipStreamSynchronize(s));
+    unpack(ct, h, C, nc);
+    return DCS_OK;
+  });
+}
+
 int dcs_test_permute(int ct_in, int ct_out, int rank, const int* dims, const int* perm, int conj,
                      int batch, int variant, const double* in, double* out, void* stream) {
   return guarded([&]() -> int {

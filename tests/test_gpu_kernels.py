@@ -386,3 +386,36 @@ def test_permute_tree_full_size(capi):
     for variant in (0, 2):
         y = capi.dcs_test_permute(F32, F32, x, perm, False, variant)
         np.testing.assert_array_equal(y, ref)
+
+
+@pytest.mark.parametrize("ct", [F32, F64])
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("d0,d1,k,wl,wr", [(3, 5, 7, 1, 4), (16, 32, 40, 4, 4), (33, 70, 65, 4, 1),
+                                           (9, 40, 16, 2, 4), (70, 33, 130, 4, 2),
+                                           (64, 64, 256, 4, 4)])
+def test_gemm_gate_epilogue(capi, ct, direction, d0, d1, k, wl, wr):
+    """The contraction with the gate operator applied in its epilogue (on the
+    matrix cores) against the product followed by the operator, for every
+    tile shape, and bit-identical across tile shapes."""
+    rng = np.random.default_rng(d0 * 13 + d1 * 7 + k + wl * 3 + wr + direction)
+    w = _rand(rng, wl, 2, 2, wr)
+    if direction == 0:
+        a, b = _rand(rng, d0 * wl, k), _rand(rng, k, 2 * d1)
+    else:
+        a, b = _rand(rng, 2 * d0, k), _rand(rng, d1 * wr, k)
+    if ct == F32:
+        a, b, w = (z.astype(np.complex64).astype(np.complex128) for z in (a, b, w))
+    if direction == 0:
+        ref = np.einsum("awty,wstv->asvy", (a @ b).reshape(d0, wl, 2, d1), w).reshape(-1)
+    else:
+        ref = np.einsum("xtcv,wstv->wxsc", (a @ b.T).reshape(d0, 2, d1, wr), w).reshape(-1)
+    scale = np.max(np.abs(ref))
+    tol = 1e-12 if ct == F64 else 2e-5
+    first = None
+    for variant in ([0, 1, 2, 3, 4] if ct == F32 else [0, 1, 2, 3]):
+        out = capi.dcs_test_gemm_gate(ct, direction, a, b, w, variant)
+        assert np.max(np.abs(out - ref)) <= tol * scale, f"variant {variant}"
+        if first is None:
+            first = out
+        else:
+            np.testing.assert_array_equal(out, first, err_msg=f"variant {variant}")
