@@ -73,12 +73,6 @@ constexpr int NT = 256, PAD = 4;
 template <typename R>
 constexpr int gemm_bk() { return 8; }
 
-// Explicit fused multiply-adds in the operator epilogue: every tile shape
-// then performs exactly the same operations (the compiler may not contract
-// the products differently in different instantiations), so results stay
-// bit-identical across tile shapes.
-__device__ __forceinline__ float efma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double efma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int q = total >> 3, r = total & 7;

@@ -953,7 +953,6 @@ int dcs_ctx_tuning_load(dcs_ctx* ctx, const char* path) {
     if (txt.find("dcs-gemm-tiles-1") == std::string::npos)
       return fail(DCS_EINVAL, "not a tile-shape table");
     size_t pos = 0;
-    int loaded = 0;
     while ((pos = txt.find("\"key\": [", pos)) != std::string::npos) {
       pos += 8;
       TuneKey k{};
@@ -965,7 +964,6 @@ int dcs_ctx_tuning_load(dcs_ctx* ctx, const char* path) {
         return fail(DCS_EINVAL, "malformed tile-shape entry");
       if (best < 0 || best >= gemm_variants(k[3])) return fail(DCS_EINVAL, "bad tile shape id");
       ctx->tune[k].best = best;
-      ++loaded;
       pos += used;
     }
     return DCS_OK;
