@@ -272,6 +272,7 @@ template <int NW>
 __device__ __noinline__ void panel_second_pass(
     double2* P, double2* Wp, int nbk, int mp) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
   double2* part0 = Wp;
   double2* part1 = Wp + 256;
   double2 g[4], z2[4];
@@ -371,6 +372,7 @@ __device__ __forceinline__ bool panel_cholqr(double2 (&a)[MAXB][4], int m, int k
   asm volatile("" : "+v"(tid));
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
+  const double2 zero = make_double2(0.0, 0.0);
   double2* part0 = Wp;         // X1, then T
   double2* part1 = Wp + 256;   // staging, then R2^{-1} U^{-1}
 
