@@ -84,6 +84,17 @@ int dcs_test_copy(const void *src, void *dst, size_t bytes, int reps, void *stre
 int dcs_test_permute(int ct_in, int ct_out, int rank, const int *dims, const int *perm, int conj,
                      int batch, int variant, const double *in, double *out, void *stream);
 
+/* Host only (no device call): the tiled kernel's plan for the transposition
+ * of dcs_test_permute with elements of esize bytes (8 or 16).  *planned = 1
+ * with the plan in out (pi, pc, pa, po, pitch, tiles, elements per thread,
+ * ni, nc, na, nr, then the leg descriptors: I extents and LDS weights, C
+ * extents, input strides and LDS weights, A extents and output strides, the
+ * tile-indexing legs' extents, input strides and output strides), or 0 when
+ * the tiled kernel does not take the transposition.  For checking the
+ * planner's index maps on the host. */
+int dcs_test_permute_plan(int rank, const int *dims, const int *perm, int esize, int *out,
+                          int out_len, int *planned);
+
 /* The same transposition on device buffers (`in`: batch items of the input
  * storage type, `out`: batch items of the output type, both device memory),
  * `reps` times, enqueued on the stream without synchronisation.  For timing

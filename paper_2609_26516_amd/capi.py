@@ -40,7 +40,8 @@ EXPORTED = [
     "dcs_tree_collapse", "dcs_tree_export",
 ]
 EXPORTED_TESTING = ["dcs_test_gemm", "dcs_test_mpo", "dcs_test_qr", "dcs_test_copy",
-                    "dcs_test_permute", "dcs_test_permute_dev", "dcs_test_gemm_gate"]
+                    "dcs_test_permute", "dcs_test_permute_dev", "dcs_test_gemm_gate",
+                    "dcs_test_permute_plan"]
 
 
 class DcsError(RuntimeError):
@@ -117,6 +118,7 @@ _SIGS = {
     "dcs_test_copy": (c_int, [_P, _P, ctypes.c_size_t, c_int, _P]),
     "dcs_test_permute": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_DP, _DP, _P]),
     "dcs_test_gemm_gate": (c_int, [c_int] * 8 + [_DP, _DP, _DP, _DP, _P]),
+    "dcs_test_permute_plan": (c_int, [c_int, _IP, _IP, c_int, _IP, c_int, _IP]),
     "dcs_test_permute_dev": (c_int, [c_int] * 3 + [_IP, _IP] + [c_int] * 3 + [_P, _P, c_int, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -562,3 +564,31 @@ def dcs_test_gemm_gate(ct, direction, a, b, w, variant=0, stream=0) -> np.ndarra
                                    _dp(a.view(np.float64)), _dp(b.view(np.float64)),
                                    _dp(w.view(np.float64)), _dp(c.view(np.float64)), stream))
     return c
+
+
+def dcs_test_permute_plan(dims, perm, esize=8):
+    """The tiled transposition kernel's plan (host only): a dict, or None when
+    the tiled kernel does not take the transposition."""
+    dims = [int(d) for d in dims]
+    perm = [int(p) for p in perm]
+    d = (ctypes.c_int * len(dims))(*dims)
+    p = (ctypes.c_int * len(perm))(*perm)
+    out = (ctypes.c_int * 512)()
+    planned = ctypes.c_int(0)
+    _check(_lib.dcs_test_permute_plan(len(dims), d, p, esize, out, 512, ctypes.byref(planned)))
+    if not planned.value:
+        return None
+    v = list(out)
+    keys = ["pi", "pc", "pa", "po", "pitch", "tiles", "ept", "ni", "nc", "na", "nr"]
+    plan = dict(zip(keys, v[:11]))
+    pos = 11
+
+    def take(n):
+        nonlocal pos
+        r = v[pos:pos + n]
+        pos += n
+        return r
+    ni, nc, na, nr = plan["ni"], plan["nc"], plan["na"], plan["nr"]
+    plan.update(i_ext=take(ni), i_lds=take(ni), c_ext=take(nc), c_in=take(nc), c_lds=take(nc),
+                a_ext=take(na), a_out=take(na), r_ext=take(nr), r_in=take(nr), r_out=take(nr))
+    return plan

@@ -227,6 +227,13 @@ struct PermuteArgs {
 enum { PERMUTE_AUTO = 0, PERMUTE_ELEMENTWISE = 1, PERMUTE_TILED = 2 };
 hipError_t launch_permute(int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s,
                           int variant = PERMUTE_AUTO);
+// The tiled kernel's plan for a transposition (host only, for tests): pi, pc,
+// pa, po, pitch, tiles, elements per thread, ni, nc, na, nr, then the leg
+// descriptors (I: extents, LDS weights; C: extents, input strides, LDS
+// weights; A: extents, output strides; rest: extents, input strides, output
+// strides).  False when the tiled kernel does not take the transposition or
+// out_len is too small.
+bool permute_tile_plan(const PermuteArgs& a, int esize, int* out, int out_len);
 
 // Sum of the split-K partial products of a contraction (complex128):
 // out[item][e] = sum_{s < parts} part[item][s * mn + e] for e < mn, the

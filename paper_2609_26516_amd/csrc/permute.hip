@@ -431,6 +431,26 @@ hipError_t launch_ksum(const KsumArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool permute_tile_plan(const PermuteArgs& a, int esize, int* out, int out_len) {
+  PermuteTileArgs t;
+  int ept = 0;
+  if (!plan_tiled(a, esize, &t, &ept)) return false;
+  std::vector<int> v{t.pi, t.pc, t.pa, t.po, t.pitch, (int)t.tiles, ept, t.ni, t.nc, t.na, t.nr};
+  v.insert(v.end(), t.i_ext, t.i_ext + t.ni);
+  v.insert(v.end(), t.i_lds, t.i_lds + t.ni);
+  v.insert(v.end(), t.c_ext, t.c_ext + t.nc);
+  v.insert(v.end(), t.c_in, t.c_in + t.nc);
+  v.insert(v.end(), t.c_lds, t.c_lds + t.nc);
+  v.insert(v.end(), t.a_ext, t.a_ext + t.na);
+  v.insert(v.end(), t.a_out, t.a_out + t.na);
+  v.insert(v.end(), t.r_ext, t.r_ext + t.nr);
+  v.insert(v.end(), t.r_in, t.r_in + t.nr);
+  v.insert(v.end(), t.r_out, t.r_out + t.nr);
+  if ((int)v.size() > out_len) return false;
+  std::copy(v.begin(), v.end(), out);
+  return true;
+}
+
 hipError_t launch_permute(int ct_in, int ct_out, const PermuteArgs& a, hipStream_t s,
                           int variant) {
   if (a.batch <= 0 || a.total <= 0) return hipSuccess;

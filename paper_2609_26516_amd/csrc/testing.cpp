@@ -403,6 +403,20 @@ int dcs_test_permute(int ct_in, int ct_out, int rank, const int* dims, const int
   });
 }
 
+int dcs_test_permute_plan(int rank, const int* dims, const int* perm, int esize, int* out,
+                          int out_len, int* planned) {
+  return guarded([&]() -> int {
+    if ((esize != 8 && esize != 16) || !out || !planned || out_len < 0)
+      return testing_fail(DCS_EINVAL, "bad permute plan arguments");
+    PermuteArgs a;
+    const int ct = esize == 8 ? CT_F32 : CT_F64;
+    int rc = permute_args(ct, ct, rank, dims, perm, 0, 1, 0, &a);
+    if (rc) return rc;
+    *planned = permute_tile_plan(a, esize, out, out_len) ? 1 : 0;
+    return DCS_OK;
+  });
+}
+
 int dcs_test_permute_dev(int ct_in, int ct_out, int rank, const int* dims, const int* perm,
                          int conj, int batch, int variant, const void* in, void* out, int reps,
                          void* stream) {
